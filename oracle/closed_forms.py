@@ -1,0 +1,118 @@
+"""Exact potentials for the paper's benchmark densities (test infrastructure).
+
+TEST INFRASTRUCTURE: imported only by the tests, the smoke check and the
+benchmark's CPU leg.  Each pair (rho, u*) satisfies ``-Lap u* = rho`` with
+``u* -> 0``; where the paper prints rho, the formula here is ``-Lap u*``
+derived from the printed u* (and checked symbolically in the tests).
+
+  * normalised Gaussian and its erf potential (Section 3.2, eq. gaussian);
+  * two superposed Gaussians (eq. gaussians);
+  * anisotropic Gaussian u* (eq. anis);
+  * oscillating u* = exp(-r^2/s^2) cos(w r^2) (eq. osci).  The printed rho
+    carries ``-4 w^2 r^2 cos(w r^2)``; ``-Lap u*`` has ``+4 w^2 r^2 cos``;
+  * bump u* = exp(-d/(1 - r^2/R^2)) (eq. bump).  The printed rho's exponent and
+    its ``-d R^2 r^2`` term do not match u*; ``-Lap u*`` is
+    ``2 d R^2 (3R^4 - 2R^2 r^2 - r^4 - 2 d R^2 r^2)/(R^2 - r^2)^4
+    exp(-d R^2/(R^2 - r^2))``.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+from scipy.special import erf
+
+
+def paper_grid(N: int, lo: float = -2.0, hi: float = 2.0):
+    """The paper's node grid: N points per axis including both box ends,
+    spacing ``(hi - lo)/(N - 1)``.  Returns (h, X, Y, Z) broadcastable."""
+    h = (hi - lo) / (N - 1)
+    xs = lo + h * np.arange(N)
+    return h, xs[:, None, None], xs[None, :, None], xs[None, None, :]
+
+
+def erf_potential(r, sigma):
+    """Potential of the unit-mass Gaussian of standard deviation sigma:
+    ``erf(r/(sqrt(2) sigma)) / (4 pi r)``, with its limit at r = 0."""
+    r = np.asarray(r, dtype=np.float64)
+    safe = np.where(r > 0, r, 1.0)
+    val = erf(safe / (math.sqrt(2.0) * sigma)) / (4.0 * math.pi * safe)
+    return np.where(r > 0, val, math.sqrt(2.0 / math.pi) / (4.0 * math.pi * sigma))
+
+
+def gaussian_pair(X, Y, Z, sigma, centre=(0.0, 0.0, 0.0)):
+    r = np.sqrt((X - centre[0]) ** 2 + (Y - centre[1]) ** 2 + (Z - centre[2]) ** 2)
+    rho = np.exp(-r * r / (2.0 * sigma * sigma)) / ((2.0 * math.pi) ** 1.5 * sigma ** 3)
+    return rho, erf_potential(r, sigma)
+
+
+def unnormalised_gaussian_potential(r, a):
+    """Potential of ``exp(-|x|^2/a^2)``: ``sqrt(pi) a^3 erf(r/a) / (4 r)``,
+    equal to ``a^2/2`` at r = 0."""
+    r = np.asarray(r, dtype=np.float64)
+    safe = np.where(r > 0, r, 1.0)
+    val = math.sqrt(math.pi) * a ** 3 * erf(safe / a) / (4.0 * safe)
+    return np.where(r > 0, val, 0.5 * a * a)
+
+
+def two_gaussians_pair(X, Y, Z, d=(0.1, -0.05, 0.05), s1=0.2, s2=0.1):
+    r1, u1 = gaussian_pair(X, Y, Z, s1, d)
+    r2, u2 = gaussian_pair(X, Y, Z, s2, tuple(-v for v in d))
+    return 0.5 * (r1 + r2), 0.5 * (u1 + u2)
+
+
+def anisotropic_pair(X, Y, Z, sig=(0.30, 0.20, 0.28), c=(0.0, 0.0, 0.0)):
+    sx, sy, sz = sig
+    dx, dy, dz = X - c[0], Y - c[1], Z - c[2]
+    u = np.exp(-dx ** 2 / sx ** 2 - dy ** 2 / sy ** 2 - dz ** 2 / sz ** 2)
+    rho = -(4 * dx ** 2 / sx ** 4 + 4 * dy ** 2 / sy ** 4 + 4 * dz ** 2 / sz ** 4
+            - 2 / sx ** 2 - 2 / sy ** 2 - 2 / sz ** 2) * u
+    return rho, u
+
+
+def oscillating_pair(X, Y, Z, sigma=0.3, omega=20.0, c=(0.0, 0.0, 0.0)):
+    g = (X - c[0]) ** 2 + (Y - c[1]) ** 2 + (Z - c[2]) ** 2
+    e = np.exp(-g / sigma ** 2)
+    u = e * np.cos(omega * g)
+    rho = (e * (6 * omega * np.sin(omega * g) + 4 * omega ** 2 * g * np.cos(omega * g))
+           - (4 * g / sigma ** 4 - 6 / sigma ** 2) * e * np.cos(omega * g)
+           - 8 * omega * g / sigma ** 2 * e * np.sin(omega * g))
+    return rho, u
+
+
+def oscillating_rho_as_printed(X, Y, Z, sigma=0.3, omega=20.0):
+    """eq. osci exactly as printed (with ``-4 w^2 r^2 cos``), for the test that
+    shows it does not reproduce the paper's own error table."""
+    g = X ** 2 + Y ** 2 + Z ** 2
+    e = np.exp(-g / sigma ** 2)
+    return (e * (6 * omega * np.sin(omega * g) - 4 * omega ** 2 * g * np.cos(omega * g))
+            - (4 * g / sigma ** 4 - 6 / sigma ** 2) * e * np.cos(omega * g)
+            - 8 * omega * g / sigma ** 2 * e * np.sin(omega * g))
+
+
+def bump_pair(X, Y, Z, d=10.0, R=2.0, c=(0.0, 0.0, 0.0)):
+    r2 = (X - c[0]) ** 2 + (Y - c[1]) ** 2 + (Z - c[2]) ** 2
+    inside = r2 < R * R
+    den = np.where(inside, R * R - r2, 1.0)
+    e = np.where(inside, np.exp(-d * R * R / den), 0.0)
+    u = e
+    rho = np.where(inside, 2 * d * R ** 2 * (3 * R ** 4 - 2 * R ** 2 * r2 - r2 ** 2
+                                            - 2 * d * R ** 2 * r2) / den ** 4 * e, 0.0)
+    return rho, u
+
+
+def relative_max_error(u, u_ref):
+    """The paper's E: max |u - u_h| / max |u| over the grid (eq. error_infty)."""
+    return float(np.max(np.abs(u - u_ref)) / np.max(np.abs(u_ref)))
+
+
+def cube_abs_integral(a: float) -> float:
+    """``int_{[-a,a]^3} |y| dy``: by symmetry 8 octants, each 3 times the
+    region where y1 is the largest coordinate; with ``y2 = y1 s, y3 = y1 t``
+    that region gives ``int_0^a y1^3 dy1 * I = a^4 I / 4``, so the total is
+    ``6 a^4 I`` with the smooth ``I = int_0^1 int_0^1 sqrt(1 + s^2 + t^2) ds dt``
+    (mpmath, 30 digits)."""
+    import mpmath as mp
+    mp.mp.dps = 30
+    I = mp.quad(lambda s, t: mp.sqrt(1 + s * s + t * t), [0, 1], [0, 1])
+    return float(6 * mp.mpf(a) ** 4 * I)

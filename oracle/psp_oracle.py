@@ -1,0 +1,395 @@
+"""CPU FP64 oracle for the super-potential Gaussian-sum FFT Poisson solve.
+
+TEST INFRASTRUCTURE.  Only the tests, the smoke check and the CPU-baseline leg
+of the benchmark may import this module.  It shares no code with the GPU
+library: its own Gaussian-sum construction, its own Gauss-Legendre 1D
+quadrature, a plain triple loop for the kernel spectrum, its own naive
+recursive mixed-radix (2 and 3) FFT, and a direct (FFT-free) evaluation of the
+discrete convolution operator.  Everything is float64 numpy.
+
+The method (Exl & Schaffer, "Near-field-free super-potential FFT method for
+the three-dimensional free-space Poisson equation"):
+
+  * the free-space problem ``-Lap u = rho`` on R^3 with ``u -> 0`` (Section 1,
+    eq. problem1) has ``u = U * rho`` with ``U = 1/(4 pi |x|)`` (eq. conv);
+  * ``u = Lap v`` with ``v = V * rho`` and the biharmonic kernel
+    ``V(y) = |y|/(8 pi)`` (eq. superpot, superpot1);
+  * rho is zero-padded by a factor 2 per axis, so the periodic box has side
+    ``L = 2 n h`` and the kernel is truncated to ``[-L/2, L/2]^3``
+    (Section 2, eq. conv2 and the Fourier series that follows it);
+  * ``u = -(2 pi/L)^2 sum_k |k|^2 Vhat_k rhohat_k e^{2 pi i k.x/L}``
+    (eq. convtheorem, written for a general period L instead of L = 2);
+  * ``Vhat_k`` is the Fourier integral of V over the truncation box
+    (eq. Gten0), replaced by that of the Gaussian-sum approximation
+    ``V_GS(y) = |y|^2 sum_s w_s exp(-a_s |y|^2)`` (eq. sin_1_x, gs_x), which
+    separates into products of 1D integrals (eq. Gten_sep);
+  * the solve is Algorithm 2: FFT of the padded rho, multiply, inverse FFT,
+    crop; the precompute is Algorithm 1.
+
+Readings of points the paper leaves open (each also listed in the design
+notes of the repository):
+
+  * Sinc quadrature (Section 2 after the Gamma-integral identity): the
+    substitution ``t = e^u`` in ``1/r = (2/sqrt(pi)) int_0^inf e^{-r^2 t^2} dt``
+    and the trapezoid rule in u with R nodes ``u_s = u0 + s*tau``.  The step
+    tau and offset u0 are fixed, not fitted, by balancing three error
+    estimates at a common level ``eta = e^{-x}``: discretisation
+    ``exp(-pi^2/(2 tau))``, left truncation at ``r = delta`` and right
+    truncation at ``r = eps``; x solves ``(R-1) tau = u_max - u0`` by a fixed
+    100-step bisection on [1, 80].
+  * ``eps = 1e-4 * L/2`` (the paper's default cutoff in units where L = 2) and
+    ``delta = sqrt(3) * L/2`` (the corner of the truncation box).
+  * The 1D integrals run over the full truncation interval ``[-L/2, L/2]``.
+  * The DFT normalisation ``1/(2n)^3`` and the factor ``-(2 pi/L)^2`` are
+    folded into one real multiplier per wavenumber.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+__all__ = [
+    "default_eps_delta", "gs_parameters", "gs_weights", "gs_biharmonic",
+    "gauss_legendre", "tables_1d", "spectrum_octant", "multiplier_octant",
+    "fft_naive", "fftn_naive", "solve", "solve_padded", "direct_operator",
+    "direct_points", "Setup", "setup",
+]
+
+# --------------------------------------------------------------------------
+# Algorithm 1, step 1: Gaussian-sum weights and exponents (Section 2,
+# eq. sin_1_x and gs_x).
+# --------------------------------------------------------------------------
+
+
+def default_eps_delta(n: int, h: float):
+    """Cutoff eps and outer radius delta for an n-point axis of spacing h."""
+    half = n * h          # L/2 with L = 2 n h
+    return 1e-4 * half, math.sqrt(3.0) * half
+
+
+def _count_fn(x: float, eps: float, delta: float) -> float:
+    # number of trapezoid steps needed to span [u0, u_max] at error level e^-x
+    tau = math.pi ** 2 / (2.0 * x)
+    u0 = -x - math.log(2.0 * delta / math.sqrt(math.pi))
+    umax = math.log(math.sqrt(x) / eps)
+    return (umax - u0) / tau
+
+
+def gs_parameters(R: int, eps: float, delta: float):
+    """Trapezoid step tau and first node u0 for an R-term sinc quadrature of
+    1/r on (eps, delta] (sinc quadrature, Section 2)."""
+    if R < 1:
+        raise ValueError("R must be >= 1")
+    target = float(R - 1)
+    lo, hi = 1.0, 80.0
+    for _ in range(100):
+        mid = 0.5 * (lo + hi)
+        if _count_fn(mid, eps, delta) > target:
+            hi = mid
+        else:
+            lo = mid
+    x = lo
+    tau = math.pi ** 2 / (2.0 * x)
+    u0 = -x - math.log(2.0 * delta / math.sqrt(math.pi))
+    return tau, u0
+
+
+def gs_weights(R: int, eps: float, delta: float):
+    """Weights w_s and exponents a_s, s = 0..R-1, with
+    ``1/(8 pi r) ~= sum_s w_s exp(-a_s r^2)`` on (eps, delta] (eq. sin_1_x).
+
+    From ``1/r = (2/sqrt(pi)) int exp(-r^2 e^{2u} + u) du`` the trapezoid
+    rule gives ``a_s = e^{2 u_s}`` and ``w_s = tau e^{u_s} / (4 pi^{3/2})``.
+    """
+    tau, u0 = gs_parameters(R, eps, delta)
+    omega = np.empty(R)
+    alpha = np.empty(R)
+    c = tau / (4.0 * math.pi ** 1.5)
+    for s in range(R):
+        u = u0 + s * tau
+        alpha[s] = math.exp(2.0 * u)
+        omega[s] = c * math.exp(u)
+    return omega, alpha
+
+
+def gs_biharmonic(r, omega, alpha):
+    """``V_GS(r) = r^2 sum_s w_s exp(-a_s r^2)`` (eq. gs_x), elementwise in r."""
+    r = np.asarray(r, dtype=np.float64)
+    r2 = r * r
+    acc = np.zeros_like(r2)
+    for w, a in zip(omega, alpha):
+        acc += w * np.exp(-a * r2)
+    return r2 * acc
+
+
+# --------------------------------------------------------------------------
+# Algorithm 1, step 2: 1D integrals of eq. Gten_sep by composite
+# Gauss-Legendre quadrature, then the tensor assembly by a plain loop.
+# --------------------------------------------------------------------------
+
+
+def gauss_legendre(m: int):
+    """Nodes and weights of the m-point Gauss-Legendre rule on [-1, 1],
+    by Newton iteration on the three-term Legendre recurrence."""
+    x = np.cos(math.pi * (np.arange(1, m + 1) - 0.25) / (m + 0.5))
+    for _ in range(100):
+        p0 = np.ones_like(x)
+        p1 = x.copy()
+        for k in range(2, m + 1):
+            p0, p1 = p1, ((2 * k - 1) * x * p1 - (k - 1) * p0) / k
+        dp = m * (x * p1 - p0) / (x * x - 1.0)
+        dx = p1 / dp
+        x = x - dx
+        if np.max(np.abs(dx)) < 1e-16:
+            break
+    p0 = np.ones_like(x)
+    p1 = x.copy()
+    for k in range(2, m + 1):
+        p0, p1 = p1, ((2 * k - 1) * x * p1 - (k - 1) * p0) / k
+    dp = m * (x * p1 - p0) / (x * x - 1.0)
+    w = 2.0 / ((1.0 - x * x) * dp * dp)
+    order = np.argsort(x)
+    return x[order], w[order]
+
+
+_GL_POINTS = 24
+
+
+def tables_1d(alpha, n: int, L: float):
+    """``J0[s,k] = int_{-L/2}^{L/2} exp(-a_s y^2) cos(2 pi k y / L) dy`` and
+    ``J2[s,k] = int_{-L/2}^{L/2} y^2 exp(-a_s y^2) cos(2 pi k y / L) dy`` for
+    k = 0..n (eq. Gten_sep with the period L in place of 2).
+
+    Both integrands are even in y, so the integral is twice the one over
+    [0, b] with ``b = min(L/2, 9/sqrt(a_s))`` (beyond 9/sqrt(a) the Gaussian
+    is below e^-81).  The interval is split into equal panels no wider than
+    ``min(L/(2n+2), 1/sqrt(a_s))`` (a fraction of the shortest cosine period
+    and of the Gaussian width) with a 24-point Gauss-Legendre rule on each.
+    """
+    alpha = np.asarray(alpha, dtype=np.float64)
+    xg, wg = gauss_legendre(_GL_POINTS)
+    k = np.arange(n + 1, dtype=np.float64)
+    J0 = np.empty((alpha.size, n + 1))
+    J2 = np.empty((alpha.size, n + 1))
+    for s, a in enumerate(alpha):
+        b = min(L / 2.0, 9.0 / math.sqrt(a))
+        width = min(L / (2.0 * n + 2.0), 1.0 / math.sqrt(a), b)
+        panels = int(math.ceil(b / width - 1e-12))
+        edges = np.linspace(0.0, b, panels + 1)
+        mid = 0.5 * (edges[:-1] + edges[1:])
+        half = 0.5 * (edges[1:] - edges[:-1])
+        y = (mid[:, None] + half[:, None] * xg[None, :]).ravel()
+        wy = (half[:, None] * wg[None, :]).ravel()
+        g = np.exp(-a * y * y) * wy
+        c = np.cos((2.0 * math.pi / L) * np.outer(k, y))
+        J0[s] = 2.0 * (c @ g)
+        J2[s] = 2.0 * (c @ (y * y * g))
+    return J0, J2
+
+
+def spectrum_octant(omega, J0, J2):
+    """``Vhat[a,b,c] = sum_s w_s (J2_s(a) J0_s(b) J0_s(c) + J0_s(a) J2_s(b)
+    J0_s(c) + J0_s(a) J0_s(b) J2_s(c))`` for a, b, c in 0..n (eq. Gten_sep).
+
+    Vhat is even in every wavenumber component, so this octant of
+    non-negative |k_p| holds the whole padded-grid spectrum.  A plain loop
+    over the Gaussian-sum terms, one outer product per term and direction.
+    """
+    n1 = J0.shape[1]
+    V = np.zeros((n1, n1, n1))
+    for s in range(len(omega)):
+        j0 = J0[s]
+        j2 = J2[s]
+        V += omega[s] * (j2[:, None, None] * j0[None, :, None] * j0[None, None, :]
+                         + j0[:, None, None] * j2[None, :, None] * j0[None, None, :]
+                         + j0[:, None, None] * j0[None, :, None] * j2[None, None, :])
+    return V
+
+
+def multiplier_octant(V, n: int, L: float):
+    """``m[a,b,c] = -(2 pi/L)^2 (a^2+b^2+c^2) Vhat[a,b,c] / (2n)^3``.
+
+    The spectral Laplacian ``-(2 pi/L)^2 |k|^2`` of eq. convtheorem times the
+    kernel spectrum, with the 1/(2n)^3 of the forward DFT (the trapezoid
+    approximation of the Fourier coefficients) folded in.
+    """
+    a = np.arange(n + 1, dtype=np.float64)
+    k2 = a[:, None, None] ** 2 + a[None, :, None] ** 2 + a[None, None, :] ** 2
+    return -((2.0 * math.pi / L) ** 2) * k2 * V / float((2 * n) ** 3)
+
+
+class Setup:
+    """Everything Algorithm 1 precomputes for one (n, h, R, eps, delta)."""
+
+    def __init__(self, n, h, R, eps=None, delta=None):
+        d_eps, d_delta = default_eps_delta(n, h)
+        self.n, self.h, self.R = n, h, R
+        self.L = 2.0 * n * h
+        self.eps = d_eps if eps is None else eps
+        self.delta = d_delta if delta is None else delta
+        self.omega, self.alpha = gs_weights(R, self.eps, self.delta)
+        self.J0, self.J2 = tables_1d(self.alpha, n, self.L)
+        self.V = spectrum_octant(self.omega, self.J0, self.J2)
+        self.m = multiplier_octant(self.V, n, self.L)
+
+    def full_multiplier(self):
+        """The multiplier on the whole padded (2n)^3 grid, DFT index order."""
+        n = self.n
+        idx = np.arange(2 * n)
+        a = np.minimum(idx, 2 * n - idx)     # |k| for k = idx or idx - 2n
+        return self.m[np.ix_(a, a, a)]
+
+
+def setup(n, h, R, eps=None, delta=None) -> Setup:
+    return Setup(n, h, R, eps, delta)
+
+
+# --------------------------------------------------------------------------
+# The oracle's own FFT: recursive decimation in time, radix 2 and 3,
+# full complex, no pruning.
+# --------------------------------------------------------------------------
+
+
+def fft_naive(x, sign: int = -1):
+    """Unnormalised DFT ``X[k] = sum_j x[j] exp(sign 2 pi i j k / N)`` along the
+    last axis, for N a product of 2s and 3s."""
+    x = np.asarray(x, dtype=np.complex128)
+    N = x.shape[-1]
+    if N == 1:
+        return x.copy()
+    if N % 2 == 0:
+        p = 2
+    elif N % 3 == 0:
+        p = 3
+    else:
+        raise ValueError("length %d is not a product of 2s and 3s" % N)
+    M = N // p
+    subs = [fft_naive(x[..., r::p], sign) for r in range(p)]
+    k = np.arange(N)
+    out = np.zeros(x.shape[:-1] + (N,), dtype=np.complex128)
+    for r in range(p):
+        ang = sign * 2.0 * math.pi * ((r * k) % N) / N
+        tw = np.cos(ang) + 1j * np.sin(ang)
+        out += tw * subs[r][..., k % M]
+    return out
+
+
+def fftn_naive(x, sign: int = -1):
+    """fft_naive along every axis of a 3D array."""
+    y = np.asarray(x, dtype=np.complex128)
+    for ax in range(3):
+        y = np.moveaxis(fft_naive(np.moveaxis(y, ax, -1), sign), -1, ax)
+    return y
+
+
+# --------------------------------------------------------------------------
+# Algorithm 2: pad, forward FFT, multiply, inverse FFT, crop.
+# --------------------------------------------------------------------------
+
+
+def solve_padded(rho, h, R, eps=None, delta=None, su: Setup | None = None):
+    """The uncropped (2n)^3 result of Algorithm 2 (real part)."""
+    rho = np.asarray(rho, dtype=np.float64)
+    n = rho.shape[0]
+    assert rho.shape == (n, n, n)
+    if su is None:
+        su = setup(n, h, R, eps, delta)
+    pad = np.zeros((2 * n,) * 3, dtype=np.complex128)
+    pad[:n, :n, :n] = rho                       # zero padding, factor 2
+    rhohat = fftn_naive(pad, -1)                # forward DFT (1/(2n)^3 is in m)
+    prod = su.full_multiplier() * rhohat        # multiply (eq. convtheorem)
+    return fftn_naive(prod, +1).real            # inverse sum, real part
+
+
+def solve(rho, h, R, eps=None, delta=None, su: Setup | None = None):
+    """u on the original n^3 grid (Algorithm 2 with the crop)."""
+    n = np.asarray(rho).shape[0]
+    return solve_padded(rho, h, R, eps, delta, su)[:n, :n, :n]
+
+
+# --------------------------------------------------------------------------
+# The same discrete operator without any FFT: a Toeplitz convolution whose
+# stencil factors into 1D sums.
+# --------------------------------------------------------------------------
+
+
+def _stencil_factors(su: Setup):
+    """1D stencils over offsets d = -(n-1)..(n-1) for every Gaussian-sum term:
+    ``F[f](d) = sum_{k=-n}^{n-1} f(|k|) exp(i pi k d / n)`` for
+    f in {J0, J2, k^2 J0, k^2 J2}."""
+    n = su.n
+    k = np.arange(-n, n)
+    d = np.arange(-(n - 1), n)
+    ak = np.abs(k)
+    # real because f(|k|) is even in k except for the single k = -n term,
+    # whose phase exp(-i pi d) = (-1)^d is real
+    phase = np.cos(math.pi * np.outer(d, k) / n)
+    k2 = (ak * ak).astype(np.float64)
+    A0 = su.J0[:, ak] @ phase.T
+    A2 = su.J2[:, ak] @ phase.T
+    B0 = (su.J0[:, ak] * k2) @ phase.T
+    B2 = (su.J2[:, ak] * k2) @ phase.T
+    return A0, A2, B0, B2
+
+
+def _separable_terms(su: Setup):
+    """Yield (s, coef, (t1, t2, t3)) for the stencil
+    ``c_d = sum coef * F_t1(d1) F_t2(d2) F_t3(d3)``: the product of
+    ``-(2 pi/L)^2/(2n)^3 (k1^2+k2^2+k3^2)`` with the three rank-one terms of
+    eq. Gten_sep, expanded into nine separable terms per Gaussian-sum term.
+    Factor types: 0 = J0, 1 = J2, 2 = k^2 J0, 3 = k^2 J2."""
+    C = -((2.0 * math.pi / su.L) ** 2) / float((2 * su.n) ** 3)
+    for s in range(len(su.omega)):
+        for q in range(3):            # which axis carries J2
+            for p2 in range(3):       # which axis carries the k^2 factor
+                ts = tuple((2 if p == p2 else 0) + (1 if p == q else 0) for p in range(3))
+                yield s, C * su.omega[s], ts
+
+
+def direct_operator(rho, h, R, eps=None, delta=None, su: Setup | None = None):
+    """u_j = sum_m c_{j-m} rho_m over the whole grid, no FFT.  Cost
+    O(R n^4) through the separable stencil; intended for n <= 32."""
+    rho = np.asarray(rho, dtype=np.float64)
+    n = rho.shape[0]
+    if su is None:
+        su = setup(n, h, R, eps, delta)
+    F = _stencil_factors(su)
+    j = np.arange(n)
+    off = (j[:, None] - j[None, :]) + (n - 1)     # index of d = j - m
+    u = np.zeros_like(rho)
+    for s, coef, (t1, t2, t3) in _separable_terms(su):
+        T1, T2, T3 = F[t1][s][off], F[t2][s][off], F[t3][s][off]
+        t = np.tensordot(rho, T3, axes=([2], [1]))          # (m1, m2, j3)
+        t = np.tensordot(t, T2, axes=([1], [1]))             # (m1, j3, j2)
+        t = np.tensordot(t, T1, axes=([0], [1]))             # (j3, j2, j1)
+        u += coef * np.transpose(t, (2, 1, 0))
+    return u
+
+
+def direct_points(rho, points, h, R, eps=None, delta=None, su: Setup | None = None):
+    """u at selected grid indices ``points`` (array of shape (P, 3)) by the
+    same FFT-free Toeplitz sum; usable at any n."""
+    rho = np.asarray(rho, dtype=np.float64)
+    n = rho.shape[0]
+    if su is None:
+        su = setup(n, h, R, eps, delta)
+    F = _stencil_factors(su)
+    pts = np.asarray(points, dtype=np.int64).reshape(-1, 3)
+    m = np.arange(n)
+    j3s, inv3 = np.unique(pts[:, 2], return_inverse=True)
+    out = np.zeros(pts.shape[0])
+    rho2 = rho.reshape(n * n, n)
+    d3 = (j3s[:, None] - m[None, :]) + (n - 1)
+    d1 = (pts[:, 0][:, None] - m[None, :]) + (n - 1)
+    d2 = (pts[:, 1][:, None] - m[None, :]) + (n - 1)
+    cache = {}
+    for s, coef, (t1, t2, t3) in _separable_terms(su):
+        key = (s, t3)
+        if key not in cache:
+            cache.clear() if len(cache) > 8 else None
+            cache[key] = (rho2 @ F[t3][s][d3].T).reshape(n, n, -1)[:, :, inv3]
+        tp = cache[key]                                        # (m1, m2, P)
+        out += coef * np.einsum("pa,pb,abp->p", F[t1][s][d1], F[t2][s][d2], tp,
+                                optimize=True)
+    return out
