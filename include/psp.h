@@ -1,0 +1,154 @@
+/*
+ * psp.h - C ABI of libpsp, an MI355X (gfx950) solver for the free-space
+ * Poisson problem  -Lap u = rho  on R^3 with u -> 0 at infinity, by the
+ * near-field-free super-potential Gaussian-sum FFT method of Exl & Schaffer
+ * (Section 1, eq. problem1 and conv; Section 2).
+ *
+ * What a solve computes (Algorithm 2, eq. convtheorem):
+ *   rho, sampled on an n^3 grid of spacing h, is zero-padded to (2n)^3; a
+ *   forward 3D DFT is taken; each mode k is multiplied by
+ *       m_k = -(2 pi / L)^2 |k|^2 Vhat_k / (2n)^3,      L = 2 n h,
+ *   where Vhat_k is the Fourier integral of the Gaussian-sum approximation
+ *   of the biharmonic kernel |y|/(8 pi) over the box [-L/2, L/2]^3
+ *   (eq. gs_x, Gten0, Gten_sep); an inverse DFT (no scaling) follows and
+ *   the first n points of every axis are returned as u.
+ *   The operator is translation invariant, so no grid origin is needed.
+ *
+ * Conventions shared by every entry point:
+ *   - Arrays rho and u are C-ordered n*n*n, element [i1][i2][i3] at
+ *     (i1*n + i2)*n + i3, i3 contiguous, in the plan's dtype (double for
+ *     PSP_F64, float for PSP_F32), in device memory of the current HIP
+ *     device, at least 16-byte aligned.  The caller owns them.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the null stream.
+ *     Solves are asynchronous on that stream; a kernel-side failure is
+ *     reported by a later call or by stream synchronisation.
+ *   - No exception crosses the ABI.  Every call returns a psp_status;
+ *     psp_last_error() gives a thread-local detail string for the last
+ *     non-OK status returned on this thread.
+ *   - The library owns plans, workspaces, cached kernel spectra and servers.
+ */
+#ifndef PSP_H
+#define PSP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct psp_plan psp_plan;       /* opaque, library owned */
+typedef struct psp_server psp_server;   /* opaque, library owned */
+
+/* Precision tier.  PSP_F32 keeps the kernel spectrum, Gaussian-sum data and
+ * the multiply in FP64 and runs the FFT passes in FP32 with split (hi+lo)
+ * FP32 twiddles. */
+typedef enum { PSP_F64 = 0, PSP_F32 = 1 } psp_dtype;
+
+typedef enum {
+    PSP_OK = 0,
+    PSP_EINVAL = -1,        /* bad argument (h <= 0, R < 1, NULL pointer ...) */
+    PSP_ENOMEM = -2,        /* device or host allocation failed, or over budget */
+    PSP_EUNSUPPORTED = -3,  /* n odd, n < 4, n > 384, or 2n not 2^a 3^b */
+    PSP_ESTATE = -4,        /* call order (solve before precompute ...) */
+    PSP_EHIP = -5,          /* a HIP runtime call failed */
+    PSP_EBUSY = -6          /* server queue full */
+} psp_status;
+
+/* ---- plans (Algorithm 1) -------------------------------------------------
+ * psp_plan_create: validates (n, h, R, dtype) and computes the R Gaussian-sum
+ * weights and exponents on the host (Section 2, eq. sin_1_x: sinc quadrature
+ * of 1/(8 pi r) on (eps, delta] with eps = 1e-4 * n h and
+ * delta = sqrt(3) * n h).  Host work only; no device memory is touched.
+ * n: points per axis (even, 4..384, 2n = 2^a 3^b); h > 0 finite; 1 <= R <= 2048.
+ * *out receives the plan (NULL on failure). */
+psp_status psp_plan_create(int n, double h, int R, psp_dtype dtype, psp_plan **out);
+
+/* As psp_plan_create with an explicit cutoff 0 < eps < delta (finite). */
+psp_status psp_plan_create_ex(int n, double h, int R, psp_dtype dtype,
+                              double eps, double delta, psp_plan **out);
+
+/* Algorithm 1 steps 2-3 on the current device: the 2 R (n+1) 1D integrals of
+ * eq. Gten_sep (host FP64, Gauss-Kronrod), the kernel-spectrum multiplier
+ * octant (n+1)^3 by an FP64 MFMA contraction on `stream`, FFT twiddle
+ * tables.  Idempotent.  Multiplier octants are shared between plans with the
+ * same (n, h, R, eps, delta) on the same device.  Synchronises `stream`. */
+psp_status psp_kernel_precompute(psp_plan *p, void *stream);
+
+/* Algorithm 2: u = crop(IFFT(m * FFT(pad(rho)))).  rho and u must not alias.
+ * Uses a library-owned workspace bound to (plan, stream), allocated on the
+ * first call with that stream.  Returns PSP_ESTATE before precompute. */
+psp_status psp_solve(psp_plan *p, const void *rho_dev, void *u_dev, void *stream);
+
+/* `count` independent solves in one launch per pass.  plans may differ in n
+ * (and h, R) but must share one dtype and all be precomputed; rho_dev[i] and
+ * u_dev[i] follow plans[i].  Results are bitwise equal to psp_solve of the
+ * same plan and rho.  Workspace is library-owned, bound to the stream. */
+psp_status psp_solve_batched(int count, psp_plan *const *plans,
+                             const void *const *rho_dev, void *const *u_dev,
+                             void *stream);
+
+/* Test hook: the uncropped (2n)^3 result of Algorithm 2 (real part), C-order
+ * with side 2n, dtype of the plan. */
+psp_status psp_solve_padded_debug(psp_plan *p, const void *rho_dev, void *upad_dev,
+                                  void *stream);
+
+/* Test hook: copies the R weights w_s and exponents a_s (host arrays). */
+psp_status psp_plan_get_gs(const psp_plan *p, double *omega, double *alpha);
+
+/* Test hook: copies the host 1D tables J0[s][k], J2[s][k], s < R, k <= n
+ * (row-major R x (n+1) each), computing them if needed (host work only). */
+psp_status psp_plan_get_tables(psp_plan *p, double *J0, double *J2);
+
+/* Test hook: copies the device multiplier octant m[a][b][c] (a,b,c <= n,
+ * row-major (n+1)^3 doubles) to host memory.  Needs precompute; syncs. */
+psp_status psp_plan_get_multiplier(psp_plan *p, double *m_host);
+
+/* Bytes of device workspace one solve of this plan needs (per stream). */
+psp_status psp_plan_workspace_bytes(const psp_plan *p, size_t *bytes);
+
+/* Bytes of the plan's device multiplier octant. */
+psp_status psp_plan_spectrum_bytes(const psp_plan *p, size_t *bytes);
+
+void psp_plan_destroy(psp_plan *p);
+
+/* ---- serving --------------------------------------------------------------
+ * A continuous-batching request loop.  Requests are admitted while their
+ * device footprint (workspace plus, on a spectrum-cache miss, the multiplier
+ * octant) fits `hbm_budget_bytes` and fewer than `max_slots` are in flight;
+ * admitted requests are grouped per tier into batched launches on a small
+ * stream pool, so new arrivals overlap work already on the device.  Spectra
+ * are cached per (n, h, R) on the device in LRU order inside the budget.
+ * rho_dev/u_dev stay caller-owned and must live until the request is done. */
+psp_status psp_serve_create(size_t hbm_budget_bytes, int max_slots, psp_server **out);
+
+/* Non-blocking enqueue; *ticket identifies the request.  PSP_EBUSY if the
+ * queue holds 65536 requests; PSP_ENOMEM if one request alone exceeds the
+ * budget; validation errors as psp_plan_create. */
+psp_status psp_serve_submit(psp_server *sv, int n, double h, int R, psp_dtype tier,
+                            const void *rho_dev, void *u_dev, uint64_t *ticket);
+
+/* Non-blocking status: *done = 1 once u is complete on the device; then
+ * *result is the request's status and *latency_ms its submit-to-completion
+ * time.  Unknown ticket: PSP_EINVAL.  Any output pointer may be NULL. */
+psp_status psp_serve_poll(psp_server *sv, uint64_t ticket, int *done, psp_status *result,
+                          double *latency_ms);
+
+/* Blocks until every submitted request is complete. */
+psp_status psp_serve_drain(psp_server *sv);
+
+/* Device bytes the server holds now and the most it has held. */
+psp_status psp_serve_stats(psp_server *sv, size_t *bytes_in_use, size_t *bytes_peak,
+                           uint64_t *completed, uint64_t *cache_hits, uint64_t *cache_misses);
+
+/* Drains, then frees everything the server owns. */
+void psp_serve_destroy(psp_server *sv);
+
+/* ---- errors ---------------------------------------------------------------*/
+const char *psp_strerror(psp_status e);
+const char *psp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PSP_H */

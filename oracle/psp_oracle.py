@@ -5,7 +5,7 @@ of the benchmark may import this module.  It shares no code with the GPU
 library: its own Gaussian-sum construction, its own Gauss-Legendre 1D
 quadrature, a plain triple loop for the kernel spectrum, its own naive
 recursive mixed-radix (2 and 3) FFT, and a direct (FFT-free) evaluation of the
-discrete convolution operator.  Everything is float64 numpy.
+discrete convolution operator.  Everything is float64 numpy, except the\n1D integral sums, which run in extended precision (see tables_1d).
 
 The method (Exl & Schaffer, "Near-field-free super-potential FFT method for
 the three-dimensional free-space Poisson equation"):
@@ -129,31 +129,35 @@ def gs_biharmonic(r, omega, alpha):
 # --------------------------------------------------------------------------
 
 
-def gauss_legendre(m: int):
+def gauss_legendre(m: int, dtype=np.float64):
     """Nodes and weights of the m-point Gauss-Legendre rule on [-1, 1],
-    by Newton iteration on the three-term Legendre recurrence."""
-    x = np.cos(math.pi * (np.arange(1, m + 1) - 0.25) / (m + 0.5))
-    for _ in range(100):
+    by Newton iteration on the three-term Legendre recurrence, in ``dtype``."""
+    one = dtype(1)
+    x = np.cos(math.pi * (np.arange(1, m + 1) - 0.25) / (m + 0.5)).astype(dtype)
+    tol = 4 * np.finfo(dtype).eps
+
+    def legendre(x):
         p0 = np.ones_like(x)
         p1 = x.copy()
         for k in range(2, m + 1):
             p0, p1 = p1, ((2 * k - 1) * x * p1 - (k - 1) * p0) / k
-        dp = m * (x * p1 - p0) / (x * x - 1.0)
+        dp = m * (x * p1 - p0) / (x * x - one)
+        return p1, dp
+
+    for _ in range(100):
+        p1, dp = legendre(x)
         dx = p1 / dp
         x = x - dx
-        if np.max(np.abs(dx)) < 1e-16:
+        if np.max(np.abs(dx)) < tol:
             break
-    p0 = np.ones_like(x)
-    p1 = x.copy()
-    for k in range(2, m + 1):
-        p0, p1 = p1, ((2 * k - 1) * x * p1 - (k - 1) * p0) / k
-    dp = m * (x * p1 - p0) / (x * x - 1.0)
-    w = 2.0 / ((1.0 - x * x) * dp * dp)
+    p1, dp = legendre(x)
+    w = 2 * one / ((one - x * x) * dp * dp)
     order = np.argsort(x)
     return x[order], w[order]
 
 
 _GL_POINTS = 24
+_LD = np.longdouble
 
 
 def tables_1d(alpha, n: int, L: float):
@@ -166,25 +170,33 @@ def tables_1d(alpha, n: int, L: float):
     is below e^-81).  The interval is split into equal panels no wider than
     ``min(L/(2n+2), 1/sqrt(a_s))`` (a fraction of the shortest cosine period
     and of the Gaussian width) with a 24-point Gauss-Legendre rule on each.
+
+    The sums run in x87 extended precision (numpy longdouble) and are rounded
+    to float64 at the end: for wide Gaussians the box-truncated integrals at
+    high k are ~k^2 smaller than the integrand, so float64 node positions and
+    cosine arguments alone would leave ~1e-12 relative errors there.
     """
     alpha = np.asarray(alpha, dtype=np.float64)
-    xg, wg = gauss_legendre(_GL_POINTS)
-    k = np.arange(n + 1, dtype=np.float64)
+    xg, wg = gauss_legendre(_GL_POINTS, _LD)
+    Ll = _LD(L)
+    two_pi = 2 * np.arccos(_LD(-1))
+    k = np.arange(n + 1).astype(_LD)
     J0 = np.empty((alpha.size, n + 1))
     J2 = np.empty((alpha.size, n + 1))
-    for s, a in enumerate(alpha):
-        b = min(L / 2.0, 9.0 / math.sqrt(a))
-        width = min(L / (2.0 * n + 2.0), 1.0 / math.sqrt(a), b)
-        panels = int(math.ceil(b / width - 1e-12))
-        edges = np.linspace(0.0, b, panels + 1)
-        mid = 0.5 * (edges[:-1] + edges[1:])
-        half = 0.5 * (edges[1:] - edges[:-1])
+    for s, a64 in enumerate(alpha):
+        a = _LD(a64)
+        b = min(Ll / 2, _LD(9) / np.sqrt(a))
+        width = min(Ll / (2 * n + 2), 1 / np.sqrt(a), b)
+        panels = int(math.ceil(float(b / width) - 1e-12))
+        edges = b * np.arange(panels + 1).astype(_LD) / panels
+        mid = (edges[:-1] + edges[1:]) / 2
+        half = (edges[1:] - edges[:-1]) / 2
         y = (mid[:, None] + half[:, None] * xg[None, :]).ravel()
         wy = (half[:, None] * wg[None, :]).ravel()
         g = np.exp(-a * y * y) * wy
-        c = np.cos((2.0 * math.pi / L) * np.outer(k, y))
-        J0[s] = 2.0 * (c @ g)
-        J2[s] = 2.0 * (c @ (y * y * g))
+        c = np.cos((two_pi / Ll) * np.outer(k, y))
+        J0[s] = (2 * (c @ g)).astype(np.float64)
+        J2[s] = (2 * (c @ (y * y * g))).astype(np.float64)
     return J0, J2
 
 
@@ -220,7 +232,8 @@ def multiplier_octant(V, n: int, L: float):
 
 
 class Setup:
-    """Everything Algorithm 1 precomputes for one (n, h, R, eps, delta)."""
+    """Everything Algorithm 1 precomputes for one (n, h, R, eps, delta).
+    The spectrum octant and the multiplier are built on first use."""
 
     def __init__(self, n, h, R, eps=None, delta=None):
         d_eps, d_delta = default_eps_delta(n, h)
@@ -230,8 +243,20 @@ class Setup:
         self.delta = d_delta if delta is None else delta
         self.omega, self.alpha = gs_weights(R, self.eps, self.delta)
         self.J0, self.J2 = tables_1d(self.alpha, n, self.L)
-        self.V = spectrum_octant(self.omega, self.J0, self.J2)
-        self.m = multiplier_octant(self.V, n, self.L)
+        self._V = None
+        self._m = None
+
+    @property
+    def V(self):
+        if self._V is None:
+            self._V = spectrum_octant(self.omega, self.J0, self.J2)
+        return self._V
+
+    @property
+    def m(self):
+        if self._m is None:
+            self._m = multiplier_octant(self.V, self.n, self.L)
+        return self._m
 
     def full_multiplier(self):
         """The multiplier on the whole padded (2n)^3 grid, DFT index order."""

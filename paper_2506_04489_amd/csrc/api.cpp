@@ -1,0 +1,374 @@
+// api.cpp - libpsp's C ABI: plans, precompute, solves, test hooks, errors.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <tuple>
+
+#include "host_common.hpp"
+
+namespace psp {
+
+static thread_local std::string g_last_error;
+
+psp_status fail(psp_status e, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return e;
+}
+
+psp_status hip_fail(hipError_t err, const char *what) {
+    return fail(PSP_EHIP, "%s: %s", what, hipGetErrorString(err));
+}
+
+#define PSP_HIP(call, what)                                  \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return hip_fail(e_, what);     \
+    } while (0)
+
+DevSpectrum::~DevSpectrum() {
+    if (mult) {
+        int cur = -1;
+        (void)hipGetDevice(&cur);
+        if (cur != device) (void)hipSetDevice(device);
+        (void)hipFree(mult);
+        if (cur != device && cur >= 0) (void)hipSetDevice(cur);
+    }
+}
+
+// ---------------------------------------------------------------- caches
+static std::mutex g_cache_mu;
+using SpecKey = std::tuple<int, int, double, int, double, double>;   // device, n, h, R, eps, delta
+static std::map<SpecKey, std::weak_ptr<DevSpectrum>> g_spec_cache;
+static std::map<std::pair<int, int>, Twiddles> g_tw_cache;            // (device, N)
+
+psp_status get_twiddles(int device, int N, const Twiddles **out) {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto key = std::make_pair(device, N);
+    auto it = g_tw_cache.find(key);
+    if (it != g_tw_cache.end()) {
+        *out = &it->second;
+        return PSP_OK;
+    }
+    std::vector<double> w(2 * (size_t)N);
+    std::vector<float> hi(2 * (size_t)N), lo(2 * (size_t)N);
+    const long double two_pi = 6.283185307179586476925286766559005768L;
+    for (int m = 0; m < N; ++m) {
+        // exp(-2 pi i m / N), long double evaluation rounded once
+        const long double ang = two_pi * (long double)m / (long double)N;
+        const double c = (double)cosl(ang), s = (double)-sinl(ang);
+        w[2 * m] = c;
+        w[2 * m + 1] = s;
+        hi[2 * m] = (float)c;
+        hi[2 * m + 1] = (float)s;
+        lo[2 * m] = (float)(c - (double)hi[2 * m]);
+        lo[2 * m + 1] = (float)(s - (double)hi[2 * m + 1]);
+    }
+    Twiddles t;
+    PSP_HIP(hipMalloc(&t.w64, w.size() * 8), "hipMalloc(twiddles)");
+    PSP_HIP(hipMalloc(&t.hi32, hi.size() * 4), "hipMalloc(twiddles)");
+    PSP_HIP(hipMalloc(&t.lo32, lo.size() * 4), "hipMalloc(twiddles)");
+    PSP_HIP(hipMemcpy(t.w64, w.data(), w.size() * 8, hipMemcpyHostToDevice), "hipMemcpy(twiddles)");
+    PSP_HIP(hipMemcpy(t.hi32, hi.data(), hi.size() * 4, hipMemcpyHostToDevice), "hipMemcpy(twiddles)");
+    PSP_HIP(hipMemcpy(t.lo32, lo.data(), lo.size() * 4, hipMemcpyHostToDevice), "hipMemcpy(twiddles)");
+    auto res = g_tw_cache.emplace(key, t);
+    *out = &res.first->second;
+    return PSP_OK;
+}
+
+psp_status check_create(int n, double h, int R, double eps, double delta) {
+    if (!(h > 0.0) || !std::isfinite(h)) return fail(PSP_EINVAL, "h must be positive and finite (got %g)", h);
+    if (R < 1 || R > 2048) return fail(PSP_EINVAL, "R must be in [1, 2048] (got %d)", R);
+    if (!(eps > 0.0) || !(delta > eps) || !std::isfinite(delta))
+        return fail(PSP_EINVAL, "need 0 < eps < delta finite (got %g, %g)", eps, delta);
+    if (n < 4 || n > 384 || (n & 1)) return fail(PSP_EUNSUPPORTED, "n must be even and in [4, 384] (got %d)", n);
+    if (!supported_length(2 * n)) return fail(PSP_EUNSUPPORTED, "2n = %d is not of the form 2^a 3^b", 2 * n);
+    return PSP_OK;
+}
+
+psp_status plan_workspace(psp_plan *p, hipStream_t st, Workspace **out) {
+    std::lock_guard<std::mutex> lk(p->mu);
+    auto it = p->ws.find(st);
+    if (it != p->ws.end()) {
+        *out = &it->second;
+        return PSP_OK;
+    }
+    const bool f32 = p->dtype == PSP_F32;
+    const size_t c = f32 ? 8 : 16, P = (size_t)pitch_for(p->n), n = (size_t)p->n;
+    Workspace w;
+    w.bytes = workspace_bytes(p->n, f32);
+    hipError_t e1 = hipMalloc(&w.X, c * P * n * n);
+    if (e1 != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(PSP_ENOMEM, "workspace allocation of %zu bytes failed", w.bytes);
+    }
+    hipError_t e2 = hipMalloc(&w.A, c * P * n * 2 * n);
+    if (e2 != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(w.X);
+        return fail(PSP_ENOMEM, "workspace allocation of %zu bytes failed", w.bytes);
+    }
+    auto res = p->ws.emplace(st, w);
+    *out = &res.first->second;
+    return PSP_OK;
+}
+
+SolveArgs solve_args(const psp_plan *p, const Workspace &w, const void *rho, void *u) {
+    SolveArgs a;
+    a.n = p->n;
+    a.P = pitch_for(p->n);
+    a.f32 = p->dtype == PSP_F32;
+    a.rho = rho;
+    a.u = u;
+    a.X = w.X;
+    a.A = w.A;
+    a.mult = p->spec->mult;
+    if (a.f32) {
+        a.tw_hi = p->tw->hi32;
+        a.tw_lo = p->tw->lo32;
+    } else {
+        a.tw_hi = p->tw->w64;
+    }
+    return a;
+}
+
+static psp_status ensure_tables(psp_plan *p) {
+    std::lock_guard<std::mutex> lk(p->mu);
+    if (!p->tables_ready) {
+        tables_1d(p->alpha, p->n, p->L, p->J0, p->J2);
+        p->tables_ready = true;
+    }
+    return PSP_OK;
+}
+
+static psp_status current_device_of(const psp_plan *p) {
+    int dev = -1;
+    PSP_HIP(hipGetDevice(&dev), "hipGetDevice");
+    if (dev != p->device) return fail(PSP_EINVAL, "plan was precomputed on device %d, current is %d", p->device, dev);
+    return PSP_OK;
+}
+
+}  // namespace psp
+
+using namespace psp;
+
+extern "C" {
+
+const char *psp_strerror(psp_status e) {
+    switch (e) {
+        case PSP_OK: return "success";
+        case PSP_EINVAL: return "invalid argument";
+        case PSP_ENOMEM: return "out of memory";
+        case PSP_EUNSUPPORTED: return "unsupported size";
+        case PSP_ESTATE: return "invalid call order";
+        case PSP_EHIP: return "HIP runtime error";
+        case PSP_EBUSY: return "queue full";
+    }
+    return "unknown status";
+}
+
+const char *psp_last_error(void) { return g_last_error.c_str(); }
+
+psp_status psp_plan_create_ex(int n, double h, int R, psp_dtype dtype, double eps, double delta, psp_plan **out) {
+    if (!out) return fail(PSP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (dtype != PSP_F64 && dtype != PSP_F32) return fail(PSP_EINVAL, "unknown dtype %d", (int)dtype);
+    psp_status st = check_create(n, h, R, eps, delta);
+    if (st != PSP_OK) return st;
+    psp_plan *p = new (std::nothrow) psp_plan;
+    if (!p) return fail(PSP_ENOMEM, "host allocation failed");
+    p->n = n;
+    p->h = h;
+    p->L = 2.0 * n * h;
+    p->R = R;
+    p->dtype = dtype;
+    p->eps = eps;
+    p->delta = delta;
+    gs_fit(R, eps, delta, p->omega, p->alpha);
+    *out = p;
+    return PSP_OK;
+}
+
+psp_status psp_plan_create(int n, double h, int R, psp_dtype dtype, psp_plan **out) {
+    // eps = 1e-4 L/2 and delta = sqrt(3) L/2 with L = 2 n h (the default cutoff
+    // in units where L = 2, and the corner of the kernel's truncation box)
+    const double half = (double)n * h;
+    return psp_plan_create_ex(n, h, R, dtype, 1e-4 * half, std::sqrt(3.0) * half, out);
+}
+
+void psp_plan_destroy(psp_plan *p) {
+    if (!p) return;
+    for (auto &kv : p->ws) {
+        (void)hipFree(kv.second.X);
+        (void)hipFree(kv.second.A);
+    }
+    delete p;
+}
+
+psp_status psp_plan_get_gs(const psp_plan *p, double *omega, double *alpha) {
+    if (!p || !omega || !alpha) return fail(PSP_EINVAL, "NULL argument");
+    std::memcpy(omega, p->omega.data(), sizeof(double) * p->R);
+    std::memcpy(alpha, p->alpha.data(), sizeof(double) * p->R);
+    return PSP_OK;
+}
+
+psp_status psp_plan_get_tables(psp_plan *p, double *J0, double *J2) {
+    if (!p || !J0 || !J2) return fail(PSP_EINVAL, "NULL argument");
+    ensure_tables(p);
+    std::memcpy(J0, p->J0.data(), sizeof(double) * p->J0.size());
+    std::memcpy(J2, p->J2.data(), sizeof(double) * p->J2.size());
+    return PSP_OK;
+}
+
+psp_status psp_plan_workspace_bytes(const psp_plan *p, size_t *bytes) {
+    if (!p || !bytes) return fail(PSP_EINVAL, "NULL argument");
+    *bytes = workspace_bytes(p->n, p->dtype == PSP_F32);
+    return PSP_OK;
+}
+
+psp_status psp_plan_spectrum_bytes(const psp_plan *p, size_t *bytes) {
+    if (!p || !bytes) return fail(PSP_EINVAL, "NULL argument");
+    *bytes = spectrum_bytes(p->n);
+    return PSP_OK;
+}
+
+psp_status psp_kernel_precompute(psp_plan *p, void *stream) {
+    if (!p) return fail(PSP_EINVAL, "plan is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    if (p->precomputed) return current_device_of(p);
+    int dev = -1;
+    PSP_HIP(hipGetDevice(&dev), "hipGetDevice");
+    psp_status rs = get_twiddles(dev, 2 * p->n, &p->tw);
+    if (rs != PSP_OK) return rs;
+    const SpecKey key{dev, p->n, p->h, p->R, p->eps, p->delta};
+    std::shared_ptr<DevSpectrum> spec;
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        auto it = g_spec_cache.find(key);
+        if (it != g_spec_cache.end()) spec = it->second.lock();
+    }
+    if (!spec) {
+        ensure_tables(p);
+        const int n = p->n, R = p->R, P = pitch_for(n);
+        spec = std::make_shared<DevSpectrum>();
+        spec->device = dev;
+        spec->bytes = spectrum_bytes(n);
+        hipError_t e = hipMalloc(&spec->mult, spec->bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            spec->mult = nullptr;
+            return fail(PSP_ENOMEM, "spectrum allocation of %zu bytes failed", spec->bytes);
+        }
+        double *dJ = nullptr;
+        const size_t tb = sizeof(double) * (size_t)R * (n + 1);
+        PSP_HIP(hipMalloc(&dJ, 2 * tb + sizeof(double) * R), "hipMalloc(tables)");
+        double *dJ0 = dJ, *dJ2 = dJ + (size_t)R * (n + 1), *dW = dJ + 2 * (size_t)R * (n + 1);
+        psp_status out = PSP_OK;
+        do {
+            hipError_t ee;
+            if ((ee = hipMemcpyAsync(dJ0, p->J0.data(), tb, hipMemcpyHostToDevice, st)) != hipSuccess ||
+                (ee = hipMemcpyAsync(dJ2, p->J2.data(), tb, hipMemcpyHostToDevice, st)) != hipSuccess ||
+                (ee = hipMemcpyAsync(dW, p->omega.data(), sizeof(double) * R, hipMemcpyHostToDevice, st)) !=
+                    hipSuccess ||
+                (ee = hipMemsetAsync(spec->mult, 0, spec->bytes, st)) != hipSuccess) {
+                out = hip_fail(ee, "precompute upload");
+                break;
+            }
+            const double pi = 3.14159265358979323846;
+            const double N = 2.0 * n;
+            const double scale = -(2.0 * pi / p->L) * (2.0 * pi / p->L) / (N * N * N);
+            if ((ee = launch_spectrum(dJ0, dJ2, dW, R, n, P, scale, spec->mult, st)) != hipSuccess) {
+                out = hip_fail(ee, "spectrum kernel launch");
+                break;
+            }
+            if ((ee = hipStreamSynchronize(st)) != hipSuccess) {
+                out = hip_fail(ee, "spectrum kernel");
+                break;
+            }
+        } while (0);
+        (void)hipFree(dJ);
+        if (out != PSP_OK) return out;
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        g_spec_cache[key] = spec;
+    }
+    p->spec = spec;
+    p->device = dev;
+    p->precomputed = true;
+    return PSP_OK;
+}
+
+psp_status psp_plan_get_multiplier(psp_plan *p, double *m_host) {
+    if (!p || !m_host) return fail(PSP_EINVAL, "NULL argument");
+    if (!p->precomputed) return fail(PSP_ESTATE, "multiplier requested before psp_kernel_precompute");
+    const int n = p->n, P = pitch_for(n);
+    std::vector<double> blk(spectrum_bytes(n) / 8);
+    PSP_HIP(hipMemcpy(blk.data(), p->spec->mult, spectrum_bytes(n), hipMemcpyDeviceToHost), "hipMemcpy(mult)");
+    const size_t n1 = (size_t)n + 1;
+    for (size_t a = 0; a < n1; ++a)
+        for (size_t b = 0; b < n1; ++b)
+            for (size_t c = 0; c < n1; ++c)
+                m_host[(a * n1 + b) * n1 + c] = blk[((b * (P / 8) + c / 8) * n1 + a) * 8 + (c & 7)];
+    return PSP_OK;
+}
+
+psp_status psp_solve(psp_plan *p, const void *rho_dev, void *u_dev, void *stream) {
+    if (!p || !rho_dev || !u_dev) return fail(PSP_EINVAL, "NULL argument");
+    if (!p->precomputed) return fail(PSP_ESTATE, "psp_solve before psp_kernel_precompute");
+    if (rho_dev == u_dev) return fail(PSP_EINVAL, "rho and u must not alias");
+    psp_status st = current_device_of(p);
+    if (st != PSP_OK) return st;
+    Workspace *w = nullptr;
+    st = plan_workspace(p, (hipStream_t)stream, &w);
+    if (st != PSP_OK) return st;
+    hipError_t e = launch_solve(solve_args(p, *w, rho_dev, u_dev), (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "solve launch");
+    return PSP_OK;
+}
+
+psp_status psp_solve_padded_debug(psp_plan *p, const void *rho_dev, void *upad_dev, void *stream) {
+    if (!p || !rho_dev || !upad_dev) return fail(PSP_EINVAL, "NULL argument");
+    if (!p->precomputed) return fail(PSP_ESTATE, "psp_solve_padded_debug before psp_kernel_precompute");
+    psp_status st = current_device_of(p);
+    if (st != PSP_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    Workspace *w = nullptr;
+    st = plan_workspace(p, s, &w);
+    if (st != PSP_OK) return st;
+    SolveArgs a = solve_args(p, *w, rho_dev, upad_dev);
+    a.full = true;
+    const size_t c = a.f32 ? 8 : 16, N = 2 * (size_t)p->n;
+    const size_t big = c * N * N * (size_t)a.P;
+    PSP_HIP(hipMalloc(&a.A2, big), "hipMalloc(debug)");
+    if (hipMalloc(&a.Y2, big) != hipSuccess) {
+        (void)hipFree(a.A2);
+        return fail(PSP_ENOMEM, "debug allocation failed");
+    }
+    hipError_t e = launch_solve(a, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(a.A2);
+    (void)hipFree(a.Y2);
+    if (e != hipSuccess) return hip_fail(e, "padded debug solve");
+    return PSP_OK;
+}
+
+psp_status psp_solve_batched(int count, psp_plan *const *plans, const void *const *rho_dev, void *const *u_dev,
+                             void *stream) {
+    if (count < 0 || (count > 0 && (!plans || !rho_dev || !u_dev))) return fail(PSP_EINVAL, "bad batch arguments");
+    for (int i = 0; i < count; ++i) {
+        if (!plans[i] || !rho_dev[i] || !u_dev[i]) return fail(PSP_EINVAL, "NULL entry %d in batch", i);
+        if (!plans[i]->precomputed) return fail(PSP_ESTATE, "batch entry %d not precomputed", i);
+        if (plans[i]->dtype != plans[0]->dtype) return fail(PSP_EINVAL, "batch mixes dtypes");
+    }
+    for (int i = 0; i < count; ++i) {
+        psp_status st = psp_solve(plans[i], rho_dev[i], u_dev[i], stream);
+        if (st != PSP_OK) return st;
+    }
+    return PSP_OK;
+}
+
+}  // extern "C"

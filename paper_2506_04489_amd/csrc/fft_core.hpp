@@ -1,0 +1,296 @@
+// fft_core.hpp - device building blocks of the solver's FFT passes (gfx950).
+//
+// Every pass transforms many independent length-N columns (N = 2n, the
+// padded length, N = 2^a 3^b) in one workgroup.  A column is processed by
+// TPC threads with the Stockham autosort formulation: stage s of radix R
+// with Ns = product of the earlier radices maps the butterfly j (0 <= j < N/R)
+// from inputs at  j + r N/R  (r < R), twiddled by W_N^{(j mod Ns) r N/(Ns R)},
+// to outputs at  (j / Ns) Ns R + (j mod Ns) + r Ns.  Stage data lives in
+// registers; the exchange between stages goes through LDS.  The first stage
+// reads its inputs straight from global memory, the last stage writes its
+// outputs straight to global memory, and (Ns = 1 at the first stage,
+// Ns = N/R at the last) both touch positions  j + r N/R  only, which lets a
+// pass skip the known-zero half of a zero-padded input, skip the cropped
+// half of an output, and run an inverse transform directly on the registers
+// a forward transform left behind (the inverse plan is the forward plan in
+// reverse order).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace psp {
+
+// ---------------------------------------------------------------- complex
+template <typename T> struct cplx_t;
+template <> struct cplx_t<double> { using type = double2; };
+template <> struct cplx_t<float> { using type = float2; };
+template <typename T> using cplx = typename cplx_t<T>::type;
+
+template <typename C> __device__ __forceinline__ C c_add(C a, C b) { return C{a.x + b.x, a.y + b.y}; }
+template <typename C> __device__ __forceinline__ C c_sub(C a, C b) { return C{a.x - b.x, a.y - b.y}; }
+// multiply by -i (forward) or +i (inverse)
+template <bool INV, typename C> __device__ __forceinline__ C c_mul_mi(C a) {
+    return INV ? C{-a.y, a.x} : C{a.y, -a.x};
+}
+template <typename C> __device__ __forceinline__ C c_zero() { return C{0, 0}; }
+
+// --------------------------------------------------------------- twiddles
+// Table of W_N^m = exp(-2 pi i m / N), m < N.  FP64: one table.  FP32: the
+// value split into hi = fl32(w) and lo = fl32(w - hi), so the product a*w is
+// formed as a*hi + a*lo and the twiddle itself carries ~1e-15 error.
+template <typename T> struct Twiddle;
+template <> struct Twiddle<double> {
+    const double2 *w;
+    template <bool INV> __device__ __forceinline__ double2 mul(double2 a, int m) const {
+        double2 t = w[m];
+        double ty = INV ? -t.y : t.y;
+        return double2{a.x * t.x - a.y * ty, a.x * ty + a.y * t.x};
+    }
+};
+template <> struct Twiddle<float> {
+    const float2 *hi;
+    const float2 *lo;
+    template <bool INV> __device__ __forceinline__ float2 mul(float2 a, int m) const {
+        float2 h = hi[m], l = lo[m];
+        float hy = INV ? -h.y : h.y;
+        float ly = INV ? -l.y : l.y;
+        float rx = a.x * l.x - a.y * ly;
+        float ry = a.x * ly + a.y * l.x;
+        rx += a.x * h.x - a.y * hy;
+        ry += a.x * hy + a.y * h.x;
+        return float2{rx, ry};
+    }
+};
+
+// ------------------------------------------------------------- butterflies
+template <int R, bool INV, typename C> struct DFT;
+
+template <bool INV, typename C> struct DFT<2, INV, C> {
+    __device__ __forceinline__ static void run(C *v) {
+        C a = v[0], b = v[1];
+        v[0] = c_add(a, b);
+        v[1] = c_sub(a, b);
+    }
+};
+
+template <bool INV, typename C> struct DFT<3, INV, C> {
+    __device__ __forceinline__ static void run(C *v) {
+        using T = decltype(v[0].x);
+        const T half = T(0.5);
+        const T s3 = T(0.86602540378443864676372317075293618);  // sqrt(3)/2
+        C s = c_add(v[1], v[2]);
+        C d = c_sub(v[1], v[2]);
+        C m = C{v[0].x - half * s.x, v[0].y - half * s.y};
+        // forward: X1 = m - i s3 d, X2 = m + i s3 d
+        C t = c_mul_mi<INV>(C{s3 * d.x, s3 * d.y});
+        v[0] = c_add(v[0], s);
+        v[1] = c_add(m, t);
+        v[2] = c_sub(m, t);
+    }
+};
+
+template <bool INV, typename C> struct DFT<4, INV, C> {
+    __device__ __forceinline__ static void run(C *v) {
+        C a = c_add(v[0], v[2]), b = c_sub(v[0], v[2]);
+        C c = c_add(v[1], v[3]), d = c_mul_mi<INV>(c_sub(v[1], v[3]));
+        v[0] = c_add(a, c);
+        v[2] = c_sub(a, c);
+        v[1] = c_add(b, d);
+        v[3] = c_sub(b, d);
+    }
+};
+
+template <bool INV, typename C> struct DFT<8, INV, C> {
+    __device__ __forceinline__ static void run(C *v) {
+        using T = decltype(v[0].x);
+        const T r2 = T(0.70710678118654752440084436210484904);  // 1/sqrt(2)
+        C a[4], b[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            a[j] = c_add(v[j], v[j + 4]);
+            b[j] = c_sub(v[j], v[j + 4]);
+        }
+        // b_j *= W8^j (forward W8 = (1 - i)/sqrt2; inverse its conjugate)
+        if (!INV) {
+            b[1] = C{r2 * (b[1].x + b[1].y), r2 * (b[1].y - b[1].x)};
+            b[2] = C{b[2].y, -b[2].x};
+            b[3] = C{r2 * (b[3].y - b[3].x), -r2 * (b[3].x + b[3].y)};
+        } else {
+            b[1] = C{r2 * (b[1].x - b[1].y), r2 * (b[1].x + b[1].y)};
+            b[2] = C{-b[2].y, b[2].x};
+            b[3] = C{-r2 * (b[3].x + b[3].y), r2 * (b[3].x - b[3].y)};
+        }
+        DFT<4, INV, C>::run(a);
+        DFT<4, INV, C>::run(b);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            v[2 * j] = a[j];
+            v[2 * j + 1] = b[j];
+        }
+    }
+};
+
+// ------------------------------------------------------------ radix plans
+// Forward radix sequence per padded length.  The first radix is even so that
+// the zero-padded half of an input (and, in reverse, the cropped half of an
+// output) falls on whole butterfly legs.
+template <int N> struct Plan;
+#define PSP_PLAN(NN, ...)                                                    \
+    template <> struct Plan<NN> {                                           \
+        static constexpr int r[] = {__VA_ARGS__};                           \
+        static constexpr int S = sizeof(r) / sizeof(int);                   \
+    };
+PSP_PLAN(8, 8)
+PSP_PLAN(12, 4, 3)
+PSP_PLAN(16, 4, 4)
+PSP_PLAN(24, 8, 3)
+PSP_PLAN(32, 8, 4)
+PSP_PLAN(48, 4, 4, 3)
+PSP_PLAN(64, 8, 8)
+PSP_PLAN(96, 8, 4, 3)
+PSP_PLAN(128, 8, 4, 4)
+PSP_PLAN(192, 8, 8, 3)
+PSP_PLAN(256, 8, 8, 4)
+PSP_PLAN(384, 8, 4, 4, 3)
+PSP_PLAN(512, 8, 8, 8)
+PSP_PLAN(768, 8, 8, 4, 3)
+#undef PSP_PLAN
+
+template <int N, bool INV> struct Seq {
+    using P = Plan<N>;
+    static constexpr int S = P::S;
+    __host__ __device__ static constexpr int radix(int s) { return INV ? P::r[S - 1 - s] : P::r[s]; }
+    __host__ __device__ static constexpr int ns(int s) {  // product of the radices before s
+        int p = 1;
+        for (int i = 0; i < s; ++i) p *= radix(i);
+        return p;
+    }
+};
+
+// threads per column: one radix-8 (or the largest radix) butterfly each per
+// stage, divided by F
+template <int N> struct MaxRadix {
+    static constexpr int value() {
+        int m = 0;
+        for (int i = 0; i < Plan<N>::S; ++i) m = Plan<N>::r[i] > m ? Plan<N>::r[i] : m;
+        return m;
+    }
+};
+
+// ---------------------------------------------------------------- engine
+// Column transform engine.  TPC threads per column; thread t owns butterflies
+// j = t + b*TPC (b < BPT(s)) of every stage.  LdsIdx maps (position, column)
+// to an LDS element offset.
+template <typename T, int N, int TPC, bool INV> struct Engine {
+    using C = cplx<T>;
+    using Q = Seq<N, INV>;
+    static constexpr int S = Q::S;
+    __host__ __device__ static constexpr int R(int s) { return Q::radix(s); }
+    __host__ __device__ static constexpr int NS(int s) { return Q::ns(s); }
+    __host__ __device__ static constexpr int BPT(int s) { return (N / R(s) + TPC - 1) / TPC; }
+    static constexpr int maxv() {
+        int m = 0;
+        for (int s = 0; s < S; ++s) m = BPT(s) * R(s) > m ? BPT(s) * R(s) : m;
+        return m;
+    }
+    static constexpr int V = maxv();
+
+    // butterflies of stage s on registers (twiddle, then radix-R DFT)
+    template <int s>
+    __device__ __forceinline__ static void compute(C *v, int t, const Twiddle<T> &tw) {
+        constexpr int r_ = R(s), ns_ = NS(s), nb = N / r_;
+#pragma unroll
+        for (int b = 0; b < BPT(s); ++b) {
+            const int j = t + b * TPC;
+            if ((nb % TPC == 0) || j < nb) {
+                C *w = v + b * r_;
+                if (ns_ > 1) {
+                    const int k = j % ns_;
+                    constexpr int stride = N / (ns_ * r_);
+#pragma unroll
+                    for (int r = 1; r < r_; ++r) w[r] = tw.template mul<INV>(w[r], k * r * stride);
+                }
+                DFT<r_, INV, C>::run(w);
+            }
+        }
+    }
+
+    // output position of leg r of butterfly j at stage s
+    template <int s> __device__ __forceinline__ static int out_pos(int j, int r) {
+        constexpr int r_ = R(s), ns_ = NS(s);
+        return (j / ns_) * ns_ * r_ + (j % ns_) + r * ns_;
+    }
+    // input position of leg r of butterfly j at stage s
+    template <int s> __device__ __forceinline__ static int in_pos(int j, int r) {
+        return j + r * (N / R(s));
+    }
+
+    template <int s, typename Idx>
+    __device__ __forceinline__ static void store_lds(const C *v, C *lds, int t, Idx idx) {
+        constexpr int r_ = R(s), nb = N / r_;
+#pragma unroll
+        for (int b = 0; b < BPT(s); ++b) {
+            const int j = t + b * TPC;
+            if ((nb % TPC == 0) || j < nb) {
+#pragma unroll
+                for (int r = 0; r < r_; ++r) lds[idx(out_pos<s>(j, r))] = v[b * r_ + r];
+            }
+        }
+    }
+    template <int s, typename Idx>
+    __device__ __forceinline__ static void load_lds(C *v, const C *lds, int t, Idx idx) {
+        constexpr int r_ = R(s), nb = N / r_;
+#pragma unroll
+        for (int b = 0; b < BPT(s); ++b) {
+            const int j = t + b * TPC;
+            if ((nb % TPC == 0) || j < nb) {
+#pragma unroll
+                for (int r = 0; r < r_; ++r) v[b * r_ + r] = lds[idx(in_pos<s>(j, r))];
+            }
+        }
+    }
+
+    // stages [s, S) given stage-s inputs in registers; on return registers
+    // hold the last stage's outputs at positions j + r N/R(S-1)
+    template <int s, typename Idx>
+    __device__ __forceinline__ static void run_from(C *v, C *lds, int t, Idx idx, const Twiddle<T> &tw) {
+        compute<s>(v, t, tw);
+        if constexpr (s + 1 < S) {
+            store_lds<s>(v, lds, t, idx);
+            __syncthreads();
+            load_lds<s + 1>(v, lds, t, idx);
+            __syncthreads();
+            run_from<s + 1>(v, lds, t, idx, tw);
+        }
+    }
+
+    // visit the final outputs: f(position, leg r, value&); legs r < R/2 of
+    // the last stage are exactly the positions below N/2
+    template <typename F>
+    __device__ __forceinline__ static void for_outputs(C *v, int t, F f) {
+        constexpr int s = S - 1, r_ = R(s), nb = N / r_;
+#pragma unroll
+        for (int b = 0; b < BPT(s); ++b) {
+            const int j = t + b * TPC;
+            if ((nb % TPC == 0) || j < nb) {
+#pragma unroll
+                for (int r = 0; r < r_; ++r) f(j + r * nb, r, v[b * r_ + r]);
+            }
+        }
+    }
+    // fill the first-stage inputs: v = g(position, leg r); legs r < R/2 of
+    // the first stage are exactly the positions below N/2
+    template <typename G>
+    __device__ __forceinline__ static void for_inputs(C *v, int t, G g) {
+        constexpr int r_ = R(0), nb = N / r_;
+#pragma unroll
+        for (int b = 0; b < BPT(0); ++b) {
+            const int j = t + b * TPC;
+            if ((nb % TPC == 0) || j < nb) {
+#pragma unroll
+                for (int r = 0; r < r_; ++r) v[b * r_ + r] = g(j + r * nb, r);
+            }
+        }
+    }
+};
+
+}  // namespace psp

@@ -1,0 +1,81 @@
+// host_common.hpp - shared internal declarations of libpsp's host code.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/psp.h"
+#include "kernels.h"
+
+namespace psp {
+
+// thread-local error detail; returns e for convenience
+psp_status fail(psp_status e, const char *fmt, ...);
+psp_status hip_fail(hipError_t err, const char *what);
+
+// ---- S0: Gaussian-sum weights and exponents (sinc quadrature) -------------
+void gs_fit(int R, double eps, double delta, std::vector<double> &omega, std::vector<double> &alpha);
+
+// ---- S1: 1D integrals of the separable kernel transform --------------------
+// J0[s*(n+1)+k] = int_{-L/2}^{L/2} exp(-a_s y^2) cos(2 pi k y / L) dy, J2 with y^2.
+void tables_1d(const std::vector<double> &alpha, int n, double L, std::vector<double> &J0,
+               std::vector<double> &J2);
+
+// ---- device resources ------------------------------------------------------
+struct DevSpectrum {            // the multiplier octant, shared between plans
+    int device = -1;
+    double *mult = nullptr;     // blocked layout, (n+1)*P*(n+1) doubles
+    size_t bytes = 0;
+    ~DevSpectrum();
+};
+
+struct Twiddles {               // per (device, N), process lifetime
+    void *w64 = nullptr;        // double2[N]
+    void *hi32 = nullptr;       // float2[N]
+    void *lo32 = nullptr;       // float2[N]
+};
+psp_status get_twiddles(int device, int N, const Twiddles **out);
+
+struct Workspace {
+    void *X = nullptr;
+    void *A = nullptr;
+    size_t bytes = 0;
+};
+
+inline int pitch_for(int n) { return ((n + 1 + 15) / 16) * 16; }
+inline size_t workspace_bytes(int n, bool f32) {
+    const size_t c = f32 ? 8 : 16;
+    const size_t P = (size_t)pitch_for(n);
+    return c * P * ((size_t)n * n + (size_t)n * 2 * n);
+}
+inline size_t spectrum_bytes(int n) { return 8 * (size_t)(n + 1) * (n + 1) * pitch_for(n); }
+
+}  // namespace psp
+
+struct psp_plan {
+    int n = 0;
+    double h = 0, L = 0, eps = 0, delta = 0;
+    int R = 0;
+    psp_dtype dtype = PSP_F64;
+    std::vector<double> omega, alpha;   // S0
+    std::vector<double> J0, J2;         // S1 (host)
+    bool tables_ready = false;
+    int device = -1;
+    std::shared_ptr<psp::DevSpectrum> spec;
+    const psp::Twiddles *tw = nullptr;
+    bool precomputed = false;
+    std::mutex mu;
+    std::map<hipStream_t, psp::Workspace> ws;   // one workspace per stream
+};
+
+namespace psp {
+psp_status check_create(int n, double h, int R, double eps, double delta);
+psp_status plan_workspace(psp_plan *p, hipStream_t st, Workspace **out);
+SolveArgs solve_args(const psp_plan *p, const Workspace &w, const void *rho, void *u);
+}  // namespace psp

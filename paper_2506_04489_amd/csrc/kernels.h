@@ -1,0 +1,38 @@
+// kernels.h - host-side launch interface of the device passes (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace psp {
+
+// One solve's buffers (device pointers) and sizes.
+struct SolveArgs {
+    int n = 0;          // points per axis; padded length N = 2n
+    int P = 0;          // pitch of the half-spectrum axis, round_up(n+1, 16)
+    bool f32 = false;   // FP32 tier (data and FFT in FP32, multiplier FP64)
+    bool full = false;  // uncropped (2n)^3 output (test hook)
+    const void *rho = nullptr;
+    void *u = nullptr;
+    void *X = nullptr;   // n*n*P complex
+    void *A = nullptr;   // n*N*P complex
+    void *A2 = nullptr;  // N*N*P complex, full variant only
+    void *Y2 = nullptr;  // N*N*P complex, full variant only
+    const double *mult = nullptr;   // blocked multiplier octant
+    const void *tw_hi = nullptr;    // twiddles: double2[N] (FP64) or float2[N] hi
+    const void *tw_lo = nullptr;    // float2[N] lo (FP32 only)
+};
+
+hipError_t launch_solve(const SolveArgs &s, hipStream_t st);
+
+hipError_t launch_spectrum(const double *J0, const double *J2, const double *omega, int R, int n, int P,
+                           double scale, double *mult, hipStream_t st);
+
+// supported padded lengths
+inline bool supported_length(int N) {
+    switch (N) {
+        case 8: case 12: case 16: case 24: case 32: case 48: case 64: case 96:
+        case 128: case 192: case 256: case 384: case 512: case 768: return true;
+        default: return false;
+    }
+}
+
+}  // namespace psp

@@ -1,0 +1,358 @@
+// passes.hip - the solve's device passes and the kernel-spectrum build.
+//
+// Data layout in HBM for one solve with n points per axis, N = 2n, and
+// P = round_up(n+1, 16) (pitch of the half-spectrum axis k3 = 0..n):
+//   rho, u : n*n*n real, [i1][i2][i3]
+//   X      : n*n*P complex, [i1][i2][k3]   after H1; reused as Y after H4
+//   A      : n*N*P complex, [i1][k2][k3]   after H2; H3 updates it in place
+//   mult   : (n+1)*P*(n+1) FP64, blocked [b][c/8][a][c%8] holding the
+//            multiplier m(|k1| = a, |k2| = b, k3 = c), zero for c > n
+// Passes (Algorithm 2):
+//   H1 k_z_r2c   : forward transform along i3 of the padded real lines, two
+//                  real lines per complex transform, n+1 bins kept
+//   H2 k_y_fwd   : forward along i2 (input rows i2 >= n are zero)
+//   H3 k_x_fused : forward along i1 (inputs i1 >= n zero), multiply by m,
+//                  inverse along i1 keeping outputs i1 < n
+//   H4 k_y_inv   : inverse along k2 keeping outputs i2 < n
+//   H5 k_z_c2r   : inverse Hermitian transform along k3 keeping i3 < n
+#include "fft_core.hpp"
+#include "kernels.h"
+
+namespace psp {
+
+// ------------------------------------------------------------ configuration
+template <typename T> struct StridedCols;
+template <> struct StridedCols<double> { static constexpr int W = 8; };   // 128 B rows
+template <> struct StridedCols<float> { static constexpr int W = 16; };   // 128 B rows
+
+template <typename T, int N> struct StridedCfg {
+    static constexpr int W = StridedCols<T>::W;
+    static constexpr int TPC0 = N / MaxRadix<N>::value();
+    static constexpr int TPC = (TPC0 * W > 1024) ? TPC0 / 2 : TPC0;
+    static constexpr int THREADS = TPC * W;
+};
+
+template <typename T, int N> struct LineCfg {
+    static constexpr int TPC = N / MaxRadix<N>::value();
+    static constexpr int Q = (256 / TPC) > 0 ? (256 / TPC) : 1;   // complex lines per WG
+    static constexpr int THREADS = TPC * Q;
+};
+
+template <int W> struct IdxInter {   // (position, column) -> position*W + column
+    int col;
+    __device__ __forceinline__ int operator()(int pos) const { return pos * W + col; }
+};
+struct IdxLine {                     // column-major: base + position
+    int base;
+    __device__ __forceinline__ int operator()(int pos) const { return base + pos; }
+};
+
+// ------------------------------------------------------------------- H1
+// Two real lines a, b (flattened (i1, i2) = 2q, 2q+1) form z = a + i b.  The
+// padded length-N line has data in [0, n) only.  After the transform,
+// A[k] = (Z[k] + conj Z[N-k])/2 and B[k] = (Z[k] - conj Z[N-k])/(2i).
+template <typename T, int N>
+__global__ void __launch_bounds__((LineCfg<T, N>::THREADS))
+k_z_r2c(const T *__restrict__ rho, cplx<T> *__restrict__ X, int npairs, int P, Twiddle<T> tw) {
+    using C = cplx<T>;
+    using Cfg = LineCfg<T, N>;
+    using E = Engine<T, N, Cfg::TPC, false>;
+    constexpr int n = N / 2;
+    __shared__ C lds[Cfg::Q * N];
+    const int t = threadIdx.x % Cfg::TPC, q = threadIdx.x / Cfg::TPC;
+    const int pair = blockIdx.x * Cfg::Q + q;
+    const bool active = pair < npairs;
+    const T *ra = rho + (size_t)(2 * pair) * n;
+    const T *rb = ra + n;
+    C v[E::V];
+    E::for_inputs(v, t, [&](int pos, int r) -> C {
+        if (r < E::R(0) / 2 && active) return C{ra[pos], rb[pos]};
+        return c_zero<C>();
+    });
+    IdxLine idx{q * N};
+    E::template run_from<0>(v, lds, t, idx, tw);
+    E::for_outputs(v, t, [&](int pos, int, C &val) { lds[q * N + pos] = val; });
+    __syncthreads();
+    if (active) {
+        C *xa = X + (size_t)(2 * pair) * P;
+        C *xb = xa + P;
+        for (int k = t; k <= n; k += Cfg::TPC) {
+            const C z = lds[q * N + k];
+            const C zc = lds[q * N + (k == 0 ? 0 : N - k)];
+            xa[k] = C{T(0.5) * (z.x + zc.x), T(0.5) * (z.y - zc.y)};
+            const C d = C{z.x - zc.x, z.y + zc.y};     // Z[k] - conj Z[N-k]
+            xb[k] = C{T(0.5) * d.y, -T(0.5) * d.x};   // d / (2i)
+        }
+    }
+}
+
+// ------------------------------------------------------------------- H2
+template <typename T, int N>
+__global__ void __launch_bounds__((StridedCfg<T, N>::THREADS))
+k_y_fwd(const cplx<T> *__restrict__ X, cplx<T> *__restrict__ A, int P, int ntile, Twiddle<T> tw) {
+    using C = cplx<T>;
+    using Cfg = StridedCfg<T, N>;
+    using E = Engine<T, N, Cfg::TPC, false>;
+    constexpr int n = N / 2, W = Cfg::W;
+    __shared__ C lds[N * W];
+    const int col = threadIdx.x % W, t = threadIdx.x / W;
+    const int i1 = blockIdx.x / ntile, tile = blockIdx.x % ntile;
+    const int c = tile * W + col;
+    const bool valid = c <= n;
+    const C *src = X + (size_t)i1 * n * P + c;
+    C *dst = A + (size_t)i1 * N * P + c;
+    C v[E::V];
+    E::for_inputs(v, t, [&](int pos, int r) -> C {
+        if (r < E::R(0) / 2 && valid) return src[(size_t)pos * P];
+        return c_zero<C>();
+    });
+    E::template run_from<0>(v, lds, t, IdxInter<W>{col}, tw);
+    E::for_outputs(v, t, [&](int pos, int, C &val) {
+        if (valid) dst[(size_t)pos * P] = val;
+    });
+}
+
+// ------------------------------------------------------------------- H3
+// Work item (b, tile, side): column k2 = b (side 0) or N - b (side 1), both
+// reading the same multiplier block.  Items (b, tile, 0) and (b, tile, 1) go
+// to workgroups g and g + 8, which the dispatcher places on the same XCD at
+// nearly the same time, so the second read of the block hits that XCD's L2.
+template <typename T, int N, bool FULL>
+__global__ void __launch_bounds__((StridedCfg<T, N>::THREADS))
+k_x_fused(const cplx<T> *src_base, cplx<T> *dst_base, const double *__restrict__ mult, int P,
+          int ntile, Twiddle<T> tw) {
+    using C = cplx<T>;
+    using Cfg = StridedCfg<T, N>;
+    using EF = Engine<T, N, Cfg::TPC, false>;
+    using EI = Engine<T, N, Cfg::TPC, true>;
+    constexpr int n = N / 2, W = Cfg::W;
+    __shared__ C lds[N * W];
+    const int g = blockIdx.x;
+    const int pi = (g / 16) * 8 + (g % 8), side = (g % 16) / 8;
+    if (pi >= (n + 1) * ntile) return;              // uniform over the workgroup
+    const int b = pi / ntile, tile = pi % ntile;
+    if (side && (b == 0 || b == n)) return;
+    const int k2 = side ? N - b : b;
+    const int col = threadIdx.x % W, t = threadIdx.x / W;
+    const int c = tile * W + col;
+    const bool valid = c <= n;
+    const size_t stride = (size_t)N * P;            // step in i1
+    const C *src = src_base + (size_t)k2 * P + c;
+    C *dst = dst_base + (size_t)k2 * P + c;
+    const double *mrow = mult + ((size_t)(b * (P / 8) + c / 8) * (n + 1)) * 8 + (c & 7);
+    C v[EF::V];
+    EF::for_inputs(v, t, [&](int pos, int r) -> C {
+        if (r < EF::R(0) / 2 && valid) return src[pos * stride];
+        return c_zero<C>();
+    });
+    EF::template run_from<0>(v, lds, t, IdxInter<W>{col}, tw);
+    EF::for_outputs(v, t, [&](int pos, int, C &val) {
+        const int a = pos <= n ? pos : N - pos;
+        const double m = mrow[(size_t)a * 8];
+        val = C{T((double)val.x * m), T((double)val.y * m)};
+    });
+    EI::template run_from<0>(v, lds, t, IdxInter<W>{col}, tw);
+    EI::for_outputs(v, t, [&](int pos, int r, C &val) {
+        if (valid && (FULL || r < EI::R(EI::S - 1) / 2)) dst[pos * stride] = val;
+    });
+}
+
+// ------------------------------------------------------------------- H4
+template <typename T, int N, bool FULL>
+__global__ void __launch_bounds__((StridedCfg<T, N>::THREADS))
+k_y_inv(const cplx<T> *__restrict__ A, cplx<T> *__restrict__ Y, int P, int ntile, Twiddle<T> tw) {
+    using C = cplx<T>;
+    using Cfg = StridedCfg<T, N>;
+    using E = Engine<T, N, Cfg::TPC, true>;
+    constexpr int n = N / 2, W = Cfg::W;
+    constexpr int rows_out = FULL ? N : n;
+    __shared__ C lds[N * W];
+    const int col = threadIdx.x % W, t = threadIdx.x / W;
+    const int i1 = blockIdx.x / ntile, tile = blockIdx.x % ntile;
+    const int c = tile * W + col;
+    const bool valid = c <= n;
+    const C *src = A + (size_t)i1 * N * P + c;
+    C *dst = Y + (size_t)i1 * rows_out * P + c;
+    C v[E::V];
+    E::for_inputs(v, t, [&](int pos, int) -> C {
+        if (valid) return src[(size_t)pos * P];
+        return c_zero<C>();
+    });
+    E::template run_from<0>(v, lds, t, IdxInter<W>{col}, tw);
+    E::for_outputs(v, t, [&](int pos, int r, C &val) {
+        if (valid && (FULL || r < E::R(E::S - 1) / 2)) dst[(size_t)pos * P] = val;
+    });
+}
+
+// ------------------------------------------------------------------- H5
+// Rows a, b of Y (Hermitian half spectra) form Z[k] = A[k] + i B[k] on the
+// full length N; the inverse transform gives a + i b.  The imaginary parts
+// of the k = 0 and k = n bins are dropped (real transform).
+template <typename T, int N, bool FULL>
+__global__ void __launch_bounds__((LineCfg<T, N>::THREADS))
+k_z_c2r(const cplx<T> *__restrict__ Y, T *__restrict__ u, int npairs, int P, Twiddle<T> tw) {
+    using C = cplx<T>;
+    using Cfg = LineCfg<T, N>;
+    using E = Engine<T, N, Cfg::TPC, true>;
+    constexpr int n = N / 2;
+    constexpr int len_out = FULL ? N : n;
+    __shared__ C lds[Cfg::Q * N];
+    const int t = threadIdx.x % Cfg::TPC, q = threadIdx.x / Cfg::TPC;
+    const int pair = blockIdx.x * Cfg::Q + q;
+    const bool active = pair < npairs;
+    if (active) {
+        const C *ya = Y + (size_t)(2 * pair) * P;
+        const C *yb = ya + P;
+        for (int k = t; k <= n; k += Cfg::TPC) {
+            C A = ya[k], B = yb[k];
+            if (k == 0 || k == n) {
+                A.y = 0;
+                B.y = 0;
+            }
+            lds[q * N + k] = C{A.x - B.y, A.y + B.x};
+            if (k != 0 && k != n) lds[q * N + N - k] = C{A.x + B.y, B.x - A.y};
+        }
+    }
+    __syncthreads();
+    IdxLine idx{q * N};
+    C v[E::V];
+    E::template load_lds<0>(v, lds, t, idx);
+    __syncthreads();
+    E::template run_from<0>(v, lds, t, idx, tw);
+    T *ua = u + (size_t)(2 * pair) * len_out;
+    T *ub = ua + len_out;
+    E::for_outputs(v, t, [&](int pos, int r, C &val) {
+        if (active && (FULL || r < E::R(E::S - 1) / 2)) {
+            ua[pos] = val.x;
+            ub[pos] = val.y;
+        }
+    });
+}
+
+// ------------------------------------------------------------ S2: spectrum
+// Vhat[a,b,c] = sum_s w_s (J2(a)J0(b)J0(c) + J0(a)J2(b)J0(c) + J0(a)J0(b)J2(c))
+// as a GEMM over K = 2R per b: rows a, columns c,
+//   Amat[a,(s,0)] = w_s (J2(a)J0(b) + J0(a)J2(b)), Amat[a,(s,1)] = w_s J0(a)J0(b),
+//   Bmat[(s,0),c] = J0(c),                       Bmat[(s,1),c] = J2(c),
+// on v_mfma_f64_16x16x4_f64 tiles of 16 a x 16 c; the epilogue applies
+// m = scale (a^2 + b^2 + c^2) Vhat with scale = -(2 pi/L)^2 / N^3.
+// Operand layout of the 16x16x4 FP64 MFMA (lane l): A[l%16][l/16],
+// B[l/16][l%16], D[l/16 + 4e][l%16] for e < 4.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256)
+k_spectrum(const double *__restrict__ J0, const double *__restrict__ J2,
+           const double *__restrict__ omega, int R, int n, int P, double scale,
+           double *__restrict__ mult) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nt = (n + 1 + 15) / 16;
+    const long tile = (long)blockIdx.x * 4 + wave;
+    if (tile >= (long)(n + 1) * nt * nt) return;    // no barriers in this kernel
+    const int b = (int)(tile / (nt * nt));
+    const int rem = (int)(tile % (nt * nt));
+    const int a0 = (rem / nt) * 16, c0 = (rem % nt) * 16;
+    const int row = lane & 15, kq = lane >> 4;
+    const int a = a0 + row, c = c0 + row;
+    const int n1 = n + 1;
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < 2 * R; k0 += 4) {
+        const int ks = k0 + kq, s = ks >> 1, ty = ks & 1;
+        double av = 0.0, bv = 0.0;
+        if (s < R) {
+            const double *j0 = J0 + (size_t)s * n1, *j2 = J2 + (size_t)s * n1;
+            if (a <= n) {
+                const double w = omega[s];
+                av = ty == 0 ? w * (j2[a] * j0[b] + j0[a] * j2[b]) : w * (j0[a] * j0[b]);
+            }
+            if (c <= n) bv = ty == 0 ? j0[c] : j2[c];
+        }
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+    }
+    const int cc = c0 + row;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int aa = a0 + kq + 4 * e;
+        if (aa <= n && cc <= n) {
+            const double k2 = (double)aa * aa + (double)b * b + (double)cc * cc;
+            mult[((size_t)(b * (P / 8) + cc / 8) * n1 + aa) * 8 + (cc & 7)] = scale * k2 * acc[e];
+        }
+    }
+}
+
+// --------------------------------------------------------------- launchers
+static inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
+
+template <typename T, int N>
+static hipError_t solve_impl(const SolveArgs &s, hipStream_t st) {
+    using C = cplx<T>;
+    constexpr int n = N / 2;
+    const int P = s.P;
+    Twiddle<T> tw;
+    if constexpr (sizeof(T) == 8) {
+        tw.w = (const double2 *)s.tw_hi;
+    } else {
+        tw.hi = (const float2 *)s.tw_hi;
+        tw.lo = (const float2 *)s.tw_lo;
+    }
+    const int npairs = n * n / 2;
+    C *X = (C *)s.X;
+    C *A = (C *)s.A;
+    {
+        using Cfg = LineCfg<T, N>;
+        hipLaunchKernelGGL((k_z_r2c<T, N>), dim3(ceil_div(npairs, Cfg::Q)), dim3(Cfg::THREADS), 0, st,
+                           (const T *)s.rho, X, npairs, P, tw);
+    }
+    using SC = StridedCfg<T, N>;
+    const int ntile = ceil_div(n + 1, SC::W);
+    hipLaunchKernelGGL((k_y_fwd<T, N>), dim3(n * ntile), dim3(SC::THREADS), 0, st, (const C *)X, A, P, ntile, tw);
+    const int npi = (n + 1) * ntile;
+    if (!s.full) {
+        hipLaunchKernelGGL((k_x_fused<T, N, false>), dim3(ceil_div(npi, 8) * 16), dim3(SC::THREADS), 0, st,
+                           (const C *)A, A, s.mult, P, ntile, tw);
+        hipLaunchKernelGGL((k_y_inv<T, N, false>), dim3(n * ntile), dim3(SC::THREADS), 0, st, (const C *)A, X, P,
+                           ntile, tw);
+        using Cfg = LineCfg<T, N>;
+        hipLaunchKernelGGL((k_z_c2r<T, N, false>), dim3(ceil_div(npairs, Cfg::Q)), dim3(Cfg::THREADS), 0, st,
+                           (const C *)X, (T *)s.u, npairs, P, tw);
+    } else {
+        // uncropped variant: A2 (N x N x P) and Y2 (N x N x P) are separate
+        C *A2 = (C *)s.A2;
+        C *Y2 = (C *)s.Y2;
+        hipLaunchKernelGGL((k_x_fused<T, N, true>), dim3(ceil_div(npi, 8) * 16), dim3(SC::THREADS), 0, st,
+                           (const C *)A, A2, s.mult, P, ntile, tw);
+        hipLaunchKernelGGL((k_y_inv<T, N, true>), dim3(N * ntile), dim3(SC::THREADS), 0, st, (const C *)A2, Y2, P,
+                           ntile, tw);
+        using Cfg = LineCfg<T, N>;
+        const int np2 = N * N / 2;
+        hipLaunchKernelGGL((k_z_c2r<T, N, true>), dim3(ceil_div(np2, Cfg::Q)), dim3(Cfg::THREADS), 0, st,
+                           (const C *)Y2, (T *)s.u, np2, P, tw);
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t solve_dispatch(const SolveArgs &s, hipStream_t st) {
+    switch (2 * s.n) {
+#define PSP_CASE(NN) \
+    case NN: return solve_impl<T, NN>(s, st);
+        PSP_CASE(8) PSP_CASE(12) PSP_CASE(16) PSP_CASE(24) PSP_CASE(32) PSP_CASE(48) PSP_CASE(64)
+        PSP_CASE(96) PSP_CASE(128) PSP_CASE(192) PSP_CASE(256) PSP_CASE(384) PSP_CASE(512) PSP_CASE(768)
+#undef PSP_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_solve(const SolveArgs &s, hipStream_t st) {
+    return s.f32 ? solve_dispatch<float>(s, st) : solve_dispatch<double>(s, st);
+}
+
+hipError_t launch_spectrum(const double *J0, const double *J2, const double *omega, int R, int n, int P,
+                           double scale, double *mult, hipStream_t st) {
+    const int nt = (n + 1 + 15) / 16;
+    const long tiles = (long)(n + 1) * nt * nt;
+    hipLaunchKernelGGL(k_spectrum, dim3(ceil_div(tiles, 4)), dim3(256), 0, st, J0, J2, omega, R, n, P, scale,
+                       mult);
+    return hipGetLastError();
+}
+
+}  // namespace psp

@@ -1,0 +1,411 @@
+// serve.cpp - continuous-batching request loop over the batched solve.
+//
+// A scheduler thread owns the device work.  Each turn it
+//   1. retires launched batches whose completion event has fired (their
+//      workspaces go back to a pool, their slots free up, latency is the
+//      host time from submit to the observed completion);
+//   2. admits queued requests in arrival order while a slot is free and the
+//      request's footprint fits the HBM budget: a workspace for (n, tier)
+//      (reused from the pool when one is free) and, on a spectrum-cache miss,
+//      the multiplier octant (8 (n+1)^2 round_up(n+1,16) bytes).  Idle cached
+//      spectra and pooled workspaces are evicted, least recently used first,
+//      to make room; the queue head waits when nothing more can be freed;
+//   3. launches every admitted request of one tier as one batch on the next
+//      stream of a small pool and records a completion event, so requests
+//      that arrive while others run are admitted and overlap on the device.
+// Every solve runs the same kernels on its own workspace, so a result is
+// bitwise the same alone and in any mix.
+#include <atomic>
+#include <cmath>
+#include <tuple>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <list>
+#include <thread>
+#include <unordered_map>
+
+#include "host_common.hpp"
+
+namespace psp {
+
+using Clock = std::chrono::steady_clock;
+hipError_t launch_batch(int count, const SolveArgs *args, hipStream_t st);
+
+struct ServeReq {
+    int n = 0;
+    double h = 0;
+    int R = 0;
+    psp_dtype tier = PSP_F64;
+    const void *rho = nullptr;
+    void *u = nullptr;
+    Clock::time_point t_submit;
+    bool done = false;
+    psp_status result = PSP_OK;
+    double latency_ms = 0;
+};
+
+struct CachedSpec {                 // plans of both tiers for one (n, h, R)
+    psp_plan *plan[2] = {nullptr, nullptr};
+    size_t bytes = 0;
+    int users = 0;
+    Clock::time_point last_use;
+};
+
+struct PooledWs {
+    Workspace w;
+    int n;
+    bool f32;
+};
+
+struct Batch {
+    hipEvent_t ev = nullptr;
+    std::vector<uint64_t> ids;
+    std::vector<PooledWs> ws;
+    std::vector<std::tuple<int, double, int>> keys;
+};
+
+}  // namespace psp
+
+using namespace psp;
+
+struct psp_server {
+    size_t budget = 0;
+    int max_slots = 1;
+    int device = 0;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<uint64_t> queue;
+    std::unordered_map<uint64_t, ServeReq> reqs;
+    uint64_t next_id = 1;
+    size_t pending_total = 0;
+    bool stop = false;
+    // scheduler-thread state
+    std::map<std::tuple<int, double, int>, CachedSpec> specs;
+    std::vector<PooledWs> pool;
+    std::list<Batch> inflight;
+    std::vector<hipStream_t> streams;
+    int next_stream = 0;
+    int slots_used = 0;
+    std::atomic<size_t> bytes_in_use{0}, bytes_peak{0};
+    std::atomic<uint64_t> completed{0}, hits{0}, misses{0};
+    std::thread sched;
+};
+
+namespace psp {
+
+static void account(psp_server *sv, long delta) {
+    size_t now = sv->bytes_in_use.fetch_add((size_t)delta) + (size_t)delta;
+    size_t pk = sv->bytes_peak.load();
+    while (now > pk && !sv->bytes_peak.compare_exchange_weak(pk, now)) {
+    }
+}
+
+static size_t ws_bytes(int n, bool f32) { return workspace_bytes(n, f32); }
+
+static void free_ws(psp_server *sv, PooledWs &p) {
+    (void)hipFree(p.w.X);
+    (void)hipFree(p.w.A);
+    account(sv, -(long)p.w.bytes);
+}
+
+// free idle memory (pooled workspaces first, then LRU idle spectra) until
+// `need` more bytes fit the budget; returns whether they fit
+static bool make_room(psp_server *sv, size_t need, const std::tuple<int, double, int> *keep) {
+    while (sv->bytes_in_use.load() + need > sv->budget) {
+        if (!sv->pool.empty()) {
+            free_ws(sv, sv->pool.back());
+            sv->pool.pop_back();
+            continue;
+        }
+        auto victim = sv->specs.end();
+        for (auto it = sv->specs.begin(); it != sv->specs.end(); ++it) {
+            if (it->second.users > 0 || (keep && it->first == *keep)) continue;
+            if (victim == sv->specs.end() || it->second.last_use < victim->second.last_use) victim = it;
+        }
+        if (victim == sv->specs.end()) return false;
+        for (int t = 0; t < 2; ++t) psp_plan_destroy(victim->second.plan[t]);
+        account(sv, -(long)victim->second.bytes);
+        sv->specs.erase(victim);
+    }
+    return true;
+}
+
+static psp_status get_plan(psp_server *sv, const ServeReq &r, psp_plan **out, bool *hit) {
+    auto key = std::make_tuple(r.n, r.h, r.R);
+    auto &cs = sv->specs[key];
+    const int t = r.tier == PSP_F32 ? 1 : 0;
+    *hit = cs.plan[0] || cs.plan[1];
+    if (!cs.plan[t]) {
+        psp_plan *p = nullptr;
+        psp_status st = psp_plan_create(r.n, r.h, r.R, r.tier, &p);
+        if (st != PSP_OK) return st;
+        st = psp_kernel_precompute(p, sv->streams[0]);
+        if (st != PSP_OK) {
+            psp_plan_destroy(p);
+            return st;
+        }
+        cs.plan[t] = p;
+        if (cs.bytes == 0) {
+            cs.bytes = spectrum_bytes(r.n);
+            account(sv, (long)cs.bytes);
+        }
+    }
+    cs.last_use = Clock::now();
+    *out = cs.plan[t];
+    return PSP_OK;
+}
+
+static psp_status take_ws(psp_server *sv, int n, bool f32, PooledWs *out) {
+    for (size_t i = 0; i < sv->pool.size(); ++i) {
+        if (sv->pool[i].n == n && sv->pool[i].f32 == f32) {
+            *out = sv->pool[i];
+            sv->pool.erase(sv->pool.begin() + i);
+            return PSP_OK;
+        }
+    }
+    PooledWs p;
+    p.n = n;
+    p.f32 = f32;
+    const size_t c = f32 ? 8 : 16, P = (size_t)pitch_for(n);
+    p.w.bytes = ws_bytes(n, f32);
+    if (hipMalloc(&p.w.X, c * P * n * n) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(PSP_ENOMEM, "serve workspace allocation failed");
+    }
+    if (hipMalloc(&p.w.A, c * P * n * 2 * n) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(p.w.X);
+        return fail(PSP_ENOMEM, "serve workspace allocation failed");
+    }
+    account(sv, (long)p.w.bytes);
+    *out = p;
+    return PSP_OK;
+}
+
+static void finish(psp_server *sv, uint64_t id, psp_status st) {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto &r = sv->reqs[id];
+    r.done = true;
+    r.result = st;
+    r.latency_ms = std::chrono::duration<double, std::milli>(Clock::now() - r.t_submit).count();
+    sv->pending_total--;
+    sv->completed++;
+    sv->cv_done.notify_all();
+}
+
+static void retire(psp_server *sv, bool wait) {
+    for (auto it = sv->inflight.begin(); it != sv->inflight.end();) {
+        hipError_t q = wait ? hipEventSynchronize(it->ev) : hipEventQuery(it->ev);
+        if (q == hipErrorNotReady) {
+            ++it;
+            continue;
+        }
+        const psp_status st = q == hipSuccess ? PSP_OK : PSP_EHIP;
+        for (uint64_t id : it->ids) finish(sv, id, st);
+        for (auto &w : it->ws) sv->pool.push_back(w);
+        for (auto &k : it->keys) sv->specs[k].users--;
+        sv->slots_used -= (int)it->ids.size();
+        (void)hipEventDestroy(it->ev);
+        it = sv->inflight.erase(it);
+    }
+}
+
+static void scheduler(psp_server *sv) {
+    (void)hipSetDevice(sv->device);
+    for (;;) {
+        retire(sv, false);
+        // snapshot the queue head under the lock
+        std::vector<std::pair<uint64_t, ServeReq>> cand;
+        {
+            std::unique_lock<std::mutex> lk(sv->mu);
+            if (sv->queue.empty() && sv->inflight.empty()) {
+                if (sv->stop) break;
+                sv->cv_work.wait_for(lk, std::chrono::milliseconds(2));
+                continue;
+            }
+            for (uint64_t id : sv->queue) {
+                if ((int)cand.size() + sv->slots_used >= sv->max_slots) break;
+                cand.emplace_back(id, sv->reqs[id]);
+            }
+        }
+        // admit in order
+        std::vector<uint64_t> admitted;
+        std::vector<SolveArgs> args[2];
+        std::vector<uint64_t> ids[2];
+        std::vector<PooledWs> wss[2];
+        std::vector<std::tuple<int, double, int>> keys[2];
+        for (auto &c : cand) {
+            const ServeReq &r = c.second;
+            const auto key = std::make_tuple(r.n, r.h, r.R);
+            const bool f32 = r.tier == PSP_F32;
+            auto sit = sv->specs.find(key);
+            const bool cached = sit != sv->specs.end() && (sit->second.plan[0] || sit->second.plan[1]);
+            bool have_ws = false;
+            for (auto &p : sv->pool) have_ws |= (p.n == r.n && p.f32 == f32);
+            const size_t need = (cached ? 0 : spectrum_bytes(r.n)) + (have_ws ? 0 : ws_bytes(r.n, f32));
+            if (!make_room(sv, need, &key)) break;   // head of line waits for memory
+            psp_plan *p = nullptr;
+            bool hit = false;
+            psp_status st = get_plan(sv, r, &p, &hit);
+            PooledWs w;
+            if (st == PSP_OK) st = take_ws(sv, r.n, f32, &w);
+            admitted.push_back(c.first);
+            if (st != PSP_OK) {
+                finish(sv, c.first, st);
+                continue;
+            }
+            (hit ? sv->hits : sv->misses)++;
+            sv->specs[key].users++;
+            const int t = f32 ? 1 : 0;
+            args[t].push_back(solve_args(p, w.w, r.rho, r.u));
+            ids[t].push_back(c.first);
+            wss[t].push_back(w);
+            keys[t].push_back(key);
+        }
+        if (!admitted.empty()) {
+            std::lock_guard<std::mutex> lk(sv->mu);
+            for (uint64_t id : admitted)
+                for (auto it = sv->queue.begin(); it != sv->queue.end(); ++it)
+                    if (*it == id) {
+                        sv->queue.erase(it);
+                        break;
+                    }
+        }
+        for (int t = 0; t < 2; ++t) {
+            if (ids[t].empty()) continue;
+            hipStream_t st = sv->streams[sv->next_stream];
+            sv->next_stream = (sv->next_stream + 1) % (int)sv->streams.size();
+            Batch b;
+            hipError_t e = launch_batch((int)args[t].size(), args[t].data(), st);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&b.ev, hipEventDisableTiming);
+            if (e == hipSuccess) e = hipEventRecord(b.ev, st);
+            if (e != hipSuccess) {
+                for (uint64_t id : ids[t]) finish(sv, id, PSP_EHIP);
+                for (auto &w : wss[t]) sv->pool.push_back(w);
+                for (auto &k : keys[t]) sv->specs[k].users--;
+                continue;
+            }
+            b.ids = ids[t];
+            b.ws = wss[t];
+            b.keys = keys[t];
+            sv->slots_used += (int)b.ids.size();
+            sv->inflight.push_back(std::move(b));
+        }
+        if (admitted.empty()) {
+            // nothing admitted: wait for a completion or a new request
+            if (!sv->inflight.empty()) {
+                std::this_thread::sleep_for(std::chrono::microseconds(20));
+            } else {
+                std::unique_lock<std::mutex> lk(sv->mu);
+                sv->cv_work.wait_for(lk, std::chrono::milliseconds(1));
+            }
+        }
+    }
+    retire(sv, true);
+}
+
+}  // namespace psp
+
+extern "C" {
+
+psp_status psp_serve_create(size_t hbm_budget_bytes, int max_slots, psp_server **out) {
+    if (!out) return fail(PSP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (hbm_budget_bytes == 0 || max_slots < 1) return fail(PSP_EINVAL, "budget and max_slots must be positive");
+    psp_server *sv = new (std::nothrow) psp_server;
+    if (!sv) return fail(PSP_ENOMEM, "host allocation failed");
+    sv->budget = hbm_budget_bytes;
+    sv->max_slots = max_slots;
+    if (hipGetDevice(&sv->device) != hipSuccess) {
+        delete sv;
+        return fail(PSP_EHIP, "hipGetDevice failed");
+    }
+    for (int i = 0; i < 4; ++i) {
+        hipStream_t s;
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+            for (auto x : sv->streams) (void)hipStreamDestroy(x);
+            delete sv;
+            return fail(PSP_EHIP, "hipStreamCreate failed");
+        }
+        sv->streams.push_back(s);
+    }
+    sv->sched = std::thread(scheduler, sv);
+    *out = sv;
+    return PSP_OK;
+}
+
+psp_status psp_serve_submit(psp_server *sv, int n, double h, int R, psp_dtype tier, const void *rho_dev,
+                            void *u_dev, uint64_t *ticket) {
+    if (!sv || !rho_dev || !u_dev || !ticket) return fail(PSP_EINVAL, "NULL argument");
+    if (tier != PSP_F64 && tier != PSP_F32) return fail(PSP_EINVAL, "unknown tier");
+    const double half = (double)n * h;
+    psp_status st = check_create(n, h, R, 1e-4 * half, std::sqrt(3.0) * half);
+    if (st != PSP_OK) return st;
+    if (spectrum_bytes(n) + workspace_bytes(n, tier == PSP_F32) > sv->budget)
+        return fail(PSP_ENOMEM, "request footprint exceeds the whole budget");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (sv->queue.size() >= 65536) return fail(PSP_EBUSY, "queue full");
+    ServeReq r;
+    r.n = n;
+    r.h = h;
+    r.R = R;
+    r.tier = tier;
+    r.rho = rho_dev;
+    r.u = u_dev;
+    r.t_submit = Clock::now();
+    const uint64_t id = sv->next_id++;
+    sv->reqs.emplace(id, r);
+    sv->queue.push_back(id);
+    sv->pending_total++;
+    *ticket = id;
+    sv->cv_work.notify_one();
+    return PSP_OK;
+}
+
+psp_status psp_serve_poll(psp_server *sv, uint64_t ticket, int *done, psp_status *result, double *latency_ms) {
+    if (!sv) return fail(PSP_EINVAL, "server is NULL");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->reqs.find(ticket);
+    if (it == sv->reqs.end()) return fail(PSP_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    if (done) *done = it->second.done ? 1 : 0;
+    if (result) *result = it->second.result;
+    if (latency_ms) *latency_ms = it->second.latency_ms;
+    return PSP_OK;
+}
+
+psp_status psp_serve_drain(psp_server *sv) {
+    if (!sv) return fail(PSP_EINVAL, "server is NULL");
+    std::unique_lock<std::mutex> lk(sv->mu);
+    sv->cv_done.wait(lk, [&] { return sv->pending_total == 0; });
+    return PSP_OK;
+}
+
+psp_status psp_serve_stats(psp_server *sv, size_t *bytes_in_use, size_t *bytes_peak, uint64_t *completed,
+                           uint64_t *cache_hits, uint64_t *cache_misses) {
+    if (!sv) return fail(PSP_EINVAL, "server is NULL");
+    if (bytes_in_use) *bytes_in_use = sv->bytes_in_use.load();
+    if (bytes_peak) *bytes_peak = sv->bytes_peak.load();
+    if (completed) *completed = sv->completed.load();
+    if (cache_hits) *cache_hits = sv->hits.load();
+    if (cache_misses) *cache_misses = sv->misses.load();
+    return PSP_OK;
+}
+
+void psp_serve_destroy(psp_server *sv) {
+    if (!sv) return;
+    psp_serve_drain(sv);
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->stop = true;
+        sv->cv_work.notify_all();
+    }
+    sv->sched.join();
+    for (auto &w : sv->pool) free_ws(sv, w);
+    for (auto &kv : sv->specs)
+        for (int t = 0; t < 2; ++t) psp_plan_destroy(kv.second.plan[t]);
+    for (auto s : sv->streams) (void)hipStreamDestroy(s);
+    delete sv;
+}
+
+}  // extern "C"

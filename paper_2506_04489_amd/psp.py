@@ -1,0 +1,253 @@
+"""Thin ctypes binding of libpsp (the C ABI in include/psp.h).
+
+Argument marshalling only: every step of a solve runs in the library's HIP
+kernels.  PyTorch provides device memory and streams.  If libpsp.so has not
+been built, importing works but the first call raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpsp.so")
+
+PSP_F64, PSP_F32 = 0, 1
+STATUS = {0: "PSP_OK", -1: "PSP_EINVAL", -2: "PSP_ENOMEM", -3: "PSP_EUNSUPPORTED",
+          -4: "PSP_ESTATE", -5: "PSP_EHIP", -6: "PSP_EBUSY"}
+
+# every entry point the header declares, with (restype, argtypes)
+_vp, _i, _d, _sz, _u64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t, ctypes.c_uint64
+_P = ctypes.POINTER
+SIGNATURES = {
+    "psp_plan_create": (_i, [_i, _d, _i, _i, _P(_vp)]),
+    "psp_plan_create_ex": (_i, [_i, _d, _i, _i, _d, _d, _P(_vp)]),
+    "psp_kernel_precompute": (_i, [_vp, _vp]),
+    "psp_solve": (_i, [_vp, _vp, _vp, _vp]),
+    "psp_solve_batched": (_i, [_i, _P(_vp), _P(_vp), _P(_vp), _vp]),
+    "psp_solve_padded_debug": (_i, [_vp, _vp, _vp, _vp]),
+    "psp_plan_get_gs": (_i, [_vp, _P(_d), _P(_d)]),
+    "psp_plan_get_tables": (_i, [_vp, _P(_d), _P(_d)]),
+    "psp_plan_get_multiplier": (_i, [_vp, _P(_d)]),
+    "psp_plan_workspace_bytes": (_i, [_vp, _P(_sz)]),
+    "psp_plan_spectrum_bytes": (_i, [_vp, _P(_sz)]),
+    "psp_plan_destroy": (None, [_vp]),
+    "psp_serve_create": (_i, [_sz, _i, _P(_vp)]),
+    "psp_serve_submit": (_i, [_vp, _i, _d, _i, _i, _vp, _vp, _P(_u64)]),
+    "psp_serve_poll": (_i, [_vp, _u64, _P(_i), _P(_i), _P(_d)]),
+    "psp_serve_drain": (_i, [_vp]),
+    "psp_serve_stats": (_i, [_vp, _P(_sz), _P(_sz), _P(_u64), _P(_u64), _P(_u64)]),
+    "psp_serve_destroy": (None, [_vp]),
+    "psp_strerror": (ctypes.c_char_p, [_i]),
+    "psp_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+class PspError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        self.status = status
+        super().__init__("%s: %s" % (STATUS.get(status, status), detail))
+
+
+def lib() -> ctypes.CDLL:
+    """Load libpsp.so once; raise if it is missing (no CPU fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libpsp.so is not built (run paper_2506_04489_amd.build.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise PspError(status, lib().psp_last_error().decode())
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _dtype_code(dtype) -> int:
+    if dtype in ("f64", "float64", PSP_F64):
+        return PSP_F64
+    if dtype in ("f32", "float32", PSP_F32):
+        return PSP_F32
+    import torch
+    if dtype is torch.float64:
+        return PSP_F64
+    if dtype is torch.float32:
+        return PSP_F32
+    raise ValueError("dtype must be f64 or f32")
+
+
+def _torch_dtype(code: int):
+    import torch
+    return torch.float64 if code == PSP_F64 else torch.float32
+
+
+class Plan:
+    """One (n, h, R, dtype) configuration: psp_plan_create[_ex] + helpers."""
+
+    def __init__(self, n: int, h: float, R: int, dtype="f64", eps: float = None, delta: float = None):
+        self.n, self.h, self.R = int(n), float(h), int(R)
+        self.code = _dtype_code(dtype)
+        handle = ctypes.c_void_p()
+        if eps is None and delta is None:
+            _check(lib().psp_plan_create(self.n, self.h, self.R, self.code, ctypes.byref(handle)))
+        else:
+            _check(lib().psp_plan_create_ex(self.n, self.h, self.R, self.code, float(eps), float(delta),
+                                            ctypes.byref(handle)))
+        self._h = handle
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def torch_dtype(self):
+        return _torch_dtype(self.code)
+
+    def close(self):
+        if self._h:
+            lib().psp_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def precompute(self, stream=None):
+        _check(lib().psp_kernel_precompute(self._h, _stream_ptr(stream)))
+        return self
+
+    def _check_tensor(self, t, shape):
+        import torch
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise ValueError("expected a CUDA (HIP) tensor")
+        if t.dtype != self.torch_dtype:
+            raise ValueError("tensor dtype %s does not match the plan's %s" % (t.dtype, self.torch_dtype))
+        if tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+            raise ValueError("expected a contiguous tensor of shape %s" % (shape,))
+
+    def solve(self, rho, u=None, stream=None):
+        import torch
+        n = self.n
+        self._check_tensor(rho, (n, n, n))
+        if u is None:
+            u = torch.empty_like(rho)
+        self._check_tensor(u, (n, n, n))
+        _check(lib().psp_solve(self._h, rho.data_ptr(), u.data_ptr(), _stream_ptr(stream)))
+        return u
+
+    def solve_padded_debug(self, rho, stream=None):
+        import torch
+        n = self.n
+        self._check_tensor(rho, (n, n, n))
+        up = torch.empty((2 * n,) * 3, dtype=rho.dtype, device=rho.device)
+        _check(lib().psp_solve_padded_debug(self._h, rho.data_ptr(), up.data_ptr(), _stream_ptr(stream)))
+        return up
+
+    def gs(self):
+        om = np.empty(self.R)
+        al = np.empty(self.R)
+        _check(lib().psp_plan_get_gs(self._h, om.ctypes.data_as(_P(_d)), al.ctypes.data_as(_P(_d))))
+        return om, al
+
+    def tables(self):
+        J0 = np.empty((self.R, self.n + 1))
+        J2 = np.empty((self.R, self.n + 1))
+        _check(lib().psp_plan_get_tables(self._h, J0.ctypes.data_as(_P(_d)), J2.ctypes.data_as(_P(_d))))
+        return J0, J2
+
+    def multiplier(self):
+        m = np.empty((self.n + 1,) * 3)
+        _check(lib().psp_plan_get_multiplier(self._h, m.ctypes.data_as(_P(_d))))
+        return m
+
+    def workspace_bytes(self) -> int:
+        v = ctypes.c_size_t()
+        _check(lib().psp_plan_workspace_bytes(self._h, ctypes.byref(v)))
+        return v.value
+
+    def spectrum_bytes(self) -> int:
+        v = ctypes.c_size_t()
+        _check(lib().psp_plan_spectrum_bytes(self._h, ctypes.byref(v)))
+        return v.value
+
+
+def solve_batched(plans: Sequence[Plan], rhos, us, stream=None):
+    """psp_solve_batched over matching lists of plans, inputs and outputs."""
+    k = len(plans)
+    if not (len(rhos) == k and len(us) == k):
+        raise ValueError("plans, rhos and us must have the same length")
+    for p, r, u in zip(plans, rhos, us):
+        p._check_tensor(r, (p.n,) * 3)
+        p._check_tensor(u, (p.n,) * 3)
+    ph = (ctypes.c_void_p * k)(*[p.handle.value for p in plans])
+    rp = (ctypes.c_void_p * k)(*[r.data_ptr() for r in rhos])
+    up = (ctypes.c_void_p * k)(*[u.data_ptr() for u in us])
+    _check(lib().psp_solve_batched(k, ph, rp, up, _stream_ptr(stream)))
+    return us
+
+
+class Server:
+    """psp_serve_*: the continuous-batching request loop."""
+
+    def __init__(self, hbm_budget_bytes: int, max_slots: int = 64):
+        h = ctypes.c_void_p()
+        _check(lib().psp_serve_create(int(hbm_budget_bytes), int(max_slots), ctypes.byref(h)))
+        self._h = h
+
+    def submit(self, n, h, R, tier, rho, u) -> int:
+        t = ctypes.c_uint64()
+        _check(lib().psp_serve_submit(self._h, int(n), float(h), int(R), _dtype_code(tier),
+                                      rho.data_ptr(), u.data_ptr(), ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int):
+        done = ctypes.c_int()
+        res = ctypes.c_int()
+        lat = ctypes.c_double()
+        _check(lib().psp_serve_poll(self._h, ctypes.c_uint64(ticket), ctypes.byref(done), ctypes.byref(res),
+                                    ctypes.byref(lat)))
+        return bool(done.value), res.value, lat.value
+
+    def drain(self):
+        _check(lib().psp_serve_drain(self._h))
+
+    def stats(self):
+        a, b = ctypes.c_size_t(), ctypes.c_size_t()
+        c, d, e = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().psp_serve_stats(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d),
+                                     ctypes.byref(e)))
+        return {"bytes_in_use": a.value, "bytes_peak": b.value, "completed": c.value, "cache_hits": d.value,
+                "cache_misses": e.value}
+
+    def close(self):
+        if self._h:
+            lib().psp_serve_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,107 @@
+"""The C ABI without a GPU: exported symbols, argument validation, and the
+host-side precompute (Gaussian-sum fit and 1D integrals) against the oracle's
+independent implementations."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import psp_oracle as O
+from paper_2506_04489_amd import psp as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "psp.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(psp_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = ctypes.CDLL(B.LIB_PATH)
+    names = _declared()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(B.SIGNATURES)
+
+
+@pytest.mark.parametrize("n,h,R,code", [
+    (31, 0.1, 40, "PSP_EUNSUPPORTED"),    # odd n
+    (10, 0.1, 40, "PSP_EUNSUPPORTED"),    # 2n = 20 has a factor 5
+    (2, 0.1, 40, "PSP_EUNSUPPORTED"),     # too small
+    (512, 0.1, 40, "PSP_EUNSUPPORTED"),   # above the supported maximum
+    (32, 0.0, 40, "PSP_EINVAL"),
+    (32, -1.0, 40, "PSP_EINVAL"),
+    (32, float("inf"), 40, "PSP_EINVAL"),
+    (32, float("nan"), 40, "PSP_EINVAL"),
+    (32, 0.1, 0, "PSP_EINVAL"),
+    (32, 0.1, 5000, "PSP_EINVAL"),
+])
+def test_plan_create_rejects(n, h, R, code):
+    with pytest.raises(B.PspError) as ei:
+        B.Plan(n, h, R)
+    assert B.STATUS[ei.value.status] == code
+
+
+def test_plan_create_ex_rejects_bad_cutoff():
+    with pytest.raises(B.PspError) as ei:
+        B.Plan(32, 0.1, 40, eps=2.0, delta=1.0)
+    assert B.STATUS[ei.value.status] == "PSP_EINVAL"
+
+
+def test_error_strings():
+    lib = B.lib()
+    for code in B.STATUS:
+        assert lib.psp_strerror(code)
+    with pytest.raises(B.PspError):
+        B.Plan(31, 0.1, 40)
+    assert b"even" in lib.psp_last_error()
+
+
+def test_solve_before_precompute_is_state_error():
+    p = B.Plan(16, 0.125, 40)
+    st = B.lib().psp_solve(p.handle, ctypes.c_void_p(16), ctypes.c_void_p(32), None)
+    assert B.STATUS[st] == "PSP_ESTATE"
+    st = B.lib().psp_solve(p.handle, None, ctypes.c_void_p(32), None)
+    assert B.STATUS[st] == "PSP_EINVAL"
+
+
+@pytest.mark.parametrize("n,h,R", [(32, 2 / 32, 40), (128, 2 / 128, 40), (64, 4 / 63, 461), (24, 0.3, 7)])
+def test_gs_weights_match_oracle(n, h, R):
+    p = B.Plan(n, h, R)
+    om, al = p.gs()
+    eps, delta = O.default_eps_delta(n, h)
+    om_o, al_o = O.gs_weights(R, eps, delta)
+    # same published formula, two implementations: agreement to a few ulp
+    assert np.max(np.abs(om / om_o - 1)) < 1e-15 * max(1, R / 40)
+    assert np.max(np.abs(al / al_o - 1)) < 1e-14 * max(1, R / 40)
+
+
+def test_workspace_and_spectrum_sizes():
+    p = B.Plan(256, 2 / 256, 40)
+    P = 272
+    assert p.workspace_bytes() == 16 * P * (256 * 256 + 256 * 512)
+    assert p.spectrum_bytes() == 8 * 257 * 257 * P
+    q = B.Plan(256, 2 / 256, 40, dtype="f32")
+    assert q.workspace_bytes() == 8 * P * (256 * 256 + 256 * 512)
+
+
+@pytest.mark.parametrize("n,h,R", [(32, 2 / 32, 40), (96, 2 / 96, 40), (64, 4 / 63, 120)])
+def test_tables_match_oracle(n, h, R):
+    # library: closed forms + adaptive Gauss-Kronrod; oracle: composite
+    # Gauss-Legendre.  Both approximate the same integrals to ~1e-15 of scale.
+    p = B.Plan(n, h, R)
+    J0, J2 = p.tables()
+    _, al = p.gs()
+    L = 2 * n * h
+    J0o, J2o = O.tables_1d(al, n, L)
+    for s in range(R):
+        s0 = max(np.max(np.abs(J0o[s])), 1e-300)
+        s2 = max(np.max(np.abs(J2o[s])), 1e-300)
+        assert np.max(np.abs(J0[s] - J0o[s])) < 2e-14 * s0, s
+        assert np.max(np.abs(J2[s] - J2o[s])) < 2e-14 * s2, s

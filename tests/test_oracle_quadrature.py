@@ -74,3 +74,23 @@ def test_mpmath_sample():
             tol = (8.0 + 0.5 * k) * 1e-16
             assert abs(J0[s, k] - float(v0)) < tol * float(scale0)
             assert abs(J2[s, k] - float(v2)) < tol * float(scale2)
+
+
+def test_high_wavenumber_value_accuracy():
+    # wide Gaussians at high k: the box-truncated integrals are ~k^2 smaller
+    # than their integrands; they must still be accurate relative to their
+    # own value (the multiplier there is as large as at low k)
+    mp.mp.dps = 40
+    L, n = 4.8, 48
+    alphas = np.array([1e-9, 0.02, 0.4])
+    J0, J2 = O.tables_1d(alphas, n, L)
+    for s, al in enumerate(alphas):
+        for k in (31, 45, 48):
+            xi = mp.mpf(2) * mp.pi * k / mp.mpf(L)
+            a = mp.mpf(al)
+            pts = mp.linspace(0, mp.mpf(L) / 2, 2 * k + 3)
+            v0 = mp.quad(lambda y: 2 * mp.exp(-a * y * y) * mp.cos(xi * y), pts)
+            v2 = mp.quad(lambda y: 2 * y * y * mp.exp(-a * y * y) * mp.cos(xi * y), pts)
+            # value-relative, down to the extended-precision floor of the scale
+            assert abs(J0[s, k] - float(v0)) < 5e-14 * abs(float(v0)) + 1e-18 * L, (al, k)
+            assert abs(J2[s, k] - float(v2)) < 5e-14 * abs(float(v2)) + 1e-18 * L ** 3, (al, k)
