@@ -104,11 +104,30 @@ psp_status psp_plan_get_tables(psp_plan *p, double *J0, double *J2);
  * row-major (n+1)^3 doubles) to host memory.  Needs precompute; syncs. */
 psp_status psp_plan_get_multiplier(psp_plan *p, double *m_host);
 
+/* Tuning: the forward i2, fused i1 and inverse i2 passes run over the
+ * half-spectrum axis k3 in chunks of `k3_tiles` tiles (8 k3 bins per tile
+ * in FP64, 16 in FP32), so the padded intermediate is a chunk-sized buffer
+ * instead of the whole n x 2n x (n+1) intermediate.  0 (the default) is
+ * one chunk, the fastest; smaller chunks trade some speed for workspace
+ * memory (the serving loop uses chunk buffers of at most 64 MB).  Frees the
+ * plan's workspaces; call it while no solve of this plan is in flight. */
+psp_status psp_plan_set_chunk(psp_plan *p, int k3_tiles);
+
 /* Bytes of device workspace one solve of this plan needs (per stream). */
 psp_status psp_plan_workspace_bytes(const psp_plan *p, size_t *bytes);
 
 /* Bytes of the plan's device multiplier octant. */
 psp_status psp_plan_spectrum_bytes(const psp_plan *p, size_t *bytes);
+
+/* Per-pass device timing.  psp_profile_enable makes the next `max_solves`
+ * psp_solve calls of this plan record 6 HIP events on their own stream:
+ * before each of the 5 passes (forward i3, forward i2, fused i1 with the
+ * multiply, inverse i2, inverse i3) and after the last.  psp_profile_read
+ * waits for them and returns the number of recorded solves and the average
+ * milliseconds of each pass (pass_ms[0..4]) and of the whole solve
+ * (pass_ms[5]); it then clears the recording.  pass_ms has 6 entries. */
+psp_status psp_profile_enable(psp_plan *p, int max_solves);
+psp_status psp_profile_read(psp_plan *p, int *count, double *pass_ms);
 
 void psp_plan_destroy(psp_plan *p);
 

@@ -91,6 +91,40 @@ psp_status check_create(int n, double h, int R, double eps, double delta) {
     return PSP_OK;
 }
 
+psp_status alloc_workspace(int n, bool f32, int chunk_tiles, Workspace *w) {
+    const size_t c = f32 ? 8 : 16, P = (size_t)pitch_for(n), PA = (size_t)chunk_pitch(n, f32, chunk_tiles);
+    w->bytes = workspace_bytes(n, f32, chunk_tiles);
+    w->X = w->A = nullptr;
+    if (hipMalloc(&w->X, c * P * n * n) != hipSuccess) {
+        (void)hipGetLastError();
+        w->X = nullptr;
+        return fail(PSP_ENOMEM, "workspace allocation of %zu bytes failed", w->bytes);
+    }
+    if (hipMalloc(&w->A, c * PA * n * 2 * n) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(w->X);
+        w->X = w->A = nullptr;
+        return fail(PSP_ENOMEM, "workspace allocation of %zu bytes failed", w->bytes);
+    }
+    return PSP_OK;
+}
+
+void free_workspace(Workspace *w) {
+    if (w->X) (void)hipFree(w->X);
+    if (w->A) (void)hipFree(w->A);
+    w->X = w->A = nullptr;
+}
+
+// H2-H4 chunk size used where workspace memory matters (the serving loop):
+// the chunk buffer stays within 64 MB
+int default_chunk_tiles(int n, bool f32) {
+    const size_t c = f32 ? 8 : 16, W = (size_t)strided_width(f32);
+    const size_t per_tile = c * W * (size_t)n * 2 * n;
+    const size_t target = 64ull << 20;
+    size_t t = target / per_tile;
+    return (int)std::max<size_t>(1, t);
+}
+
 psp_status plan_workspace(psp_plan *p, hipStream_t st, Workspace **out) {
     std::lock_guard<std::mutex> lk(p->mu);
     auto it = p->ws.find(st);
@@ -98,21 +132,9 @@ psp_status plan_workspace(psp_plan *p, hipStream_t st, Workspace **out) {
         *out = &it->second;
         return PSP_OK;
     }
-    const bool f32 = p->dtype == PSP_F32;
-    const size_t c = f32 ? 8 : 16, P = (size_t)pitch_for(p->n), n = (size_t)p->n;
     Workspace w;
-    w.bytes = workspace_bytes(p->n, f32);
-    hipError_t e1 = hipMalloc(&w.X, c * P * n * n);
-    if (e1 != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(PSP_ENOMEM, "workspace allocation of %zu bytes failed", w.bytes);
-    }
-    hipError_t e2 = hipMalloc(&w.A, c * P * n * 2 * n);
-    if (e2 != hipSuccess) {
-        (void)hipGetLastError();
-        (void)hipFree(w.X);
-        return fail(PSP_ENOMEM, "workspace allocation of %zu bytes failed", w.bytes);
-    }
+    psp_status rs = alloc_workspace(p->n, p->dtype == PSP_F32, p->chunk_tiles, &w);
+    if (rs != PSP_OK) return rs;
     auto res = p->ws.emplace(st, w);
     *out = &res.first->second;
     return PSP_OK;
@@ -127,6 +149,7 @@ SolveArgs solve_args(const psp_plan *p, const Workspace &w, const void *rho, voi
     a.u = u;
     a.X = w.X;
     a.A = w.A;
+    a.chunk_tiles = p->chunk_tiles;
     a.mult = p->spec->mult;
     if (a.f32) {
         a.tw_hi = p->tw->hi32;
@@ -189,6 +212,7 @@ psp_status psp_plan_create_ex(int n, double h, int R, psp_dtype dtype, double ep
     p->dtype = dtype;
     p->eps = eps;
     p->delta = delta;
+    p->chunk_tiles = 0;   // one chunk: fastest for a single solve
     gs_fit(R, eps, delta, p->omega, p->alpha);
     *out = p;
     return PSP_OK;
@@ -201,12 +225,16 @@ psp_status psp_plan_create(int n, double h, int R, psp_dtype dtype, psp_plan **o
     return psp_plan_create_ex(n, h, R, dtype, 1e-4 * half, std::sqrt(3.0) * half, out);
 }
 
+static void profile_clear(psp_plan *p) {
+    for (auto e : p->prof_ev) (void)hipEventDestroy(e);
+    p->prof_ev.clear();
+    p->prof_cap = p->prof_used = 0;
+}
+
 void psp_plan_destroy(psp_plan *p) {
     if (!p) return;
-    for (auto &kv : p->ws) {
-        (void)hipFree(kv.second.X);
-        (void)hipFree(kv.second.A);
-    }
+    profile_clear(p);
+    for (auto &kv : p->ws) free_workspace(&kv.second);
     delete p;
 }
 
@@ -227,7 +255,7 @@ psp_status psp_plan_get_tables(psp_plan *p, double *J0, double *J2) {
 
 psp_status psp_plan_workspace_bytes(const psp_plan *p, size_t *bytes) {
     if (!p || !bytes) return fail(PSP_EINVAL, "NULL argument");
-    *bytes = workspace_bytes(p->n, p->dtype == PSP_F32);
+    *bytes = workspace_bytes(p->n, p->dtype == PSP_F32, p->chunk_tiles);
     return PSP_OK;
 }
 
@@ -325,8 +353,78 @@ psp_status psp_solve(psp_plan *p, const void *rho_dev, void *u_dev, void *stream
     Workspace *w = nullptr;
     st = plan_workspace(p, (hipStream_t)stream, &w);
     if (st != PSP_OK) return st;
-    hipError_t e = launch_solve(solve_args(p, *w, rho_dev, u_dev), (hipStream_t)stream);
+    SolveArgs a = solve_args(p, *w, rho_dev, u_dev);
+    {
+        std::lock_guard<std::mutex> lk(p->mu);
+        if (p->prof_used < p->prof_cap) {
+            a.ev = &p->prof_ev[(size_t)p->prof_nev * p->prof_used++];
+            a.nev = p->prof_nev;
+        }
+    }
+    hipError_t e = launch_solve(a, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "solve launch");
+    return PSP_OK;
+}
+
+psp_status psp_profile_enable(psp_plan *p, int max_solves) {
+    if (!p || max_solves < 0 || max_solves > 100000) return fail(PSP_EINVAL, "bad profile arguments");
+    std::lock_guard<std::mutex> lk(p->mu);
+    profile_clear(p);
+    p->prof_nev = profile_events(p->n, p->dtype == PSP_F32, p->chunk_tiles);
+    p->prof_ev.resize((size_t)p->prof_nev * max_solves, nullptr);
+    for (auto &e : p->prof_ev) {
+        if (hipEventCreate(&e) != hipSuccess) {
+            e = nullptr;
+            profile_clear(p);
+            return fail(PSP_EHIP, "hipEventCreate failed");
+        }
+    }
+    p->prof_cap = max_solves;
+    return PSP_OK;
+}
+
+psp_status psp_profile_read(psp_plan *p, int *count, double *pass_ms) {
+    if (!p || !count || !pass_ms) return fail(PSP_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(p->mu);
+    for (int i = 0; i < 6; ++i) pass_ms[i] = 0.0;
+    *count = p->prof_used;
+    const int nev = p->prof_nev, nch = (nev - 3) / 3;
+    auto el = [](hipEvent_t a, hipEvent_t b, double *acc) -> hipError_t {
+        float ms = 0;
+        hipError_t e = hipEventElapsedTime(&ms, a, b);
+        *acc += ms;
+        return e;
+    };
+    for (int k = 0; k < p->prof_used; ++k) {
+        hipEvent_t *ev = &p->prof_ev[(size_t)nev * k];
+        PSP_HIP(hipEventSynchronize(ev[nev - 1]), "hipEventSynchronize");
+        PSP_HIP(el(ev[0], ev[1], &pass_ms[0]), "hipEventElapsedTime");
+        for (int c = 0; c < nch; ++c) {
+            PSP_HIP(el(ev[1 + 3 * c], ev[2 + 3 * c], &pass_ms[1]), "hipEventElapsedTime");
+            PSP_HIP(el(ev[2 + 3 * c], ev[3 + 3 * c], &pass_ms[2]), "hipEventElapsedTime");
+            PSP_HIP(el(ev[3 + 3 * c], ev[4 + 3 * c], &pass_ms[3]), "hipEventElapsedTime");
+        }
+        PSP_HIP(el(ev[1 + 3 * nch], ev[2 + 3 * nch], &pass_ms[4]), "hipEventElapsedTime");
+        PSP_HIP(el(ev[0], ev[2 + 3 * nch], &pass_ms[5]), "hipEventElapsedTime");
+    }
+    if (p->prof_used > 0)
+        for (int i = 0; i < 6; ++i) pass_ms[i] /= p->prof_used;
+    profile_clear(p);
+    return PSP_OK;
+}
+
+psp_status psp_plan_set_chunk(psp_plan *p, int k3_tiles) {
+    if (!p || k3_tiles < 0) return fail(PSP_EINVAL, "bad chunk arguments");
+    std::lock_guard<std::mutex> lk(p->mu);
+    if (p->prof_cap > 0) return fail(PSP_ESTATE, "cannot change the chunking while profiling");
+    const int t = k3_tiles;
+    if (t != p->chunk_tiles) {
+        // existing workspaces were sized for the old chunk
+        if (!p->ws.empty()) (void)hipDeviceSynchronize();
+        for (auto &kv : p->ws) free_workspace(&kv.second);
+        p->ws.clear();
+        p->chunk_tiles = t;
+    }
     return PSP_OK;
 }
 

@@ -40,10 +40,40 @@ template <typename C> __device__ __forceinline__ C c_zero() { return C{0, 0}; }
 template <typename T> struct Twiddle;
 template <> struct Twiddle<double> {
     const double2 *w;
-    template <bool INV> __device__ __forceinline__ double2 mul(double2 a, int m) const {
-        double2 t = w[m];
-        double ty = INV ? -t.y : t.y;
+    template <bool INV> __device__ __forceinline__ static double2 cmul(double2 a, double2 t) {
+        const double ty = INV ? -t.y : t.y;
         return double2{a.x * t.x - a.y * ty, a.x * ty + a.y * t.x};
+    }
+    template <bool INV> __device__ __forceinline__ double2 mul(double2 a, int m) const { return cmul<INV>(a, w[m]); }
+    // v[r] *= W^{m r}, r = 1..R-1, from the single table entry W^m: powers
+    // by a multiplication tree of depth <= 3 (a few ulp), one load instead
+    // of R-1 (wave-wide loads cost L1 return bandwidth per lane)
+    template <int R, bool INV> __device__ __forceinline__ void apply(double2 *v, int m) const {
+        const double2 w1 = w[m];
+        if constexpr (R == 2) {
+            v[1] = cmul<INV>(v[1], w1);
+        } else if constexpr (R == 3) {
+            const double2 w2 = cmul<false>(w1, w1);
+            v[1] = cmul<INV>(v[1], w1);
+            v[2] = cmul<INV>(v[2], w2);
+        } else if constexpr (R == 4) {
+            const double2 w2 = cmul<false>(w1, w1), w3 = cmul<false>(w2, w1);
+            v[1] = cmul<INV>(v[1], w1);
+            v[2] = cmul<INV>(v[2], w2);
+            v[3] = cmul<INV>(v[3], w3);
+        } else {
+            static_assert(R == 8, "radix");
+            const double2 w2 = cmul<false>(w1, w1), w4 = cmul<false>(w2, w2);
+            const double2 w3 = cmul<false>(w2, w1), w5 = cmul<false>(w4, w1);
+            const double2 w6 = cmul<false>(w4, w2), w7 = cmul<false>(w4, w3);
+            v[1] = cmul<INV>(v[1], w1);
+            v[2] = cmul<INV>(v[2], w2);
+            v[3] = cmul<INV>(v[3], w3);
+            v[4] = cmul<INV>(v[4], w4);
+            v[5] = cmul<INV>(v[5], w5);
+            v[6] = cmul<INV>(v[6], w6);
+            v[7] = cmul<INV>(v[7], w7);
+        }
     }
 };
 template <> struct Twiddle<float> {
@@ -58,6 +88,12 @@ template <> struct Twiddle<float> {
         rx += a.x * h.x - a.y * hy;
         ry += a.x * hy + a.y * h.x;
         return float2{rx, ry};
+    }
+    // v[r] *= W^{m r}: every power from the split table (an FP32 product
+    // of split twiddles would lose their extra precision)
+    template <int R, bool INV> __device__ __forceinline__ void apply(float2 *v, int m) const {
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[r] = mul<INV>(v[r], m * r);
     }
 };
 
@@ -206,8 +242,7 @@ template <typename T, int N, int TPC, bool INV> struct Engine {
                 if (ns_ > 1) {
                     const int k = j % ns_;
                     constexpr int stride = N / (ns_ * r_);
-#pragma unroll
-                    for (int r = 1; r < r_; ++r) w[r] = tw.template mul<INV>(w[r], k * r * stride);
+                    tw.template apply<r_, INV>(w, k * stride);
                 }
                 DFT<r_, INV, C>::run(w);
             }
@@ -249,17 +284,86 @@ template <typename T, int N, int TPC, bool INV> struct Engine {
         }
     }
 
-    // stages [s, S) given stage-s inputs in registers; on return registers
-    // hold the last stage's outputs at positions j + r N/R(S-1)
+    // half-buffer exchange: phase ph moves the values whose position lies in
+    // [ph N/2, (ph+1) N/2) through an LDS buffer of N/2 positions
     template <int s, typename Idx>
+    __device__ __forceinline__ static void store_half(const C *v, C *lds, int t, Idx idx, int ph) {
+        constexpr int r_ = R(s), nb = N / r_;
+#pragma unroll
+        for (int b = 0; b < BPT(s); ++b) {
+            const int j = t + b * TPC;
+            if ((nb % TPC == 0) || j < nb) {
+#pragma unroll
+                for (int r = 0; r < r_; ++r) {
+                    const int pos = out_pos<s>(j, r);
+                    if ((pos >= N / 2) == (ph == 1)) lds[idx(pos - ph * (N / 2))] = v[b * r_ + r];
+                }
+            }
+        }
+    }
+    template <int s, typename Idx>
+    __device__ __forceinline__ static void load_half(C *v, const C *lds, int t, Idx idx, int ph) {
+        constexpr int r_ = R(s), nb = N / r_;
+#pragma unroll
+        for (int b = 0; b < BPT(s); ++b) {
+            const int j = t + b * TPC;
+            if ((nb % TPC == 0) || j < nb) {
+#pragma unroll
+                for (int r = 0; r < r_; ++r) {
+                    const int pos = in_pos<s>(j, r);
+                    // for even radices the upper half is exactly legs r >= R/2
+                    const bool upper = (r_ % 2 == 0) ? (r >= r_ / 2) : (pos >= N / 2);
+                    if (upper == (ph == 1)) v[b * r_ + r] = lds[idx(pos - ph * (N / 2))];
+                }
+            }
+        }
+    }
+
+    // copy the lower-half inputs of stage s from lo into v
+    template <int s>
+    __device__ __forceinline__ static void merge_lower(C *v, const C *lo, int t) {
+        constexpr int r_ = R(s), nb = N / r_;
+#pragma unroll
+        for (int b = 0; b < BPT(s); ++b) {
+            const int j = t + b * TPC;
+            if ((nb % TPC == 0) || j < nb) {
+#pragma unroll
+                for (int r = 0; r < r_; ++r) {
+                    const int pos = in_pos<s>(j, r);
+                    const bool upper = (r_ % 2 == 0) ? (r >= r_ / 2) : (pos >= N / 2);
+                    if (!upper) v[b * r_ + r] = lo[b * r_ + r];
+                }
+            }
+        }
+    }
+
+    // stages [s, S) given stage-s inputs in registers; on return registers
+    // hold the last stage's outputs at positions j + r N/R(S-1).  SPLIT: each
+    // exchange goes through an LDS buffer of N/2 positions in two phases.
+    template <int s, bool SPLIT = false, typename Idx>
     __device__ __forceinline__ static void run_from(C *v, C *lds, int t, Idx idx, const Twiddle<T> &tw) {
         compute<s>(v, t, tw);
         if constexpr (s + 1 < S) {
-            store_lds<s>(v, lds, t, idx);
-            __syncthreads();
-            load_lds<s + 1>(v, lds, t, idx);
-            __syncthreads();
-            run_from<s + 1>(v, lds, t, idx, tw);
+            if constexpr (SPLIT) {
+                // the phase-0 inputs of stage s+1 must not overwrite stage-s
+                // outputs still waiting for phase 1: stage them in lo[]
+                C lo[V];
+                store_half<s>(v, lds, t, idx, 0);
+                __syncthreads();
+                load_half<s + 1>(lo, lds, t, idx, 0);
+                __syncthreads();
+                store_half<s>(v, lds, t, idx, 1);
+                __syncthreads();
+                load_half<s + 1>(v, lds, t, idx, 1);
+                __syncthreads();
+                merge_lower<s + 1>(v, lo, t);
+            } else {
+                store_lds<s>(v, lds, t, idx);
+                __syncthreads();
+                load_lds<s + 1>(v, lds, t, idx);
+                __syncthreads();
+            }
+            run_from<s + 1, SPLIT>(v, lds, t, idx, tw);
         }
     }
 

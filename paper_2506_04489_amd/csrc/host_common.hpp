@@ -49,11 +49,20 @@ struct Workspace {
 };
 
 inline int pitch_for(int n) { return ((n + 1 + 15) / 16) * 16; }
-inline size_t workspace_bytes(int n, bool f32) {
-    const size_t c = f32 ? 8 : 16;
-    const size_t P = (size_t)pitch_for(n);
-    return c * P * ((size_t)n * n + (size_t)n * 2 * n);
+// k3 columns of the H2-H4 chunk buffer for a chunk of `chunk_tiles` tiles
+inline int chunk_pitch(int n, bool f32, int chunk_tiles) {
+    const int W = strided_width(f32), ntile = (n + 1 + W - 1) / W;
+    const int ct = chunk_tiles > 0 && chunk_tiles < ntile ? chunk_tiles : ntile;
+    return ct * W;
 }
+inline size_t workspace_bytes(int n, bool f32, int chunk_tiles) {
+    const size_t c = f32 ? 8 : 16;
+    const size_t P = (size_t)pitch_for(n), PA = (size_t)chunk_pitch(n, f32, chunk_tiles);
+    return c * (P * (size_t)n * n + PA * (size_t)n * 2 * n);
+}
+psp_status alloc_workspace(int n, bool f32, int chunk_tiles, Workspace *w);
+void free_workspace(Workspace *w);
+int default_chunk_tiles(int n, bool f32);
 inline size_t spectrum_bytes(int n) { return 8 * (size_t)(n + 1) * (n + 1) * pitch_for(n); }
 
 }  // namespace psp
@@ -72,6 +81,10 @@ struct psp_plan {
     bool precomputed = false;
     std::mutex mu;
     std::map<hipStream_t, psp::Workspace> ws;   // one workspace per stream
+    int chunk_tiles = 0;                        // H2-H4 chunking (0: one chunk)
+    // per-pass profiling: profile_events() events per recorded solve
+    std::vector<hipEvent_t> prof_ev;
+    int prof_cap = 0, prof_used = 0, prof_nev = 0;
 };
 
 namespace psp {

@@ -13,15 +13,29 @@ struct SolveArgs {
     const void *rho = nullptr;
     void *u = nullptr;
     void *X = nullptr;   // n*n*P complex
-    void *A = nullptr;   // n*N*P complex
+    void *A = nullptr;   // chunk buffer: n*N*(chunk_tiles*W) complex
+    int chunk_tiles = 0; // k3 tiles per H2-H4 chunk (0: all tiles in one chunk)
     void *A2 = nullptr;  // N*N*P complex, full variant only
     void *Y2 = nullptr;  // N*N*P complex, full variant only
     const double *mult = nullptr;   // blocked multiplier octant
     const void *tw_hi = nullptr;    // twiddles: double2[N] (FP64) or float2[N] hi
     const void *tw_lo = nullptr;    // float2[N] lo (FP32 only)
+    hipEvent_t *ev = nullptr;       // optional profiling events (see solve_impl), nev of them
+    int nev = 0;
 };
 
 hipError_t launch_solve(const SolveArgs &s, hipStream_t st);
+
+// k3 tile width of the strided passes (8 for FP64, 16 for FP32)
+int strided_width(bool f32);
+
+// number of H2-H4 chunks and profiling events of one solve
+inline int chunk_count(int n, bool f32, int chunk_tiles) {
+    const int W = strided_width(f32), ntile = (n + 1 + W - 1) / W;
+    const int ct = chunk_tiles > 0 && chunk_tiles < ntile ? chunk_tiles : ntile;
+    return (ntile + ct - 1) / ct;
+}
+inline int profile_events(int n, bool f32, int chunk_tiles) { return 3 * chunk_count(n, f32, chunk_tiles) + 3; }
 
 hipError_t launch_spectrum(const double *J0, const double *J2, const double *omega, int R, int n, int P,
                            double scale, double *mult, hipStream_t st);

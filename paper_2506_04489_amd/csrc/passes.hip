@@ -15,6 +15,8 @@
 //                  inverse along i1 keeping outputs i1 < n
 //   H4 k_y_inv   : inverse along k2 keeping outputs i2 < n
 //   H5 k_z_c2r   : inverse Hermitian transform along k3 keeping i3 < n
+#include <algorithm>
+
 #include "fft_core.hpp"
 #include "kernels.h"
 
@@ -25,26 +27,46 @@ template <typename T> struct StridedCols;
 template <> struct StridedCols<double> { static constexpr int W = 8; };   // 128 B rows
 template <> struct StridedCols<float> { static constexpr int W = 16; };   // 128 B rows
 
+// occupancy of one workgroup configuration on a CU (160 KB LDS, at most 32
+// waves of 64 lanes)
+constexpr int wgs_per_cu(int threads, int lds_bytes) {
+    const int by_waves = 32 / ((threads + 63) / 64);
+    const int by_lds = lds_bytes > 0 ? (160 * 1024) / lds_bytes : by_waves;
+    return by_waves < by_lds ? by_waves : by_lds;
+}
+
 template <typename T, int N> struct StridedCfg {
     static constexpr int W = StridedCols<T>::W;
     static constexpr int TPC0 = N / MaxRadix<N>::value();
     static constexpr int TPC = (TPC0 * W > 1024) ? TPC0 / 2 : TPC0;
     static constexpr int THREADS = TPC * W;
+    static constexpr int FULL_LDS = N * W * (int)sizeof(cplx<T>);
+    // exchange through half-size buffers when the LDS, not the wave count,
+    // limits how many workgroups share a CU
+    // (measured on MI355X: not faster for the FP64 n = 256 passes, so off;
+    // PSP_SPLIT_EXCHANGE=1 at build time turns it on where it raises occupancy)
+#ifdef PSP_SPLIT_EXCHANGE
+    static constexpr bool SPLIT = wgs_per_cu(THREADS, FULL_LDS / 2) > wgs_per_cu(THREADS, FULL_LDS);
+#else
+    static constexpr bool SPLIT = false;
+#endif
+    static constexpr int LDS_ELEMS = SPLIT ? N * W / 2 : N * W;
 };
 
 template <typename T, int N> struct LineCfg {
     static constexpr int TPC = N / MaxRadix<N>::value();
     static constexpr int Q = (256 / TPC) > 0 ? (256 / TPC) : 1;   // complex lines per WG
     static constexpr int THREADS = TPC * Q;
+    static constexpr int LINE = N + N / 8;                          // padded line in LDS
 };
 
 template <int W> struct IdxInter {   // (position, column) -> position*W + column
     int col;
     __device__ __forceinline__ int operator()(int pos) const { return pos * W + col; }
 };
-struct IdxLine {                     // column-major: base + position
+struct IdxLine {                     // column-major, one padding slot per 8 positions
     int base;
-    __device__ __forceinline__ int operator()(int pos) const { return base + pos; }
+    __device__ __forceinline__ int operator()(int pos) const { return base + pos + (pos >> 3); }
 };
 
 // ------------------------------------------------------------------- H1
@@ -58,7 +80,7 @@ k_z_r2c(const T *__restrict__ rho, cplx<T> *__restrict__ X, int npairs, int P, T
     using Cfg = LineCfg<T, N>;
     using E = Engine<T, N, Cfg::TPC, false>;
     constexpr int n = N / 2;
-    __shared__ C lds[Cfg::Q * N];
+    __shared__ C lds[Cfg::Q * Cfg::LINE];
     const int t = threadIdx.x % Cfg::TPC, q = threadIdx.x / Cfg::TPC;
     const int pair = blockIdx.x * Cfg::Q + q;
     const bool active = pair < npairs;
@@ -69,16 +91,16 @@ k_z_r2c(const T *__restrict__ rho, cplx<T> *__restrict__ X, int npairs, int P, T
         if (r < E::R(0) / 2 && active) return C{ra[pos], rb[pos]};
         return c_zero<C>();
     });
-    IdxLine idx{q * N};
+    IdxLine idx{q * Cfg::LINE};
     E::template run_from<0>(v, lds, t, idx, tw);
-    E::for_outputs(v, t, [&](int pos, int, C &val) { lds[q * N + pos] = val; });
+    E::for_outputs(v, t, [&](int pos, int, C &val) { lds[idx(pos)] = val; });
     __syncthreads();
     if (active) {
         C *xa = X + (size_t)(2 * pair) * P;
         C *xb = xa + P;
         for (int k = t; k <= n; k += Cfg::TPC) {
-            const C z = lds[q * N + k];
-            const C zc = lds[q * N + (k == 0 ? 0 : N - k)];
+            const C z = lds[idx(k)];
+            const C zc = lds[idx(k == 0 ? 0 : N - k)];
             xa[k] = C{T(0.5) * (z.x + zc.x), T(0.5) * (z.y - zc.y)};
             const C d = C{z.x - zc.x, z.y + zc.y};     // Z[k] - conj Z[N-k]
             xb[k] = C{T(0.5) * d.y, -T(0.5) * d.x};   // d / (2i)
@@ -86,30 +108,49 @@ k_z_r2c(const T *__restrict__ rho, cplx<T> *__restrict__ X, int npairs, int P, T
     }
 }
 
+// ------------------------------------------------------------------- H2-H4
+// The strided passes work on a chunk of W-wide k3 tiles [tile0, tile0 +
+// ntile).  The padded intermediate of a chunk is A[i1][k2][c] with the
+// chunk-local column c < pa = ntile_chunk W as its contiguous axis (measured
+// faster on MI355X than a tile-major layout: the i2 passes then touch rows
+// only a few KB apart).  X/Y rows are [i1][i2][k3] with pitch P and the
+// global column cg = tile0 W + c, which also decides validity (cg <= n) and
+// the multiplier entry.
+template <typename T> struct StridedIO {
+    const cplx<T> *src;
+    cplx<T> *dst;
+    int tile0;      // first tile of the chunk
+    int ntile;      // tiles in the chunk
+    int pa;         // k3 pitch of the chunk buffer A
+};
+
+template <int N, int W>
+__device__ __forceinline__ size_t a_index(int pa, int tile, int k2, int i1, int w) {
+    return ((size_t)i1 * N + k2) * pa + (size_t)tile * W + w;
+}
+
 // ------------------------------------------------------------------- H2
 template <typename T, int N>
 __global__ void __launch_bounds__((StridedCfg<T, N>::THREADS))
-k_y_fwd(const cplx<T> *__restrict__ X, cplx<T> *__restrict__ A, int P, int ntile, Twiddle<T> tw) {
+k_y_fwd(StridedIO<T> io, int P, Twiddle<T> tw) {
     using C = cplx<T>;
     using Cfg = StridedCfg<T, N>;
     using E = Engine<T, N, Cfg::TPC, false>;
     constexpr int n = N / 2, W = Cfg::W;
-    __shared__ C lds[N * W];
+    __shared__ C lds[Cfg::LDS_ELEMS];
     const int col = threadIdx.x % W, t = threadIdx.x / W;
-    const int i1 = blockIdx.x / ntile, tile = blockIdx.x % ntile;
-    const int c = tile * W + col;
-    const bool valid = c <= n;
-    const C *src = X + (size_t)i1 * n * P + c;
-    C *dst = A + (size_t)i1 * N * P + c;
+    const int i1 = blockIdx.x / io.ntile, tile = blockIdx.x % io.ntile;
+    const int cg = (io.tile0 + tile) * W + col;
+    const bool valid = cg <= n;
+    const C *src = io.src + (size_t)i1 * n * P + cg;               // rows i2 of X
+    C *dst = io.dst + a_index<N, W>(io.pa, tile, 0, i1, col);       // rows k2 of A
     C v[E::V];
     E::for_inputs(v, t, [&](int pos, int r) -> C {
         if (r < E::R(0) / 2 && valid) return src[(size_t)pos * P];
         return c_zero<C>();
     });
-    E::template run_from<0>(v, lds, t, IdxInter<W>{col}, tw);
-    E::for_outputs(v, t, [&](int pos, int, C &val) {
-        if (valid) dst[(size_t)pos * P] = val;
-    });
+    E::template run_from<0, Cfg::SPLIT>(v, lds, t, IdxInter<W>{col}, tw);
+    E::for_outputs(v, t, [&](int pos, int, C &val) { dst[(size_t)pos * io.pa] = val; });
 }
 
 // ------------------------------------------------------------------- H3
@@ -117,68 +158,85 @@ k_y_fwd(const cplx<T> *__restrict__ X, cplx<T> *__restrict__ A, int P, int ntile
 // reading the same multiplier block.  Items (b, tile, 0) and (b, tile, 1) go
 // to workgroups g and g + 8, which the dispatcher places on the same XCD at
 // nearly the same time, so the second read of the block hits that XCD's L2.
+// FULL (test hook): all N outputs of the inverse go to A2[i1][k2][k3] (pitch P).
 template <typename T, int N, bool FULL>
 __global__ void __launch_bounds__((StridedCfg<T, N>::THREADS))
-k_x_fused(const cplx<T> *src_base, cplx<T> *dst_base, const double *__restrict__ mult, int P,
-          int ntile, Twiddle<T> tw) {
+k_x_fused(StridedIO<T> io, const double *__restrict__ mult, int P, Twiddle<T> tw) {
     using C = cplx<T>;
     using Cfg = StridedCfg<T, N>;
     using EF = Engine<T, N, Cfg::TPC, false>;
     using EI = Engine<T, N, Cfg::TPC, true>;
     constexpr int n = N / 2, W = Cfg::W;
-    __shared__ C lds[N * W];
+    __shared__ C lds[Cfg::LDS_ELEMS];
     const int g = blockIdx.x;
     const int pi = (g / 16) * 8 + (g % 8), side = (g % 16) / 8;
-    if (pi >= (n + 1) * ntile) return;              // uniform over the workgroup
-    const int b = pi / ntile, tile = pi % ntile;
+    if (pi >= (n + 1) * io.ntile) return;           // uniform over the workgroup
+    const int b = pi / io.ntile, tile = pi % io.ntile;
     if (side && (b == 0 || b == n)) return;
     const int k2 = side ? N - b : b;
     const int col = threadIdx.x % W, t = threadIdx.x / W;
-    const int c = tile * W + col;
-    const bool valid = c <= n;
-    const size_t stride = (size_t)N * P;            // step in i1
-    const C *src = src_base + (size_t)k2 * P + c;
-    C *dst = dst_base + (size_t)k2 * P + c;
-    const double *mrow = mult + ((size_t)(b * (P / 8) + c / 8) * (n + 1)) * 8 + (c & 7);
+    const int cg = (io.tile0 + tile) * W + col;
+    const bool valid = cg <= n;
+    const C *src = io.src + a_index<N, W>(io.pa, tile, k2, 0, col);  // rows i1
+    const size_t step = (size_t)N * io.pa;
+    const double *mrow = mult + ((size_t)(b * (P / 8) + cg / 8) * (n + 1)) * 8 + (cg & 7);
     C v[EF::V];
     EF::for_inputs(v, t, [&](int pos, int r) -> C {
-        if (r < EF::R(0) / 2 && valid) return src[pos * stride];
+        if (r < EF::R(0) / 2 && valid) return src[pos * step];
         return c_zero<C>();
     });
-    EF::template run_from<0>(v, lds, t, IdxInter<W>{col}, tw);
+    EF::template run_from<0, Cfg::SPLIT>(v, lds, t, IdxInter<W>{col}, tw);
     EF::for_outputs(v, t, [&](int pos, int, C &val) {
         const int a = pos <= n ? pos : N - pos;
         const double m = mrow[(size_t)a * 8];
         val = C{T((double)val.x * m), T((double)val.y * m)};
     });
-    EI::template run_from<0>(v, lds, t, IdxInter<W>{col}, tw);
-    EI::for_outputs(v, t, [&](int pos, int r, C &val) {
-        if (valid && (FULL || r < EI::R(EI::S - 1) / 2)) dst[pos * stride] = val;
-    });
+    EI::template run_from<0, Cfg::SPLIT>(v, lds, t, IdxInter<W>{col}, tw);
+    if constexpr (!FULL) {
+        C *dst = io.dst + a_index<N, W>(io.pa, tile, k2, 0, col);
+        EI::for_outputs(v, t, [&](int pos, int r, C &val) {
+            if (valid && r < EI::R(EI::S - 1) / 2) dst[pos * step] = val;
+        });
+    } else {
+        C *dst = io.dst + (size_t)k2 * P + cg;
+        EI::for_outputs(v, t, [&](int pos, int, C &val) {
+            if (valid) dst[(size_t)pos * N * P] = val;
+        });
+    }
 }
 
 // ------------------------------------------------------------------- H4
+// FULL (test hook): reads A2[i1][k2][k3] for all N rows i1 and writes all N
+// outputs to Y2[i1][i2][k3] (pitch P).
 template <typename T, int N, bool FULL>
 __global__ void __launch_bounds__((StridedCfg<T, N>::THREADS))
-k_y_inv(const cplx<T> *__restrict__ A, cplx<T> *__restrict__ Y, int P, int ntile, Twiddle<T> tw) {
+k_y_inv(StridedIO<T> io, int P, Twiddle<T> tw) {
     using C = cplx<T>;
     using Cfg = StridedCfg<T, N>;
     using E = Engine<T, N, Cfg::TPC, true>;
     constexpr int n = N / 2, W = Cfg::W;
-    constexpr int rows_out = FULL ? N : n;
-    __shared__ C lds[N * W];
+    __shared__ C lds[Cfg::LDS_ELEMS];
     const int col = threadIdx.x % W, t = threadIdx.x / W;
-    const int i1 = blockIdx.x / ntile, tile = blockIdx.x % ntile;
-    const int c = tile * W + col;
-    const bool valid = c <= n;
-    const C *src = A + (size_t)i1 * N * P + c;
-    C *dst = Y + (size_t)i1 * rows_out * P + c;
+    const int i1 = blockIdx.x / io.ntile, tile = blockIdx.x % io.ntile;
+    const int cg = (io.tile0 + tile) * W + col;
+    const bool valid = cg <= n;
     C v[E::V];
-    E::for_inputs(v, t, [&](int pos, int) -> C {
-        if (valid) return src[(size_t)pos * P];
-        return c_zero<C>();
-    });
-    E::template run_from<0>(v, lds, t, IdxInter<W>{col}, tw);
+    if constexpr (!FULL) {
+        const C *src = io.src + a_index<N, W>(io.pa, tile, 0, i1, col);  // rows k2
+        E::for_inputs(v, t, [&](int pos, int) -> C {
+            if (valid) return src[(size_t)pos * io.pa];
+            return c_zero<C>();
+        });
+    } else {
+        const C *src = io.src + (size_t)i1 * N * P + cg;
+        E::for_inputs(v, t, [&](int pos, int) -> C {
+            if (valid) return src[(size_t)pos * P];
+            return c_zero<C>();
+        });
+    }
+    E::template run_from<0, Cfg::SPLIT>(v, lds, t, IdxInter<W>{col}, tw);
+    constexpr int rows_out = FULL ? N : n;
+    C *dst = io.dst + (size_t)i1 * rows_out * P + cg;
     E::for_outputs(v, t, [&](int pos, int r, C &val) {
         if (valid && (FULL || r < E::R(E::S - 1) / 2)) dst[(size_t)pos * P] = val;
     });
@@ -196,28 +254,26 @@ k_z_c2r(const cplx<T> *__restrict__ Y, T *__restrict__ u, int npairs, int P, Twi
     using E = Engine<T, N, Cfg::TPC, true>;
     constexpr int n = N / 2;
     constexpr int len_out = FULL ? N : n;
-    __shared__ C lds[Cfg::Q * N];
+    __shared__ C lds[Cfg::Q * Cfg::LINE];
     const int t = threadIdx.x % Cfg::TPC, q = threadIdx.x / Cfg::TPC;
     const int pair = blockIdx.x * Cfg::Q + q;
     const bool active = pair < npairs;
-    if (active) {
-        const C *ya = Y + (size_t)(2 * pair) * P;
-        const C *yb = ya + P;
-        for (int k = t; k <= n; k += Cfg::TPC) {
-            C A = ya[k], B = yb[k];
-            if (k == 0 || k == n) {
-                A.y = 0;
-                B.y = 0;
-            }
-            lds[q * N + k] = C{A.x - B.y, A.y + B.x};
-            if (k != 0 && k != n) lds[q * N + N - k] = C{A.x + B.y, B.x - A.y};
-        }
-    }
-    __syncthreads();
-    IdxLine idx{q * N};
+    const C *ya = Y + (size_t)(2 * pair) * P;
+    const C *yb = ya + P;
     C v[E::V];
-    E::template load_lds<0>(v, lds, t, idx);
-    __syncthreads();
+    // Z[k] = A[k] + i B[k] for k <= n, conj A[N-k] + i conj B[N-k] above
+    E::for_inputs(v, t, [&](int pos, int) -> C {
+        if (!active) return c_zero<C>();
+        const int k = pos <= n ? pos : N - pos;
+        C A = ya[k], B = yb[k];
+        if (k == 0 || k == n) {
+            A.y = 0;
+            B.y = 0;
+        }
+        if (pos <= n) return C{A.x - B.y, A.y + B.x};
+        return C{A.x + B.y, B.x - A.y};
+    });
+    IdxLine idx{q * Cfg::LINE};
     E::template run_from<0>(v, lds, t, idx, tw);
     T *ua = u + (size_t)(2 * pair) * len_out;
     T *ub = ua + len_out;
@@ -282,6 +338,8 @@ k_spectrum(const double *__restrict__ J0, const double *__restrict__ J2,
 // --------------------------------------------------------------- launchers
 static inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
 
+int strided_width(bool f32) { return f32 ? StridedCols<float>::W : StridedCols<double>::W; }
+
 template <typename T, int N>
 static hipError_t solve_impl(const SolveArgs &s, hipStream_t st) {
     using C = cplx<T>;
@@ -297,34 +355,53 @@ static hipError_t solve_impl(const SolveArgs &s, hipStream_t st) {
     const int npairs = n * n / 2;
     C *X = (C *)s.X;
     C *A = (C *)s.A;
-    {
-        using Cfg = LineCfg<T, N>;
-        hipLaunchKernelGGL((k_z_r2c<T, N>), dim3(ceil_div(npairs, Cfg::Q)), dim3(Cfg::THREADS), 0, st,
-                           (const T *)s.rho, X, npairs, P, tw);
-    }
+    // profiling events: [0] before H1, per chunk c: [1+3c] before H2,
+    // [2+3c] before H3, [3+3c] before H4; [1+3C] before H5, [2+3C] after it
+    auto mark = [&](int i) {
+        if (s.ev && i < s.nev) (void)hipEventRecord(s.ev[i], st);
+    };
     using SC = StridedCfg<T, N>;
-    const int ntile = ceil_div(n + 1, SC::W);
-    hipLaunchKernelGGL((k_y_fwd<T, N>), dim3(n * ntile), dim3(SC::THREADS), 0, st, (const C *)X, A, P, ntile, tw);
-    const int npi = (n + 1) * ntile;
+    using LC = LineCfg<T, N>;
+    constexpr int W = SC::W;
+    const int ntile = ceil_div(n + 1, W);
+    mark(0);
+    hipLaunchKernelGGL((k_z_r2c<T, N>), dim3(ceil_div(npairs, LC::Q)), dim3(LC::THREADS), 0, st,
+                       (const T *)s.rho, X, npairs, P, tw);
     if (!s.full) {
-        hipLaunchKernelGGL((k_x_fused<T, N, false>), dim3(ceil_div(npi, 8) * 16), dim3(SC::THREADS), 0, st,
-                           (const C *)A, A, s.mult, P, ntile, tw);
-        hipLaunchKernelGGL((k_y_inv<T, N, false>), dim3(n * ntile), dim3(SC::THREADS), 0, st, (const C *)A, X, P,
-                           ntile, tw);
-        using Cfg = LineCfg<T, N>;
-        hipLaunchKernelGGL((k_z_c2r<T, N, false>), dim3(ceil_div(npairs, Cfg::Q)), dim3(Cfg::THREADS), 0, st,
+        // H2 -> H3 -> H4 per chunk of k3 tiles; A holds one chunk
+        const int ct = s.chunk_tiles > 0 ? std::min(s.chunk_tiles, ntile) : ntile;
+        const int nchunks = ceil_div(ntile, ct);
+        for (int ch = 0; ch < nchunks; ++ch) {
+            const int t0 = ch * ct, nt = std::min(ct, ntile - t0);
+            StridedIO<T> h2{X, A, t0, nt, ct * W};
+            StridedIO<T> h3{A, A, t0, nt, ct * W};
+            StridedIO<T> h4{A, X, t0, nt, ct * W};
+            mark(1 + 3 * ch);
+            hipLaunchKernelGGL((k_y_fwd<T, N>), dim3(n * nt), dim3(SC::THREADS), 0, st, h2, P, tw);
+            mark(2 + 3 * ch);
+            hipLaunchKernelGGL((k_x_fused<T, N, false>), dim3(ceil_div((long)(n + 1) * nt, 8) * 16),
+                               dim3(SC::THREADS), 0, st, h3, s.mult, P, tw);
+            mark(3 + 3 * ch);
+            hipLaunchKernelGGL((k_y_inv<T, N, false>), dim3(n * nt), dim3(SC::THREADS), 0, st, h4, P, tw);
+        }
+        mark(1 + 3 * nchunks);
+        hipLaunchKernelGGL((k_z_c2r<T, N, false>), dim3(ceil_div(npairs, LC::Q)), dim3(LC::THREADS), 0, st,
                            (const C *)X, (T *)s.u, npairs, P, tw);
+        mark(2 + 3 * nchunks);
     } else {
-        // uncropped variant: A2 (N x N x P) and Y2 (N x N x P) are separate
+        // uncropped variant (one chunk): A2 and Y2 (N x N x P, row layout)
+        // receive all N outputs of the inverse transforms
         C *A2 = (C *)s.A2;
         C *Y2 = (C *)s.Y2;
-        hipLaunchKernelGGL((k_x_fused<T, N, true>), dim3(ceil_div(npi, 8) * 16), dim3(SC::THREADS), 0, st,
-                           (const C *)A, A2, s.mult, P, ntile, tw);
-        hipLaunchKernelGGL((k_y_inv<T, N, true>), dim3(N * ntile), dim3(SC::THREADS), 0, st, (const C *)A2, Y2, P,
-                           ntile, tw);
-        using Cfg = LineCfg<T, N>;
+        StridedIO<T> h2{X, A, 0, ntile, ntile * W};
+        StridedIO<T> h3{A, A2, 0, ntile, ntile * W};
+        StridedIO<T> h4{A2, Y2, 0, ntile, ntile * W};
+        hipLaunchKernelGGL((k_y_fwd<T, N>), dim3(n * ntile), dim3(SC::THREADS), 0, st, h2, P, tw);
+        hipLaunchKernelGGL((k_x_fused<T, N, true>), dim3(ceil_div((long)(n + 1) * ntile, 8) * 16),
+                           dim3(SC::THREADS), 0, st, h3, s.mult, P, tw);
+        hipLaunchKernelGGL((k_y_inv<T, N, true>), dim3(N * ntile), dim3(SC::THREADS), 0, st, h4, P, tw);
         const int np2 = N * N / 2;
-        hipLaunchKernelGGL((k_z_c2r<T, N, true>), dim3(ceil_div(np2, Cfg::Q)), dim3(Cfg::THREADS), 0, st,
+        hipLaunchKernelGGL((k_z_c2r<T, N, true>), dim3(ceil_div(np2, LC::Q)), dim3(LC::THREADS), 0, st,
                            (const C *)Y2, (T *)s.u, np2, P, tw);
     }
     return hipGetLastError();

@@ -101,12 +101,12 @@ static void account(psp_server *sv, long delta) {
     }
 }
 
-static size_t ws_bytes(int n, bool f32) { return workspace_bytes(n, f32); }
+static size_t ws_bytes(int n, bool f32) { return workspace_bytes(n, f32, default_chunk_tiles(n, f32)); }
 
 static void free_ws(psp_server *sv, PooledWs &p) {
-    (void)hipFree(p.w.X);
-    (void)hipFree(p.w.A);
-    account(sv, -(long)p.w.bytes);
+    const size_t b = p.w.bytes;
+    free_workspace(&p.w);
+    account(sv, -(long)b);
 }
 
 // free idle memory (pooled workspaces first, then LRU idle spectra) until
@@ -167,17 +167,8 @@ static psp_status take_ws(psp_server *sv, int n, bool f32, PooledWs *out) {
     PooledWs p;
     p.n = n;
     p.f32 = f32;
-    const size_t c = f32 ? 8 : 16, P = (size_t)pitch_for(n);
-    p.w.bytes = ws_bytes(n, f32);
-    if (hipMalloc(&p.w.X, c * P * n * n) != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(PSP_ENOMEM, "serve workspace allocation failed");
-    }
-    if (hipMalloc(&p.w.A, c * P * n * 2 * n) != hipSuccess) {
-        (void)hipGetLastError();
-        (void)hipFree(p.w.X);
-        return fail(PSP_ENOMEM, "serve workspace allocation failed");
-    }
+    psp_status st = alloc_workspace(n, f32, default_chunk_tiles(n, f32), &p.w);
+    if (st != PSP_OK) return st;
     account(sv, (long)p.w.bytes);
     *out = p;
     return PSP_OK;
@@ -342,7 +333,7 @@ psp_status psp_serve_submit(psp_server *sv, int n, double h, int R, psp_dtype ti
     const double half = (double)n * h;
     psp_status st = check_create(n, h, R, 1e-4 * half, std::sqrt(3.0) * half);
     if (st != PSP_OK) return st;
-    if (spectrum_bytes(n) + workspace_bytes(n, tier == PSP_F32) > sv->budget)
+    if (spectrum_bytes(n) + ws_bytes(n, tier == PSP_F32) > sv->budget)
         return fail(PSP_ENOMEM, "request footprint exceeds the whole budget");
     std::lock_guard<std::mutex> lk(sv->mu);
     if (sv->queue.size() >= 65536) return fail(PSP_EBUSY, "queue full");

@@ -35,6 +35,9 @@ SIGNATURES = {
     "psp_plan_workspace_bytes": (_i, [_vp, _P(_sz)]),
     "psp_plan_spectrum_bytes": (_i, [_vp, _P(_sz)]),
     "psp_plan_destroy": (None, [_vp]),
+    "psp_profile_enable": (_i, [_vp, _i]),
+    "psp_plan_set_chunk": (_i, [_vp, _i]),
+    "psp_profile_read": (_i, [_vp, _P(_i), _P(_d)]),
     "psp_serve_create": (_i, [_sz, _i, _P(_vp)]),
     "psp_serve_submit": (_i, [_vp, _i, _d, _i, _i, _vp, _vp, _P(_u64)]),
     "psp_serve_poll": (_i, [_vp, _u64, _P(_i), _P(_i), _P(_d)]),
@@ -181,6 +184,20 @@ class Plan:
         m = np.empty((self.n + 1,) * 3)
         _check(lib().psp_plan_get_multiplier(self._h, m.ctypes.data_as(_P(_d))))
         return m
+
+    def set_chunk(self, k3_tiles: int):
+        _check(lib().psp_plan_set_chunk(self._h, int(k3_tiles)))
+        return self
+
+    def profile_enable(self, max_solves: int):
+        _check(lib().psp_profile_enable(self._h, int(max_solves)))
+
+    def profile_read(self):
+        """(count, [ms of passes H1..H5], ms of the whole solve)."""
+        cnt = ctypes.c_int()
+        ms = np.zeros(6)
+        _check(lib().psp_profile_read(self._h, ctypes.byref(cnt), ms.ctypes.data_as(_P(_d))))
+        return cnt.value, ms[:5].tolist(), float(ms[5])
 
     def workspace_bytes(self) -> int:
         v = ctypes.c_size_t()

@@ -83,12 +83,16 @@ def test_gs_weights_match_oracle(n, h, R):
 
 
 def test_workspace_and_spectrum_sizes():
+    # X: n*n*P complex; chunk buffer: n*2n*(tiles*W) complex with W = 8 (FP64)
+    # or 16 (FP32) k3 bins per tile; by default one chunk of all tiles
     p = B.Plan(256, 2 / 256, 40)
     P = 272
-    assert p.workspace_bytes() == 16 * P * (256 * 256 + 256 * 512)
+    assert p.workspace_bytes() == 16 * (P * 256 * 256 + 264 * 256 * 512)
     assert p.spectrum_bytes() == 8 * 257 * 257 * P
     q = B.Plan(256, 2 / 256, 40, dtype="f32")
-    assert q.workspace_bytes() == 8 * P * (256 * 256 + 256 * 512)
+    assert q.workspace_bytes() == 8 * (P * 256 * 256 + 272 * 256 * 512)
+    p.set_chunk(4)
+    assert p.workspace_bytes() == 16 * (P * 256 * 256 + 32 * 256 * 512)
 
 
 @pytest.mark.parametrize("n,h,R", [(32, 2 / 32, 40), (96, 2 / 96, 40), (64, 4 / 63, 120)])

@@ -168,3 +168,24 @@ def test_padded_debug_and_spectral_residual():
     print("spectral residual (R=40) %.2e" % res)
     assert res < 5e-3
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("n,dtype", [(24, "f64"), (48, "f64"), (48, "f32"), (64, "f32")])
+def test_chunked_strided_passes_bitwise(n, dtype):
+    # the k3 chunking of the strided passes changes no arithmetic: every
+    # chunk size (ragged last chunk included) gives the same bits
+    import torch
+    h = 2.0 / n
+    rng = np.random.default_rng(400 + n)
+    td = torch.float64 if dtype == "f64" else torch.float32
+    rho = to_dev(rng.standard_normal((n, n, n)), td)
+    p = B.Plan(n, h, 40, dtype=dtype).precompute()
+    ref = None
+    for tiles in (1000, 1, 2, 3):
+        p.set_chunk(tiles)
+        u = p.solve(rho)
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = u.clone()
+        else:
+            assert torch.equal(u, ref), tiles
