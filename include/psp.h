@@ -80,10 +80,13 @@ psp_status psp_kernel_precompute(psp_plan *p, void *stream);
  * first call with that stream.  Returns PSP_ESTATE before precompute. */
 psp_status psp_solve(psp_plan *p, const void *rho_dev, void *u_dev, void *stream);
 
-/* `count` independent solves in one launch per pass.  plans may differ in n
- * (and h, R) but must share one dtype and all be precomputed; rho_dev[i] and
- * u_dev[i] follow plans[i].  Results are bitwise equal to psp_solve of the
- * same plan and rho.  Workspace is library-owned, bound to the stream. */
+/* `count` (<= 65535) independent solves: one launch per pass for each
+ * distinct n in the batch (the pass kernels read each solve's pointers from
+ * a device job table).  plans may differ in n (and h, R) but must share one
+ * dtype and device and all be precomputed; rho_dev[i] and u_dev[i] follow
+ * plans[i].  Results are bitwise equal to psp_solve of the same plan and rho.
+ * Workspaces (one per solve of the batch) are library-owned, bound to the
+ * stream and reused by later batches on it. */
 psp_status psp_solve_batched(int count, psp_plan *const *plans,
                              const void *const *rho_dev, void *const *u_dev,
                              void *stream);
@@ -109,8 +112,8 @@ psp_status psp_plan_get_multiplier(psp_plan *p, double *m_host);
  * in FP64, 16 in FP32), so the padded intermediate is a chunk-sized buffer
  * instead of the whole n x 2n x (n+1) intermediate.  0 (the default) is
  * one chunk, the fastest; smaller chunks trade some speed for workspace
- * memory (the serving loop uses chunk buffers of at most 64 MB).  Frees the
- * plan's workspaces; call it while no solve of this plan is in flight. */
+ * memory.  Frees the plan's workspaces; call it while no solve of this plan
+ * is in flight.  Batched solves and graphs always use one chunk. */
 psp_status psp_plan_set_chunk(psp_plan *p, int k3_tiles);
 
 /* Bytes of device workspace one solve of this plan needs (per stream). */
@@ -130,6 +133,21 @@ psp_status psp_profile_enable(psp_plan *p, int max_solves);
 psp_status psp_profile_read(psp_plan *p, int *count, double *pass_ms);
 
 void psp_plan_destroy(psp_plan *p);
+
+/* ---- captured solves (hipGraph) -------------------------------------------
+ * psp_graph_capture records one solve of (plan, rho_dev, u_dev) as a HIP graph
+ * with its own workspace; psp_graph_launch replays it on `stream` (one host
+ * call for all passes).  psp_graph_capture_batched does the same for a
+ * batch (as psp_solve_batched; the graph owns the workspaces and the device
+ * job table).  Replays of one graph must not overlap each other; the graph
+ * keeps pointers to rho/u and to the plans' spectra, which must outlive it.
+ * Capture synchronises `stream`. */
+typedef struct psp_graph psp_graph;
+psp_status psp_graph_capture(psp_plan *p, const void *rho_dev, void *u_dev, void *stream, psp_graph **out);
+psp_status psp_graph_capture_batched(int count, psp_plan *const *plans, const void *const *rho_dev,
+                                     void *const *u_dev, void *stream, psp_graph **out);
+psp_status psp_graph_launch(psp_graph *g, void *stream);
+void psp_graph_destroy(psp_graph *g);
 
 /* ---- serving --------------------------------------------------------------
  * A continuous-batching request loop.  Requests are admitted while their

@@ -19,7 +19,7 @@ OUT = os.path.join(HERE, "libpsp.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 ARCH = "gfx950"
 
-SOURCES = ["passes.hip", "batched.hip", "setup.cpp", "api.cpp", "serve.cpp"]
+SOURCES = ["passes.hip", "batched.hip", "setup.cpp", "api.cpp", "serve.cpp", "graph.cpp"]
 
 COMMON = [
     "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",

@@ -115,16 +115,6 @@ void free_workspace(Workspace *w) {
     w->X = w->A = nullptr;
 }
 
-// H2-H4 chunk size used where workspace memory matters (the serving loop):
-// the chunk buffer stays within 64 MB
-int default_chunk_tiles(int n, bool f32) {
-    const size_t c = f32 ? 8 : 16, W = (size_t)strided_width(f32);
-    const size_t per_tile = c * W * (size_t)n * 2 * n;
-    const size_t target = 64ull << 20;
-    size_t t = target / per_tile;
-    return (int)std::max<size_t>(1, t);
-}
-
 psp_status plan_workspace(psp_plan *p, hipStream_t st, Workspace **out) {
     std::lock_guard<std::mutex> lk(p->mu);
     auto it = p->ws.find(st);
@@ -451,21 +441,6 @@ psp_status psp_solve_padded_debug(psp_plan *p, const void *rho_dev, void *upad_d
     (void)hipFree(a.A2);
     (void)hipFree(a.Y2);
     if (e != hipSuccess) return hip_fail(e, "padded debug solve");
-    return PSP_OK;
-}
-
-psp_status psp_solve_batched(int count, psp_plan *const *plans, const void *const *rho_dev, void *const *u_dev,
-                             void *stream) {
-    if (count < 0 || (count > 0 && (!plans || !rho_dev || !u_dev))) return fail(PSP_EINVAL, "bad batch arguments");
-    for (int i = 0; i < count; ++i) {
-        if (!plans[i] || !rho_dev[i] || !u_dev[i]) return fail(PSP_EINVAL, "NULL entry %d in batch", i);
-        if (!plans[i]->precomputed) return fail(PSP_ESTATE, "batch entry %d not precomputed", i);
-        if (plans[i]->dtype != plans[0]->dtype) return fail(PSP_EINVAL, "batch mixes dtypes");
-    }
-    for (int i = 0; i < count; ++i) {
-        psp_status st = psp_solve(plans[i], rho_dev[i], u_dev[i], stream);
-        if (st != PSP_OK) return st;
-    }
     return PSP_OK;
 }
 

@@ -1,0 +1,155 @@
+// graph.cpp - solves captured as HIP graphs.  A graph owns its workspaces
+// and (for batches) its device job table, written before capture, so its
+// replays read nothing from library state that later calls may change.
+#include <algorithm>
+#include <vector>
+
+#include "host_common.hpp"
+
+struct psp_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<psp::Workspace> ws;
+    psp::Job *table = nullptr;   // device
+    int device = -1;
+};
+
+namespace psp {
+
+static void graph_free(psp_graph *g) {
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    for (auto &w : g->ws) free_workspace(&w);
+    if (g->table) (void)hipFree(g->table);
+    delete g;
+}
+
+// capture `record` on a private stream forked from `stream`
+template <typename F>
+static psp_status capture(psp_graph *g, hipStream_t stream, F record) {
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return fail(PSP_EHIP, "hipStreamCreate");
+    // everything the graph reads was written on `stream` before this call
+    hipError_t e = hipStreamSynchronize(stream);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(cs);
+        return hip_fail(e, "hipStreamBeginCapture");
+    }
+    hipError_t le = record(cs);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(cs, &graph);
+    (void)hipStreamDestroy(cs);
+    if (le != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return hip_fail(le, "launch during capture");
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    g->graph = graph;
+    e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    return PSP_OK;
+}
+
+}  // namespace psp
+
+using namespace psp;
+
+extern "C" {
+
+psp_status psp_graph_capture(psp_plan *p, const void *rho_dev, void *u_dev, void *stream, psp_graph **out) {
+    if (!out) return fail(PSP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!p || !rho_dev || !u_dev) return fail(PSP_EINVAL, "NULL argument");
+    if (!p->precomputed) return fail(PSP_ESTATE, "capture before psp_kernel_precompute");
+    if (rho_dev == u_dev) return fail(PSP_EINVAL, "rho and u must not alias");
+    psp_graph *g = new (std::nothrow) psp_graph;
+    if (!g) return fail(PSP_ENOMEM, "host allocation failed");
+    g->device = p->device;
+    g->ws.resize(1);
+    psp_status rs = alloc_workspace(p->n, p->dtype == PSP_F32, 0, &g->ws[0]);
+    if (rs != PSP_OK) {
+        g->ws.clear();
+        graph_free(g);
+        return rs;
+    }
+    SolveArgs a = solve_args(p, g->ws[0], rho_dev, u_dev);
+    a.chunk_tiles = 0;
+    rs = capture(g, (hipStream_t)stream, [&](hipStream_t cs) { return launch_solve(a, cs); });
+    if (rs != PSP_OK) {
+        graph_free(g);
+        return rs;
+    }
+    *out = g;
+    return PSP_OK;
+}
+
+psp_status psp_graph_capture_batched(int count, psp_plan *const *plans, const void *const *rho_dev,
+                                     void *const *u_dev, void *stream, psp_graph **out) {
+    if (!out) return fail(PSP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (count < 1 || count > 65535 || !plans || !rho_dev || !u_dev) return fail(PSP_EINVAL, "bad batch arguments");
+    for (int i = 0; i < count; ++i) {
+        if (!plans[i] || !rho_dev[i] || !u_dev[i]) return fail(PSP_EINVAL, "NULL entry %d in batch", i);
+        if (!plans[i]->precomputed) return fail(PSP_ESTATE, "batch entry %d not precomputed", i);
+        if (plans[i]->dtype != plans[0]->dtype) return fail(PSP_EINVAL, "batch mixes dtypes");
+    }
+    const bool f32 = plans[0]->dtype == PSP_F32;
+    psp_graph *g = new (std::nothrow) psp_graph;
+    if (!g) return fail(PSP_ENOMEM, "host allocation failed");
+    g->device = plans[0]->device;
+    // group by n: the table is sorted by n, each group a contiguous slice
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return plans[a]->n < plans[b]->n; });
+    g->ws.resize(count);
+    std::vector<Job> jobs(count);
+    for (int k = 0; k < count; ++k) {
+        const int i = order[k];
+        psp_status rs = alloc_workspace(plans[i]->n, f32, 0, &g->ws[k]);
+        if (rs != PSP_OK) {
+            g->ws.resize(k);
+            graph_free(g);
+            return rs;
+        }
+        jobs[k] = Job{rho_dev[i], u_dev[i], g->ws[k].X, g->ws[k].A, plans[i]->spec->mult, nullptr, nullptr};
+    }
+    if (hipMalloc((void **)&g->table, count * sizeof(Job)) != hipSuccess ||
+        hipMemcpy(g->table, jobs.data(), count * sizeof(Job), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipGetLastError();
+        graph_free(g);
+        return fail(PSP_ENOMEM, "graph job table allocation failed");
+    }
+    psp_status rs = capture(g, (hipStream_t)stream, [&](hipStream_t cs) -> hipError_t {
+        int k = 0;
+        while (k < count) {
+            int j = k;
+            const int n = plans[order[k]]->n;
+            while (j < count && plans[order[j]]->n == n) ++j;
+            const Twiddles *tw = plans[order[k]]->tw;
+            hipError_t e = launch_group(n, f32, g->table + k, j - k, f32 ? tw->hi32 : tw->w64,
+                                        f32 ? tw->lo32 : nullptr, cs);
+            if (e != hipSuccess) return e;
+            k = j;
+        }
+        return hipSuccess;
+    });
+    if (rs != PSP_OK) {
+        graph_free(g);
+        return rs;
+    }
+    *out = g;
+    return PSP_OK;
+}
+
+psp_status psp_graph_launch(psp_graph *g, void *stream) {
+    if (!g || !g->exec) return fail(PSP_EINVAL, "graph is NULL");
+    hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return PSP_OK;
+}
+
+void psp_graph_destroy(psp_graph *g) { graph_free(g); }
+
+}  // extern "C"

@@ -62,7 +62,6 @@ inline size_t workspace_bytes(int n, bool f32, int chunk_tiles) {
 }
 psp_status alloc_workspace(int n, bool f32, int chunk_tiles, Workspace *w);
 void free_workspace(Workspace *w);
-int default_chunk_tiles(int n, bool f32);
 inline size_t spectrum_bytes(int n) { return 8 * (size_t)(n + 1) * (n + 1) * pitch_for(n); }
 
 }  // namespace psp

@@ -4,6 +4,17 @@
 
 namespace psp {
 
+// One solve's device pointers as the pass kernels see them.
+struct Job {
+    const void *rho = nullptr;
+    void *u = nullptr;
+    void *X = nullptr;           // n*n*P complex
+    void *A = nullptr;           // chunk buffer
+    const double *mult = nullptr;
+    void *A2 = nullptr;          // uncropped variant only
+    void *Y2 = nullptr;          // uncropped variant only
+};
+
 // One solve's buffers (device pointers) and sizes.
 struct SolveArgs {
     int n = 0;          // points per axis; padded length N = 2n
@@ -25,6 +36,12 @@ struct SolveArgs {
 };
 
 hipError_t launch_solve(const SolveArgs &s, hipStream_t st);
+
+// `count` solves of the same n and tier in one launch per pass; `table_dev`
+// is a device array of `count` jobs, each with a workspace of one chunk
+// holding all tiles (chunk_tiles = 0)
+hipError_t launch_group(int n, bool f32, const Job *table_dev, int count, const void *tw_hi, const void *tw_lo,
+                        hipStream_t st);
 
 // k3 tile width of the strided passes (8 for FP64, 16 for FP32)
 int strided_width(bool f32);

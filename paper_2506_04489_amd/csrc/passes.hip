@@ -69,22 +69,32 @@ struct IdxLine {                     // column-major, one padding slot per 8 pos
     __device__ __forceinline__ int operator()(int pos) const { return base + pos + (pos >> 3); }
 };
 
+// Per-solve device pointers.  A single solve passes them as a kernel
+// argument; a batched launch passes a device table and takes entry
+// blockIdx.y (every solve of one launch has the same padded length).
+struct JobRef {
+    Job arg;
+    const Job *table;
+    __device__ __forceinline__ Job get() const { return table ? table[blockIdx.y] : arg; }
+};
+
 // ------------------------------------------------------------------- H1
 // Two real lines a, b (flattened (i1, i2) = 2q, 2q+1) form z = a + i b.  The
 // padded length-N line has data in [0, n) only.  After the transform,
 // A[k] = (Z[k] + conj Z[N-k])/2 and B[k] = (Z[k] - conj Z[N-k])/(2i).
 template <typename T, int N>
 __global__ void __launch_bounds__((LineCfg<T, N>::THREADS))
-k_z_r2c(const T *__restrict__ rho, cplx<T> *__restrict__ X, int npairs, int P, Twiddle<T> tw) {
+k_z_r2c(JobRef jr, int P, Twiddle<T> tw) {
     using C = cplx<T>;
     using Cfg = LineCfg<T, N>;
     using E = Engine<T, N, Cfg::TPC, false>;
-    constexpr int n = N / 2;
+    constexpr int n = N / 2, npairs = n * n / 2;
     __shared__ C lds[Cfg::Q * Cfg::LINE];
+    const Job jb = jr.get();
     const int t = threadIdx.x % Cfg::TPC, q = threadIdx.x / Cfg::TPC;
     const int pair = blockIdx.x * Cfg::Q + q;
     const bool active = pair < npairs;
-    const T *ra = rho + (size_t)(2 * pair) * n;
+    const T *ra = (const T *)jb.rho + (size_t)(2 * pair) * n;
     const T *rb = ra + n;
     C v[E::V];
     E::for_inputs(v, t, [&](int pos, int r) -> C {
@@ -96,7 +106,7 @@ k_z_r2c(const T *__restrict__ rho, cplx<T> *__restrict__ X, int npairs, int P, T
     E::for_outputs(v, t, [&](int pos, int, C &val) { lds[idx(pos)] = val; });
     __syncthreads();
     if (active) {
-        C *xa = X + (size_t)(2 * pair) * P;
+        C *xa = (C *)jb.X + (size_t)(2 * pair) * P;
         C *xb = xa + P;
         for (int k = t; k <= n; k += Cfg::TPC) {
             const C z = lds[idx(k)];
@@ -116,9 +126,7 @@ k_z_r2c(const T *__restrict__ rho, cplx<T> *__restrict__ X, int npairs, int P, T
 // only a few KB apart).  X/Y rows are [i1][i2][k3] with pitch P and the
 // global column cg = tile0 W + c, which also decides validity (cg <= n) and
 // the multiplier entry.
-template <typename T> struct StridedIO {
-    const cplx<T> *src;
-    cplx<T> *dst;
+struct Chunk {
     int tile0;      // first tile of the chunk
     int ntile;      // tiles in the chunk
     int pa;         // k3 pitch of the chunk buffer A
@@ -132,25 +140,26 @@ __device__ __forceinline__ size_t a_index(int pa, int tile, int k2, int i1, int 
 // ------------------------------------------------------------------- H2
 template <typename T, int N>
 __global__ void __launch_bounds__((StridedCfg<T, N>::THREADS))
-k_y_fwd(StridedIO<T> io, int P, Twiddle<T> tw) {
+k_y_fwd(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
     using C = cplx<T>;
     using Cfg = StridedCfg<T, N>;
     using E = Engine<T, N, Cfg::TPC, false>;
     constexpr int n = N / 2, W = Cfg::W;
     __shared__ C lds[Cfg::LDS_ELEMS];
+    const Job jb = jr.get();
     const int col = threadIdx.x % W, t = threadIdx.x / W;
-    const int i1 = blockIdx.x / io.ntile, tile = blockIdx.x % io.ntile;
-    const int cg = (io.tile0 + tile) * W + col;
+    const int i1 = blockIdx.x / ck.ntile, tile = blockIdx.x % ck.ntile;
+    const int cg = (ck.tile0 + tile) * W + col;
     const bool valid = cg <= n;
-    const C *src = io.src + (size_t)i1 * n * P + cg;               // rows i2 of X
-    C *dst = io.dst + a_index<N, W>(io.pa, tile, 0, i1, col);       // rows k2 of A
+    const C *src = (const C *)jb.X + (size_t)i1 * n * P + cg;            // rows i2 of X
+    C *dst = (C *)jb.A + a_index<N, W>(ck.pa, tile, 0, i1, col);         // rows k2 of A
     C v[E::V];
     E::for_inputs(v, t, [&](int pos, int r) -> C {
         if (r < E::R(0) / 2 && valid) return src[(size_t)pos * P];
         return c_zero<C>();
     });
     E::template run_from<0, Cfg::SPLIT>(v, lds, t, IdxInter<W>{col}, tw);
-    E::for_outputs(v, t, [&](int pos, int, C &val) { dst[(size_t)pos * io.pa] = val; });
+    E::for_outputs(v, t, [&](int pos, int, C &val) { dst[(size_t)pos * ck.pa] = val; });
 }
 
 // ------------------------------------------------------------------- H3
@@ -161,7 +170,7 @@ k_y_fwd(StridedIO<T> io, int P, Twiddle<T> tw) {
 // FULL (test hook): all N outputs of the inverse go to A2[i1][k2][k3] (pitch P).
 template <typename T, int N, bool FULL>
 __global__ void __launch_bounds__((StridedCfg<T, N>::THREADS))
-k_x_fused(StridedIO<T> io, const double *__restrict__ mult, int P, Twiddle<T> tw) {
+k_x_fused(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
     using C = cplx<T>;
     using Cfg = StridedCfg<T, N>;
     using EF = Engine<T, N, Cfg::TPC, false>;
@@ -170,16 +179,17 @@ k_x_fused(StridedIO<T> io, const double *__restrict__ mult, int P, Twiddle<T> tw
     __shared__ C lds[Cfg::LDS_ELEMS];
     const int g = blockIdx.x;
     const int pi = (g / 16) * 8 + (g % 8), side = (g % 16) / 8;
-    if (pi >= (n + 1) * io.ntile) return;           // uniform over the workgroup
-    const int b = pi / io.ntile, tile = pi % io.ntile;
+    if (pi >= (n + 1) * ck.ntile) return;           // uniform over the workgroup
+    const int b = pi / ck.ntile, tile = pi % ck.ntile;
     if (side && (b == 0 || b == n)) return;
+    const Job jb = jr.get();
     const int k2 = side ? N - b : b;
     const int col = threadIdx.x % W, t = threadIdx.x / W;
-    const int cg = (io.tile0 + tile) * W + col;
+    const int cg = (ck.tile0 + tile) * W + col;
     const bool valid = cg <= n;
-    const C *src = io.src + a_index<N, W>(io.pa, tile, k2, 0, col);  // rows i1
-    const size_t step = (size_t)N * io.pa;
-    const double *mrow = mult + ((size_t)(b * (P / 8) + cg / 8) * (n + 1)) * 8 + (cg & 7);
+    const C *src = (const C *)jb.A + a_index<N, W>(ck.pa, tile, k2, 0, col);   // rows i1
+    const size_t step = (size_t)N * ck.pa;
+    const double *mrow = jb.mult + ((size_t)(b * (P / 8) + cg / 8) * (n + 1)) * 8 + (cg & 7);
     C v[EF::V];
     EF::for_inputs(v, t, [&](int pos, int r) -> C {
         if (r < EF::R(0) / 2 && valid) return src[pos * step];
@@ -193,12 +203,12 @@ k_x_fused(StridedIO<T> io, const double *__restrict__ mult, int P, Twiddle<T> tw
     });
     EI::template run_from<0, Cfg::SPLIT>(v, lds, t, IdxInter<W>{col}, tw);
     if constexpr (!FULL) {
-        C *dst = io.dst + a_index<N, W>(io.pa, tile, k2, 0, col);
+        C *dst = (C *)jb.A + a_index<N, W>(ck.pa, tile, k2, 0, col);
         EI::for_outputs(v, t, [&](int pos, int r, C &val) {
             if (valid && r < EI::R(EI::S - 1) / 2) dst[pos * step] = val;
         });
     } else {
-        C *dst = io.dst + (size_t)k2 * P + cg;
+        C *dst = (C *)jb.A2 + (size_t)k2 * P + cg;
         EI::for_outputs(v, t, [&](int pos, int, C &val) {
             if (valid) dst[(size_t)pos * N * P] = val;
         });
@@ -210,25 +220,26 @@ k_x_fused(StridedIO<T> io, const double *__restrict__ mult, int P, Twiddle<T> tw
 // outputs to Y2[i1][i2][k3] (pitch P).
 template <typename T, int N, bool FULL>
 __global__ void __launch_bounds__((StridedCfg<T, N>::THREADS))
-k_y_inv(StridedIO<T> io, int P, Twiddle<T> tw) {
+k_y_inv(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
     using C = cplx<T>;
     using Cfg = StridedCfg<T, N>;
     using E = Engine<T, N, Cfg::TPC, true>;
     constexpr int n = N / 2, W = Cfg::W;
     __shared__ C lds[Cfg::LDS_ELEMS];
+    const Job jb = jr.get();
     const int col = threadIdx.x % W, t = threadIdx.x / W;
-    const int i1 = blockIdx.x / io.ntile, tile = blockIdx.x % io.ntile;
-    const int cg = (io.tile0 + tile) * W + col;
+    const int i1 = blockIdx.x / ck.ntile, tile = blockIdx.x % ck.ntile;
+    const int cg = (ck.tile0 + tile) * W + col;
     const bool valid = cg <= n;
     C v[E::V];
     if constexpr (!FULL) {
-        const C *src = io.src + a_index<N, W>(io.pa, tile, 0, i1, col);  // rows k2
+        const C *src = (const C *)jb.A + a_index<N, W>(ck.pa, tile, 0, i1, col);   // rows k2
         E::for_inputs(v, t, [&](int pos, int) -> C {
-            if (valid) return src[(size_t)pos * io.pa];
+            if (valid) return src[(size_t)pos * ck.pa];
             return c_zero<C>();
         });
     } else {
-        const C *src = io.src + (size_t)i1 * N * P + cg;
+        const C *src = (const C *)jb.A2 + (size_t)i1 * N * P + cg;
         E::for_inputs(v, t, [&](int pos, int) -> C {
             if (valid) return src[(size_t)pos * P];
             return c_zero<C>();
@@ -236,7 +247,7 @@ k_y_inv(StridedIO<T> io, int P, Twiddle<T> tw) {
     }
     E::template run_from<0, Cfg::SPLIT>(v, lds, t, IdxInter<W>{col}, tw);
     constexpr int rows_out = FULL ? N : n;
-    C *dst = io.dst + (size_t)i1 * rows_out * P + cg;
+    C *dst = (C *)(FULL ? jb.Y2 : jb.X) + (size_t)i1 * rows_out * P + cg;
     E::for_outputs(v, t, [&](int pos, int r, C &val) {
         if (valid && (FULL || r < E::R(E::S - 1) / 2)) dst[(size_t)pos * P] = val;
     });
@@ -245,20 +256,23 @@ k_y_inv(StridedIO<T> io, int P, Twiddle<T> tw) {
 // ------------------------------------------------------------------- H5
 // Rows a, b of Y (Hermitian half spectra) form Z[k] = A[k] + i B[k] on the
 // full length N; the inverse transform gives a + i b.  The imaginary parts
-// of the k = 0 and k = n bins are dropped (real transform).
+// of the k = 0 and k = n bins are dropped (real transform).  FULL: rows of
+// Y2 (N*N lines) and all N outputs.
 template <typename T, int N, bool FULL>
 __global__ void __launch_bounds__((LineCfg<T, N>::THREADS))
-k_z_c2r(const cplx<T> *__restrict__ Y, T *__restrict__ u, int npairs, int P, Twiddle<T> tw) {
+k_z_c2r(JobRef jr, int P, Twiddle<T> tw) {
     using C = cplx<T>;
     using Cfg = LineCfg<T, N>;
     using E = Engine<T, N, Cfg::TPC, true>;
     constexpr int n = N / 2;
     constexpr int len_out = FULL ? N : n;
+    constexpr int npairs = FULL ? N * N / 2 : n * n / 2;
     __shared__ C lds[Cfg::Q * Cfg::LINE];
+    const Job jb = jr.get();
     const int t = threadIdx.x % Cfg::TPC, q = threadIdx.x / Cfg::TPC;
     const int pair = blockIdx.x * Cfg::Q + q;
     const bool active = pair < npairs;
-    const C *ya = Y + (size_t)(2 * pair) * P;
+    const C *ya = (const C *)(FULL ? jb.Y2 : jb.X) + (size_t)(2 * pair) * P;
     const C *yb = ya + P;
     C v[E::V];
     // Z[k] = A[k] + i B[k] for k <= n, conj A[N-k] + i conj B[N-k] above
@@ -275,7 +289,7 @@ k_z_c2r(const cplx<T> *__restrict__ Y, T *__restrict__ u, int npairs, int P, Twi
     });
     IdxLine idx{q * Cfg::LINE};
     E::template run_from<0>(v, lds, t, idx, tw);
-    T *ua = u + (size_t)(2 * pair) * len_out;
+    T *ua = (T *)jb.u + (size_t)(2 * pair) * len_out;
     T *ub = ua + len_out;
     E::for_outputs(v, t, [&](int pos, int r, C &val) {
         if (active && (FULL || r < E::R(E::S - 1) / 2)) {
@@ -340,78 +354,78 @@ static inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
 
 int strided_width(bool f32) { return f32 ? StridedCols<float>::W : StridedCols<double>::W; }
 
-template <typename T, int N>
-static hipError_t solve_impl(const SolveArgs &s, hipStream_t st) {
-    using C = cplx<T>;
-    constexpr int n = N / 2;
-    const int P = s.P;
+template <typename T, int N> static Twiddle<T> twiddle_of(const void *hi, const void *lo) {
     Twiddle<T> tw;
     if constexpr (sizeof(T) == 8) {
-        tw.w = (const double2 *)s.tw_hi;
+        (void)lo;
+        tw.w = (const double2 *)hi;
     } else {
-        tw.hi = (const float2 *)s.tw_hi;
-        tw.lo = (const float2 *)s.tw_lo;
+        tw.hi = (const float2 *)hi;
+        tw.lo = (const float2 *)lo;
     }
-    const int npairs = n * n / 2;
-    C *X = (C *)s.X;
-    C *A = (C *)s.A;
+    return tw;
+}
+
+// the five passes for `count` solves of one padded length: a single solve
+// (table == nullptr, pointers in `one`) or a table of `count` jobs
+template <typename T, int N>
+static hipError_t passes_impl(const Job &one, const Job *table, int count, int P, int chunk_tiles, bool full,
+                              const void *tw_hi, const void *tw_lo, hipEvent_t *ev, int nev, hipStream_t st) {
+    constexpr int n = N / 2;
+    const Twiddle<T> tw = twiddle_of<T, N>(tw_hi, tw_lo);
+    const JobRef jr{one, table};
     // profiling events: [0] before H1, per chunk c: [1+3c] before H2,
     // [2+3c] before H3, [3+3c] before H4; [1+3C] before H5, [2+3C] after it
     auto mark = [&](int i) {
-        if (s.ev && i < s.nev) (void)hipEventRecord(s.ev[i], st);
+        if (ev && i < nev) (void)hipEventRecord(ev[i], st);
     };
     using SC = StridedCfg<T, N>;
     using LC = LineCfg<T, N>;
     constexpr int W = SC::W;
     const int ntile = ceil_div(n + 1, W);
+    const int y = count;
     mark(0);
-    hipLaunchKernelGGL((k_z_r2c<T, N>), dim3(ceil_div(npairs, LC::Q)), dim3(LC::THREADS), 0, st,
-                       (const T *)s.rho, X, npairs, P, tw);
-    if (!s.full) {
+    hipLaunchKernelGGL((k_z_r2c<T, N>), dim3(ceil_div(n * n / 2, LC::Q), y), dim3(LC::THREADS), 0, st, jr, P, tw);
+    if (!full) {
         // H2 -> H3 -> H4 per chunk of k3 tiles; A holds one chunk
-        const int ct = s.chunk_tiles > 0 ? std::min(s.chunk_tiles, ntile) : ntile;
+        const int ct = chunk_tiles > 0 ? std::min(chunk_tiles, ntile) : ntile;
         const int nchunks = ceil_div(ntile, ct);
         for (int ch = 0; ch < nchunks; ++ch) {
             const int t0 = ch * ct, nt = std::min(ct, ntile - t0);
-            StridedIO<T> h2{X, A, t0, nt, ct * W};
-            StridedIO<T> h3{A, A, t0, nt, ct * W};
-            StridedIO<T> h4{A, X, t0, nt, ct * W};
+            const Chunk ck{t0, nt, ct * W};
             mark(1 + 3 * ch);
-            hipLaunchKernelGGL((k_y_fwd<T, N>), dim3(n * nt), dim3(SC::THREADS), 0, st, h2, P, tw);
+            hipLaunchKernelGGL((k_y_fwd<T, N>), dim3(n * nt, y), dim3(SC::THREADS), 0, st, jr, ck, P, tw);
             mark(2 + 3 * ch);
-            hipLaunchKernelGGL((k_x_fused<T, N, false>), dim3(ceil_div((long)(n + 1) * nt, 8) * 16),
-                               dim3(SC::THREADS), 0, st, h3, s.mult, P, tw);
+            hipLaunchKernelGGL((k_x_fused<T, N, false>), dim3(ceil_div((long)(n + 1) * nt, 8) * 16, y),
+                               dim3(SC::THREADS), 0, st, jr, ck, P, tw);
             mark(3 + 3 * ch);
-            hipLaunchKernelGGL((k_y_inv<T, N, false>), dim3(n * nt), dim3(SC::THREADS), 0, st, h4, P, tw);
+            hipLaunchKernelGGL((k_y_inv<T, N, false>), dim3(n * nt, y), dim3(SC::THREADS), 0, st, jr, ck, P, tw);
         }
         mark(1 + 3 * nchunks);
-        hipLaunchKernelGGL((k_z_c2r<T, N, false>), dim3(ceil_div(npairs, LC::Q)), dim3(LC::THREADS), 0, st,
-                           (const C *)X, (T *)s.u, npairs, P, tw);
+        hipLaunchKernelGGL((k_z_c2r<T, N, false>), dim3(ceil_div(n * n / 2, LC::Q), y), dim3(LC::THREADS), 0, st,
+                           jr, P, tw);
         mark(2 + 3 * nchunks);
     } else {
         // uncropped variant (one chunk): A2 and Y2 (N x N x P, row layout)
         // receive all N outputs of the inverse transforms
-        C *A2 = (C *)s.A2;
-        C *Y2 = (C *)s.Y2;
-        StridedIO<T> h2{X, A, 0, ntile, ntile * W};
-        StridedIO<T> h3{A, A2, 0, ntile, ntile * W};
-        StridedIO<T> h4{A2, Y2, 0, ntile, ntile * W};
-        hipLaunchKernelGGL((k_y_fwd<T, N>), dim3(n * ntile), dim3(SC::THREADS), 0, st, h2, P, tw);
-        hipLaunchKernelGGL((k_x_fused<T, N, true>), dim3(ceil_div((long)(n + 1) * ntile, 8) * 16),
-                           dim3(SC::THREADS), 0, st, h3, s.mult, P, tw);
-        hipLaunchKernelGGL((k_y_inv<T, N, true>), dim3(N * ntile), dim3(SC::THREADS), 0, st, h4, P, tw);
-        const int np2 = N * N / 2;
-        hipLaunchKernelGGL((k_z_c2r<T, N, true>), dim3(ceil_div(np2, LC::Q)), dim3(LC::THREADS), 0, st,
-                           (const C *)Y2, (T *)s.u, np2, P, tw);
+        const Chunk ck{0, ntile, ntile * W};
+        hipLaunchKernelGGL((k_y_fwd<T, N>), dim3(n * ntile, y), dim3(SC::THREADS), 0, st, jr, ck, P, tw);
+        hipLaunchKernelGGL((k_x_fused<T, N, true>), dim3(ceil_div((long)(n + 1) * ntile, 8) * 16, y),
+                           dim3(SC::THREADS), 0, st, jr, ck, P, tw);
+        hipLaunchKernelGGL((k_y_inv<T, N, true>), dim3(N * ntile, y), dim3(SC::THREADS), 0, st, jr, ck, P, tw);
+        hipLaunchKernelGGL((k_z_c2r<T, N, true>), dim3(ceil_div(N * N / 2, LC::Q), y), dim3(LC::THREADS), 0, st,
+                           jr, P, tw);
     }
     return hipGetLastError();
 }
 
 template <typename T>
-static hipError_t solve_dispatch(const SolveArgs &s, hipStream_t st) {
-    switch (2 * s.n) {
+static hipError_t passes_dispatch(int N, const Job &one, const Job *table, int count, int P, int chunk_tiles,
+                                  bool full, const void *tw_hi, const void *tw_lo, hipEvent_t *ev, int nev,
+                                  hipStream_t st) {
+    switch (N) {
 #define PSP_CASE(NN) \
-    case NN: return solve_impl<T, NN>(s, st);
+    case NN: return passes_impl<T, NN>(one, table, count, P, chunk_tiles, full, tw_hi, tw_lo, ev, nev, st);
         PSP_CASE(8) PSP_CASE(12) PSP_CASE(16) PSP_CASE(24) PSP_CASE(32) PSP_CASE(48) PSP_CASE(64)
         PSP_CASE(96) PSP_CASE(128) PSP_CASE(192) PSP_CASE(256) PSP_CASE(384) PSP_CASE(512) PSP_CASE(768)
 #undef PSP_CASE
@@ -420,7 +434,19 @@ static hipError_t solve_dispatch(const SolveArgs &s, hipStream_t st) {
 }
 
 hipError_t launch_solve(const SolveArgs &s, hipStream_t st) {
-    return s.f32 ? solve_dispatch<float>(s, st) : solve_dispatch<double>(s, st);
+    const Job one{s.rho, s.u, s.X, s.A, s.mult, s.A2, s.Y2};
+    return s.f32 ? passes_dispatch<float>(2 * s.n, one, nullptr, 1, s.P, s.chunk_tiles, s.full, s.tw_hi, s.tw_lo,
+                                          s.ev, s.nev, st)
+                 : passes_dispatch<double>(2 * s.n, one, nullptr, 1, s.P, s.chunk_tiles, s.full, s.tw_hi,
+                                           s.tw_lo, s.ev, s.nev, st);
+}
+
+hipError_t launch_group(int n, bool f32, const Job *table_dev, int count, const void *tw_hi, const void *tw_lo,
+                        hipStream_t st) {
+    const Job none{};
+    const int P = ((n + 1 + 15) / 16) * 16;
+    return f32 ? passes_dispatch<float>(2 * n, none, table_dev, count, P, 0, false, tw_hi, tw_lo, nullptr, 0, st)
+               : passes_dispatch<double>(2 * n, none, table_dev, count, P, 0, false, tw_hi, tw_lo, nullptr, 0, st);
 }
 
 hipError_t launch_spectrum(const double *J0, const double *J2, const double *omega, int R, int n, int P,

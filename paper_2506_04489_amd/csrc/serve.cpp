@@ -101,7 +101,8 @@ static void account(psp_server *sv, long delta) {
     }
 }
 
-static size_t ws_bytes(int n, bool f32) { return workspace_bytes(n, f32, default_chunk_tiles(n, f32)); }
+// requests run in grouped batch launches, whose workspaces hold all k3 tiles
+static size_t ws_bytes(int n, bool f32) { return workspace_bytes(n, f32, 0); }
 
 static void free_ws(psp_server *sv, PooledWs &p) {
     const size_t b = p.w.bytes;
@@ -167,7 +168,7 @@ static psp_status take_ws(psp_server *sv, int n, bool f32, PooledWs *out) {
     PooledWs p;
     p.n = n;
     p.f32 = f32;
-    psp_status st = alloc_workspace(n, f32, default_chunk_tiles(n, f32), &p.w);
+    psp_status st = alloc_workspace(n, f32, 0, &p.w);
     if (st != PSP_OK) return st;
     account(sv, (long)p.w.bytes);
     *out = p;

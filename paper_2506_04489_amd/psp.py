@@ -38,6 +38,10 @@ SIGNATURES = {
     "psp_profile_enable": (_i, [_vp, _i]),
     "psp_plan_set_chunk": (_i, [_vp, _i]),
     "psp_profile_read": (_i, [_vp, _P(_i), _P(_d)]),
+    "psp_graph_capture": (_i, [_vp, _vp, _vp, _vp, _P(_vp)]),
+    "psp_graph_capture_batched": (_i, [_i, _P(_vp), _P(_vp), _P(_vp), _vp, _P(_vp)]),
+    "psp_graph_launch": (_i, [_vp, _vp]),
+    "psp_graph_destroy": (None, [_vp]),
     "psp_serve_create": (_i, [_sz, _i, _P(_vp)]),
     "psp_serve_submit": (_i, [_vp, _i, _d, _i, _i, _vp, _vp, _P(_u64)]),
     "psp_serve_poll": (_i, [_vp, _u64, _P(_i), _P(_i), _P(_d)]),
@@ -223,6 +227,50 @@ def solve_batched(plans: Sequence[Plan], rhos, us, stream=None):
     up = (ctypes.c_void_p * k)(*[u.data_ptr() for u in us])
     _check(lib().psp_solve_batched(k, ph, rp, up, _stream_ptr(stream)))
     return us
+
+
+class Graph:
+    """A solve (or batch) captured as a HIP graph: psp_graph_*."""
+
+    def __init__(self, handle, keep):
+        self._h = handle
+        self._keep = keep            # tensors and plans the graph points into
+
+    @classmethod
+    def capture(cls, plan: "Plan", rho, u, stream=None):
+        plan._check_tensor(rho, (plan.n,) * 3)
+        plan._check_tensor(u, (plan.n,) * 3)
+        h = ctypes.c_void_p()
+        _check(lib().psp_graph_capture(plan.handle, rho.data_ptr(), u.data_ptr(), _stream_ptr(stream),
+                                       ctypes.byref(h)))
+        return cls(h, (plan, rho, u))
+
+    @classmethod
+    def capture_batched(cls, plans, rhos, us, stream=None):
+        k = len(plans)
+        for p, r, u in zip(plans, rhos, us):
+            p._check_tensor(r, (p.n,) * 3)
+            p._check_tensor(u, (p.n,) * 3)
+        ph = (ctypes.c_void_p * k)(*[p.handle.value for p in plans])
+        rp = (ctypes.c_void_p * k)(*[r.data_ptr() for r in rhos])
+        up = (ctypes.c_void_p * k)(*[u.data_ptr() for u in us])
+        h = ctypes.c_void_p()
+        _check(lib().psp_graph_capture_batched(k, ph, rp, up, _stream_ptr(stream), ctypes.byref(h)))
+        return cls(h, (list(plans), list(rhos), list(us)))
+
+    def launch(self, stream=None):
+        _check(lib().psp_graph_launch(self._h, _stream_ptr(stream)))
+
+    def close(self):
+        if self._h:
+            lib().psp_graph_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Server:

@@ -1,0 +1,103 @@
+"""The serving loop on the GPU: every result is bitwise the same alone and in
+the mix; admission against the HBM budget; error paths."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2506_04489_amd import densities as D
+from paper_2506_04489_amd import psp as B
+from tests.gpu_util import announce
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _name(request):
+    announce(request.node.nodeid)
+    yield
+
+
+def _wait(sv, tickets, timeout=120.0):
+    t0 = time.time()
+    pending = set(tickets)
+    while pending:
+        for t in list(pending):
+            done, res, lat = sv.poll(t)
+            if done:
+                pending.discard(t)
+        if time.time() - t0 > timeout:
+            raise TimeoutError("requests not done: %d" % len(pending))
+        time.sleep(0.001)
+
+
+def test_served_results_equal_alone():
+    import torch
+    reqs = D.serving_workload(count=24, rate=1000.0, seed=D.SERVE_SEED)
+    sv = B.Server(hbm_budget_bytes=200 << 30, max_slots=16)
+    rhos, us, tickets = [], [], []
+    for r in reqs:
+        td = torch.float64 if r.tier == "f64" else torch.float32
+        rho = D.request_density(r, xp=torch, device="cuda").to(td).contiguous()
+        torch.cuda.synchronize()
+        u = torch.empty_like(rho)
+        rhos.append(rho)
+        us.append(u)
+        tickets.append(sv.submit(r.n, r.h, 40, r.tier, rho, u))
+    _wait(sv, tickets)
+    lats = []
+    for t in tickets:
+        done, res, lat = sv.poll(t)
+        assert done and res == 0
+        lats.append(lat)
+    st = sv.stats()
+    assert st["completed"] == len(reqs)
+    assert st["cache_misses"] >= 1 and st["cache_hits"] >= 1
+    print("latency p50 %.2f ms p99 %.2f ms, peak %.2f GB" % (np.percentile(lats, 50), np.percentile(lats, 99),
+                                                              st["bytes_peak"] / 2 ** 30))
+    sv.close()
+    plans = {}
+    for r, rho, u in zip(reqs, rhos, us):
+        key = (r.n, r.tier)
+        if key not in plans:
+            plans[key] = B.Plan(r.n, r.h, 40, dtype=r.tier).precompute()
+        alone = plans[key].solve(rho)
+        torch.cuda.synchronize()
+        assert torch.equal(u, alone), key
+
+
+def test_small_budget_queues_and_completes():
+    import torch
+    # room for one n = 64 request at a time: the rest wait in the queue
+    n, h = 64, 2.0 / 64
+    p = B.Plan(n, h, 40)
+    one = p.workspace_bytes() + p.spectrum_bytes()
+    sv = B.Server(hbm_budget_bytes=int(one * 1.5), max_slots=4)
+    rho = D.gaussian(n, h, -1.0, 0.15, xp=torch, device="cuda").contiguous()
+    us = [torch.empty_like(rho) for _ in range(6)]
+    tickets = [sv.submit(n, h, 40, "f64", rho, u) for u in us]
+    _wait(sv, tickets)
+    st = sv.stats()
+    assert st["bytes_peak"] <= int(one * 1.5)
+    ref = p.precompute().solve(rho)
+    torch.cuda.synchronize()
+    for u in us:
+        assert torch.equal(u, ref)
+    sv.close()
+
+
+def test_submit_errors():
+    import torch
+    sv = B.Server(hbm_budget_bytes=1 << 20, max_slots=2)
+    rho = torch.zeros((64,) * 3, dtype=torch.float64, device="cuda")
+    u = torch.empty_like(rho)
+    with pytest.raises(B.PspError) as ei:
+        sv.submit(64, 2 / 64, 40, "f64", rho, u)          # larger than the whole budget
+    assert B.STATUS[ei.value.status] == "PSP_ENOMEM"
+    with pytest.raises(B.PspError) as ei:
+        sv.submit(63, 2 / 63, 40, "f64", rho, u)
+    assert B.STATUS[ei.value.status] == "PSP_EUNSUPPORTED"
+    with pytest.raises(B.PspError) as ei:
+        sv.poll(123456)
+    assert B.STATUS[ei.value.status] == "PSP_EINVAL"
+    sv.close()
