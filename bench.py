@@ -21,6 +21,31 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, published
+COPY_CAL_BYTES = 1 << 30   # plain device copy used to calibrate the byte counters
+TRAFFIC_FILE = os.path.join(HERE, "profiles", "traffic_passes_n256.txt")
+KERNEL_SOURCES = ["paper_2506_04489_amd/csrc/fft_core.hpp", "paper_2506_04489_amd/csrc/passes.hip"]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(HERE, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """Per-launch HBM bytes of each pass from the committed counter summary,
+    or None when the pass kernels changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.loads(next(l for l in f if l.startswith("{")))
+    except (OSError, StopIteration, ValueError):
+        return None
+    if rec.get("source_sha256") != kernel_source_hash():
+        return None
+    return rec
 
 
 def pass_bytes(n: int, real_bytes: int):
@@ -65,6 +90,112 @@ def time_tier(torch, B, D, n, dtype, steps, warmup, chunk=0):
             "precompute_s": t_pre, "u": u}
 
 
+def bench_batched(torch, B, D, dtype, reps=5):
+    """The batched workload: 64 seeded Gaussian mixtures, n ~ U{32,48,64,96,128}.
+    One-at-a-time psp_solve, one psp_solve_batched, and the batch replayed as
+    a captured graph, in solves/s."""
+    td = torch.float64 if dtype == "f64" else torch.float32
+    items = D.batched_workload(count=64, seed=D.BATCH_SEED)
+    plans = {}
+    for it in items:
+        if it.n not in plans:
+            plans[it.n] = B.Plan(it.n, it.h, 40, dtype=dtype).precompute()
+    ps = [plans[it.n] for it in items]
+    rhos = [it.mixture.sample(it.n, it.h, it.x0, xp=torch, device="cuda").to(td).contiguous() for it in items]
+    us = [torch.empty_like(r) for r in rhos]
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    t_single = timed(lambda: [p.solve(r, u) for p, r, u in zip(ps, rhos, us)])
+    t_batch = timed(lambda: B.solve_batched(ps, rhos, us))
+    g = B.Graph.capture_batched(ps, rhos, us)
+    t_graph = timed(lambda: g.launch())
+    g.close()
+    pts = sum(it.n ** 3 for it in items)
+    return {"count": len(items), "sizes": sorted({it.n for it in items}),
+            "one_at_a_time_solves_per_s": round(len(items) / t_single, 1),
+            "batched_solves_per_s": round(len(items) / t_batch, 1),
+            "graph_batched_solves_per_s": round(len(items) / t_graph, 1),
+            "batched_mpts_per_s": round(pts / t_batch / 1e6, 1),
+            "speedup_batched_vs_single": round(t_single / t_batch, 2)}
+
+
+def bench_serving(torch, B, D, count=2000, rates=(0.25, 0.5, 0.9, 1.2), budget=200 << 30, slots=64):
+    """The serving stream: Poisson arrivals, n from {64..384}, 50/50 tiers and
+    density families; spectra cached per (n, h, R) (warmed first).  For each
+    rate (a multiple of the measured capacity) the latency percentiles from
+    submit to completion and the achieved throughput."""
+    import numpy as np
+    reqs = D.serving_workload(count=count, rate=1.0, seed=D.SERVE_SEED)
+    sv = B.Server(hbm_budget_bytes=budget, max_slots=slots)
+    # inputs: a few distinct densities per (n, tier, family), reused; outputs
+    # from per-(n, tier) rings of buffers whose previous request must be done
+    pool, rings = {}, {}
+    for r in reqs:
+        key = (r.n, r.tier, r.kind)
+        if key not in pool:
+            td = torch.float64 if r.tier == "f64" else torch.float32
+            pool[key] = [D.request_density(q, xp=torch, device="cuda").to(td).contiguous()
+                         for q in [x for x in reqs if (x.n, x.tier, x.kind) == key][:2]]
+        rk = (r.n, r.tier)
+        if rk not in rings:
+            rings[rk] = {"bufs": [torch.empty_like(pool[key][0]) for _ in range(16)], "owner": [None] * 16, "next": 0}
+    torch.cuda.synchronize()
+
+    def run(rate):
+        t0 = time.perf_counter()
+        tickets = []
+        for i, r in enumerate(reqs):
+            due = t0 + r.t_arrival / rate
+            while time.perf_counter() < due:
+                pass
+            ring = rings[(r.n, r.tier)]
+            slot = ring["next"]
+            ring["next"] = (slot + 1) % len(ring["bufs"])
+            prev = ring["owner"][slot]
+            while prev is not None and not sv.poll(prev)[0]:
+                time.sleep(0.0002)
+            rho = pool[(r.n, r.tier, r.kind)][i % len(pool[(r.n, r.tier, r.kind)])]
+            t = sv.submit(r.n, r.h, 40, r.tier, rho, ring["bufs"][slot])
+            ring["owner"][slot] = t
+            tickets.append(t)
+        sv.drain()
+        wall = time.perf_counter() - t0
+        lat = np.array([sv.poll(t)[2] for t in tickets])
+        return wall, lat
+
+    # warm the spectrum cache and workspaces: one request per (n, tier)
+    warm = []
+    for (n, tier), ring in rings.items():
+        key = next(k for k in pool if k[0] == n and k[1] == tier)
+        warm.append(sv.submit(n, 2.0 / n, 40, tier, pool[key][0], ring["bufs"][0]))
+    sv.drain()
+    # capacity: the whole stream submitted at once
+    wall, lat = run(1e9)
+    cap = count / wall
+    out = {"requests": count, "capacity_req_per_s": round(cap, 1), "rates": []}
+    pts = sum(r.n ** 3 for r in reqs)
+    for f in rates:
+        wall, lat = run(cap * f)
+        out["rates"].append({"load": f, "rate_req_per_s": round(cap * f, 1),
+                             "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                             "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                             "achieved_req_per_s": round(count / wall, 1),
+                             "achieved_mpts_per_s": round(pts / wall / 1e6, 1)})
+    st = sv.stats()
+    out["bytes_peak_GB"] = round(st["bytes_peak"] / 2 ** 30, 2)
+    out["cache_hits"], out["cache_misses"] = st["cache_hits"], st["cache_misses"]
+    sv.close()
+    return out
+
+
 def cpu_baseline(n: int, budget_s: float = 12.0):
     """The oracle (as it stands) on a bounded sample of the same workload: its
     naive FFT on a batch of length-2n pencils, scaled to one full solve
@@ -101,6 +232,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-f32", action="store_true", help="skip the FP32 tier")
     ap.add_argument("--chunk", type=int, default=0, help="k3 tiles per H2-H4 chunk (0: library default)")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched workload")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
+    ap.add_argument("--serve-count", type=int, default=2000)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 1 GiB device copy (reference for byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         sys.stderr.write("bench.py measures one GPU: this build has no multi-GPU path "
@@ -112,6 +248,13 @@ def main():
     from paper_2506_04489_amd import psp as B
     B.lib()                                   # fail loudly if libpsp.so is missing
     n = args.n
+    if args.copy_calibration:
+        a = torch.ones(COPY_CAL_BYTES // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     res = time_tier(torch, B, D, n, "f64", args.steps, args.warmup, args.chunk)
     ms = 1e3 * res["wall_s"] / args.steps
     value = args.steps / res["wall_s"]
@@ -120,7 +263,7 @@ def main():
     achieved = pb[dom] / (res["pass_ms"][dom] * 1e-3) / 1e9
     b_alg_fused = 16 * n ** 3 + 128 * n * n * (n + 1) + 8 * (n + 1) ** 3
     out = {
-        "metric": "FP64 solves/s at 256^3 (<=1e-12 rel err vs oracle)",
+        "metric": "FP64 solves/s at 256^3 (<=1e-12 rel err vs oracle); served p50/p99 ms",
         "value": round(value, 3),
         "unit": "solves/s",
         "n_gpus": 1,
@@ -139,6 +282,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": PASS_NAMES[dom], "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None, "alg_bytes_per_launch": pb[dom]},
+        "kernel_source_sha256": kernel_source_hash(),
         "passes": {PASS_NAMES[i]: {"ms": round(res["pass_ms"][i], 4),
                                    "alg_GBps": round(pb[i] / (res["pass_ms"][i] * 1e-3) / 1e9, 1)}
                    for i in range(5)},
@@ -148,6 +292,10 @@ def main():
         "precompute_s": round(res["precompute_s"], 3),
         "paper_context": "MATLAB on i7-8565U, FP64, 128^3: 0.536 s/solve (Table 1); no 256^3 or GPU number",
     }
+    tr = measured_traffic() if n == 256 else None
+    if tr is not None and PASS_NAMES[dom] in tr.get("passes", {}):
+        out["roofline"]["traffic"] = tr["passes"][PASS_NAMES[dom]]["bytes"]
+        out["roofline"]["traffic_source"] = os.path.relpath(TRAFFIC_FILE, HERE)
     if not args.no_f32:
         r32 = time_tier(torch, B, D, n, "f32", args.steps, args.warmup, args.chunk)
         # FP32-tier error against the FP64 result of the same workload
@@ -157,6 +305,14 @@ def main():
                            "ms_per_step": round(1e3 * r32["wall_s"] / args.steps, 4),
                            "pass_ms": [round(v, 4) for v in r32["pass_ms"]],
                            "err_vs_f64_tier": err}
+    if not args.no_batched:
+        out["batched"] = {t: bench_batched(torch, B, D, t) for t in ("f64", "f32")}
+    if not args.no_serve:
+        out["served"] = bench_serving(torch, B, D, count=args.serve_count)
+        loads = out["served"]["rates"]
+        if loads:
+            near = min(loads, key=lambda x: abs(x["load"] - 0.9))
+            out["served_p50_ms"], out["served_p99_ms"] = near["p50_ms"], near["p99_ms"]
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(n)
     print(json.dumps(out))

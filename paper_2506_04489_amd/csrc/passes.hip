@@ -274,20 +274,24 @@ k_z_c2r(JobRef jr, int P, Twiddle<T> tw) {
     const bool active = pair < npairs;
     const C *ya = (const C *)(FULL ? jb.Y2 : jb.X) + (size_t)(2 * pair) * P;
     const C *yb = ya + P;
-    C v[E::V];
-    // Z[k] = A[k] + i B[k] for k <= n, conj A[N-k] + i conj B[N-k] above
-    E::for_inputs(v, t, [&](int pos, int) -> C {
-        if (!active) return c_zero<C>();
-        const int k = pos <= n ? pos : N - pos;
-        C A = ya[k], B = yb[k];
-        if (k == 0 || k == n) {
-            A.y = 0;
-            B.y = 0;
-        }
-        if (pos <= n) return C{A.x - B.y, A.y + B.x};
-        return C{A.x + B.y, B.x - A.y};
-    });
     IdxLine idx{q * Cfg::LINE};
+    // each half-spectrum bin is read once (coalesced) and gives
+    // Z[k] = A[k] + i B[k] and Z[N-k] = conj A[k] + i conj B[k]
+    if (active) {
+        for (int k = t; k <= n; k += Cfg::TPC) {
+            C A = ya[k], B = yb[k];
+            if (k == 0 || k == n) {
+                A.y = 0;
+                B.y = 0;
+            }
+            lds[idx(k)] = C{A.x - B.y, A.y + B.x};
+            if (k != 0 && k != n) lds[idx(N - k)] = C{A.x + B.y, B.x - A.y};
+        }
+    }
+    __syncthreads();
+    C v[E::V];
+    E::template load_lds<0>(v, lds, t, idx);
+    __syncthreads();
     E::template run_from<0>(v, lds, t, idx, tw);
     T *ua = (T *)jb.u + (size_t)(2 * pair) * len_out;
     T *ub = ua + len_out;
@@ -310,41 +314,53 @@ k_z_c2r(JobRef jr, int P, Twiddle<T> tw) {
 // B[l/16][l%16], D[l/16 + 4e][l%16] for e < 4.
 typedef double v4d __attribute__((ext_vector_type(4)));
 
+// one wave: a 16-row a-tile for one b against CT consecutive 16-wide c-tiles;
+// the A operand of each k-step is formed once and feeds CT MFMAs
+constexpr int SPEC_CT = 4;
+
 __global__ void __launch_bounds__(256)
 k_spectrum(const double *__restrict__ J0, const double *__restrict__ J2,
            const double *__restrict__ omega, int R, int n, int P, double scale,
            double *__restrict__ mult) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int nt = (n + 1 + 15) / 16;
-    const long tile = (long)blockIdx.x * 4 + wave;
-    if (tile >= (long)(n + 1) * nt * nt) return;    // no barriers in this kernel
-    const int b = (int)(tile / (nt * nt));
-    const int rem = (int)(tile % (nt * nt));
-    const int a0 = (rem / nt) * 16, c0 = (rem % nt) * 16;
+    const int nt = (n + 1 + 15) / 16, ng = (nt + SPEC_CT - 1) / SPEC_CT;
+    const long item = (long)blockIdx.x * 4 + wave;
+    if (item >= (long)(n + 1) * nt * ng) return;    // no barriers in this kernel
+    const int b = (int)(item / (nt * ng));
+    const int rem = (int)(item % (nt * ng));
+    const int a0 = (rem / ng) * 16, cgrp = (rem % ng) * SPEC_CT;
     const int row = lane & 15, kq = lane >> 4;
-    const int a = a0 + row, c = c0 + row;
+    const int a = a0 + row;
     const int n1 = n + 1;
-    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    v4d acc[SPEC_CT];
+#pragma unroll
+    for (int q = 0; q < SPEC_CT; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
     for (int k0 = 0; k0 < 2 * R; k0 += 4) {
         const int ks = k0 + kq, s = ks >> 1, ty = ks & 1;
-        double av = 0.0, bv = 0.0;
-        if (s < R) {
-            const double *j0 = J0 + (size_t)s * n1, *j2 = J2 + (size_t)s * n1;
-            if (a <= n) {
-                const double w = omega[s];
-                av = ty == 0 ? w * (j2[a] * j0[b] + j0[a] * j2[b]) : w * (j0[a] * j0[b]);
-            }
-            if (c <= n) bv = ty == 0 ? j0[c] : j2[c];
+        double av = 0.0;
+        const double *j0 = J0 + (size_t)s * n1, *j2 = J2 + (size_t)s * n1;
+        if (s < R && a <= n) {
+            const double w = omega[s];
+            av = ty == 0 ? w * (j2[a] * j0[b] + j0[a] * j2[b]) : w * (j0[a] * j0[b]);
         }
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
-    }
-    const int cc = c0 + row;
+        const double *jb = ty == 0 ? j0 : j2;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const int aa = a0 + kq + 4 * e;
-        if (aa <= n && cc <= n) {
-            const double k2 = (double)aa * aa + (double)b * b + (double)cc * cc;
-            mult[((size_t)(b * (P / 8) + cc / 8) * n1 + aa) * 8 + (cc & 7)] = scale * k2 * acc[e];
+        for (int q = 0; q < SPEC_CT; ++q) {
+            const int c = (cgrp + q) * 16 + row;
+            const double bv = (s < R && c <= n) ? jb[c] : 0.0;
+            acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[q], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < SPEC_CT; ++q) {
+        const int cc = (cgrp + q) * 16 + row;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int aa = a0 + kq + 4 * e;
+            if (aa <= n && cc <= n) {
+                const double k2 = (double)aa * aa + (double)b * b + (double)cc * cc;
+                mult[((size_t)(b * (P / 8) + cc / 8) * n1 + aa) * 8 + (cc & 7)] = scale * k2 * acc[q][e];
+            }
         }
     }
 }
@@ -451,9 +467,9 @@ hipError_t launch_group(int n, bool f32, const Job *table_dev, int count, const 
 
 hipError_t launch_spectrum(const double *J0, const double *J2, const double *omega, int R, int n, int P,
                            double scale, double *mult, hipStream_t st) {
-    const int nt = (n + 1 + 15) / 16;
-    const long tiles = (long)(n + 1) * nt * nt;
-    hipLaunchKernelGGL(k_spectrum, dim3(ceil_div(tiles, 4)), dim3(256), 0, st, J0, J2, omega, R, n, P, scale,
+    const int nt = (n + 1 + 15) / 16, ng = (nt + SPEC_CT - 1) / SPEC_CT;
+    const long items = (long)(n + 1) * nt * ng;
+    hipLaunchKernelGGL(k_spectrum, dim3(ceil_div(items, 4)), dim3(256), 0, st, J0, J2, omega, R, n, P, scale,
                        mult);
     return hipGetLastError();
 }

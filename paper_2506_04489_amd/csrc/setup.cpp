@@ -171,10 +171,20 @@ static void tables_one(double a64, int n, double L, double *J0, double *J2) {
             const ld y = i < 8 ? c - hw * kXgk[j] : c + hw * kXgk[j];
             const ld g = hw * kWgk[j] * expl(-a * y * y);
             const ld g2 = g * y * y;
+            // cos(k w y) for k = 0..n by rotation in extended precision,
+            // re-anchored with cosl/sinl every 32 steps (drift below 1e-17)
+            const ld th = w * y, c1 = cosl(th), s1 = sinl(th);
+            ld ck = 1.0L, sk = 0.0L;
             for (int k = 0; k <= n; ++k) {
-                const ld cs = cosl(w * (ld)k * y);
-                s0[k] += g * cs;
-                s2[k] += g2 * cs;
+                if ((k & 31) == 0 && k > 0) {
+                    ck = cosl((ld)k * th);
+                    sk = sinl((ld)k * th);
+                }
+                s0[k] += g * ck;
+                s2[k] += g2 * ck;
+                const ld cn = ck * c1 - sk * s1;
+                sk = sk * c1 + ck * s1;
+                ck = cn;
             }
         }
     }
