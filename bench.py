@@ -65,12 +65,12 @@ def pass_bytes(n: int, real_bytes: int):
 PASS_NAMES = ["H1_z_r2c", "H2_y_fwd", "H3_x_fused", "H4_y_inv", "H5_z_c2r"]
 
 
-def time_tier(torch, B, D, n, dtype, steps, warmup, chunk=0):
+def time_tier(torch, B, D, n, dtype, steps, warmup, chunk=0, group=0):
     h = 2.0 / n
     td = torch.float64 if dtype == "f64" else torch.float32
     t0 = time.perf_counter()
     plan = B.Plan(n, h, 40, dtype=dtype).precompute()
-    plan.set_chunk(chunk)
+    plan.set_tuning(chunk, group)
     t_pre = time.perf_counter() - t0
     rho = D.bump(n, h, -1.0, 0.6, xp=torch, device="cuda").to(td).contiguous()
     u = torch.empty_like(rho)
@@ -180,7 +180,23 @@ def bench_serving(torch, B, D, count=2000, rates=(0.25, 0.5, 0.9, 1.2), budget=2
     # capacity: the whole stream submitted at once
     wall, lat = run(1e9)
     cap = count / wall
-    out = {"requests": count, "capacity_req_per_s": round(cap, 1), "rates": []}
+    # one-at-a-time baseline: the same requests as consecutive psp_solve calls
+    plans = {}
+    for r in reqs:
+        if (r.n, r.tier) not in plans:
+            plans[(r.n, r.tier)] = B.Plan(r.n, r.h, 40, dtype=r.tier).precompute()
+    def seq():
+        for i, r in enumerate(reqs):
+            k = (r.n, r.tier, r.kind)
+            plans[(r.n, r.tier)].solve(pool[k][i % len(pool[k])], rings[(r.n, r.tier)]["bufs"][0])
+    seq()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq()
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    out = {"requests": count, "capacity_req_per_s": round(cap, 1),
+           "one_at_a_time_req_per_s": round(count / t_seq, 1), "rates": []}
     pts = sum(r.n ** 3 for r in reqs)
     for f in rates:
         wall, lat = run(cap * f)
@@ -232,6 +248,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-f32", action="store_true", help="skip the FP32 tier")
     ap.add_argument("--chunk", type=int, default=0, help="k3 tiles per H2-H4 chunk (0: library default)")
+    ap.add_argument("--group", type=int, default=0, help="i1 slabs per H1-H2/H4-H5 group (0: library default)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched workload")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
     ap.add_argument("--serve-count", type=int, default=2000)
@@ -255,7 +272,7 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    res = time_tier(torch, B, D, n, "f64", args.steps, args.warmup, args.chunk)
+    res = time_tier(torch, B, D, n, "f64", args.steps, args.warmup, args.chunk, args.group)
     ms = 1e3 * res["wall_s"] / args.steps
     value = args.steps / res["wall_s"]
     pb = pass_bytes(n, 8)
@@ -297,7 +314,7 @@ def main():
         out["roofline"]["traffic"] = tr["passes"][PASS_NAMES[dom]]["bytes"]
         out["roofline"]["traffic_source"] = os.path.relpath(TRAFFIC_FILE, HERE)
     if not args.no_f32:
-        r32 = time_tier(torch, B, D, n, "f32", args.steps, args.warmup, args.chunk)
+        r32 = time_tier(torch, B, D, n, "f32", args.steps, args.warmup, args.chunk, args.group)
         # FP32-tier error against the FP64 result of the same workload
         u64 = res["u"]
         err = float((r32["u"].double() - u64).abs().max() / u64.abs().max())

@@ -107,14 +107,16 @@ psp_status psp_plan_get_tables(psp_plan *p, double *J0, double *J2);
  * row-major (n+1)^3 doubles) to host memory.  Needs precompute; syncs. */
 psp_status psp_plan_get_multiplier(psp_plan *p, double *m_host);
 
-/* Tuning: the forward i2, fused i1 and inverse i2 passes run over the
- * half-spectrum axis k3 in chunks of `k3_tiles` tiles (8 k3 bins per tile
- * in FP64, 16 in FP32), so the padded intermediate is a chunk-sized buffer
- * instead of the whole n x 2n x (n+1) intermediate.  0 (the default) is
- * one chunk, the fastest; smaller chunks trade some speed for workspace
- * memory.  Frees the plan's workspaces; call it while no solve of this plan
- * is in flight.  Batched solves and graphs always use one chunk. */
-psp_status psp_plan_set_chunk(psp_plan *p, int k3_tiles);
+/* Tuning of single solves (batched solves and graphs use the defaults).
+ * k3_tiles > 0: the forward i2, fused i1 and inverse i2 passes run over the
+ *   half-spectrum axis k3 in chunks of k3_tiles tiles (8 bins per tile in
+ *   FP64, 16 in FP32), with a chunk-sized padded intermediate.
+ * i1_group > 0 (with one chunk): the forward i3 -> i2 and inverse i2 -> i3
+ *   passes run over groups of i1_group slabs, with a group-sized i3
+ *   intermediate that can stay in the last-level cache between the two.
+ * 0, 0 (the default) is one chunk and no grouping.  Frees the plan's
+ * workspaces; call it while no solve of this plan is in flight. */
+psp_status psp_plan_set_tuning(psp_plan *p, int k3_tiles, int i1_group);
 
 /* Bytes of device workspace one solve of this plan needs (per stream). */
 psp_status psp_plan_workspace_bytes(const psp_plan *p, size_t *bytes);

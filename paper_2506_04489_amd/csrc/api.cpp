@@ -91,11 +91,12 @@ psp_status check_create(int n, double h, int R, double eps, double delta) {
     return PSP_OK;
 }
 
-psp_status alloc_workspace(int n, bool f32, int chunk_tiles, Workspace *w) {
+psp_status alloc_workspace(int n, bool f32, int chunk_tiles, Workspace *w, int i1_group) {
     const size_t c = f32 ? 8 : 16, P = (size_t)pitch_for(n), PA = (size_t)chunk_pitch(n, f32, chunk_tiles);
-    w->bytes = workspace_bytes(n, f32, chunk_tiles);
+    const size_t xs = (size_t)x_slabs(n, f32, chunk_tiles, i1_group);
+    w->bytes = workspace_bytes(n, f32, chunk_tiles, i1_group);
     w->X = w->A = nullptr;
-    if (hipMalloc(&w->X, c * P * n * n) != hipSuccess) {
+    if (hipMalloc(&w->X, c * P * xs * n) != hipSuccess) {
         (void)hipGetLastError();
         w->X = nullptr;
         return fail(PSP_ENOMEM, "workspace allocation of %zu bytes failed", w->bytes);
@@ -123,7 +124,7 @@ psp_status plan_workspace(psp_plan *p, hipStream_t st, Workspace **out) {
         return PSP_OK;
     }
     Workspace w;
-    psp_status rs = alloc_workspace(p->n, p->dtype == PSP_F32, p->chunk_tiles, &w);
+    psp_status rs = alloc_workspace(p->n, p->dtype == PSP_F32, p->chunk_tiles, &w, p->i1_group);
     if (rs != PSP_OK) return rs;
     auto res = p->ws.emplace(st, w);
     *out = &res.first->second;
@@ -140,6 +141,7 @@ SolveArgs solve_args(const psp_plan *p, const Workspace &w, const void *rho, voi
     a.X = w.X;
     a.A = w.A;
     a.chunk_tiles = p->chunk_tiles;
+    a.i1_group = p->i1_group;
     a.mult = p->spec->mult;
     if (a.f32) {
         a.tw_hi = p->tw->hi32;
@@ -218,6 +220,7 @@ psp_status psp_plan_create(int n, double h, int R, psp_dtype dtype, psp_plan **o
 static void profile_clear(psp_plan *p) {
     for (auto e : p->prof_ev) (void)hipEventDestroy(e);
     p->prof_ev.clear();
+    p->prof_pass.clear();
     p->prof_cap = p->prof_used = 0;
 }
 
@@ -245,7 +248,7 @@ psp_status psp_plan_get_tables(psp_plan *p, double *J0, double *J2) {
 
 psp_status psp_plan_workspace_bytes(const psp_plan *p, size_t *bytes) {
     if (!p || !bytes) return fail(PSP_EINVAL, "NULL argument");
-    *bytes = workspace_bytes(p->n, p->dtype == PSP_F32, p->chunk_tiles);
+    *bytes = workspace_bytes(p->n, p->dtype == PSP_F32, p->chunk_tiles, p->i1_group);
     return PSP_OK;
 }
 
@@ -347,8 +350,10 @@ psp_status psp_solve(psp_plan *p, const void *rho_dev, void *u_dev, void *stream
     {
         std::lock_guard<std::mutex> lk(p->mu);
         if (p->prof_used < p->prof_cap) {
-            a.ev = &p->prof_ev[(size_t)p->prof_nev * p->prof_used++];
+            a.ev = &p->prof_ev[(size_t)p->prof_nev * p->prof_used];
+            a.ev_pass = &p->prof_pass[(size_t)p->prof_nev * p->prof_used];
             a.nev = p->prof_nev;
+            p->prof_used++;
         }
     }
     hipError_t e = launch_solve(a, (hipStream_t)stream);
@@ -360,8 +365,9 @@ psp_status psp_profile_enable(psp_plan *p, int max_solves) {
     if (!p || max_solves < 0 || max_solves > 100000) return fail(PSP_EINVAL, "bad profile arguments");
     std::lock_guard<std::mutex> lk(p->mu);
     profile_clear(p);
-    p->prof_nev = profile_events(p->n, p->dtype == PSP_F32, p->chunk_tiles);
+    p->prof_nev = solve_launches(p->n, p->dtype == PSP_F32, p->chunk_tiles, p->i1_group) + 1;
     p->prof_ev.resize((size_t)p->prof_nev * max_solves, nullptr);
+    p->prof_pass.assign((size_t)p->prof_nev * max_solves, -1);
     for (auto &e : p->prof_ev) {
         if (hipEventCreate(&e) != hipSuccess) {
             e = nullptr;
@@ -378,24 +384,19 @@ psp_status psp_profile_read(psp_plan *p, int *count, double *pass_ms) {
     std::lock_guard<std::mutex> lk(p->mu);
     for (int i = 0; i < 6; ++i) pass_ms[i] = 0.0;
     *count = p->prof_used;
-    const int nev = p->prof_nev, nch = (nev - 3) / 3;
-    auto el = [](hipEvent_t a, hipEvent_t b, double *acc) -> hipError_t {
-        float ms = 0;
-        hipError_t e = hipEventElapsedTime(&ms, a, b);
-        *acc += ms;
-        return e;
-    };
+    const int nev = p->prof_nev;
     for (int k = 0; k < p->prof_used; ++k) {
         hipEvent_t *ev = &p->prof_ev[(size_t)nev * k];
+        const int *pass = &p->prof_pass[(size_t)nev * k];
         PSP_HIP(hipEventSynchronize(ev[nev - 1]), "hipEventSynchronize");
-        PSP_HIP(el(ev[0], ev[1], &pass_ms[0]), "hipEventElapsedTime");
-        for (int c = 0; c < nch; ++c) {
-            PSP_HIP(el(ev[1 + 3 * c], ev[2 + 3 * c], &pass_ms[1]), "hipEventElapsedTime");
-            PSP_HIP(el(ev[2 + 3 * c], ev[3 + 3 * c], &pass_ms[2]), "hipEventElapsedTime");
-            PSP_HIP(el(ev[3 + 3 * c], ev[4 + 3 * c], &pass_ms[3]), "hipEventElapsedTime");
+        for (int i = 0; i + 1 < nev; ++i) {
+            float ms = 0;
+            PSP_HIP(hipEventElapsedTime(&ms, ev[i], ev[i + 1]), "hipEventElapsedTime");
+            if (pass[i] >= 0 && pass[i] < 5) pass_ms[pass[i]] += ms;
         }
-        PSP_HIP(el(ev[1 + 3 * nch], ev[2 + 3 * nch], &pass_ms[4]), "hipEventElapsedTime");
-        PSP_HIP(el(ev[0], ev[2 + 3 * nch], &pass_ms[5]), "hipEventElapsedTime");
+        float tot = 0;
+        PSP_HIP(hipEventElapsedTime(&tot, ev[0], ev[nev - 1]), "hipEventElapsedTime");
+        pass_ms[5] += tot;
     }
     if (p->prof_used > 0)
         for (int i = 0; i < 6; ++i) pass_ms[i] /= p->prof_used;
@@ -403,17 +404,17 @@ psp_status psp_profile_read(psp_plan *p, int *count, double *pass_ms) {
     return PSP_OK;
 }
 
-psp_status psp_plan_set_chunk(psp_plan *p, int k3_tiles) {
-    if (!p || k3_tiles < 0) return fail(PSP_EINVAL, "bad chunk arguments");
+psp_status psp_plan_set_tuning(psp_plan *p, int k3_tiles, int i1_group) {
+    if (!p || k3_tiles < 0 || i1_group < 0) return fail(PSP_EINVAL, "bad tuning arguments");
     std::lock_guard<std::mutex> lk(p->mu);
-    if (p->prof_cap > 0) return fail(PSP_ESTATE, "cannot change the chunking while profiling");
-    const int t = k3_tiles;
-    if (t != p->chunk_tiles) {
-        // existing workspaces were sized for the old chunk
+    if (p->prof_cap > 0) return fail(PSP_ESTATE, "cannot change the tuning while profiling");
+    if (k3_tiles != p->chunk_tiles || i1_group != p->i1_group) {
+        // existing workspaces were sized for the old layout
         if (!p->ws.empty()) (void)hipDeviceSynchronize();
         for (auto &kv : p->ws) free_workspace(&kv.second);
         p->ws.clear();
-        p->chunk_tiles = t;
+        p->chunk_tiles = k3_tiles;
+        p->i1_group = i1_group;
     }
     return PSP_OK;
 }

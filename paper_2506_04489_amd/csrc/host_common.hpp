@@ -55,12 +55,18 @@ inline int chunk_pitch(int n, bool f32, int chunk_tiles) {
     const int ct = chunk_tiles > 0 && chunk_tiles < ntile ? chunk_tiles : ntile;
     return ct * W;
 }
-inline size_t workspace_bytes(int n, bool f32, int chunk_tiles) {
+// i1 slabs the X buffer holds: one group when i1 grouping applies (one chunk)
+inline int x_slabs(int n, bool f32, int chunk_tiles, int i1_group) {
+    const int W = strided_width(f32), ntile = (n + 1 + W - 1) / W;
+    const bool one_chunk = chunk_tiles <= 0 || chunk_tiles >= ntile;
+    return (one_chunk && i1_group > 0 && i1_group < n) ? i1_group : n;
+}
+inline size_t workspace_bytes(int n, bool f32, int chunk_tiles, int i1_group = 0) {
     const size_t c = f32 ? 8 : 16;
     const size_t P = (size_t)pitch_for(n), PA = (size_t)chunk_pitch(n, f32, chunk_tiles);
-    return c * (P * (size_t)n * n + PA * (size_t)n * 2 * n);
+    return c * (P * (size_t)x_slabs(n, f32, chunk_tiles, i1_group) * n + PA * (size_t)n * 2 * n);
 }
-psp_status alloc_workspace(int n, bool f32, int chunk_tiles, Workspace *w);
+psp_status alloc_workspace(int n, bool f32, int chunk_tiles, Workspace *w, int i1_group = 0);
 void free_workspace(Workspace *w);
 inline size_t spectrum_bytes(int n) { return 8 * (size_t)(n + 1) * (n + 1) * pitch_for(n); }
 
@@ -81,8 +87,10 @@ struct psp_plan {
     std::mutex mu;
     std::map<hipStream_t, psp::Workspace> ws;   // one workspace per stream
     int chunk_tiles = 0;                        // H2-H4 chunking (0: one chunk)
-    // per-pass profiling: profile_events() events per recorded solve
+    int i1_group = 0;                           // H1-H2 / H4-H5 i1 grouping (0: none)
+    // per-pass profiling: prof_nev events (and launch-to-pass ids) per solve
     std::vector<hipEvent_t> prof_ev;
+    std::vector<int> prof_pass;
     int prof_cap = 0, prof_used = 0, prof_nev = 0;
 };
 

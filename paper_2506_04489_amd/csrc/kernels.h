@@ -26,12 +26,14 @@ struct SolveArgs {
     void *X = nullptr;   // n*n*P complex
     void *A = nullptr;   // chunk buffer: n*N*(chunk_tiles*W) complex
     int chunk_tiles = 0; // k3 tiles per H2-H4 chunk (0: all tiles in one chunk)
+    int i1_group = 0;    // i1 slabs per H1-H2 / H4-H5 group (0: all; X then holds one group)
     void *A2 = nullptr;  // N*N*P complex, full variant only
     void *Y2 = nullptr;  // N*N*P complex, full variant only
     const double *mult = nullptr;   // blocked multiplier octant
     const void *tw_hi = nullptr;    // twiddles: double2[N] (FP64) or float2[N] hi
     const void *tw_lo = nullptr;    // float2[N] lo (FP32 only)
-    hipEvent_t *ev = nullptr;       // optional profiling events (see solve_impl), nev of them
+    hipEvent_t *ev = nullptr;       // optional profiling events, one before each launch and one after
+    int *ev_pass = nullptr;         // host array: pass (0..4) of each launch, -1 for the last event
     int nev = 0;
 };
 
@@ -46,16 +48,12 @@ hipError_t launch_group(int n, bool f32, const Job *table_dev, int count, const 
 // k3 tile width of the strided passes (8 for FP64, 16 for FP32)
 int strided_width(bool f32);
 
-// number of H2-H4 chunks and profiling events of one solve
-inline int chunk_count(int n, bool f32, int chunk_tiles) {
-    const int W = strided_width(f32), ntile = (n + 1 + W - 1) / W;
-    const int ct = chunk_tiles > 0 && chunk_tiles < ntile ? chunk_tiles : ntile;
-    return (ntile + ct - 1) / ct;
-}
-inline int profile_events(int n, bool f32, int chunk_tiles) { return 3 * chunk_count(n, f32, chunk_tiles) + 3; }
-
+// the kernel-spectrum multiplier octant (FP64 MFMA contraction)
 hipError_t launch_spectrum(const double *J0, const double *J2, const double *omega, int R, int n, int P,
                            double scale, double *mult, hipStream_t st);
+
+// kernel launches of one solve (its profiling events are one more)
+int solve_launches(int n, bool f32, int chunk_tiles, int i1_group);
 
 // supported padded lengths
 inline bool supported_length(int N) {

@@ -84,11 +84,11 @@ struct JobRef {
 // A[k] = (Z[k] + conj Z[N-k])/2 and B[k] = (Z[k] - conj Z[N-k])/(2i).
 template <typename T, int N>
 __global__ void __launch_bounds__((LineCfg<T, N>::THREADS))
-k_z_r2c(JobRef jr, int P, Twiddle<T> tw) {
+k_z_r2c(JobRef jr, int npairs, int P, Twiddle<T> tw) {
     using C = cplx<T>;
     using Cfg = LineCfg<T, N>;
     using E = Engine<T, N, Cfg::TPC, false>;
-    constexpr int n = N / 2, npairs = n * n / 2;
+    constexpr int n = N / 2;
     __shared__ C lds[Cfg::Q * Cfg::LINE];
     const Job jb = jr.get();
     const int t = threadIdx.x % Cfg::TPC, q = threadIdx.x / Cfg::TPC;
@@ -260,13 +260,12 @@ k_y_inv(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
 // Y2 (N*N lines) and all N outputs.
 template <typename T, int N, bool FULL>
 __global__ void __launch_bounds__((LineCfg<T, N>::THREADS))
-k_z_c2r(JobRef jr, int P, Twiddle<T> tw) {
+k_z_c2r(JobRef jr, int npairs, int P, Twiddle<T> tw) {
     using C = cplx<T>;
     using Cfg = LineCfg<T, N>;
     using E = Engine<T, N, Cfg::TPC, true>;
     constexpr int n = N / 2;
     constexpr int len_out = FULL ? N : n;
-    constexpr int npairs = FULL ? N * N / 2 : n * n / 2;
     __shared__ C lds[Cfg::Q * Cfg::LINE];
     const Job jb = jr.get();
     const int t = threadIdx.x % Cfg::TPC, q = threadIdx.x / Cfg::TPC;
@@ -383,65 +382,128 @@ template <typename T, int N> static Twiddle<T> twiddle_of(const void *hi, const 
 }
 
 // the five passes for `count` solves of one padded length: a single solve
-// (table == nullptr, pointers in `one`) or a table of `count` jobs
+// (table == nullptr, pointers in `one`) or a table of `count` jobs.
+//   chunk_tiles > 0: H2-H4 over chunks of k3 tiles (A holds one chunk);
+//   i1_group > 0 (single solve, one chunk): H1->H2 and H4->H5 over groups of
+//   i1 slabs, X holding one group, so the i3 intermediate of a group is
+//   written and read back while it can still sit in the last-level cache.
+// Profiling: event i is recorded before launch i (and one after the last);
+// ev_pass[i] receives the pass (0..4) of launch i.
 template <typename T, int N>
-static hipError_t passes_impl(const Job &one, const Job *table, int count, int P, int chunk_tiles, bool full,
-                              const void *tw_hi, const void *tw_lo, hipEvent_t *ev, int nev, hipStream_t st) {
+static hipError_t passes_impl(const Job &one, const Job *table, int count, int P, int chunk_tiles, int i1_group,
+                              bool full, const void *tw_hi, const void *tw_lo, hipEvent_t *ev, int *ev_pass, int nev,
+                              hipStream_t st) {
     constexpr int n = N / 2;
     const Twiddle<T> tw = twiddle_of<T, N>(tw_hi, tw_lo);
-    const JobRef jr{one, table};
-    // profiling events: [0] before H1, per chunk c: [1+3c] before H2,
-    // [2+3c] before H3, [3+3c] before H4; [1+3C] before H5, [2+3C] after it
-    auto mark = [&](int i) {
-        if (ev && i < nev) (void)hipEventRecord(ev[i], st);
+    int launch = 0;
+    auto mark = [&](int pass) {
+        if (ev && launch < nev) {
+            (void)hipEventRecord(ev[launch], st);
+            if (ev_pass) ev_pass[launch] = pass;
+        }
+        ++launch;
     };
     using SC = StridedCfg<T, N>;
     using LC = LineCfg<T, N>;
     constexpr int W = SC::W;
     const int ntile = ceil_div(n + 1, W);
     const int y = count;
-    mark(0);
-    hipLaunchKernelGGL((k_z_r2c<T, N>), dim3(ceil_div(n * n / 2, LC::Q), y), dim3(LC::THREADS), 0, st, jr, P, tw);
-    if (!full) {
-        // H2 -> H3 -> H4 per chunk of k3 tiles; A holds one chunk
-        const int ct = chunk_tiles > 0 ? std::min(chunk_tiles, ntile) : ntile;
-        const int nchunks = ceil_div(ntile, ct);
-        for (int ch = 0; ch < nchunks; ++ch) {
-            const int t0 = ch * ct, nt = std::min(ct, ntile - t0);
-            const Chunk ck{t0, nt, ct * W};
-            mark(1 + 3 * ch);
-            hipLaunchKernelGGL((k_y_fwd<T, N>), dim3(n * nt, y), dim3(SC::THREADS), 0, st, jr, ck, P, tw);
-            mark(2 + 3 * ch);
-            hipLaunchKernelGGL((k_x_fused<T, N, false>), dim3(ceil_div((long)(n + 1) * nt, 8) * 16, y),
-                               dim3(SC::THREADS), 0, st, jr, ck, P, tw);
-            mark(3 + 3 * ch);
-            hipLaunchKernelGGL((k_y_inv<T, N, false>), dim3(n * nt, y), dim3(SC::THREADS), 0, st, jr, ck, P, tw);
-        }
-        mark(1 + 3 * nchunks);
-        hipLaunchKernelGGL((k_z_c2r<T, N, false>), dim3(ceil_div(n * n / 2, LC::Q), y), dim3(LC::THREADS), 0, st,
-                           jr, P, tw);
-        mark(2 + 3 * nchunks);
-    } else {
+    if (full) {
         // uncropped variant (one chunk): A2 and Y2 (N x N x P, row layout)
         // receive all N outputs of the inverse transforms
+        const JobRef jr{one, table};
         const Chunk ck{0, ntile, ntile * W};
+        hipLaunchKernelGGL((k_z_r2c<T, N>), dim3(ceil_div(n * n / 2, LC::Q), y), dim3(LC::THREADS), 0, st, jr,
+                           n * n / 2, P, tw);
         hipLaunchKernelGGL((k_y_fwd<T, N>), dim3(n * ntile, y), dim3(SC::THREADS), 0, st, jr, ck, P, tw);
         hipLaunchKernelGGL((k_x_fused<T, N, true>), dim3(ceil_div((long)(n + 1) * ntile, 8) * 16, y),
                            dim3(SC::THREADS), 0, st, jr, ck, P, tw);
         hipLaunchKernelGGL((k_y_inv<T, N, true>), dim3(N * ntile, y), dim3(SC::THREADS), 0, st, jr, ck, P, tw);
         hipLaunchKernelGGL((k_z_c2r<T, N, true>), dim3(ceil_div(N * N / 2, LC::Q), y), dim3(LC::THREADS), 0, st,
-                           jr, P, tw);
+                           jr, N * N / 2, P, tw);
+        return hipGetLastError();
     }
+    const int ct = chunk_tiles > 0 ? std::min(chunk_tiles, ntile) : ntile;
+    const int nchunks = ceil_div(ntile, ct);
+    const int G = (table == nullptr && nchunks == 1 && i1_group > 0 && i1_group < n) ? i1_group : n;
+    const int PA = ct * W;
+    // H1 (+ H2 when grouped) per i1 group
+    for (int g0 = 0; g0 < n; g0 += G) {
+        const int gs = std::min(G, n - g0);
+        Job j = one;
+        if (!table) {
+            j.rho = (const T *)one.rho + (size_t)g0 * n * n;
+            j.A = (cplx<T> *)one.A + (size_t)g0 * N * PA;
+        }
+        const JobRef jr{j, table};
+        mark(0);
+        hipLaunchKernelGGL((k_z_r2c<T, N>), dim3(ceil_div(gs * n / 2, LC::Q), y), dim3(LC::THREADS), 0, st, jr,
+                           gs * n / 2, P, tw);
+        if (G < n) {
+            const Chunk ck{0, ntile, PA};
+            mark(1);
+            hipLaunchKernelGGL((k_y_fwd<T, N>), dim3(gs * ntile, y), dim3(SC::THREADS), 0, st, jr, ck, P, tw);
+        }
+    }
+    const JobRef jr{one, table};
+    for (int ch = 0; ch < nchunks; ++ch) {
+        const int t0 = ch * ct, nt = std::min(ct, ntile - t0);
+        const Chunk ck{t0, nt, PA};
+        if (G == n) {
+            mark(1);
+            hipLaunchKernelGGL((k_y_fwd<T, N>), dim3(n * nt, y), dim3(SC::THREADS), 0, st, jr, ck, P, tw);
+        }
+        mark(2);
+        hipLaunchKernelGGL((k_x_fused<T, N, false>), dim3(ceil_div((long)(n + 1) * nt, 8) * 16, y),
+                           dim3(SC::THREADS), 0, st, jr, ck, P, tw);
+        if (G == n) {
+            mark(3);
+            hipLaunchKernelGGL((k_y_inv<T, N, false>), dim3(n * nt, y), dim3(SC::THREADS), 0, st, jr, ck, P, tw);
+        }
+    }
+    // (H4 +) H5 per i1 group
+    for (int g0 = 0; g0 < n; g0 += G) {
+        const int gs = std::min(G, n - g0);
+        Job j = one;
+        if (!table) {
+            j.u = (T *)one.u + (size_t)g0 * n * n;
+            j.A = (cplx<T> *)one.A + (size_t)g0 * N * PA;
+        }
+        const JobRef jrg{j, table};
+        if (G < n) {
+            const Chunk ck{0, ntile, PA};
+            mark(3);
+            hipLaunchKernelGGL((k_y_inv<T, N, false>), dim3(gs * ntile, y), dim3(SC::THREADS), 0, st, jrg, ck, P,
+                               tw);
+        }
+        mark(4);
+        hipLaunchKernelGGL((k_z_c2r<T, N, false>), dim3(ceil_div(gs * n / 2, LC::Q), y), dim3(LC::THREADS), 0, st,
+                           jrg, gs * n / 2, P, tw);
+    }
+    mark(-1);
     return hipGetLastError();
+}
+
+// launches (and so profiling events minus one) of one solve
+int solve_launches(int n, bool f32, int chunk_tiles, int i1_group) {
+    const int W = f32 ? StridedCols<float>::W : StridedCols<double>::W;
+    const int ntile = ceil_div(n + 1, W);
+    const int ct = chunk_tiles > 0 ? std::min(chunk_tiles, ntile) : ntile;
+    const int nchunks = ceil_div(ntile, ct);
+    const bool grouped = nchunks == 1 && i1_group > 0 && i1_group < n;
+    if (grouped) return 4 * ceil_div(n, i1_group) + 1;
+    return 2 + 3 * nchunks;
 }
 
 template <typename T>
 static hipError_t passes_dispatch(int N, const Job &one, const Job *table, int count, int P, int chunk_tiles,
-                                  bool full, const void *tw_hi, const void *tw_lo, hipEvent_t *ev, int nev,
-                                  hipStream_t st) {
+                                  int i1_group, bool full, const void *tw_hi, const void *tw_lo, hipEvent_t *ev,
+                                  int *ev_pass, int nev, hipStream_t st) {
     switch (N) {
-#define PSP_CASE(NN) \
-    case NN: return passes_impl<T, NN>(one, table, count, P, chunk_tiles, full, tw_hi, tw_lo, ev, nev, st);
+#define PSP_CASE(NN)                                                                                          \
+    case NN:                                                                                                  \
+        return passes_impl<T, NN>(one, table, count, P, chunk_tiles, i1_group, full, tw_hi, tw_lo, ev, ev_pass, \
+                                  nev, st);
         PSP_CASE(8) PSP_CASE(12) PSP_CASE(16) PSP_CASE(24) PSP_CASE(32) PSP_CASE(48) PSP_CASE(64)
         PSP_CASE(96) PSP_CASE(128) PSP_CASE(192) PSP_CASE(256) PSP_CASE(384) PSP_CASE(512) PSP_CASE(768)
 #undef PSP_CASE
@@ -451,18 +513,20 @@ static hipError_t passes_dispatch(int N, const Job &one, const Job *table, int c
 
 hipError_t launch_solve(const SolveArgs &s, hipStream_t st) {
     const Job one{s.rho, s.u, s.X, s.A, s.mult, s.A2, s.Y2};
-    return s.f32 ? passes_dispatch<float>(2 * s.n, one, nullptr, 1, s.P, s.chunk_tiles, s.full, s.tw_hi, s.tw_lo,
-                                          s.ev, s.nev, st)
-                 : passes_dispatch<double>(2 * s.n, one, nullptr, 1, s.P, s.chunk_tiles, s.full, s.tw_hi,
-                                           s.tw_lo, s.ev, s.nev, st);
+    return s.f32 ? passes_dispatch<float>(2 * s.n, one, nullptr, 1, s.P, s.chunk_tiles, s.i1_group, s.full, s.tw_hi,
+                                          s.tw_lo, s.ev, s.ev_pass, s.nev, st)
+                 : passes_dispatch<double>(2 * s.n, one, nullptr, 1, s.P, s.chunk_tiles, s.i1_group, s.full,
+                                           s.tw_hi, s.tw_lo, s.ev, s.ev_pass, s.nev, st);
 }
 
 hipError_t launch_group(int n, bool f32, const Job *table_dev, int count, const void *tw_hi, const void *tw_lo,
                         hipStream_t st) {
     const Job none{};
     const int P = ((n + 1 + 15) / 16) * 16;
-    return f32 ? passes_dispatch<float>(2 * n, none, table_dev, count, P, 0, false, tw_hi, tw_lo, nullptr, 0, st)
-               : passes_dispatch<double>(2 * n, none, table_dev, count, P, 0, false, tw_hi, tw_lo, nullptr, 0, st);
+    return f32 ? passes_dispatch<float>(2 * n, none, table_dev, count, P, 0, 0, false, tw_hi, tw_lo, nullptr, nullptr,
+                                        0, st)
+               : passes_dispatch<double>(2 * n, none, table_dev, count, P, 0, 0, false, tw_hi, tw_lo, nullptr, nullptr,
+                                         0, st);
 }
 
 hipError_t launch_spectrum(const double *J0, const double *J2, const double *omega, int R, int n, int P,

@@ -36,7 +36,7 @@ SIGNATURES = {
     "psp_plan_spectrum_bytes": (_i, [_vp, _P(_sz)]),
     "psp_plan_destroy": (None, [_vp]),
     "psp_profile_enable": (_i, [_vp, _i]),
-    "psp_plan_set_chunk": (_i, [_vp, _i]),
+    "psp_plan_set_tuning": (_i, [_vp, _i, _i]),
     "psp_profile_read": (_i, [_vp, _P(_i), _P(_d)]),
     "psp_graph_capture": (_i, [_vp, _vp, _vp, _vp, _P(_vp)]),
     "psp_graph_capture_batched": (_i, [_i, _P(_vp), _P(_vp), _P(_vp), _vp, _P(_vp)]),
@@ -189,8 +189,8 @@ class Plan:
         _check(lib().psp_plan_get_multiplier(self._h, m.ctypes.data_as(_P(_d))))
         return m
 
-    def set_chunk(self, k3_tiles: int):
-        _check(lib().psp_plan_set_chunk(self._h, int(k3_tiles)))
+    def set_tuning(self, k3_tiles: int = 0, i1_group: int = 0):
+        _check(lib().psp_plan_set_tuning(self._h, int(k3_tiles), int(i1_group)))
         return self
 
     def profile_enable(self, max_solves: int):

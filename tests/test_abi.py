@@ -91,7 +91,7 @@ def test_workspace_and_spectrum_sizes():
     assert p.spectrum_bytes() == 8 * 257 * 257 * P
     q = B.Plan(256, 2 / 256, 40, dtype="f32")
     assert q.workspace_bytes() == 8 * (P * 256 * 256 + 272 * 256 * 512)
-    p.set_chunk(4)
+    p.set_tuning(4, 0)
     assert p.workspace_bytes() == 16 * (P * 256 * 256 + 32 * 256 * 512)
 
 

@@ -182,10 +182,30 @@ def test_chunked_strided_passes_bitwise(n, dtype):
     p = B.Plan(n, h, 40, dtype=dtype).precompute()
     ref = None
     for tiles in (1000, 1, 2, 3):
-        p.set_chunk(tiles)
+        p.set_tuning(tiles, 0)
         u = p.solve(rho)
         torch.cuda.synchronize()
         if ref is None:
             ref = u.clone()
         else:
             assert torch.equal(u, ref), tiles
+
+
+@pytest.mark.parametrize("n,dtype", [(24, "f64"), (48, "f64"), (64, "f32"), (96, "f64")])
+def test_i1_grouped_passes_bitwise(n, dtype):
+    # grouping the i3/i2 passes over i1 slabs changes no arithmetic: every
+    # group size (ragged last group included) gives the same bits
+    import torch
+    h = 2.0 / n
+    rng = np.random.default_rng(500 + n)
+    td = torch.float64 if dtype == "f64" else torch.float32
+    rho = to_dev(rng.standard_normal((n, n, n)), td)
+    p = B.Plan(n, h, 40, dtype=dtype).precompute()
+    ref = p.solve(rho).clone()
+    torch.cuda.synchronize()
+    for group in (1, 5, n // 2, n - 2):
+        p.set_tuning(0, group)
+        u = p.solve(rho)
+        torch.cuda.synchronize()
+        assert torch.equal(u, ref), group
+    p.set_tuning(0, 0)
