@@ -23,15 +23,20 @@ sys.path.insert(0, HERE)
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, published
 COPY_CAL_BYTES = 1 << 30   # plain device copy used to calibrate the byte counters
 TRAFFIC_FILE = os.path.join(HERE, "profiles", "traffic_passes_n256.txt")
-KERNEL_SOURCES = ["paper_2506_04489_amd/csrc/fft_core.hpp", "paper_2506_04489_amd/csrc/passes.hip"]
+# what decides the pass kernels of a solve: their sources and the shipped
+# launch-shape table
+KERNEL_SOURCES = ["paper_2506_04489_amd/csrc/fft_core.hpp", "paper_2506_04489_amd/csrc/passes.hpp",
+                  "paper_2506_04489_amd/tuning_gfx950.json"]
 
 
 def kernel_source_hash() -> str:
     import hashlib
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(HERE, rel), "rb") as f:
-            h.update(f.read())
+        path = os.path.join(HERE, rel)
+        if os.path.exists(path):
+            with open(path, "rb") as f:
+                h.update(f.read())
     return h.hexdigest()
 
 

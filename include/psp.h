@@ -118,6 +118,45 @@ psp_status psp_plan_get_multiplier(psp_plan *p, double *m_host);
  * workspaces; call it while no solve of this plan is in flight. */
 psp_status psp_plan_set_tuning(psp_plan *p, int k3_tiles, int i1_group);
 
+/* Launch shape of the five passes H1..H5 (index 0..4), the autotuner's search
+ * space, as two int[5] arrays:
+ *   plan[i]: radix plan of pass i: 0 the default factorisation of 2n, 1 the
+ *            alternative for 2n in {128, 256, 512, 768} (other lengths have
+ *            only 0);
+ *   tile[i]: passes 0 and 4 (transforms along i3): workgroup size, 0: 256
+ *            threads, 1: 128, 2: 512; passes 1..3 (along i2, i1, i2): 0: one
+ *            128-byte row of k3 columns per workgroup (8 FP64 or 16 FP32
+ *            columns), 1: half of one, 2: one row with the exchanges between
+ *            FFT stages through half-size LDS buffers.
+ * A tile choice changes only which workgroup transforms which column and how
+ * values move between stages: the results are bitwise the same.  A radix plan changes the rounding, not the
+ * accuracy class.  Batched solves and graphs group their members by (n,
+ * shape).  Set: PSP_EINVAL for a value out of range; call it while no solve
+ * of this plan is in flight.  Get: copies the plan's current shape. */
+psp_status psp_plan_set_shape(psp_plan *p, const int *plan, const int *tile);
+psp_status psp_plan_get_shape(const psp_plan *p, int *plan, int *tile);
+
+/* The process-wide tuning table: the shape that plans of (n, dtype) created
+ * afterwards start with (and the serving loop's plans use).  Unset entries
+ * give the default shape (all zeros).  psp_tuning_get reports it. */
+psp_status psp_tuning_set(int n, psp_dtype dtype, const int *plan, const int *tile);
+psp_status psp_tuning_get(int n, psp_dtype dtype, int *plan, int *tile);
+
+/* Autotuner: times every (radix plan, tile) candidate of every pass on this
+ * plan's own workspace on `stream` (synthetic zero input, `reps` timed
+ * solves per candidate round after one warm-up, minimum over repetitions,
+ * HIP events around each launch), picks per pass the fastest candidate (the
+ * default unless another is at least 1% faster), sets it as the plan's shape
+ * and enters it in the tuning table.  Outputs (host arrays, each may be
+ * NULL): best_plan[5], best_tile[5], best_ms[5] the chosen candidate and
+ * that pass's time in ms; cand_ms[5 * 6]: the time of candidate
+ * (plan, tile) of pass i at cand_ms[i * 6 + plan * 3 + tile], -1 where the
+ * candidate does not exist.  Allocates two n^3
+ * buffers for the duration; synchronises `stream`.  PSP_ESTATE before
+ * precompute or while profiling; PSP_EINVAL for reps outside [1, 1000]. */
+psp_status psp_autotune(psp_plan *p, int reps, void *stream, int *best_plan, int *best_tile,
+                        float *best_ms, float *cand_ms);
+
 /* Bytes of device workspace one solve of this plan needs (per stream). */
 psp_status psp_plan_workspace_bytes(const psp_plan *p, size_t *bytes);
 

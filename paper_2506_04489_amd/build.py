@@ -19,7 +19,7 @@ OUT = os.path.join(HERE, "libpsp.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 ARCH = "gfx950"
 
-SOURCES = ["passes.hip", "batched.hip", "setup.cpp", "api.cpp", "serve.cpp", "graph.cpp"]
+SOURCES = ["passes_f64.hip", "passes_f32.hip", "spectrum.hip", "batched.hip", "setup.cpp", "api.cpp", "serve.cpp", "graph.cpp", "tuning.cpp"]
 
 COMMON = [
     "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
@@ -39,9 +39,15 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
+# the FFT passes round every instantiation the same way: no automatic
+# contraction of a*b+c, the kernels write their fused multiply-adds out
+NO_CONTRACT = {"passes_f64.hip", "passes_f32.hip"}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
-    cmd = [hipcc()] + HIP_FLAGS + COMMON + ["-c", os.path.join(CSRC, src), "-o", obj]
+    extra = ["-ffp-contract=off"] if src in NO_CONTRACT else []
+    cmd = [hipcc()] + HIP_FLAGS + COMMON + extra + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("compile failed: %s\n%s\n%s" % (" ".join(cmd), r.stdout, r.stderr))

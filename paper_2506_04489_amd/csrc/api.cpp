@@ -142,6 +142,7 @@ SolveArgs solve_args(const psp_plan *p, const Workspace &w, const void *rho, voi
     a.A = w.A;
     a.chunk_tiles = p->chunk_tiles;
     a.i1_group = p->i1_group;
+    a.shape = p->shape;
     a.mult = p->spec->mult;
     if (a.f32) {
         a.tw_hi = p->tw->hi32;
@@ -205,6 +206,7 @@ psp_status psp_plan_create_ex(int n, double h, int R, psp_dtype dtype, double ep
     p->eps = eps;
     p->delta = delta;
     p->chunk_tiles = 0;   // one chunk: fastest for a single solve
+    p->shape = tuned_shape(n, dtype == PSP_F32);
     gs_fit(R, eps, delta, p->omega, p->alpha);
     *out = p;
     return PSP_OK;

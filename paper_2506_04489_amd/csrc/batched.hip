@@ -1,7 +1,8 @@
 // batched.hip - many independent solves on one stream, grouped by padded
-// length: one launch per pass per distinct n.  Each solve has its own
-// workspace (one chunk of all k3 tiles) and its pointers in a device job
-// table that the pass kernels index with blockIdx.y; the table is staged
+// length and launch shape: one launch per pass per distinct (n, shape).
+// Each solve has its own workspace (one chunk of all k3 tiles) and its
+// pointers in a device job table that the pass kernels index with
+// blockIdx.y; the table is staged
 // through pinned host memory.  Every solve runs the same kernels on the same
 // data as a single psp_solve, so the results are bitwise equal.
 #include <algorithm>
@@ -64,12 +65,16 @@ static psp_status stage_table(Staging &S, const std::vector<Job> &jobs, hipStrea
 }
 
 // launch the grouped passes for jobs already holding workspaces
-static psp_status launch_jobs(StreamBatch &B, const std::vector<Job> &jobs, const std::vector<int> &ns, bool f32,
-                              const std::vector<const Twiddles *> &tws, hipStream_t st) {
-    // order by n so that each group is a contiguous slice of the table
+static psp_status launch_jobs(StreamBatch &B, const std::vector<Job> &jobs, const std::vector<int> &ns,
+                              const std::vector<Shape> &shapes, bool f32, const std::vector<const Twiddles *> &tws,
+                              hipStream_t st) {
+    // order by (n, shape) so that each group is a contiguous slice of the table
     std::vector<int> order(jobs.size());
     for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return ns[a] < ns[b]; });
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        if (ns[a] != ns[b]) return ns[a] < ns[b];
+        return shapes[a] < shapes[b];
+    });
     std::vector<Job> sorted(jobs.size());
     for (size_t i = 0; i < order.size(); ++i) sorted[i] = jobs[order[i]];
     Job *d = nullptr;
@@ -78,10 +83,10 @@ static psp_status launch_jobs(StreamBatch &B, const std::vector<Job> &jobs, cons
     size_t i = 0;
     while (i < order.size()) {
         size_t j = i;
-        while (j < order.size() && ns[order[j]] == ns[order[i]]) ++j;
+        while (j < order.size() && ns[order[j]] == ns[order[i]] && shapes[order[j]] == shapes[order[i]]) ++j;
         const Twiddles *tw = tws[order[i]];
-        hipError_t e = launch_group(ns[order[i]], f32, d + i, (int)(j - i), f32 ? tw->hi32 : tw->w64,
-                                    f32 ? tw->lo32 : nullptr, st);
+        hipError_t e = launch_group(ns[order[i]], f32, shapes[order[i]], d + i, (int)(j - i),
+                                    f32 ? tw->hi32 : tw->w64, f32 ? tw->lo32 : nullptr, st);
         if (e != hipSuccess) return hip_fail(e, "batched pass launch");
         i = j;
     }
@@ -117,15 +122,17 @@ hipError_t launch_batch(int count, const SolveArgs *args, hipStream_t st) {
     (void)hipGetDevice(&dev);
     std::vector<Job> jobs(count);
     std::vector<int> ns(count);
+    std::vector<Shape> shapes(count);
     std::vector<const Twiddles *> tws(count);
     for (int i = 0; i < count; ++i) {
         const SolveArgs &a = args[i];
         jobs[i] = Job{a.rho, a.u, a.X, a.A, a.mult, nullptr, nullptr};
         ns[i] = a.n;
+        shapes[i] = a.shape;
         if (get_twiddles(dev, 2 * a.n, &tws[i]) != PSP_OK) return hipErrorOutOfMemory;
     }
     std::lock_guard<std::mutex> lk(g_batch_mu);
-    psp_status rs = launch_jobs(g_batch[{dev, st}], jobs, ns, args[0].f32, tws, st);
+    psp_status rs = launch_jobs(g_batch[{dev, st}], jobs, ns, shapes, args[0].f32, tws, st);
     return rs == PSP_OK ? hipSuccess : hipErrorLaunchFailure;
 }
 
@@ -158,10 +165,12 @@ extern "C" psp_status psp_solve_batched(int count, psp_plan *const *plans, const
     psp_status rs = batch_workspaces(B, ns, f32, ws);
     if (rs != PSP_OK) return rs;
     std::vector<Job> jobs(count);
+    std::vector<Shape> shapes(count);
     std::vector<const Twiddles *> tws(count);
     for (int i = 0; i < count; ++i) {
         jobs[i] = Job{rho_dev[i], u_dev[i], ws[i]->X, ws[i]->A, plans[i]->spec->mult, nullptr, nullptr};
+        shapes[i] = plans[i]->shape;
         tws[i] = plans[i]->tw;
     }
-    return launch_jobs(B, jobs, ns, f32, tws, st);
+    return launch_jobs(B, jobs, ns, shapes, f32, tws, st);
 }

@@ -33,6 +33,12 @@ template <bool INV, typename C> __device__ __forceinline__ C c_mul_mi(C a) {
 }
 template <typename C> __device__ __forceinline__ C c_zero() { return C{0, 0}; }
 
+// Fused multiply-add written out.  The pass kernels are compiled without
+// automatic contraction, so every instantiation (radix plan, tile shape,
+// batched or single) rounds the same expression the same way.
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
 // --------------------------------------------------------------- twiddles
 // Table of W_N^m = exp(-2 pi i m / N), m < N.  FP64: one table.  FP32: the
 // value split into hi = fl32(w) and lo = fl32(w - hi), so the product a*w is
@@ -42,7 +48,7 @@ template <> struct Twiddle<double> {
     const double2 *w;
     template <bool INV> __device__ __forceinline__ static double2 cmul(double2 a, double2 t) {
         const double ty = INV ? -t.y : t.y;
-        return double2{a.x * t.x - a.y * ty, a.x * ty + a.y * t.x};
+        return double2{fmadd(a.x, t.x, -(a.y * ty)), fmadd(a.x, ty, a.y * t.x)};
     }
     template <bool INV> __device__ __forceinline__ double2 mul(double2 a, int m) const { return cmul<INV>(a, w[m]); }
     // v[r] *= W^{m r}, r = 1..R-1, from the single table entry W^m: powers
@@ -83,11 +89,10 @@ template <> struct Twiddle<float> {
         float2 h = hi[m], l = lo[m];
         float hy = INV ? -h.y : h.y;
         float ly = INV ? -l.y : l.y;
-        float rx = a.x * l.x - a.y * ly;
-        float ry = a.x * ly + a.y * l.x;
-        rx += a.x * h.x - a.y * hy;
-        ry += a.x * hy + a.y * h.x;
-        return float2{rx, ry};
+        // the small lo products first, then the hi products on top
+        const float rx = fmadd(-a.y, ly, a.x * l.x);
+        const float ry = fmadd(a.y, l.x, a.x * ly);
+        return float2{fmadd(a.x, h.x, fmadd(-a.y, hy, rx)), fmadd(a.x, hy, fmadd(a.y, h.x, ry))};
     }
     // v[r] *= W^{m r}: every power from the split table (an FP32 product
     // of split twiddles would lose their extra precision)
@@ -115,7 +120,7 @@ template <bool INV, typename C> struct DFT<3, INV, C> {
         const T s3 = T(0.86602540378443864676372317075293618);  // sqrt(3)/2
         C s = c_add(v[1], v[2]);
         C d = c_sub(v[1], v[2]);
-        C m = C{v[0].x - half * s.x, v[0].y - half * s.y};
+        C m = C{fmadd(-half, s.x, v[0].x), fmadd(-half, s.y, v[0].y)};
         // forward: X1 = m - i s3 d, X2 = m + i s3 d
         C t = c_mul_mi<INV>(C{s3 * d.x, s3 * d.y});
         v[0] = c_add(v[0], s);
@@ -166,33 +171,40 @@ template <bool INV, typename C> struct DFT<8, INV, C> {
 };
 
 // ------------------------------------------------------------ radix plans
-// Forward radix sequence per padded length.  The first radix is even so that
+// Forward radix sequence per padded length; variant PV = 0 is the default,
+// PV = 1 an alternative ordering or factorisation that the autotuner may pick
+// (lengths without one repeat the default).  The first radix is even so that
 // the zero-padded half of an input (and, in reverse, the cropped half of an
 // output) falls on whole butterfly legs.
-template <int N> struct Plan;
-#define PSP_PLAN(NN, ...)                                                    \
-    template <> struct Plan<NN> {                                           \
+template <int N, int PV> struct Plan;
+#define PSP_PLAN(NN, PVV, ...)                                               \
+    template <> struct Plan<NN, PVV> {                                      \
         static constexpr int r[] = {__VA_ARGS__};                           \
         static constexpr int S = sizeof(r) / sizeof(int);                   \
     };
-PSP_PLAN(8, 8)
-PSP_PLAN(12, 4, 3)
-PSP_PLAN(16, 4, 4)
-PSP_PLAN(24, 8, 3)
-PSP_PLAN(32, 8, 4)
-PSP_PLAN(48, 4, 4, 3)
-PSP_PLAN(64, 8, 8)
-PSP_PLAN(96, 8, 4, 3)
-PSP_PLAN(128, 8, 4, 4)
-PSP_PLAN(192, 8, 8, 3)
-PSP_PLAN(256, 8, 8, 4)
-PSP_PLAN(384, 8, 4, 4, 3)
-PSP_PLAN(512, 8, 8, 8)
-PSP_PLAN(768, 8, 8, 4, 3)
+PSP_PLAN(8, 0, 8)
+PSP_PLAN(12, 0, 4, 3)
+PSP_PLAN(16, 0, 4, 4)
+PSP_PLAN(24, 0, 8, 3)
+PSP_PLAN(32, 0, 8, 4)
+PSP_PLAN(48, 0, 4, 4, 3)
+PSP_PLAN(64, 0, 8, 8)
+PSP_PLAN(96, 0, 8, 4, 3)
+PSP_PLAN(128, 0, 8, 4, 4)
+PSP_PLAN(192, 0, 8, 8, 3)
+PSP_PLAN(256, 0, 8, 8, 4)
+PSP_PLAN(384, 0, 8, 4, 4, 3)
+PSP_PLAN(512, 0, 8, 8, 8)
+PSP_PLAN(768, 0, 8, 8, 4, 3)
+// alternatives
+PSP_PLAN(128, 1, 4, 8, 4)
+PSP_PLAN(256, 1, 4, 8, 8)
+PSP_PLAN(512, 1, 8, 4, 4, 4)
+PSP_PLAN(768, 1, 8, 4, 8, 3)
 #undef PSP_PLAN
 
-template <int N, bool INV> struct Seq {
-    using P = Plan<N>;
+template <int N, bool INV, int PV> struct Seq {
+    using P = Plan<N, PV>;
     static constexpr int S = P::S;
     __host__ __device__ static constexpr int radix(int s) { return INV ? P::r[S - 1 - s] : P::r[s]; }
     __host__ __device__ static constexpr int ns(int s) {  // product of the radices before s
@@ -202,12 +214,11 @@ template <int N, bool INV> struct Seq {
     }
 };
 
-// threads per column: one radix-8 (or the largest radix) butterfly each per
-// stage, divided by F
-template <int N> struct MaxRadix {
+// threads per column: one butterfly of the largest radix each per stage
+template <int N, int PV = 0> struct MaxRadix {
     static constexpr int value() {
         int m = 0;
-        for (int i = 0; i < Plan<N>::S; ++i) m = Plan<N>::r[i] > m ? Plan<N>::r[i] : m;
+        for (int i = 0; i < Plan<N, PV>::S; ++i) m = Plan<N, PV>::r[i] > m ? Plan<N, PV>::r[i] : m;
         return m;
     }
 };
@@ -216,9 +227,9 @@ template <int N> struct MaxRadix {
 // Column transform engine.  TPC threads per column; thread t owns butterflies
 // j = t + b*TPC (b < BPT(s)) of every stage.  LdsIdx maps (position, column)
 // to an LDS element offset.
-template <typename T, int N, int TPC, bool INV> struct Engine {
+template <typename T, int N, int TPC, bool INV, int PV = 0> struct Engine {
     using C = cplx<T>;
-    using Q = Seq<N, INV>;
+    using Q = Seq<N, INV, PV>;
     static constexpr int S = Q::S;
     __host__ __device__ static constexpr int R(int s) { return Q::radix(s); }
     __host__ __device__ static constexpr int NS(int s) { return Q::ns(s); }

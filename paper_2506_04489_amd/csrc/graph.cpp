@@ -99,10 +99,13 @@ psp_status psp_graph_capture_batched(int count, psp_plan *const *plans, const vo
     psp_graph *g = new (std::nothrow) psp_graph;
     if (!g) return fail(PSP_ENOMEM, "host allocation failed");
     g->device = plans[0]->device;
-    // group by n: the table is sorted by n, each group a contiguous slice
+    // group by (n, shape): the table is sorted, each group a contiguous slice
     std::vector<int> order(count);
     for (int i = 0; i < count; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return plans[a]->n < plans[b]->n; });
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        if (plans[a]->n != plans[b]->n) return plans[a]->n < plans[b]->n;
+        return plans[a]->shape < plans[b]->shape;
+    });
     g->ws.resize(count);
     std::vector<Job> jobs(count);
     for (int k = 0; k < count; ++k) {
@@ -125,10 +128,10 @@ psp_status psp_graph_capture_batched(int count, psp_plan *const *plans, const vo
         int k = 0;
         while (k < count) {
             int j = k;
-            const int n = plans[order[k]]->n;
-            while (j < count && plans[order[j]]->n == n) ++j;
-            const Twiddles *tw = plans[order[k]]->tw;
-            hipError_t e = launch_group(n, f32, g->table + k, j - k, f32 ? tw->hi32 : tw->w64,
+            const psp_plan *p0 = plans[order[k]];
+            while (j < count && plans[order[j]]->n == p0->n && plans[order[j]]->shape == p0->shape) ++j;
+            const Twiddles *tw = p0->tw;
+            hipError_t e = launch_group(p0->n, f32, p0->shape, g->table + k, j - k, f32 ? tw->hi32 : tw->w64,
                                         f32 ? tw->lo32 : nullptr, cs);
             if (e != hipSuccess) return e;
             k = j;

@@ -88,6 +88,7 @@ struct psp_plan {
     std::map<hipStream_t, psp::Workspace> ws;   // one workspace per stream
     int chunk_tiles = 0;                        // H2-H4 chunking (0: one chunk)
     int i1_group = 0;                           // H1-H2 / H4-H5 i1 grouping (0: none)
+    psp::Shape shape;                           // launch shape of the passes
     // per-pass profiling: prof_nev events (and launch-to-pass ids) per solve
     std::vector<hipEvent_t> prof_ev;
     std::vector<int> prof_pass;
@@ -96,6 +97,8 @@ struct psp_plan {
 
 namespace psp {
 psp_status check_create(int n, double h, int R, double eps, double delta);
+// the process-wide tuned launch shape for (n, tier); the default shape if none
+Shape tuned_shape(int n, bool f32);
 psp_status plan_workspace(psp_plan *p, hipStream_t st, Workspace **out);
 SolveArgs solve_args(const psp_plan *p, const Workspace &w, const void *rho, void *u);
 }  // namespace psp

@@ -15,6 +15,45 @@ struct Job {
     void *Y2 = nullptr;          // uncropped variant only
 };
 
+// Launch shape of the five passes H1..H5 (index p = 0..4): the autotuner's
+// search space.
+//   plan[p]: radix plan of the pass (0: default, 1: the alternative where the
+//            padded length has one; a different rounding, same accuracy class)
+//   tile[p]: H1/H5 (p = 0, 4): workgroup size, 0: 256 threads, 1: 128, 2: 512;
+//            H2-H4 (p = 1..3): 0: one 128-byte row tile of k3 columns per
+//            workgroup (8 FP64 / 16 FP32 columns), 1: half of one, 2: one
+//            tile with exchanges through half-size LDS buffers
+// A tile choice only changes which workgroup transforms which column and how
+// values move between stages, so results are bitwise the same under every
+// tile choice.
+constexpr int kPasses = 5;
+constexpr int kTileChoices[kPasses] = {3, 3, 3, 3, 3};
+struct Shape {
+    int plan[kPasses] = {0, 0, 0, 0, 0};
+    int tile[kPasses] = {0, 0, 0, 0, 0};
+    bool operator==(const Shape &o) const {
+        for (int p = 0; p < kPasses; ++p)
+            if (plan[p] != o.plan[p] || tile[p] != o.tile[p]) return false;
+        return true;
+    }
+    bool operator<(const Shape &o) const {
+        for (int p = 0; p < kPasses; ++p) {
+            if (plan[p] != o.plan[p]) return plan[p] < o.plan[p];
+            if (tile[p] != o.tile[p]) return tile[p] < o.tile[p];
+        }
+        return false;
+    }
+};
+// padded lengths with an alternative radix plan
+constexpr bool alt_plan_exists(int N) { return N == 128 || N == 256 || N == 512 || N == 768; }
+inline bool shape_valid(int n, const Shape &s) {
+    for (int p = 0; p < kPasses; ++p) {
+        if (s.plan[p] < 0 || s.plan[p] > (alt_plan_exists(2 * n) ? 1 : 0)) return false;
+        if (s.tile[p] < 0 || s.tile[p] >= kTileChoices[p]) return false;
+    }
+    return true;
+}
+
 // One solve's buffers (device pointers) and sizes.
 struct SolveArgs {
     int n = 0;          // points per axis; padded length N = 2n
@@ -27,6 +66,7 @@ struct SolveArgs {
     void *A = nullptr;   // chunk buffer: n*N*(chunk_tiles*W) complex
     int chunk_tiles = 0; // k3 tiles per H2-H4 chunk (0: all tiles in one chunk)
     int i1_group = 0;    // i1 slabs per H1-H2 / H4-H5 group (0: all; X then holds one group)
+    Shape shape;         // launch shape (ignored by the uncropped variant)
     void *A2 = nullptr;  // N*N*P complex, full variant only
     void *Y2 = nullptr;  // N*N*P complex, full variant only
     const double *mult = nullptr;   // blocked multiplier octant
@@ -42,11 +82,11 @@ hipError_t launch_solve(const SolveArgs &s, hipStream_t st);
 // `count` solves of the same n and tier in one launch per pass; `table_dev`
 // is a device array of `count` jobs, each with a workspace of one chunk
 // holding all tiles (chunk_tiles = 0)
-hipError_t launch_group(int n, bool f32, const Job *table_dev, int count, const void *tw_hi, const void *tw_lo,
-                        hipStream_t st);
+hipError_t launch_group(int n, bool f32, const Shape &shape, const Job *table_dev, int count, const void *tw_hi,
+                        const void *tw_lo, hipStream_t st);
 
-// k3 tile width of the strided passes (8 for FP64, 16 for FP32)
-int strided_width(bool f32);
+// k3 columns per 128-byte row tile of the padded intermediates (8 FP64, 16 FP32)
+inline int strided_width(bool f32) { return f32 ? 16 : 8; }
 
 // the kernel-spectrum multiplier octant (FP64 MFMA contraction)
 hipError_t launch_spectrum(const double *J0, const double *J2, const double *omega, int R, int n, int P,

@@ -1,0 +1,530 @@
+// passes.hpp - the solve's device passes and their launch sequence, as
+// templates over the precision T and the padded length N; instantiated per
+// precision in passes_f64.hip and passes_f32.hip.
+//
+// Data layout in HBM for one solve with n points per axis, N = 2n, and
+// P = round_up(n+1, 16) (pitch of the half-spectrum axis k3 = 0..n):
+//   rho, u : n*n*n real, [i1][i2][i3]
+//   X      : n*n*P complex, [i1][i2][k3]   after H1; reused as Y after H4
+//   A      : n*N*pa complex, [i1][k2][k3]  after H2; H3 updates it in place
+//            (pa = the k3 columns of one chunk, a multiple of the row tile)
+//   mult   : (n+1)*P*(n+1) FP64, blocked [b][c/8][a][c%8] holding the
+//            multiplier m(|k1| = a, |k2| = b, k3 = c), zero for c > n
+// Passes (Algorithm 2):
+//   H1 k_z_r2c   : forward transform along i3 of the padded real lines, two
+//                  real lines per complex transform, n+1 bins kept
+//   H2 k_y_fwd   : forward along i2 (input rows i2 >= n are zero)
+//   H3 k_x_fused : forward along i1 (inputs i1 >= n zero), multiply by m,
+//                  inverse along i1 keeping outputs i1 < n
+//   H4 k_y_inv   : inverse along k2 keeping outputs i2 < n
+//   H5 k_z_c2r   : inverse Hermitian transform along k3 keeping i3 < n
+// Every kernel takes its radix plan PV and its tile shape (columns W or
+// threads THR per workgroup) as template parameters; the launch sequence
+// picks them per pass from a Shape.
+#pragma once
+#include <algorithm>
+#include <type_traits>
+
+#include "fft_core.hpp"
+#include "kernels.h"
+
+namespace psp {
+
+// ------------------------------------------------------------ configuration
+// k3 columns of one 128-byte row tile of X and A
+template <typename T> struct LayoutTile;
+template <> struct LayoutTile<double> { static constexpr int W = 8; };
+template <> struct LayoutTile<float> { static constexpr int W = 16; };
+
+// strided passes: W columns per workgroup, TPC threads per column; SPLIT:
+// every exchange between stages goes through an LDS buffer of half the
+// positions in two phases (half the LDS, so more workgroups per CU, for
+// twice the barriers)
+template <typename T, int N, int PV, int W, bool SPLIT_ = false> struct StridedCfg {
+    static constexpr int TPC0 = N / MaxRadix<N, PV>::value();
+    static constexpr int TPC = (TPC0 * W > 1024) ? TPC0 / 2 : TPC0;
+    static constexpr int THREADS = TPC * W;
+    static constexpr bool SPLIT = SPLIT_;
+    static constexpr int LDS_ELEMS = SPLIT ? N * W / 2 : N * W;
+    static constexpr int SUB = LayoutTile<T>::W / W;     // workgroups per row tile
+};
+
+// line passes: Q complex lines per workgroup of about THR threads
+template <typename T, int N, int PV, int THR> struct LineCfg {
+    static constexpr int TPC = N / MaxRadix<N, PV>::value();
+    static constexpr int Q = (THR / TPC) > 0 ? (THR / TPC) : 1;
+    static constexpr int THREADS = TPC * Q;
+    static constexpr int LINE = N + N / 8;                          // padded line in LDS
+};
+
+template <int W> struct IdxInter {   // (position, column) -> position*W + column
+    int col;
+    __device__ __forceinline__ int operator()(int pos) const { return pos * W + col; }
+};
+struct IdxLine {                     // column-major, one padding slot per 8 positions
+    int base;
+    __device__ __forceinline__ int operator()(int pos) const { return base + pos + (pos >> 3); }
+};
+
+// Per-solve device pointers.  A single solve passes them as a kernel
+// argument; a batched launch passes a device table and takes entry
+// blockIdx.y (every solve of one launch has the same padded length).
+struct JobRef {
+    Job arg;
+    const Job *table;
+    __device__ __forceinline__ Job get() const { return table ? table[blockIdx.y] : arg; }
+};
+
+// ------------------------------------------------------------------- H1
+// Two real lines a, b (flattened (i1, i2) = 2q, 2q+1) form z = a + i b.  The
+// padded length-N line has data in [0, n) only.  After the transform,
+// A[k] = (Z[k] + conj Z[N-k])/2 and B[k] = (Z[k] - conj Z[N-k])/(2i).
+template <typename T, int N, int PV, int THR>
+__global__ void __launch_bounds__((LineCfg<T, N, PV, THR>::THREADS))
+k_z_r2c(JobRef jr, int npairs, int P, Twiddle<T> tw) {
+    using C = cplx<T>;
+    using Cfg = LineCfg<T, N, PV, THR>;
+    using E = Engine<T, N, Cfg::TPC, false, PV>;
+    constexpr int n = N / 2;
+    __shared__ C lds[Cfg::Q * Cfg::LINE];
+    const Job jb = jr.get();
+    const int t = threadIdx.x % Cfg::TPC, q = threadIdx.x / Cfg::TPC;
+    const int pair = blockIdx.x * Cfg::Q + q;
+    const bool active = pair < npairs;
+    const T *ra = (const T *)jb.rho + (size_t)(2 * pair) * n;
+    const T *rb = ra + n;
+    C v[E::V];
+    E::for_inputs(v, t, [&](int pos, int r) -> C {
+        if (r < E::R(0) / 2 && active) return C{ra[pos], rb[pos]};
+        return c_zero<C>();
+    });
+    IdxLine idx{q * Cfg::LINE};
+    E::template run_from<0>(v, lds, t, idx, tw);
+    E::for_outputs(v, t, [&](int pos, int, C &val) { lds[idx(pos)] = val; });
+    __syncthreads();
+    if (active) {
+        C *xa = (C *)jb.X + (size_t)(2 * pair) * P;
+        C *xb = xa + P;
+        for (int k = t; k <= n; k += Cfg::TPC) {
+            const C z = lds[idx(k)];
+            const C zc = lds[idx(k == 0 ? 0 : N - k)];
+            xa[k] = C{T(0.5) * (z.x + zc.x), T(0.5) * (z.y - zc.y)};
+            const C d = C{z.x - zc.x, z.y + zc.y};     // Z[k] - conj Z[N-k]
+            xb[k] = C{T(0.5) * d.y, -T(0.5) * d.x};   // d / (2i)
+        }
+    }
+}
+
+// ------------------------------------------------------------------- H2-H4
+// The strided passes work on a chunk of k3 row tiles [tile0, tile0 + ntile)
+// (LayoutTile columns each).  The padded intermediate of a chunk is
+// A[i1][k2][c] with the chunk-local column c < pa as its contiguous axis
+// (measured faster on MI355X than a tile-major layout: the i2 passes then
+// touch rows only a few KB apart).  X/Y rows are [i1][i2][k3] with pitch P
+// and the global column cg = tile0 * LayoutTile + c, which also decides
+// validity (cg <= n) and the multiplier entry.  A workgroup of W columns
+// covers 1/SUB of a row tile.
+struct Chunk {
+    int tile0;      // first row tile of the chunk
+    int ntile;      // row tiles in the chunk
+    int pa;         // k3 pitch of the chunk buffer A
+};
+
+template <int N>
+__device__ __forceinline__ size_t a_index(int pa, int c, int k2, int i1) {
+    return ((size_t)i1 * N + k2) * pa + c;
+}
+
+// ------------------------------------------------------------------- H2
+template <typename T, int N, int PV, int W, bool SP>
+__global__ void __launch_bounds__((StridedCfg<T, N, PV, W, SP>::THREADS))
+k_y_fwd(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
+    using C = cplx<T>;
+    using Cfg = StridedCfg<T, N, PV, W, SP>;
+    using E = Engine<T, N, Cfg::TPC, false, PV>;
+    constexpr int n = N / 2;
+    __shared__ C lds[Cfg::LDS_ELEMS];
+    const Job jb = jr.get();
+    const int nsub = ck.ntile * Cfg::SUB;
+    const int col = threadIdx.x % W, t = threadIdx.x / W;
+    const int i1 = blockIdx.x / nsub, c = (blockIdx.x % nsub) * W + col;
+    const int cg = ck.tile0 * LayoutTile<T>::W + c;
+    const bool valid = cg <= n;
+    const C *src = (const C *)jb.X + (size_t)i1 * n * P + cg;      // rows i2 of X
+    C *dst = (C *)jb.A + a_index<N>(ck.pa, c, 0, i1);              // rows k2 of A
+    C v[E::V];
+    E::for_inputs(v, t, [&](int pos, int r) -> C {
+        if (r < E::R(0) / 2 && valid) return src[(size_t)pos * P];
+        return c_zero<C>();
+    });
+    E::template run_from<0, Cfg::SPLIT>(v, lds, t, IdxInter<W>{col}, tw);
+    E::for_outputs(v, t, [&](int pos, int, C &val) { dst[(size_t)pos * ck.pa] = val; });
+}
+
+// ------------------------------------------------------------------- H3
+// Work item (b, sub-tile, side): column k2 = b (side 0) or N - b (side 1),
+// both reading the same multiplier block.  Items (b, ., 0) and (b, ., 1) go
+// to workgroups g and g + 8, which the dispatcher places on the same XCD at
+// nearly the same time, so the second read of the block hits that XCD's L2.
+// FULL (test hook): all N outputs of the inverse go to A2[i1][k2][k3] (pitch P).
+template <typename T, int N, int PV, int W, bool SP, bool FULL>
+__global__ void __launch_bounds__((StridedCfg<T, N, PV, W, SP>::THREADS))
+k_x_fused(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
+    using C = cplx<T>;
+    using Cfg = StridedCfg<T, N, PV, W, SP>;
+    using EF = Engine<T, N, Cfg::TPC, false, PV>;
+    using EI = Engine<T, N, Cfg::TPC, true, PV>;
+    constexpr int n = N / 2;
+    __shared__ C lds[Cfg::LDS_ELEMS];
+    const int nsub = ck.ntile * Cfg::SUB;
+    const int g = blockIdx.x;
+    const int pi = (g / 16) * 8 + (g % 8), side = (g % 16) / 8;
+    if (pi >= (n + 1) * nsub) return;               // uniform over the workgroup
+    const int b = pi / nsub, sub = pi % nsub;
+    if (side && (b == 0 || b == n)) return;
+    const Job jb = jr.get();
+    const int k2 = side ? N - b : b;
+    const int col = threadIdx.x % W, t = threadIdx.x / W;
+    const int c = sub * W + col;
+    const int cg = ck.tile0 * LayoutTile<T>::W + c;
+    const bool valid = cg <= n;
+    const C *src = (const C *)jb.A + a_index<N>(ck.pa, c, k2, 0);   // rows i1
+    const size_t step = (size_t)N * ck.pa;
+    const double *mrow = jb.mult + ((size_t)(b * (P / 8) + cg / 8) * (n + 1)) * 8 + (cg & 7);
+    C v[EF::V];
+    EF::for_inputs(v, t, [&](int pos, int r) -> C {
+        if (r < EF::R(0) / 2 && valid) return src[pos * step];
+        return c_zero<C>();
+    });
+    EF::template run_from<0, Cfg::SPLIT>(v, lds, t, IdxInter<W>{col}, tw);
+    EF::for_outputs(v, t, [&](int pos, int, C &val) {
+        const int a = pos <= n ? pos : N - pos;
+        const double m = mrow[(size_t)a * 8];
+        val = C{T((double)val.x * m), T((double)val.y * m)};
+    });
+    EI::template run_from<0, Cfg::SPLIT>(v, lds, t, IdxInter<W>{col}, tw);
+    if constexpr (!FULL) {
+        C *dst = (C *)jb.A + a_index<N>(ck.pa, c, k2, 0);
+        EI::for_outputs(v, t, [&](int pos, int r, C &val) {
+            if (valid && r < EI::R(EI::S - 1) / 2) dst[pos * step] = val;
+        });
+    } else {
+        C *dst = (C *)jb.A2 + (size_t)k2 * P + cg;
+        EI::for_outputs(v, t, [&](int pos, int, C &val) {
+            if (valid) dst[(size_t)pos * N * P] = val;
+        });
+    }
+}
+
+// ------------------------------------------------------------------- H4
+// FULL (test hook): reads A2[i1][k2][k3] for all N rows i1 and writes all N
+// outputs to Y2[i1][i2][k3] (pitch P).
+template <typename T, int N, int PV, int W, bool SP, bool FULL>
+__global__ void __launch_bounds__((StridedCfg<T, N, PV, W, SP>::THREADS))
+k_y_inv(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
+    using C = cplx<T>;
+    using Cfg = StridedCfg<T, N, PV, W, SP>;
+    using E = Engine<T, N, Cfg::TPC, true, PV>;
+    constexpr int n = N / 2;
+    __shared__ C lds[Cfg::LDS_ELEMS];
+    const Job jb = jr.get();
+    const int nsub = ck.ntile * Cfg::SUB;
+    const int col = threadIdx.x % W, t = threadIdx.x / W;
+    const int i1 = blockIdx.x / nsub, c = (blockIdx.x % nsub) * W + col;
+    const int cg = ck.tile0 * LayoutTile<T>::W + c;
+    const bool valid = cg <= n;
+    C v[E::V];
+    if constexpr (!FULL) {
+        const C *src = (const C *)jb.A + a_index<N>(ck.pa, c, 0, i1);   // rows k2
+        E::for_inputs(v, t, [&](int pos, int) -> C {
+            if (valid) return src[(size_t)pos * ck.pa];
+            return c_zero<C>();
+        });
+    } else {
+        const C *src = (const C *)jb.A2 + (size_t)i1 * N * P + cg;
+        E::for_inputs(v, t, [&](int pos, int) -> C {
+            if (valid) return src[(size_t)pos * P];
+            return c_zero<C>();
+        });
+    }
+    E::template run_from<0, Cfg::SPLIT>(v, lds, t, IdxInter<W>{col}, tw);
+    constexpr int rows_out = FULL ? N : n;
+    C *dst = (C *)(FULL ? jb.Y2 : jb.X) + (size_t)i1 * rows_out * P + cg;
+    E::for_outputs(v, t, [&](int pos, int r, C &val) {
+        if (valid && (FULL || r < E::R(E::S - 1) / 2)) dst[(size_t)pos * P] = val;
+    });
+}
+
+// ------------------------------------------------------------------- H5
+// Rows a, b of Y (Hermitian half spectra) form Z[k] = A[k] + i B[k] on the
+// full length N; the inverse transform gives a + i b.  The imaginary parts
+// of the k = 0 and k = n bins are dropped (real transform).  FULL: rows of
+// Y2 (N*N lines) and all N outputs.
+template <typename T, int N, int PV, int THR, bool FULL>
+__global__ void __launch_bounds__((LineCfg<T, N, PV, THR>::THREADS))
+k_z_c2r(JobRef jr, int npairs, int P, Twiddle<T> tw) {
+    using C = cplx<T>;
+    using Cfg = LineCfg<T, N, PV, THR>;
+    using E = Engine<T, N, Cfg::TPC, true, PV>;
+    constexpr int n = N / 2;
+    constexpr int len_out = FULL ? N : n;
+    __shared__ C lds[Cfg::Q * Cfg::LINE];
+    const Job jb = jr.get();
+    const int t = threadIdx.x % Cfg::TPC, q = threadIdx.x / Cfg::TPC;
+    const int pair = blockIdx.x * Cfg::Q + q;
+    const bool active = pair < npairs;
+    const C *ya = (const C *)(FULL ? jb.Y2 : jb.X) + (size_t)(2 * pair) * P;
+    const C *yb = ya + P;
+    IdxLine idx{q * Cfg::LINE};
+    // each half-spectrum bin is read once (coalesced) and gives
+    // Z[k] = A[k] + i B[k] and Z[N-k] = conj A[k] + i conj B[k]
+    if (active) {
+        for (int k = t; k <= n; k += Cfg::TPC) {
+            C A = ya[k], B = yb[k];
+            if (k == 0 || k == n) {
+                A.y = 0;
+                B.y = 0;
+            }
+            lds[idx(k)] = C{A.x - B.y, A.y + B.x};
+            if (k != 0 && k != n) lds[idx(N - k)] = C{A.x + B.y, B.x - A.y};
+        }
+    }
+    __syncthreads();
+    C v[E::V];
+    E::template load_lds<0>(v, lds, t, idx);
+    __syncthreads();
+    E::template run_from<0>(v, lds, t, idx, tw);
+    T *ua = (T *)jb.u + (size_t)(2 * pair) * len_out;
+    T *ub = ua + len_out;
+    E::for_outputs(v, t, [&](int pos, int r, C &val) {
+        if (active && (FULL || r < E::R(E::S - 1) / 2)) {
+            ua[pos] = val.x;
+            ub[pos] = val.y;
+        }
+    });
+}
+
+// --------------------------------------------------------------- launchers
+inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
+
+template <typename T> static Twiddle<T> twiddle_of(const void *hi, const void *lo) {
+    Twiddle<T> tw;
+    if constexpr (sizeof(T) == 8) {
+        (void)lo;
+        tw.w = (const double2 *)hi;
+    } else {
+        tw.hi = (const float2 *)hi;
+        tw.lo = (const float2 *)lo;
+    }
+    return tw;
+}
+
+// compile-time choices from the run-time Shape entries
+template <int N, typename F> inline void with_plan(int pv, F &&f) {
+    if constexpr (alt_plan_exists(N)) {
+        if (pv == 1) {
+            f(std::integral_constant<int, 1>{});
+            return;
+        }
+    }
+    f(std::integral_constant<int, 0>{});
+}
+template <int W_, bool SP_> struct StridedTile {
+    static constexpr int W = W_;
+    static constexpr bool SP = SP_;
+};
+template <typename T, typename F> inline void with_cols(int tile, F &&f) {
+    constexpr int LW = LayoutTile<T>::W;
+    if (tile == 1)
+        f(StridedTile<LW / 2, false>{});
+    else if (tile == 2)
+        f(StridedTile<LW, true>{});
+    else
+        f(StridedTile<LW, false>{});
+}
+template <typename F> inline void with_threads(int tile, F &&f) {
+    if (tile == 1)
+        f(std::integral_constant<int, 128>{});
+    else if (tile == 2)
+        f(std::integral_constant<int, 512>{});
+    else
+        f(std::integral_constant<int, 256>{});
+}
+
+// the five passes for `count` solves of one padded length: a single solve
+// (table == nullptr, pointers in `one`) or a table of `count` jobs.
+//   chunk_tiles > 0: H2-H4 over chunks of k3 row tiles (A holds one chunk);
+//   i1_group > 0 (single solve, one chunk): H1->H2 and H4->H5 over groups of
+//   i1 slabs, X holding one group, so the i3 intermediate of a group is
+//   written and read back while it can still sit in the last-level cache.
+// Profiling: event i is recorded before launch i (and one after the last);
+// ev_pass[i] receives the pass (0..4) of launch i.
+template <typename T, int N>
+hipError_t passes_impl(const Job &one, const Job *table, int count, int P, int chunk_tiles, int i1_group,
+                       const Shape &sh, bool full, const void *tw_hi, const void *tw_lo, hipEvent_t *ev,
+                       int *ev_pass, int nev, hipStream_t st) {
+    constexpr int n = N / 2;
+    constexpr int LW = LayoutTile<T>::W;
+    const Twiddle<T> tw = twiddle_of<T>(tw_hi, tw_lo);
+    int launch = 0;
+    auto mark = [&](int pass) {
+        if (ev && launch < nev) {
+            (void)hipEventRecord(ev[launch], st);
+            if (ev_pass) ev_pass[launch] = pass;
+        }
+        ++launch;
+    };
+    const int ntile = ceil_div(n + 1, LW);
+    const int y = count;
+    if (full) {
+        // uncropped variant (one chunk, default shape): A2 and Y2 (N x N x P,
+        // row layout) receive all N outputs of the inverse transforms
+        using SC = StridedCfg<T, N, 0, LW, false>;
+        using LC = LineCfg<T, N, 0, 256>;
+        const JobRef jr{one, table};
+        const Chunk ck{0, ntile, ntile * LW};
+        hipLaunchKernelGGL((k_z_r2c<T, N, 0, 256>), dim3(ceil_div(n * n / 2, LC::Q), y), dim3(LC::THREADS), 0, st,
+                           jr, n * n / 2, P, tw);
+        hipLaunchKernelGGL((k_y_fwd<T, N, 0, LW, false>), dim3(n * ntile, y), dim3(SC::THREADS), 0, st, jr, ck, P, tw);
+        hipLaunchKernelGGL((k_x_fused<T, N, 0, LW, false, true>), dim3(ceil_div((long)(n + 1) * ntile, 8) * 16, y),
+                           dim3(SC::THREADS), 0, st, jr, ck, P, tw);
+        hipLaunchKernelGGL((k_y_inv<T, N, 0, LW, false, true>), dim3(N * ntile, y), dim3(SC::THREADS), 0, st, jr, ck, P,
+                           tw);
+        hipLaunchKernelGGL((k_z_c2r<T, N, 0, 256, true>), dim3(ceil_div(N * N / 2, LC::Q), y), dim3(LC::THREADS),
+                           0, st, jr, N * N / 2, P, tw);
+        return hipGetLastError();
+    }
+    auto h1 = [&](const JobRef &jr, int npairs) {
+        with_plan<N>(sh.plan[0], [&](auto pv) {
+            with_threads(sh.tile[0], [&](auto thr) {
+                constexpr int PV = decltype(pv)::value, THR = decltype(thr)::value;
+                using LC = LineCfg<T, N, PV, THR>;
+                hipLaunchKernelGGL((k_z_r2c<T, N, PV, THR>), dim3(ceil_div(npairs, LC::Q), y), dim3(LC::THREADS),
+                                   0, st, jr, npairs, P, tw);
+            });
+        });
+    };
+    auto h2 = [&](const JobRef &jr, const Chunk &ck, int rows) {
+        with_plan<N>(sh.plan[1], [&](auto pv) {
+            with_cols<T>(sh.tile[1], [&](auto w) {
+                constexpr int PV = decltype(pv)::value, W = decltype(w)::W;
+                constexpr bool SP = decltype(w)::SP;
+                using SC = StridedCfg<T, N, PV, W, SP>;
+                hipLaunchKernelGGL((k_y_fwd<T, N, PV, W, SP>), dim3(rows * ck.ntile * SC::SUB, y), dim3(SC::THREADS),
+                                   0, st, jr, ck, P, tw);
+            });
+        });
+    };
+    auto h3 = [&](const JobRef &jr, const Chunk &ck) {
+        with_plan<N>(sh.plan[2], [&](auto pv) {
+            with_cols<T>(sh.tile[2], [&](auto w) {
+                constexpr int PV = decltype(pv)::value, W = decltype(w)::W;
+                constexpr bool SP = decltype(w)::SP;
+                using SC = StridedCfg<T, N, PV, W, SP>;
+                hipLaunchKernelGGL((k_x_fused<T, N, PV, W, SP, false>),
+                                   dim3(ceil_div((long)(n + 1) * ck.ntile * SC::SUB, 8) * 16, y), dim3(SC::THREADS),
+                                   0, st, jr, ck, P, tw);
+            });
+        });
+    };
+    auto h4 = [&](const JobRef &jr, const Chunk &ck, int rows) {
+        with_plan<N>(sh.plan[3], [&](auto pv) {
+            with_cols<T>(sh.tile[3], [&](auto w) {
+                constexpr int PV = decltype(pv)::value, W = decltype(w)::W;
+                constexpr bool SP = decltype(w)::SP;
+                using SC = StridedCfg<T, N, PV, W, SP>;
+                hipLaunchKernelGGL((k_y_inv<T, N, PV, W, SP, false>), dim3(rows * ck.ntile * SC::SUB, y),
+                                   dim3(SC::THREADS), 0, st, jr, ck, P, tw);
+            });
+        });
+    };
+    auto h5 = [&](const JobRef &jr, int npairs) {
+        with_plan<N>(sh.plan[4], [&](auto pv) {
+            with_threads(sh.tile[4], [&](auto thr) {
+                constexpr int PV = decltype(pv)::value, THR = decltype(thr)::value;
+                using LC = LineCfg<T, N, PV, THR>;
+                hipLaunchKernelGGL((k_z_c2r<T, N, PV, THR, false>), dim3(ceil_div(npairs, LC::Q), y),
+                                   dim3(LC::THREADS), 0, st, jr, npairs, P, tw);
+            });
+        });
+    };
+    const int ct = chunk_tiles > 0 ? std::min(chunk_tiles, ntile) : ntile;
+    const int nchunks = ceil_div(ntile, ct);
+    const int G = (table == nullptr && nchunks == 1 && i1_group > 0 && i1_group < n) ? i1_group : n;
+    const int PA = ct * LW;
+    // H1 (+ H2 when grouped) per i1 group
+    for (int g0 = 0; g0 < n; g0 += G) {
+        const int gs = std::min(G, n - g0);
+        Job j = one;
+        if (!table) {
+            j.rho = (const T *)one.rho + (size_t)g0 * n * n;
+            j.A = (cplx<T> *)one.A + (size_t)g0 * N * PA;
+        }
+        const JobRef jr{j, table};
+        mark(0);
+        h1(jr, gs * n / 2);
+        if (G < n) {
+            mark(1);
+            h2(jr, Chunk{0, ntile, PA}, gs);
+        }
+    }
+    const JobRef jr{one, table};
+    for (int ch = 0; ch < nchunks; ++ch) {
+        const int t0 = ch * ct, nt = std::min(ct, ntile - t0);
+        const Chunk ck{t0, nt, PA};
+        if (G == n) {
+            mark(1);
+            h2(jr, ck, n);
+        }
+        mark(2);
+        h3(jr, ck);
+        if (G == n) {
+            mark(3);
+            h4(jr, ck, n);
+        }
+    }
+    // (H4 +) H5 per i1 group
+    for (int g0 = 0; g0 < n; g0 += G) {
+        const int gs = std::min(G, n - g0);
+        Job j = one;
+        if (!table) {
+            j.u = (T *)one.u + (size_t)g0 * n * n;
+            j.A = (cplx<T> *)one.A + (size_t)g0 * N * PA;
+        }
+        const JobRef jrg{j, table};
+        if (G < n) {
+            mark(3);
+            h4(jrg, Chunk{0, ntile, PA}, gs);
+        }
+        mark(4);
+        h5(jrg, gs * n / 2);
+    }
+    mark(-1);
+    return hipGetLastError();
+}
+
+// dispatch over the supported padded lengths
+template <typename T>
+hipError_t passes_dispatch(int N, const Job &one, const Job *table, int count, int P, int chunk_tiles, int i1_group,
+                           const Shape &sh, bool full, const void *tw_hi, const void *tw_lo, hipEvent_t *ev,
+                           int *ev_pass, int nev, hipStream_t st) {
+    switch (N) {
+#define PSP_CASE(NN)                                                                                           \
+    case NN:                                                                                                   \
+        return passes_impl<T, NN>(one, table, count, P, chunk_tiles, i1_group, sh, full, tw_hi, tw_lo, ev,     \
+                                  ev_pass, nev, st);
+        PSP_CASE(8) PSP_CASE(12) PSP_CASE(16) PSP_CASE(24) PSP_CASE(32) PSP_CASE(48) PSP_CASE(64)
+        PSP_CASE(96) PSP_CASE(128) PSP_CASE(192) PSP_CASE(256) PSP_CASE(384) PSP_CASE(512) PSP_CASE(768)
+#undef PSP_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t passes_f64(int N, const Job &one, const Job *table, int count, int P, int chunk_tiles, int i1_group,
+                      const Shape &sh, bool full, const void *tw_hi, const void *tw_lo, hipEvent_t *ev, int *ev_pass,
+                      int nev, hipStream_t st);
+hipError_t passes_f32(int N, const Job &one, const Job *table, int count, int P, int chunk_tiles, int i1_group,
+                      const Shape &sh, bool full, const void *tw_hi, const void *tw_lo, hipEvent_t *ev, int *ev_pass,
+                      int nev, hipStream_t st);
+
+}  // namespace psp

@@ -1,0 +1,117 @@
+// spectrum.hip - the kernel-spectrum build (S2) and the host entry points
+// that launch the solve passes.
+#include <algorithm>
+
+#include "fft_core.hpp"
+#include "kernels.h"
+
+namespace psp {
+
+// ------------------------------------------------------------ S2: spectrum
+// Vhat[a,b,c] = sum_s w_s (J2(a)J0(b)J0(c) + J0(a)J2(b)J0(c) + J0(a)J0(b)J2(c))
+// as a GEMM over K = 2R per b: rows a, columns c,
+//   Amat[a,(s,0)] = w_s (J2(a)J0(b) + J0(a)J2(b)), Amat[a,(s,1)] = w_s J0(a)J0(b),
+//   Bmat[(s,0),c] = J0(c),                       Bmat[(s,1),c] = J2(c),
+// on v_mfma_f64_16x16x4_f64 tiles of 16 a x 16 c; the epilogue applies
+// m = scale (a^2 + b^2 + c^2) Vhat with scale = -(2 pi/L)^2 / N^3.
+// Operand layout of the 16x16x4 FP64 MFMA (lane l): A[l%16][l/16],
+// B[l/16][l%16], D[l/16 + 4e][l%16] for e < 4.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// one wave: a 16-row a-tile for one b against CT consecutive 16-wide c-tiles;
+// the A operand of each k-step is formed once and feeds CT MFMAs
+constexpr int SPEC_CT = 4;
+
+__global__ void __launch_bounds__(256)
+k_spectrum(const double *__restrict__ J0, const double *__restrict__ J2,
+           const double *__restrict__ omega, int R, int n, int P, double scale,
+           double *__restrict__ mult) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nt = (n + 1 + 15) / 16, ng = (nt + SPEC_CT - 1) / SPEC_CT;
+    const long item = (long)blockIdx.x * 4 + wave;
+    if (item >= (long)(n + 1) * nt * ng) return;    // no barriers in this kernel
+    const int b = (int)(item / (nt * ng));
+    const int rem = (int)(item % (nt * ng));
+    const int a0 = (rem / ng) * 16, cgrp = (rem % ng) * SPEC_CT;
+    const int row = lane & 15, kq = lane >> 4;
+    const int a = a0 + row;
+    const int n1 = n + 1;
+    v4d acc[SPEC_CT];
+#pragma unroll
+    for (int q = 0; q < SPEC_CT; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < 2 * R; k0 += 4) {
+        const int ks = k0 + kq, s = ks >> 1, ty = ks & 1;
+        double av = 0.0;
+        const double *j0 = J0 + (size_t)s * n1, *j2 = J2 + (size_t)s * n1;
+        if (s < R && a <= n) {
+            const double w = omega[s];
+            av = ty == 0 ? w * (j2[a] * j0[b] + j0[a] * j2[b]) : w * (j0[a] * j0[b]);
+        }
+        const double *jb = ty == 0 ? j0 : j2;
+#pragma unroll
+        for (int q = 0; q < SPEC_CT; ++q) {
+            const int c = (cgrp + q) * 16 + row;
+            const double bv = (s < R && c <= n) ? jb[c] : 0.0;
+            acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[q], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < SPEC_CT; ++q) {
+        const int cc = (cgrp + q) * 16 + row;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int aa = a0 + kq + 4 * e;
+            if (aa <= n && cc <= n) {
+                const double k2 = (double)aa * aa + (double)b * b + (double)cc * cc;
+                mult[((size_t)(b * (P / 8) + cc / 8) * n1 + aa) * 8 + (cc & 7)] = scale * k2 * acc[q][e];
+            }
+        }
+    }
+}
+
+// --------------------------------------------------------------- launchers
+static inline int ceil_div_l(long a, long b) { return (int)((a + b - 1) / b); }
+
+hipError_t passes_f64(int N, const Job &one, const Job *table, int count, int P, int chunk_tiles, int i1_group,
+                      const Shape &sh, bool full, const void *tw_hi, const void *tw_lo, hipEvent_t *ev, int *ev_pass,
+                      int nev, hipStream_t st);
+hipError_t passes_f32(int N, const Job &one, const Job *table, int count, int P, int chunk_tiles, int i1_group,
+                      const Shape &sh, bool full, const void *tw_hi, const void *tw_lo, hipEvent_t *ev, int *ev_pass,
+                      int nev, hipStream_t st);
+
+// launches (and so profiling events minus one) of one solve
+int solve_launches(int n, bool f32, int chunk_tiles, int i1_group) {
+    const int W = strided_width(f32);
+    const int ntile = ceil_div_l(n + 1, W);
+    const int ct = chunk_tiles > 0 ? std::min(chunk_tiles, ntile) : ntile;
+    const int nchunks = ceil_div_l(ntile, ct);
+    const bool grouped = nchunks == 1 && i1_group > 0 && i1_group < n;
+    if (grouped) return 4 * ceil_div_l(n, i1_group) + 1;
+    return 2 + 3 * nchunks;
+}
+
+hipError_t launch_solve(const SolveArgs &s, hipStream_t st) {
+    const Job one{s.rho, s.u, s.X, s.A, s.mult, s.A2, s.Y2};
+    auto f = s.f32 ? passes_f32 : passes_f64;
+    return f(2 * s.n, one, nullptr, 1, s.P, s.chunk_tiles, s.i1_group, s.shape, s.full, s.tw_hi, s.tw_lo, s.ev,
+             s.ev_pass, s.nev, st);
+}
+
+hipError_t launch_group(int n, bool f32, const Shape &shape, const Job *table_dev, int count, const void *tw_hi,
+                        const void *tw_lo, hipStream_t st) {
+    const Job none{};
+    const int P = ((n + 1 + 15) / 16) * 16;
+    auto f = f32 ? passes_f32 : passes_f64;
+    return f(2 * n, none, table_dev, count, P, 0, 0, shape, false, tw_hi, tw_lo, nullptr, nullptr, 0, st);
+}
+
+hipError_t launch_spectrum(const double *J0, const double *J2, const double *omega, int R, int n, int P,
+                           double scale, double *mult, hipStream_t st) {
+    const int nt = (n + 1 + 15) / 16, ng = (nt + SPEC_CT - 1) / SPEC_CT;
+    const long items = (long)(n + 1) * nt * ng;
+    hipLaunchKernelGGL(k_spectrum, dim3(ceil_div_l(items, 4)), dim3(256), 0, st, J0, J2, omega, R, n, P, scale,
+                       mult);
+    return hipGetLastError();
+}
+
+}  // namespace psp

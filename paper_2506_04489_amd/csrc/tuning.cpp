@@ -1,0 +1,203 @@
+// tuning.cpp - launch shapes of the passes: per-plan setting, the
+// process-wide tuning table, and the autotuner that measures every
+// (radix plan, tile) candidate of every pass with HIP events.
+#include <algorithm>
+#include <cfloat>
+#include <map>
+#include <mutex>
+#include <utility>
+#include <vector>
+
+#include "host_common.hpp"
+
+namespace psp {
+
+static std::mutex g_tune_mu;
+static std::map<std::pair<int, bool>, Shape> g_tune;   // (n, f32) -> shape
+
+Shape tuned_shape(int n, bool f32) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find({n, f32});
+    return it == g_tune.end() ? Shape{} : it->second;
+}
+
+static psp_status shape_from(int n, const int *plan, const int *tile, Shape *out) {
+    if (!plan || !tile) return fail(PSP_EINVAL, "NULL shape array");
+    Shape s;
+    for (int i = 0; i < kPasses; ++i) {
+        s.plan[i] = plan[i];
+        s.tile[i] = tile[i];
+    }
+    if (!shape_valid(n, s)) return fail(PSP_EINVAL, "shape out of range for n = %d", n);
+    *out = s;
+    return PSP_OK;
+}
+
+static void shape_to(const Shape &s, int *plan, int *tile) {
+    for (int i = 0; i < kPasses; ++i) {
+        if (plan) plan[i] = s.plan[i];
+        if (tile) tile[i] = s.tile[i];
+    }
+}
+
+// candidates (radix plan, tile) of pass i for size n
+static std::vector<std::pair<int, int>> candidates(int n, int i) {
+    std::vector<std::pair<int, int>> c;
+    const int plans = alt_plan_exists(2 * n) ? 2 : 1;
+    for (int pl = 0; pl < plans; ++pl)
+        for (int tl = 0; tl < kTileChoices[i]; ++tl) c.push_back({pl, tl});
+    return c;
+}
+
+}  // namespace psp
+
+using namespace psp;
+
+extern "C" {
+
+psp_status psp_plan_set_shape(psp_plan *p, const int *plan, const int *tile) {
+    if (!p) return fail(PSP_EINVAL, "plan is NULL");
+    Shape s;
+    psp_status rs = shape_from(p->n, plan, tile, &s);
+    if (rs != PSP_OK) return rs;
+    std::lock_guard<std::mutex> lk(p->mu);
+    p->shape = s;
+    return PSP_OK;
+}
+
+psp_status psp_plan_get_shape(const psp_plan *p, int *plan, int *tile) {
+    if (!p || !plan || !tile) return fail(PSP_EINVAL, "NULL argument");
+    shape_to(p->shape, plan, tile);
+    return PSP_OK;
+}
+
+psp_status psp_tuning_set(int n, psp_dtype dtype, const int *plan, const int *tile) {
+    if (dtype != PSP_F64 && dtype != PSP_F32) return fail(PSP_EINVAL, "unknown dtype %d", (int)dtype);
+    if (n < 4 || n > 384 || (n & 1) || !supported_length(2 * n)) return fail(PSP_EUNSUPPORTED, "unsupported n = %d", n);
+    Shape s;
+    psp_status rs = shape_from(n, plan, tile, &s);
+    if (rs != PSP_OK) return rs;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[{n, dtype == PSP_F32}] = s;
+    return PSP_OK;
+}
+
+psp_status psp_tuning_get(int n, psp_dtype dtype, int *plan, int *tile) {
+    if (!plan || !tile) return fail(PSP_EINVAL, "NULL argument");
+    if (dtype != PSP_F64 && dtype != PSP_F32) return fail(PSP_EINVAL, "unknown dtype %d", (int)dtype);
+    shape_to(tuned_shape(n, dtype == PSP_F32), plan, tile);
+    return PSP_OK;
+}
+
+psp_status psp_autotune(psp_plan *p, int reps, void *stream, int *best_plan, int *best_tile, float *best_ms,
+                        float *cand_ms) {
+    if (!p) return fail(PSP_EINVAL, "plan is NULL");
+    if (reps < 1 || reps > 1000) return fail(PSP_EINVAL, "reps must be in [1, 1000] (got %d)", reps);
+    if (!p->precomputed) return fail(PSP_ESTATE, "autotune before psp_kernel_precompute");
+    {
+        std::lock_guard<std::mutex> lk(p->mu);
+        if (p->prof_cap > 0) return fail(PSP_ESTATE, "autotune while profiling");
+    }
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != p->device)
+        return fail(PSP_EINVAL, "plan was precomputed on device %d, current is %d", p->device, dev);
+    hipStream_t st = (hipStream_t)stream;
+    Workspace *w = nullptr;
+    psp_status rs = plan_workspace(p, st, &w);
+    if (rs != PSP_OK) return rs;
+    const int n = p->n;
+    const bool f32 = p->dtype == PSP_F32;
+    const size_t bytes = (size_t)n * n * n * (f32 ? 4 : 8);
+    void *rho = nullptr, *u = nullptr;
+    if (hipMalloc(&rho, bytes) != hipSuccess || hipMalloc(&u, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        if (rho) (void)hipFree(rho);
+        return fail(PSP_ENOMEM, "autotune buffers of %zu bytes failed", 2 * bytes);
+    }
+    const int nev = solve_launches(n, f32, p->chunk_tiles, p->i1_group) + 1;
+    std::vector<hipEvent_t> ev(nev, nullptr);
+    std::vector<int> ev_pass(nev, -1);
+    std::vector<std::vector<std::pair<int, int>>> cand(kPasses);
+    size_t rounds = 0;
+    for (int i = 0; i < kPasses; ++i) {
+        cand[i] = candidates(n, i);
+        rounds = std::max(rounds, cand[i].size());
+    }
+    std::vector<std::vector<float>> best(kPasses);
+    for (int i = 0; i < kPasses; ++i) best[i].assign(cand[i].size(), FLT_MAX);
+    psp_status out = PSP_OK;
+    hipError_t e = hipMemsetAsync(rho, 0, bytes, st);
+    for (int k = 0; k < nev && e == hipSuccess; ++k) e = hipEventCreate(&ev[k]);
+    if (e != hipSuccess) out = hip_fail(e, "autotune set-up");
+    // round r runs candidate r mod (count) of every pass at once: each pass
+    // is timed by its own events, so one round measures five candidates
+    for (size_t r = 0; r < rounds && out == PSP_OK; ++r) {
+        Shape s;
+        for (int i = 0; i < kPasses; ++i) {
+            const auto &c = cand[i][r % cand[i].size()];
+            s.plan[i] = c.first;
+            s.tile[i] = c.second;
+        }
+        SolveArgs a = solve_args(p, *w, rho, u);
+        a.shape = s;
+        if ((e = launch_solve(a, st)) != hipSuccess) {   // warm-up
+            out = hip_fail(e, "autotune launch");
+            break;
+        }
+        a.ev = ev.data();
+        a.ev_pass = ev_pass.data();
+        a.nev = nev;
+        for (int rep = 0; rep < reps && out == PSP_OK; ++rep) {
+            if ((e = launch_solve(a, st)) != hipSuccess || (e = hipEventSynchronize(ev[nev - 1])) != hipSuccess) {
+                out = hip_fail(e, "autotune solve");
+                break;
+            }
+            float pass_ms[kPasses] = {0, 0, 0, 0, 0};
+            for (int k = 0; k + 1 < nev; ++k) {
+                float ms = 0;
+                if ((e = hipEventElapsedTime(&ms, ev[k], ev[k + 1])) != hipSuccess) {
+                    out = hip_fail(e, "autotune timing");
+                    break;
+                }
+                if (ev_pass[k] >= 0 && ev_pass[k] < kPasses) pass_ms[ev_pass[k]] += ms;
+            }
+            for (int i = 0; i < kPasses; ++i) {
+                float &b = best[i][r % cand[i].size()];
+                b = std::min(b, pass_ms[i]);
+            }
+        }
+    }
+    if (out == PSP_OK && (e = hipStreamSynchronize(st)) != hipSuccess) out = hip_fail(e, "autotune");
+    for (auto x : ev)
+        if (x) (void)hipEventDestroy(x);
+    (void)hipFree(rho);
+    (void)hipFree(u);
+    if (out != PSP_OK) return out;
+    Shape chosen;
+    for (int i = 0; i < kPasses; ++i) {
+        size_t pick = 0;   // candidate 0 is the default shape of the pass
+        for (size_t c = 1; c < cand[i].size(); ++c)
+            if (best[i][c] < 0.99f * best[i][0] && best[i][c] < best[i][pick]) pick = c;
+        chosen.plan[i] = cand[i][pick].first;
+        chosen.tile[i] = cand[i][pick].second;
+        if (best_ms) best_ms[i] = best[i][pick];
+    }
+    {
+        std::lock_guard<std::mutex> lk(p->mu);
+        p->shape = chosen;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[{n, f32}] = chosen;
+    }
+    shape_to(chosen, best_plan, best_tile);
+    if (cand_ms) {
+        for (int i = 0; i < kPasses * 6; ++i) cand_ms[i] = -1.0f;
+        for (int i = 0; i < kPasses; ++i)
+            for (size_t c = 0; c < cand[i].size(); ++c)
+                cand_ms[i * 6 + cand[i][c].first * kTileChoices[i] + cand[i][c].second] = best[i][c];
+    }
+    return PSP_OK;
+}
+
+}  // extern "C"

@@ -37,6 +37,11 @@ SIGNATURES = {
     "psp_plan_destroy": (None, [_vp]),
     "psp_profile_enable": (_i, [_vp, _i]),
     "psp_plan_set_tuning": (_i, [_vp, _i, _i]),
+    "psp_plan_set_shape": (_i, [_vp, _P(_i), _P(_i)]),
+    "psp_plan_get_shape": (_i, [_vp, _P(_i), _P(_i)]),
+    "psp_tuning_set": (_i, [_i, _i, _P(_i), _P(_i)]),
+    "psp_tuning_get": (_i, [_i, _i, _P(_i), _P(_i)]),
+    "psp_autotune": (_i, [_vp, _i, _vp, _P(_i), _P(_i), _P(ctypes.c_float), _P(ctypes.c_float)]),
     "psp_profile_read": (_i, [_vp, _P(_i), _P(_d)]),
     "psp_graph_capture": (_i, [_vp, _vp, _vp, _vp, _P(_vp)]),
     "psp_graph_capture_batched": (_i, [_i, _P(_vp), _P(_vp), _P(_vp), _vp, _P(_vp)]),
@@ -73,6 +78,7 @@ def lib() -> ctypes.CDLL:
             fn.restype = res
             fn.argtypes = args
         _lib = L
+        _load_shipped_tuning()
     return _lib
 
 
@@ -106,6 +112,47 @@ def _dtype_code(dtype) -> int:
 def _torch_dtype(code: int):
     import torch
     return torch.float64 if code == PSP_F64 else torch.float32
+
+
+def _ints5(v):
+    v = [int(x) for x in v]
+    if len(v) != 5:
+        raise ValueError("a shape has 5 entries (passes H1..H5)")
+    return (ctypes.c_int * 5)(*v)
+
+
+def tuning_set(n: int, dtype, plan, tile):
+    """Enter a launch shape for (n, dtype) in the process-wide tuning table."""
+    _check(lib().psp_tuning_set(int(n), _dtype_code(dtype), _ints5(plan), _ints5(tile)))
+
+
+def tuning_get(n: int, dtype):
+    pa, ta = (ctypes.c_int * 5)(), (ctypes.c_int * 5)()
+    _check(lib().psp_tuning_get(int(n), _dtype_code(dtype), pa, ta))
+    return list(pa), list(ta)
+
+
+TUNING_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_gfx950.json")
+
+
+def load_tuning(path: str) -> int:
+    """Load a tuning table written by ``paper_2506_04489_amd.autotune``;
+    returns the number of entries entered."""
+    import json
+    with open(path) as f:
+        doc = json.load(f)
+    count = 0
+    for e in doc.get("entries", []):
+        tuning_set(e["n"], e["dtype"], e["plan"], e["tile"])
+        count += 1
+    return count
+
+
+def _load_shipped_tuning():
+    # PSP_TUNING_FILE names another table; "none" keeps the default shapes
+    path = os.environ.get("PSP_TUNING_FILE", TUNING_FILE)
+    if path and path != "none" and os.path.exists(path):
+        load_tuning(path)
 
 
 class Plan:
@@ -192,6 +239,31 @@ class Plan:
     def set_tuning(self, k3_tiles: int = 0, i1_group: int = 0):
         _check(lib().psp_plan_set_tuning(self._h, int(k3_tiles), int(i1_group)))
         return self
+
+    def set_shape(self, plan, tile):
+        """Launch shape of passes H1..H5: radix plan and tile choice per pass."""
+        pa, ta = _ints5(plan), _ints5(tile)
+        _check(lib().psp_plan_set_shape(self._h, pa, ta))
+        return self
+
+    def shape(self):
+        """(plan[5], tile[5]) of this plan."""
+        pa, ta = (ctypes.c_int * 5)(), (ctypes.c_int * 5)()
+        _check(lib().psp_plan_get_shape(self._h, pa, ta))
+        return list(pa), list(ta)
+
+    def autotune(self, reps: int = 5, stream=None):
+        """Time every candidate shape of every pass (psp_autotune); the plan
+        and the process-wide tuning table take the fastest.  Returns
+        {"plan": [...], "tile": [...], "pass_ms": [...], "candidates_ms": [[...] x 5]}
+        where candidates_ms[i][plan * 3 + tile] is each candidate's
+        time (-1: no such candidate)."""
+        pa, ta = (ctypes.c_int * 5)(), (ctypes.c_int * 5)()
+        ms = (ctypes.c_float * 5)()
+        cm = (ctypes.c_float * 30)()
+        _check(lib().psp_autotune(self._h, int(reps), _stream_ptr(stream), pa, ta, ms, cm))
+        cand = [[round(float(cm[i * 6 + c]), 5) for c in range(6)] for i in range(5)]
+        return {"plan": list(pa), "tile": list(ta), "pass_ms": [float(x) for x in ms], "candidates_ms": cand}
 
     def profile_enable(self, max_solves: int):
         _check(lib().psp_profile_enable(self._h, int(max_solves)))

@@ -109,3 +109,55 @@ def test_tables_match_oracle(n, h, R):
         s2 = max(np.max(np.abs(J2o[s])), 1e-300)
         assert np.max(np.abs(J0[s] - J0o[s])) < 2e-14 * s0, s
         assert np.max(np.abs(J2[s] - J2o[s])) < 2e-14 * s2, s
+
+
+# ---------------------------------------------------------------- shapes
+def test_shape_validation_and_roundtrip():
+    p = B.Plan(32, 2 / 32, 40)                       # 2n = 64: no alternative radix plan
+    assert p.shape() == B.tuning_get(32, "f64")      # new plans start from the table
+    p.set_shape([0] * 5, [2, 1, 2, 1, 1])
+    assert p.shape() == ([0] * 5, [2, 1, 2, 1, 1])
+    for plan, tile in [([1, 0, 0, 0, 0], [0] * 5),   # no alternative plan for 2n = 64
+                       ([0] * 5, [3, 0, 0, 0, 0]),   # three workgroup sizes for H1
+                       ([0] * 5, [0, 3, 0, 0, 0]),   # three tile choices for H2
+                       ([0] * 5, [0, 0, 0, 0, -1])]:
+        with pytest.raises(B.PspError) as ei:
+            p.set_shape(plan, tile)
+        assert B.STATUS[ei.value.status] == "PSP_EINVAL"
+    q = B.Plan(64, 2 / 64, 40)                       # 2n = 128 has an alternative
+    q.set_shape([1, 1, 1, 1, 1], [0] * 5)
+    assert q.shape()[0] == [1] * 5
+    with pytest.raises(ValueError):
+        q.set_shape([0] * 4, [0] * 5)
+
+
+def test_tuning_table_seeds_new_plans(tmp_path):
+    import json
+    old = B.tuning_get(96, "f32")
+    try:
+        B.tuning_set(96, "f32", [0] * 5, [1, 0, 1, 0, 2])
+        assert B.tuning_get(96, "f32") == ([0] * 5, [1, 0, 1, 0, 2])
+        assert B.Plan(96, 2 / 96, 40, dtype="f32").shape() == ([0] * 5, [1, 0, 1, 0, 2])
+        assert B.Plan(96, 2 / 96, 40, dtype="f64").shape() == B.tuning_get(96, "f64")
+        with pytest.raises(B.PspError):
+            B.tuning_set(10, "f64", [0] * 5, [0] * 5)
+        path = tmp_path / "t.json"
+        path.write_text(json.dumps({"entries": [{"n": 96, "dtype": "f32", "plan": [0] * 5,
+                                                 "tile": [2, 1, 0, 1, 0], "pass_ms": [0] * 5}]}))
+        assert B.load_tuning(str(path)) == 1
+        assert B.tuning_get(96, "f32") == ([0] * 5, [2, 1, 0, 1, 0])
+    finally:
+        B.tuning_set(96, "f32", *old)
+
+
+def test_shipped_tuning_table_is_valid():
+    import json
+    if not os.path.exists(B.TUNING_FILE):
+        pytest.skip("no tuning table shipped")
+    doc = json.load(open(B.TUNING_FILE))
+    seen = set()
+    for e in doc["entries"]:
+        key = (e["n"], e["dtype"])
+        assert key not in seen
+        seen.add(key)
+        assert B.tuning_get(e["n"], e["dtype"]) == (e["plan"], e["tile"])
