@@ -39,9 +39,11 @@ template <> struct LayoutTile<float> { static constexpr int W = 16; };
 // strided passes: W columns per workgroup, TPC threads per column; SPLIT:
 // every exchange between stages goes through an LDS buffer of half the
 // positions in two phases (half the LDS, so more workgroups per CU, for
-// twice the barriers)
-template <typename T, int N, int PV, int W, bool SPLIT_ = false> struct StridedCfg {
-    static constexpr int TPC0 = N / MaxRadix<N, PV>::value();
+// twice the barriers); HALF: half the threads per column, each with twice
+// the butterflies of a stage (fewer waves, more independent work per wave)
+template <typename T, int N, int PV, int W, bool SPLIT_ = false, bool HALF = false> struct StridedCfg {
+    static constexpr int TPC1 = N / MaxRadix<N, PV>::value();
+    static constexpr int TPC0 = (HALF && TPC1 >= 2) ? TPC1 / 2 : TPC1;
     static constexpr int TPC = (TPC0 * W > 1024) ? TPC0 / 2 : TPC0;
     static constexpr int THREADS = TPC * W;
     static constexpr bool SPLIT = SPLIT_;
@@ -136,11 +138,11 @@ __device__ __forceinline__ size_t a_index(int pa, int c, int k2, int i1) {
 }
 
 // ------------------------------------------------------------------- H2
-template <typename T, int N, int PV, int W, bool SP>
-__global__ void __launch_bounds__((StridedCfg<T, N, PV, W, SP>::THREADS))
+template <typename T, int N, int PV, int W, bool SP, bool HF>
+__global__ void __launch_bounds__((StridedCfg<T, N, PV, W, SP, HF>::THREADS))
 k_y_fwd(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
     using C = cplx<T>;
-    using Cfg = StridedCfg<T, N, PV, W, SP>;
+    using Cfg = StridedCfg<T, N, PV, W, SP, HF>;
     using E = Engine<T, N, Cfg::TPC, false, PV>;
     constexpr int n = N / 2;
     __shared__ C lds[Cfg::LDS_ELEMS];
@@ -167,11 +169,11 @@ k_y_fwd(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
 // to workgroups g and g + 8, which the dispatcher places on the same XCD at
 // nearly the same time, so the second read of the block hits that XCD's L2.
 // FULL (test hook): all N outputs of the inverse go to A2[i1][k2][k3] (pitch P).
-template <typename T, int N, int PV, int W, bool SP, bool FULL>
-__global__ void __launch_bounds__((StridedCfg<T, N, PV, W, SP>::THREADS))
+template <typename T, int N, int PV, int W, bool SP, bool HF, bool FULL>
+__global__ void __launch_bounds__((StridedCfg<T, N, PV, W, SP, HF>::THREADS))
 k_x_fused(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
     using C = cplx<T>;
-    using Cfg = StridedCfg<T, N, PV, W, SP>;
+    using Cfg = StridedCfg<T, N, PV, W, SP, HF>;
     using EF = Engine<T, N, Cfg::TPC, false, PV>;
     using EI = Engine<T, N, Cfg::TPC, true, PV>;
     constexpr int n = N / 2;
@@ -219,11 +221,11 @@ k_x_fused(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
 // ------------------------------------------------------------------- H4
 // FULL (test hook): reads A2[i1][k2][k3] for all N rows i1 and writes all N
 // outputs to Y2[i1][i2][k3] (pitch P).
-template <typename T, int N, int PV, int W, bool SP, bool FULL>
-__global__ void __launch_bounds__((StridedCfg<T, N, PV, W, SP>::THREADS))
+template <typename T, int N, int PV, int W, bool SP, bool HF, bool FULL>
+__global__ void __launch_bounds__((StridedCfg<T, N, PV, W, SP, HF>::THREADS))
 k_y_inv(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
     using C = cplx<T>;
-    using Cfg = StridedCfg<T, N, PV, W, SP>;
+    using Cfg = StridedCfg<T, N, PV, W, SP, HF>;
     using E = Engine<T, N, Cfg::TPC, true, PV>;
     constexpr int n = N / 2;
     __shared__ C lds[Cfg::LDS_ELEMS];
@@ -329,18 +331,21 @@ template <int N, typename F> inline void with_plan(int pv, F &&f) {
     }
     f(std::integral_constant<int, 0>{});
 }
-template <int W_, bool SP_> struct StridedTile {
+template <int W_, bool SP_, bool HF_> struct StridedTile {
     static constexpr int W = W_;
     static constexpr bool SP = SP_;
+    static constexpr bool HF = HF_;
 };
 template <typename T, typename F> inline void with_cols(int tile, F &&f) {
     constexpr int LW = LayoutTile<T>::W;
     if (tile == 1)
-        f(StridedTile<LW / 2, false>{});
+        f(StridedTile<LW / 2, false, false>{});
     else if (tile == 2)
-        f(StridedTile<LW, true>{});
+        f(StridedTile<LW, true, false>{});
+    else if (tile == 3)
+        f(StridedTile<LW, false, true>{});
     else
-        f(StridedTile<LW, false>{});
+        f(StridedTile<LW, false, false>{});
 }
 template <typename F> inline void with_threads(int tile, F &&f) {
     if (tile == 1)
@@ -379,16 +384,16 @@ hipError_t passes_impl(const Job &one, const Job *table, int count, int P, int c
     if (full) {
         // uncropped variant (one chunk, default shape): A2 and Y2 (N x N x P,
         // row layout) receive all N outputs of the inverse transforms
-        using SC = StridedCfg<T, N, 0, LW, false>;
+        using SC = StridedCfg<T, N, 0, LW, false, false>;
         using LC = LineCfg<T, N, 0, 256>;
         const JobRef jr{one, table};
         const Chunk ck{0, ntile, ntile * LW};
         hipLaunchKernelGGL((k_z_r2c<T, N, 0, 256>), dim3(ceil_div(n * n / 2, LC::Q), y), dim3(LC::THREADS), 0, st,
                            jr, n * n / 2, P, tw);
-        hipLaunchKernelGGL((k_y_fwd<T, N, 0, LW, false>), dim3(n * ntile, y), dim3(SC::THREADS), 0, st, jr, ck, P, tw);
-        hipLaunchKernelGGL((k_x_fused<T, N, 0, LW, false, true>), dim3(ceil_div((long)(n + 1) * ntile, 8) * 16, y),
+        hipLaunchKernelGGL((k_y_fwd<T, N, 0, LW, false, false>), dim3(n * ntile, y), dim3(SC::THREADS), 0, st, jr, ck, P, tw);
+        hipLaunchKernelGGL((k_x_fused<T, N, 0, LW, false, false, true>), dim3(ceil_div((long)(n + 1) * ntile, 8) * 16, y),
                            dim3(SC::THREADS), 0, st, jr, ck, P, tw);
-        hipLaunchKernelGGL((k_y_inv<T, N, 0, LW, false, true>), dim3(N * ntile, y), dim3(SC::THREADS), 0, st, jr, ck, P,
+        hipLaunchKernelGGL((k_y_inv<T, N, 0, LW, false, false, true>), dim3(N * ntile, y), dim3(SC::THREADS), 0, st, jr, ck, P,
                            tw);
         hipLaunchKernelGGL((k_z_c2r<T, N, 0, 256, true>), dim3(ceil_div(N * N / 2, LC::Q), y), dim3(LC::THREADS),
                            0, st, jr, N * N / 2, P, tw);
@@ -408,9 +413,9 @@ hipError_t passes_impl(const Job &one, const Job *table, int count, int P, int c
         with_plan<N>(sh.plan[1], [&](auto pv) {
             with_cols<T>(sh.tile[1], [&](auto w) {
                 constexpr int PV = decltype(pv)::value, W = decltype(w)::W;
-                constexpr bool SP = decltype(w)::SP;
-                using SC = StridedCfg<T, N, PV, W, SP>;
-                hipLaunchKernelGGL((k_y_fwd<T, N, PV, W, SP>), dim3(rows * ck.ntile * SC::SUB, y), dim3(SC::THREADS),
+                constexpr bool SP = decltype(w)::SP, HF = decltype(w)::HF;
+                using SC = StridedCfg<T, N, PV, W, SP, HF>;
+                hipLaunchKernelGGL((k_y_fwd<T, N, PV, W, SP, HF>), dim3(rows * ck.ntile * SC::SUB, y), dim3(SC::THREADS),
                                    0, st, jr, ck, P, tw);
             });
         });
@@ -419,9 +424,9 @@ hipError_t passes_impl(const Job &one, const Job *table, int count, int P, int c
         with_plan<N>(sh.plan[2], [&](auto pv) {
             with_cols<T>(sh.tile[2], [&](auto w) {
                 constexpr int PV = decltype(pv)::value, W = decltype(w)::W;
-                constexpr bool SP = decltype(w)::SP;
-                using SC = StridedCfg<T, N, PV, W, SP>;
-                hipLaunchKernelGGL((k_x_fused<T, N, PV, W, SP, false>),
+                constexpr bool SP = decltype(w)::SP, HF = decltype(w)::HF;
+                using SC = StridedCfg<T, N, PV, W, SP, HF>;
+                hipLaunchKernelGGL((k_x_fused<T, N, PV, W, SP, HF, false>),
                                    dim3(ceil_div((long)(n + 1) * ck.ntile * SC::SUB, 8) * 16, y), dim3(SC::THREADS),
                                    0, st, jr, ck, P, tw);
             });
@@ -431,9 +436,9 @@ hipError_t passes_impl(const Job &one, const Job *table, int count, int P, int c
         with_plan<N>(sh.plan[3], [&](auto pv) {
             with_cols<T>(sh.tile[3], [&](auto w) {
                 constexpr int PV = decltype(pv)::value, W = decltype(w)::W;
-                constexpr bool SP = decltype(w)::SP;
-                using SC = StridedCfg<T, N, PV, W, SP>;
-                hipLaunchKernelGGL((k_y_inv<T, N, PV, W, SP, false>), dim3(rows * ck.ntile * SC::SUB, y),
+                constexpr bool SP = decltype(w)::SP, HF = decltype(w)::HF;
+                using SC = StridedCfg<T, N, PV, W, SP, HF>;
+                hipLaunchKernelGGL((k_y_inv<T, N, PV, W, SP, HF, false>), dim3(rows * ck.ntile * SC::SUB, y),
                                    dim3(SC::THREADS), 0, st, jr, ck, P, tw);
             });
         });
