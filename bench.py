@@ -97,8 +97,9 @@ def time_tier(torch, B, D, n, dtype, steps, warmup, chunk=0, group=0):
 
 def bench_batched(torch, B, D, dtype, reps=5):
     """The batched workload: 64 seeded Gaussian mixtures, n ~ U{32,48,64,96,128}.
-    One-at-a-time psp_solve, one psp_solve_batched, and the batch replayed as
-    a captured graph, in solves/s."""
+    One-at-a-time psp_solve, one psp_solve_batched (grouped launches), the
+    batch replayed as a captured graph, and the batch through the persistent
+    kernels, in solves/s."""
     td = torch.float64 if dtype == "f64" else torch.float32
     items = D.batched_workload(count=64, seed=D.BATCH_SEED)
     plans = {}
@@ -123,11 +124,18 @@ def bench_batched(torch, B, D, dtype, reps=5):
     g = B.Graph.capture_batched(ps, rhos, us)
     t_graph = timed(lambda: g.launch())
     g.close()
+    # the same batch through the persistent kernels (one launch per pass)
+    B.set_batch_mode("persistent")
+    try:
+        t_pers = timed(lambda: B.solve_batched(ps, rhos, us))
+    finally:
+        B.set_batch_mode("grouped")
     pts = sum(it.n ** 3 for it in items)
     return {"count": len(items), "sizes": sorted({it.n for it in items}),
             "one_at_a_time_solves_per_s": round(len(items) / t_single, 1),
             "batched_solves_per_s": round(len(items) / t_batch, 1),
             "graph_batched_solves_per_s": round(len(items) / t_graph, 1),
+            "persistent_batched_solves_per_s": round(len(items) / t_pers, 1),
             "batched_mpts_per_s": round(pts / t_batch / 1e6, 1),
             "speedup_batched_vs_single": round(t_single / t_batch, 2)}
 

@@ -91,6 +91,16 @@ psp_status psp_solve_batched(int count, psp_plan *const *plans,
                              const void *const *rho_dev, void *const *u_dev,
                              void *stream);
 
+/* How batches (psp_solve_batched, psp_graph_capture_batched and the serving
+ * loop) launch their passes, process-wide, for batches started afterwards:
+ * 0 (default): one launch per pass per distinct (n, shape);
+ * 1: persistent kernels, one launch per pass for all solves with 2n <= 256
+ *    (workgroups of 384 threads take work items from an atomic counter in
+ *    the batch's device table until none is left), grouped launches for the
+ *    rest.
+ * Results are bitwise the same in both modes.  PSP_EINVAL for another value. */
+psp_status psp_set_batch_mode(int mode);
+
 /* Test hook: the uncropped (2n)^3 result of Algorithm 2 (real part), C-order
  * with side 2n, dtype of the plan. */
 psp_status psp_solve_padded_debug(psp_plan *p, const void *rho_dev, void *upad_dev,

@@ -10,7 +10,7 @@ struct psp_graph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<psp::Workspace> ws;
-    psp::Job *table = nullptr;   // device
+    unsigned char *table = nullptr;   // device batch image
     int device = -1;
 };
 
@@ -99,44 +99,44 @@ psp_status psp_graph_capture_batched(int count, psp_plan *const *plans, const vo
     psp_graph *g = new (std::nothrow) psp_graph;
     if (!g) return fail(PSP_ENOMEM, "host allocation failed");
     g->device = plans[0]->device;
-    // group by (n, shape): the table is sorted, each group a contiguous slice
-    std::vector<int> order(count);
-    for (int i = 0; i < count; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        if (plans[a]->n != plans[b]->n) return plans[a]->n < plans[b]->n;
-        return plans[a]->shape < plans[b]->shape;
-    });
     g->ws.resize(count);
-    std::vector<Job> jobs(count);
-    for (int k = 0; k < count; ++k) {
-        const int i = order[k];
-        psp_status rs = alloc_workspace(plans[i]->n, f32, 0, &g->ws[k]);
+    std::vector<BatchMember> m(count);
+    for (int i = 0; i < count; ++i) {
+        psp_status rs = alloc_workspace(plans[i]->n, f32, 0, &g->ws[i]);
         if (rs != PSP_OK) {
-            g->ws.resize(k);
+            g->ws.resize(i);
             graph_free(g);
             return rs;
         }
-        jobs[k] = Job{rho_dev[i], u_dev[i], g->ws[k].X, g->ws[k].A, plans[i]->spec->mult, nullptr, nullptr};
+        m[i].job = Job{rho_dev[i], u_dev[i], g->ws[i].X, g->ws[i].A, plans[i]->spec->mult, nullptr, nullptr};
+        m[i].n = plans[i]->n;
+        m[i].shape = plans[i]->shape;
+        m[i].tw_hi = f32 ? plans[i]->tw->hi32 : plans[i]->tw->w64;
+        m[i].tw_lo = f32 ? plans[i]->tw->lo32 : nullptr;
     }
-    if (hipMalloc((void **)&g->table, count * sizeof(Job)) != hipSuccess ||
-        hipMemcpy(g->table, jobs.data(), count * sizeof(Job), hipMemcpyHostToDevice) != hipSuccess) {
+    if (persist_prepare() != hipSuccess) {
         (void)hipGetLastError();
         graph_free(g);
-        return fail(PSP_ENOMEM, "graph job table allocation failed");
+        return fail(PSP_EHIP, "occupancy query failed");
+    }
+    // the batch image is written once, before capture; each replay clears
+    // the persistent counters with a kernel (no memset node in the graph)
+    BatchImage img;
+    std::vector<unsigned char> host;
+    if (hipMalloc((void **)&g->table, batch_image_bytes(m)) != hipSuccess) {
+        (void)hipGetLastError();
+        g->table = nullptr;
+        graph_free(g);
+        return fail(PSP_ENOMEM, "graph batch table allocation failed");
+    }
+    build_batch_image(m, f32, g->table, &img, host);
+    if (hipMemcpy(g->table, host.data(), img.bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipGetLastError();
+        graph_free(g);
+        return fail(PSP_EHIP, "graph batch table upload failed");
     }
     psp_status rs = capture(g, (hipStream_t)stream, [&](hipStream_t cs) -> hipError_t {
-        int k = 0;
-        while (k < count) {
-            int j = k;
-            const psp_plan *p0 = plans[order[k]];
-            while (j < count && plans[order[j]]->n == p0->n && plans[order[j]]->shape == p0->shape) ++j;
-            const Twiddles *tw = p0->tw;
-            hipError_t e = launch_group(p0->n, f32, p0->shape, g->table + k, j - k, f32 ? tw->hi32 : tw->w64,
-                                        f32 ? tw->lo32 : nullptr, cs);
-            if (e != hipSuccess) return e;
-            k = j;
-        }
-        return hipSuccess;
+        return launch_batch_image(m, img, f32, g->table, true, cs);
     });
     if (rs != PSP_OK) {
         graph_free(g);

@@ -67,6 +67,30 @@ inline size_t workspace_bytes(int n, bool f32, int chunk_tiles, int i1_group = 0
     return c * (P * (size_t)x_slabs(n, f32, chunk_tiles, i1_group) * n + PA * (size_t)n * 2 * n);
 }
 psp_status alloc_workspace(int n, bool f32, int chunk_tiles, Workspace *w, int i1_group = 0);
+
+// ---- batches: the device image of a batch -----------------------------------
+struct BatchMember {
+    Job job;                      // pointers; workspace of one chunk holding all tiles
+    int n = 0;
+    Shape shape;
+    const void *tw_hi = nullptr;  // twiddles of length 2n
+    const void *tw_lo = nullptr;
+};
+struct BatchImage {
+    std::vector<int> persist;     // members on the persistent path (2n <= PB_MAX_N), in table order
+    std::vector<int> grouped;     // the others, sorted by (n, shape)
+    size_t hdr_off = 0, jobs_off = 0, start_off = 0, group_off = 0, bytes = 0;
+    int total[kPasses] = {0, 0, 0, 0, 0};
+};
+size_t batch_image_bytes(const std::vector<BatchMember> &m);
+// host copy of the image for the device buffer at dev_base (its pointers
+// point into that buffer); the persistent counters are zero in it
+void build_batch_image(const std::vector<BatchMember> &m, bool f32, unsigned char *dev_base, BatchImage *img,
+                       std::vector<unsigned char> &host);
+// the passes of an uploaded image; reset: clear the counters with a kernel
+// first (graph replays)
+hipError_t launch_batch_image(const std::vector<BatchMember> &m, const BatchImage &img, bool f32,
+                              unsigned char *dev_base, bool reset, hipStream_t st);
 void free_workspace(Workspace *w);
 inline size_t spectrum_bytes(int n) { return 8 * (size_t)(n + 1) * (n + 1) * pitch_for(n); }
 

@@ -55,6 +55,47 @@ inline bool shape_valid(int n, const Shape &s) {
     return true;
 }
 
+// ------------------------------------------------ persistent batched passes
+constexpr int PB_THREADS = 384;   // workgroup size: divisible by every threads-per-column count
+constexpr int PB_MAX_N = 256;     // largest padded length on the persistent path
+
+// One solve of a persistent batch (device table entry).
+struct PJob {
+    const void *rho;
+    void *u;
+    void *X;                 // n*n*P complex
+    void *A;                 // n*N*pa complex
+    const double *mult;      // blocked multiplier octant
+    const void *tw_hi;       // twiddles of length N (FP64, or FP32 hi)
+    const void *tw_lo;       // FP32 lo
+    int N;                   // padded length
+    int P;                   // k3 pitch of X
+    int pa;                  // k3 pitch of A
+    int pv[kPasses];         // radix plan of each pass
+};
+
+// Batch header in device memory.  counter[p] must be zero when pass p
+// starts; start[p * (njobs + 1) + j] is the first item of job j in pass p
+// (start[p * (njobs + 1) + njobs] = total[p]).
+struct PBatch {
+    int counter[kPasses];
+    int total[kPasses];
+    int njobs;
+    int pad_;
+    const PJob *jobs;
+    const int *start;
+};
+
+// threads per column (strided passes) or per line (line passes) of the
+// persistent kernels for padded length N and radix plan pv
+int persist_tpc(int N, int pv);
+// occupancy queries of the persistent kernels, cached per device (call once
+// outside graph capture)
+hipError_t persist_prepare();
+// the five persistent passes over the batch whose header is at d_hdr;
+// reset: clear the counters first (a kernel, so graphs may capture it)
+hipError_t persist_launch(bool f32, PBatch *d_hdr, const int *total, bool reset, hipStream_t st);
+
 // One solve's buffers (device pointers) and sizes.
 struct SolveArgs {
     int n = 0;          // points per axis; padded length N = 2n

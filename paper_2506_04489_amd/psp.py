@@ -28,6 +28,7 @@ SIGNATURES = {
     "psp_kernel_precompute": (_i, [_vp, _vp]),
     "psp_solve": (_i, [_vp, _vp, _vp, _vp]),
     "psp_solve_batched": (_i, [_i, _P(_vp), _P(_vp), _P(_vp), _vp]),
+    "psp_set_batch_mode": (_i, [_i]),
     "psp_solve_padded_debug": (_i, [_vp, _vp, _vp, _vp]),
     "psp_plan_get_gs": (_i, [_vp, _P(_d), _P(_d)]),
     "psp_plan_get_tables": (_i, [_vp, _P(_d), _P(_d)]),
@@ -119,6 +120,15 @@ def _ints5(v):
     if len(v) != 5:
         raise ValueError("a shape has 5 entries (passes H1..H5)")
     return (ctypes.c_int * 5)(*v)
+
+
+def set_batch_mode(mode: str):
+    """'grouped' (default): one launch per pass per (n, shape); 'persistent':
+    persistent kernels over every solve with 2n <= 256."""
+    codes = {"grouped": 0, "persistent": 1}
+    if mode not in codes:
+        raise ValueError("mode must be 'grouped' or 'persistent'")
+    _check(lib().psp_set_batch_mode(codes[mode]))
 
 
 def tuning_set(n: int, dtype, plan, tile):

@@ -161,3 +161,13 @@ def test_shipped_tuning_table_is_valid():
         assert key not in seen
         seen.add(key)
         assert B.tuning_get(e["n"], e["dtype"]) == (e["plan"], e["tile"])
+
+
+def test_batch_mode_validation():
+    lib = B.lib()
+    assert lib.psp_set_batch_mode(2) == -1         # PSP_EINVAL
+    assert lib.psp_set_batch_mode(-1) == -1
+    with pytest.raises(ValueError):
+        B.set_batch_mode("fast")
+    B.set_batch_mode("persistent")
+    B.set_batch_mode("grouped")

@@ -29,8 +29,15 @@ def _setup(count, dtype, seed):
     return items, plans, rhos
 
 
+@pytest.fixture(params=["grouped", "persistent"])
+def batch_mode(request):
+    B.set_batch_mode(request.param)
+    yield request.param
+    B.set_batch_mode("grouped")
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_batched_mixed_sizes_bitwise_equal_to_single(dtype):
+def test_batched_mixed_sizes_bitwise_equal_to_single(dtype, batch_mode):
     import torch
     items, plans, rhos = _setup(24, dtype, D.BATCH_SEED)
     ps = [plans[it.n] for it in items]
@@ -43,7 +50,7 @@ def test_batched_mixed_sizes_bitwise_equal_to_single(dtype):
         assert torch.equal(u, alone), p.n
 
 
-def test_batched_parity_with_oracle():
+def test_batched_parity_with_oracle(batch_mode):
     import torch
     items, plans, rhos = _setup(6, "f64", 7)
     ps = [plans[it.n] for it in items]
@@ -59,7 +66,7 @@ def test_batched_parity_with_oracle():
         assert e <= 1e-12
 
 
-def test_batched_repeated_calls_reuse_staging():
+def test_batched_repeated_calls_reuse_staging(batch_mode):
     import torch
     items, plans, rhos = _setup(10, "f64", 11)
     ps = [plans[it.n] for it in items]
@@ -104,12 +111,13 @@ def test_graph_single_replays_match_eager():
     g.close()
 
 
-def test_graph_batched_replays_match_eager():
+def test_graph_batched_replays_match_eager(batch_mode):
     import torch
     items, plans, rhos = _setup(12, "f64", 13)
     ps = [plans[it.n] for it in items]
     us = [torch.empty_like(r) for r in rhos]
     g = B.Graph.capture_batched(ps, rhos, us)
+    B.set_batch_mode("grouped")       # replays keep the mode of their capture
     for rep in range(3):
         for r in rhos:
             r.mul_(-1.25)
@@ -119,3 +127,30 @@ def test_graph_batched_replays_match_eager():
         for p, r, u in zip(ps, rhos, us):
             assert torch.equal(u, p.solve(r)), (rep, p.n)
     g.close()
+
+
+def test_persistent_batch_covers_every_size_and_large_members():
+    """Every padded length up to 256 (radix-2 and radix-3 plans, alternative
+    radix plans) in one persistent batch, with n = 192 members taking the
+    grouped launches in the same call."""
+    import torch
+    B.set_batch_mode("persistent")
+    try:
+        sizes = [4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192]
+        ps, rhos = [], []
+        for i, n in enumerate(sizes):
+            p = B.Plan(n, 2.0 / n, 40).precompute()
+            if n in (64, 128):
+                p.set_shape([1] * 5, [0] * 5)
+            ps.append(p)
+            g = torch.Generator().manual_seed(31 + i)
+            rhos.append(torch.randn((n,) * 3, generator=g, dtype=torch.float64).cuda())
+        us = [torch.empty_like(r) for r in rhos]
+        B.solve_batched(ps, rhos, us)
+        torch.cuda.synchronize()
+        for p, r, u in zip(ps, rhos, us):
+            alone = p.solve(r)
+            torch.cuda.synchronize()
+            assert torch.equal(u, alone), p.n
+    finally:
+        B.set_batch_mode("grouped")
