@@ -138,7 +138,8 @@ psp_status psp_plan_set_tuning(psp_plan *p, int k3_tiles, int i1_group);
  *            128-byte row of k3 columns per workgroup (8 FP64 or 16 FP32
  *            columns), 1: half of one, 2: one row with the exchanges between
  *            FFT stages through half-size LDS buffers, 3: one row with half
- *            the threads per column (two butterflies per thread and stage).
+ *            the threads per column (two butterflies per thread and stage),
+ *            4: one row with both of the last two.
  * A tile choice changes only which workgroup transforms which column and how
  * values move between stages: the results are bitwise the same.  A radix plan changes the rounding, not the
  * accuracy class.  Batched solves and graphs group their members by (n,
@@ -160,8 +161,8 @@ psp_status psp_tuning_get(int n, psp_dtype dtype, int *plan, int *tile);
  * default unless another is at least 1% faster), sets it as the plan's shape
  * and enters it in the tuning table.  Outputs (host arrays, each may be
  * NULL): best_plan[5], best_tile[5], best_ms[5] the chosen candidate and
- * that pass's time in ms; cand_ms[5 * 8]: the time of candidate
- * (plan, tile) of pass i at cand_ms[i * 8 + plan * 4 + tile], -1 where the
+ * that pass's time in ms; cand_ms[5 * 10]: the time of candidate
+ * (plan, tile) of pass i at cand_ms[i * 10 + plan * 5 + tile], -1 where the
  * candidate does not exist.  Allocates two n^3
  * buffers for the duration; synchronises `stream`.  PSP_ESTATE before
  * precompute or while profiling; PSP_EINVAL for reps outside [1, 1000]. */

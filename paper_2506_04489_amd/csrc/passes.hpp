@@ -344,6 +344,8 @@ template <typename T, typename F> inline void with_cols(int tile, F &&f) {
         f(StridedTile<LW, true, false>{});
     else if (tile == 3)
         f(StridedTile<LW, false, true>{});
+    else if (tile == 4)
+        f(StridedTile<LW, true, true>{});
     else
         f(StridedTile<LW, false, false>{});
 }

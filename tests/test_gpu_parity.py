@@ -138,6 +138,18 @@ def test_config_bump_n256_sampled(dtype, tol):
     assert e <= tol
 
 
+@pytest.mark.parametrize("dtype,tol", [("f64", TOL64), ("f32", TOL32)])
+def test_largest_size_n384_sampled(dtype, tol):
+    # n = 384 (padded 768 = 2^8 * 3, the serving stream's largest size) with
+    # its tuned launch shapes, oscillatory density of the serving family
+    n = 384
+    h = 2.0 / n
+    rho = D.oscillatory(n, h, -1.0, a=0.2, omega=15.0)
+    e = _sampled_parity(rho, h, 40, dtype, 4)
+    print("oscillatory n=384 %s sampled E_par=%.3e" % (dtype, e))
+    assert e <= tol
+
+
 @pytest.mark.parametrize("n", [96, 192])
 def test_radix3_sizes_sampled(n):
     h = 2.0 / n
