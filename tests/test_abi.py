@@ -171,3 +171,7 @@ def test_batch_mode_validation():
         B.set_batch_mode("fast")
     B.set_batch_mode("persistent")
     B.set_batch_mode("grouped")
+
+
+def test_empty_batch_is_a_no_op():
+    assert B.lib().psp_solve_batched(0, None, None, None, None) == 0
