@@ -13,7 +13,9 @@ derived from the printed u* (and checked symbolically in the tests).
   * bump u* = exp(-d/(1 - r^2/R^2)) (eq. bump).  The printed rho's exponent and
     its ``-d R^2 r^2`` term do not match u*; ``-Lap u*`` is
     ``2 d R^2 (3R^4 - 2R^2 r^2 - r^4 - 2 d R^2 r^2)/(R^2 - r^2)^4
-    exp(-d R^2/(R^2 - r^2))``.
+    exp(-d R^2/(R^2 - r^2))``;
+  * the benchmark's oscillatory density through the heat semigroup, and its
+    C-infinity bump through the radial potential integral (1D quadratures).
 """
 from __future__ import annotations
 
@@ -116,3 +118,48 @@ def cube_abs_integral(a: float) -> float:
     mp.mp.dps = 30
     I = mp.quad(lambda s, t: mp.sqrt(1 + s * s + t * t), [0, 1], [0, 1])
     return float(6 * mp.mpf(a) ** 4 * I)
+
+
+def oscillatory_heat_potential(points, x0, h, a=0.2, omega=20.0, s_lo=-40.0, s_hi=12.0, m=6001):
+    """u at grid indices ``points`` (P, 3) for the density
+    ``exp(-|x|^2/a^2) sin(w x1) cos(w x2) sin(w x3)`` on the grid
+    ``x = x0 + j h``, from the heat semigroup: with -Lap u = rho and u -> 0,
+    ``u = int_0^inf (exp(t Lap) rho) dt``.  rho is a product of 1D factors
+    ``exp(-x^2/a^2) exp(i w x)`` (imaginary part for sin, real part for
+    cos), and the 1D heat flow maps that factor to
+    ``sqrt(a^2/(a^2+4t)) exp(-(x - i w a^2/2)^2/(a^2+4t) - w^2 a^2/4)``.
+    The t integral is a trapezoid rule in s = ln t on [s_lo, s_hi], where the
+    integrand is negligible at both ends."""
+    pts = np.asarray(points, dtype=np.float64).reshape(-1, 3)
+    x = x0 + h * pts
+    s = np.linspace(s_lo, s_hi, m)
+    t = np.exp(s)[None, :]
+    d = a * a + 4.0 * t
+
+    def flow(xp):
+        z = xp[:, None] - 0.5j * omega * a * a
+        return np.sqrt(a * a / d) * np.exp(-z * z / d - omega * omega * a * a / 4.0)
+
+    g = flow(x[:, 0]).imag * flow(x[:, 1]).real * flow(x[:, 2]).imag * t
+    ds = (s_hi - s_lo) / (m - 1)
+    return ds * (g.sum(axis=1) - 0.5 * (g[:, 0] + g[:, -1]))
+
+
+def bump_radial_potential(r, radius=0.6):
+    """The potential of the radial bump ``exp(-1/(1 - s^2/R^2))`` (s < R):
+    ``u(r) = (1/r) int_0^r s^2 rho(s) ds + int_r^R s rho(s) ds``, the
+    exterior-shell and interior-ball contributions of 1/(4 pi |x - y|), by
+    adaptive quadrature (relative tolerance 1e-13)."""
+    from scipy.integrate import quad
+
+    def rho(s):
+        q = 1.0 - (s / radius) ** 2
+        return math.exp(-1.0 / q) if q > 0 else 0.0
+
+    out = []
+    for rv in np.atleast_1d(np.asarray(r, dtype=np.float64)):
+        rc = min(rv, radius)
+        inner = quad(lambda s: s * s * rho(s), 0.0, rc, epsabs=0.0, epsrel=1e-13, limit=400)[0] if rc > 0 else 0.0
+        outer = quad(lambda s: s * rho(s), rc, radius, epsabs=0.0, epsrel=1e-13, limit=400)[0] if rc < radius else 0.0
+        out.append(inner / rv + outer if rv > 0 else outer)
+    return np.array(out)
