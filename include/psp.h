@@ -137,9 +137,11 @@ psp_status psp_plan_set_tuning(psp_plan *p, int k3_tiles, int i1_group);
  *            threads, 1: 128, 2: 512; passes 1..3 (along i2, i1, i2): 0: one
  *            128-byte row of k3 columns per workgroup (8 FP64 or 16 FP32
  *            columns), 1: half of one, 2: one row with the exchanges between
- *            FFT stages through half-size LDS buffers, 3: one row with half
- *            the threads per column (two butterflies per thread and stage),
- *            4: one row with both of the last two.
+ *            FFT stages through half-size LDS buffers by position half,
+ *            3: one row with half the threads per column (two butterflies
+ *            per thread and stage), 4: 2 and 3 together, 5: one row with the
+ *            exchanges through half-size LDS buffers by column half, 6: 5 and
+ *            3 together.
  * A tile choice changes only which workgroup transforms which column and how
  * values move between stages: the results are bitwise the same.  A radix plan changes the rounding, not the
  * accuracy class.  Batched solves and graphs group their members by (n,
@@ -161,8 +163,8 @@ psp_status psp_tuning_get(int n, psp_dtype dtype, int *plan, int *tile);
  * default unless another is at least 1% faster), sets it as the plan's shape
  * and enters it in the tuning table.  Outputs (host arrays, each may be
  * NULL): best_plan[5], best_tile[5], best_ms[5] the chosen candidate and
- * that pass's time in ms; cand_ms[5 * 10]: the time of candidate
- * (plan, tile) of pass i at cand_ms[i * 10 + plan * 5 + tile], -1 where the
+ * that pass's time in ms; cand_ms[5 * 14]: the time of candidate
+ * (plan, tile) of pass i at cand_ms[i * 14 + plan * 7 + tile], -1 where the
  * candidate does not exist.  Allocates two n^3
  * buffers for the duration; synchronises `stream`.  PSP_ESTATE before
  * precompute or while profiling; PSP_EINVAL for reps outside [1, 1000]. */
@@ -209,7 +211,9 @@ void psp_graph_destroy(psp_graph *g);
  * admitted requests are grouped per tier into batched launches on a small
  * stream pool, so new arrivals overlap work already on the device.  Spectra
  * are cached per (n, h, R) on the device in LRU order inside the budget.
- * rho_dev/u_dev stay caller-owned and must live until the request is done. */
+ * rho_dev/u_dev stay caller-owned and must live until the request is done;
+ * rho must be fully written (its producing work complete) when submitted,
+ * since the loop reads it on its own streams. */
 psp_status psp_serve_create(size_t hbm_budget_bytes, int max_slots, psp_server **out);
 
 /* Non-blocking enqueue; *ticket identifies the request.  PSP_EBUSY if the
@@ -220,7 +224,9 @@ psp_status psp_serve_submit(psp_server *sv, int n, double h, int R, psp_dtype ti
 
 /* Non-blocking status: *done = 1 once u is complete on the device; then
  * *result is the request's status and *latency_ms its submit-to-completion
- * time.  Unknown ticket: PSP_EINVAL.  Any output pointer may be NULL. */
+ * time.  The server keeps the outcome of the most recent 2^20 completed
+ * requests; an older or unknown ticket gives PSP_EINVAL.  Any output pointer
+ * may be NULL. */
 psp_status psp_serve_poll(psp_server *sv, uint64_t ticket, int *done, psp_status *result,
                           double *latency_ms);
 

@@ -378,6 +378,28 @@ template <typename T, int N, int TPC, bool INV, int PV = 0> struct Engine {
         }
     }
 
+    // stages [s, S) with every exchange in two phases by column half: the
+    // threads of the first half of the workgroup's columns store and load
+    // through an LDS buffer of half the columns, then those of the second
+    // half (idx addresses the half buffer).  Each thread stores all its
+    // values before loading, so no value needs a staging register.
+    template <int s, typename Idx>
+    __device__ __forceinline__ static void run_from_cols(C *v, C *lds, int t, Idx idx, const Twiddle<T> &tw,
+                                                         bool first_half) {
+        compute<s>(v, t, tw);
+        if constexpr (s + 1 < S) {
+            if (first_half) store_lds<s>(v, lds, t, idx);
+            __syncthreads();
+            if (first_half) load_lds<s + 1>(v, lds, t, idx);
+            __syncthreads();
+            if (!first_half) store_lds<s>(v, lds, t, idx);
+            __syncthreads();
+            if (!first_half) load_lds<s + 1>(v, lds, t, idx);
+            __syncthreads();
+            run_from_cols<s + 1>(v, lds, t, idx, tw, first_half);
+        }
+    }
+
     // visit the final outputs: f(position, leg r, value&); legs r < R/2 of
     // the last stage are exactly the positions below N/2
     template <typename F>

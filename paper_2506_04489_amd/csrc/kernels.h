@@ -22,14 +22,15 @@ struct Job {
 //   tile[p]: H1/H5 (p = 0, 4): workgroup size, 0: 256 threads, 1: 128, 2: 512;
 //            H2-H4 (p = 1..3): 0: one 128-byte row tile of k3 columns per
 //            workgroup (8 FP64 / 16 FP32 columns), 1: half of one, 2: one
-//            tile with exchanges through half-size LDS buffers, 3: one tile
-//            with half the threads per column (two butterflies each), 4: both
-//            of the last two
+//            tile with exchanges through half-size LDS buffers by position
+//            half, 3: one tile with half the threads per column (two
+//            butterflies each), 4: 2 and 3, 5: one tile with exchanges
+//            through half-size LDS buffers by column half, 6: 5 and 3
 // A tile choice only changes which workgroup transforms which column and how
 // values move between stages, so results are bitwise the same under every
 // tile choice.
 constexpr int kPasses = 5;
-constexpr int kTileChoices[kPasses] = {3, 5, 5, 5, 3};
+constexpr int kTileChoices[kPasses] = {3, 7, 7, 7, 3};
 struct Shape {
     int plan[kPasses] = {0, 0, 0, 0, 0};
     int tile[kPasses] = {0, 0, 0, 0, 0};

@@ -36,18 +36,19 @@ template <typename T> struct LayoutTile;
 template <> struct LayoutTile<double> { static constexpr int W = 8; };
 template <> struct LayoutTile<float> { static constexpr int W = 16; };
 
-// strided passes: W columns per workgroup, TPC threads per column; SPLIT:
-// every exchange between stages goes through an LDS buffer of half the
-// positions in two phases (half the LDS, so more workgroups per CU, for
-// twice the barriers); HALF: half the threads per column, each with twice
-// the butterflies of a stage (fewer waves, more independent work per wave)
-template <typename T, int N, int PV, int W, bool SPLIT_ = false, bool HALF = false> struct StridedCfg {
+// strided passes: W columns per workgroup, TPC threads per column.  XCH:
+// how values move between FFT stages: 0 through an LDS buffer of all N x W
+// positions; 1 in two phases by position half (half the LDS, a staging copy
+// in registers); 2 in two phases by column half (half the LDS, no staging).
+// HALF: half the threads per column, each with twice the butterflies of a
+// stage (fewer waves, more independent work per wave).
+template <typename T, int N, int PV, int W, int XCH_ = 0, bool HALF = false> struct StridedCfg {
     static constexpr int TPC1 = N / MaxRadix<N, PV>::value();
     static constexpr int TPC0 = (HALF && TPC1 >= 2) ? TPC1 / 2 : TPC1;
     static constexpr int TPC = (TPC0 * W > 1024) ? TPC0 / 2 : TPC0;
     static constexpr int THREADS = TPC * W;
-    static constexpr bool SPLIT = SPLIT_;
-    static constexpr int LDS_ELEMS = SPLIT ? N * W / 2 : N * W;
+    static constexpr int XCH = XCH_;
+    static constexpr int LDS_ELEMS = XCH ? N * W / 2 : N * W;
     static constexpr int SUB = LayoutTile<T>::W / W;     // workgroups per row tile
 };
 
@@ -67,6 +68,15 @@ struct IdxLine {                     // column-major, one padding slot per 8 pos
     int base;
     __device__ __forceinline__ int operator()(int pos) const { return base + pos + (pos >> 3); }
 };
+
+// the FFT stages of a strided pass with the configuration's exchange
+template <typename E, typename Cfg, int W, typename C, typename T>
+__device__ __forceinline__ void strided_stages(C *v, C *lds, int t, int col, const Twiddle<T> &tw) {
+    if constexpr (Cfg::XCH == 2)
+        E::template run_from_cols<0>(v, lds, t, IdxInter<W / 2>{col % (W / 2)}, tw, col < W / 2);
+    else
+        E::template run_from<0, Cfg::XCH == 1>(v, lds, t, IdxInter<W>{col}, tw);
+}
 
 // Per-solve device pointers.  A single solve passes them as a kernel
 // argument; a batched launch passes a device table and takes entry
@@ -138,11 +148,11 @@ __device__ __forceinline__ size_t a_index(int pa, int c, int k2, int i1) {
 }
 
 // ------------------------------------------------------------------- H2
-template <typename T, int N, int PV, int W, bool SP, bool HF>
-__global__ void __launch_bounds__((StridedCfg<T, N, PV, W, SP, HF>::THREADS))
+template <typename T, int N, int PV, int W, int XC, bool HF>
+__global__ void __launch_bounds__((StridedCfg<T, N, PV, W, XC, HF>::THREADS))
 k_y_fwd(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
     using C = cplx<T>;
-    using Cfg = StridedCfg<T, N, PV, W, SP, HF>;
+    using Cfg = StridedCfg<T, N, PV, W, XC, HF>;
     using E = Engine<T, N, Cfg::TPC, false, PV>;
     constexpr int n = N / 2;
     __shared__ C lds[Cfg::LDS_ELEMS];
@@ -159,7 +169,7 @@ k_y_fwd(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
         if (r < E::R(0) / 2 && valid) return src[(size_t)pos * P];
         return c_zero<C>();
     });
-    E::template run_from<0, Cfg::SPLIT>(v, lds, t, IdxInter<W>{col}, tw);
+    strided_stages<E, Cfg, W>(v, lds, t, col, tw);
     E::for_outputs(v, t, [&](int pos, int, C &val) { dst[(size_t)pos * ck.pa] = val; });
 }
 
@@ -169,11 +179,11 @@ k_y_fwd(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
 // to workgroups g and g + 8, which the dispatcher places on the same XCD at
 // nearly the same time, so the second read of the block hits that XCD's L2.
 // FULL (test hook): all N outputs of the inverse go to A2[i1][k2][k3] (pitch P).
-template <typename T, int N, int PV, int W, bool SP, bool HF, bool FULL>
-__global__ void __launch_bounds__((StridedCfg<T, N, PV, W, SP, HF>::THREADS))
+template <typename T, int N, int PV, int W, int XC, bool HF, bool FULL>
+__global__ void __launch_bounds__((StridedCfg<T, N, PV, W, XC, HF>::THREADS))
 k_x_fused(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
     using C = cplx<T>;
-    using Cfg = StridedCfg<T, N, PV, W, SP, HF>;
+    using Cfg = StridedCfg<T, N, PV, W, XC, HF>;
     using EF = Engine<T, N, Cfg::TPC, false, PV>;
     using EI = Engine<T, N, Cfg::TPC, true, PV>;
     constexpr int n = N / 2;
@@ -198,13 +208,13 @@ k_x_fused(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
         if (r < EF::R(0) / 2 && valid) return src[pos * step];
         return c_zero<C>();
     });
-    EF::template run_from<0, Cfg::SPLIT>(v, lds, t, IdxInter<W>{col}, tw);
+    strided_stages<EF, Cfg, W>(v, lds, t, col, tw);
     EF::for_outputs(v, t, [&](int pos, int, C &val) {
         const int a = pos <= n ? pos : N - pos;
         const double m = mrow[(size_t)a * 8];
         val = C{T((double)val.x * m), T((double)val.y * m)};
     });
-    EI::template run_from<0, Cfg::SPLIT>(v, lds, t, IdxInter<W>{col}, tw);
+    strided_stages<EI, Cfg, W>(v, lds, t, col, tw);
     if constexpr (!FULL) {
         C *dst = (C *)jb.A + a_index<N>(ck.pa, c, k2, 0);
         EI::for_outputs(v, t, [&](int pos, int r, C &val) {
@@ -221,11 +231,11 @@ k_x_fused(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
 // ------------------------------------------------------------------- H4
 // FULL (test hook): reads A2[i1][k2][k3] for all N rows i1 and writes all N
 // outputs to Y2[i1][i2][k3] (pitch P).
-template <typename T, int N, int PV, int W, bool SP, bool HF, bool FULL>
-__global__ void __launch_bounds__((StridedCfg<T, N, PV, W, SP, HF>::THREADS))
+template <typename T, int N, int PV, int W, int XC, bool HF, bool FULL>
+__global__ void __launch_bounds__((StridedCfg<T, N, PV, W, XC, HF>::THREADS))
 k_y_inv(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
     using C = cplx<T>;
-    using Cfg = StridedCfg<T, N, PV, W, SP, HF>;
+    using Cfg = StridedCfg<T, N, PV, W, XC, HF>;
     using E = Engine<T, N, Cfg::TPC, true, PV>;
     constexpr int n = N / 2;
     __shared__ C lds[Cfg::LDS_ELEMS];
@@ -249,7 +259,7 @@ k_y_inv(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
             return c_zero<C>();
         });
     }
-    E::template run_from<0, Cfg::SPLIT>(v, lds, t, IdxInter<W>{col}, tw);
+    strided_stages<E, Cfg, W>(v, lds, t, col, tw);
     constexpr int rows_out = FULL ? N : n;
     C *dst = (C *)(FULL ? jb.Y2 : jb.X) + (size_t)i1 * rows_out * P + cg;
     E::for_outputs(v, t, [&](int pos, int r, C &val) {
@@ -331,23 +341,22 @@ template <int N, typename F> inline void with_plan(int pv, F &&f) {
     }
     f(std::integral_constant<int, 0>{});
 }
-template <int W_, bool SP_, bool HF_> struct StridedTile {
+template <int W_, int XC_, bool HF_> struct StridedTile {
     static constexpr int W = W_;
-    static constexpr bool SP = SP_;
+    static constexpr int XC = XC_;
     static constexpr bool HF = HF_;
 };
 template <typename T, typename F> inline void with_cols(int tile, F &&f) {
     constexpr int LW = LayoutTile<T>::W;
-    if (tile == 1)
-        f(StridedTile<LW / 2, false, false>{});
-    else if (tile == 2)
-        f(StridedTile<LW, true, false>{});
-    else if (tile == 3)
-        f(StridedTile<LW, false, true>{});
-    else if (tile == 4)
-        f(StridedTile<LW, true, true>{});
-    else
-        f(StridedTile<LW, false, false>{});
+    switch (tile) {
+        case 1: f(StridedTile<LW / 2, 0, false>{}); break;
+        case 2: f(StridedTile<LW, 1, false>{}); break;
+        case 3: f(StridedTile<LW, 0, true>{}); break;
+        case 4: f(StridedTile<LW, 1, true>{}); break;
+        case 5: f(StridedTile<LW, 2, false>{}); break;
+        case 6: f(StridedTile<LW, 2, true>{}); break;
+        default: f(StridedTile<LW, 0, false>{}); break;
+    }
 }
 template <typename F> inline void with_threads(int tile, F &&f) {
     if (tile == 1)
@@ -386,16 +395,16 @@ hipError_t passes_impl(const Job &one, const Job *table, int count, int P, int c
     if (full) {
         // uncropped variant (one chunk, default shape): A2 and Y2 (N x N x P,
         // row layout) receive all N outputs of the inverse transforms
-        using SC = StridedCfg<T, N, 0, LW, false, false>;
+        using SC = StridedCfg<T, N, 0, LW, 0, false>;
         using LC = LineCfg<T, N, 0, 256>;
         const JobRef jr{one, table};
         const Chunk ck{0, ntile, ntile * LW};
         hipLaunchKernelGGL((k_z_r2c<T, N, 0, 256>), dim3(ceil_div(n * n / 2, LC::Q), y), dim3(LC::THREADS), 0, st,
                            jr, n * n / 2, P, tw);
-        hipLaunchKernelGGL((k_y_fwd<T, N, 0, LW, false, false>), dim3(n * ntile, y), dim3(SC::THREADS), 0, st, jr, ck, P, tw);
-        hipLaunchKernelGGL((k_x_fused<T, N, 0, LW, false, false, true>), dim3(ceil_div((long)(n + 1) * ntile, 8) * 16, y),
+        hipLaunchKernelGGL((k_y_fwd<T, N, 0, LW, 0, false>), dim3(n * ntile, y), dim3(SC::THREADS), 0, st, jr, ck, P, tw);
+        hipLaunchKernelGGL((k_x_fused<T, N, 0, LW, 0, false, true>), dim3(ceil_div((long)(n + 1) * ntile, 8) * 16, y),
                            dim3(SC::THREADS), 0, st, jr, ck, P, tw);
-        hipLaunchKernelGGL((k_y_inv<T, N, 0, LW, false, false, true>), dim3(N * ntile, y), dim3(SC::THREADS), 0, st, jr, ck, P,
+        hipLaunchKernelGGL((k_y_inv<T, N, 0, LW, 0, false, true>), dim3(N * ntile, y), dim3(SC::THREADS), 0, st, jr, ck, P,
                            tw);
         hipLaunchKernelGGL((k_z_c2r<T, N, 0, 256, true>), dim3(ceil_div(N * N / 2, LC::Q), y), dim3(LC::THREADS),
                            0, st, jr, N * N / 2, P, tw);
@@ -415,10 +424,11 @@ hipError_t passes_impl(const Job &one, const Job *table, int count, int P, int c
         with_plan<N>(sh.plan[1], [&](auto pv) {
             with_cols<T>(sh.tile[1], [&](auto w) {
                 constexpr int PV = decltype(pv)::value, W = decltype(w)::W;
-                constexpr bool SP = decltype(w)::SP, HF = decltype(w)::HF;
-                using SC = StridedCfg<T, N, PV, W, SP, HF>;
-                hipLaunchKernelGGL((k_y_fwd<T, N, PV, W, SP, HF>), dim3(rows * ck.ntile * SC::SUB, y), dim3(SC::THREADS),
-                                   0, st, jr, ck, P, tw);
+                constexpr int XC = decltype(w)::XC;
+                constexpr bool HF = decltype(w)::HF;
+                using SC = StridedCfg<T, N, PV, W, XC, HF>;
+                hipLaunchKernelGGL((k_y_fwd<T, N, PV, W, XC, HF>), dim3(rows * ck.ntile * SC::SUB, y),
+                                   dim3(SC::THREADS), 0, st, jr, ck, P, tw);
             });
         });
     };
@@ -426,9 +436,10 @@ hipError_t passes_impl(const Job &one, const Job *table, int count, int P, int c
         with_plan<N>(sh.plan[2], [&](auto pv) {
             with_cols<T>(sh.tile[2], [&](auto w) {
                 constexpr int PV = decltype(pv)::value, W = decltype(w)::W;
-                constexpr bool SP = decltype(w)::SP, HF = decltype(w)::HF;
-                using SC = StridedCfg<T, N, PV, W, SP, HF>;
-                hipLaunchKernelGGL((k_x_fused<T, N, PV, W, SP, HF, false>),
+                constexpr int XC = decltype(w)::XC;
+                constexpr bool HF = decltype(w)::HF;
+                using SC = StridedCfg<T, N, PV, W, XC, HF>;
+                hipLaunchKernelGGL((k_x_fused<T, N, PV, W, XC, HF, false>),
                                    dim3(ceil_div((long)(n + 1) * ck.ntile * SC::SUB, 8) * 16, y), dim3(SC::THREADS),
                                    0, st, jr, ck, P, tw);
             });
@@ -438,9 +449,10 @@ hipError_t passes_impl(const Job &one, const Job *table, int count, int P, int c
         with_plan<N>(sh.plan[3], [&](auto pv) {
             with_cols<T>(sh.tile[3], [&](auto w) {
                 constexpr int PV = decltype(pv)::value, W = decltype(w)::W;
-                constexpr bool SP = decltype(w)::SP, HF = decltype(w)::HF;
-                using SC = StridedCfg<T, N, PV, W, SP, HF>;
-                hipLaunchKernelGGL((k_y_inv<T, N, PV, W, SP, HF, false>), dim3(rows * ck.ntile * SC::SUB, y),
+                constexpr int XC = decltype(w)::XC;
+                constexpr bool HF = decltype(w)::HF;
+                using SC = StridedCfg<T, N, PV, W, XC, HF>;
+                hipLaunchKernelGGL((k_y_inv<T, N, PV, W, XC, HF, false>), dim3(rows * ck.ntile * SC::SUB, y),
                                    dim3(SC::THREADS), 0, st, jr, ck, P, tw);
             });
         });

@@ -77,6 +77,7 @@ struct psp_server {
     std::condition_variable cv_work, cv_done;
     std::deque<uint64_t> queue;
     std::unordered_map<uint64_t, ServeReq> reqs;
+    std::deque<uint64_t> finished;          // completed tickets, oldest first
     uint64_t next_id = 1;
     size_t pending_total = 0;
     bool stop = false;
@@ -175,12 +176,20 @@ static psp_status take_ws(psp_server *sv, int n, bool f32, PooledWs *out) {
     return PSP_OK;
 }
 
+// outcomes of this many completed requests stay available to psp_serve_poll
+constexpr size_t kKeepFinished = size_t(1) << 20;
+
 static void finish(psp_server *sv, uint64_t id, psp_status st) {
     std::lock_guard<std::mutex> lk(sv->mu);
     auto &r = sv->reqs[id];
     r.done = true;
     r.result = st;
     r.latency_ms = std::chrono::duration<double, std::milli>(Clock::now() - r.t_submit).count();
+    sv->finished.push_back(id);
+    while (sv->finished.size() > kKeepFinished) {
+        sv->reqs.erase(sv->finished.front());
+        sv->finished.pop_front();
+    }
     sv->pending_total--;
     sv->completed++;
     sv->cv_done.notify_all();
@@ -359,7 +368,8 @@ psp_status psp_serve_poll(psp_server *sv, uint64_t ticket, int *done, psp_status
     if (!sv) return fail(PSP_EINVAL, "server is NULL");
     std::lock_guard<std::mutex> lk(sv->mu);
     auto it = sv->reqs.find(ticket);
-    if (it == sv->reqs.end()) return fail(PSP_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    if (it == sv->reqs.end())
+        return fail(PSP_EINVAL, "unknown or expired ticket %llu", (unsigned long long)ticket);
     if (done) *done = it->second.done ? 1 : 0;
     if (result) *result = it->second.result;
     if (latency_ms) *latency_ms = it->second.latency_ms;

@@ -18,9 +18,37 @@ namespace psp {
 // B[l/16][l%16], D[l/16 + 4e][l%16] for e < 4.
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-// one wave: a 16-row a-tile for one b against CT consecutive 16-wide c-tiles;
-// the A operand of each k-step is formed once and feeds CT MFMAs
-constexpr int SPEC_CT = 4;
+// one wave: a 16-row a-tile for one b against SPEC_CT consecutive 16-wide
+// c-tiles (six: 288 columns cover n + 1 = 257 with one partial tile); the A
+// operand of each k-step is formed once and feeds SPEC_CT MFMAs, and the
+// operands of step k + 4 are loaded before the MFMAs of step k are issued,
+// so the table loads' latency overlaps the matrix work
+constexpr int SPEC_CT = 6;
+
+struct SpecOps {
+    double av;
+    double bv[SPEC_CT];
+};
+
+__device__ __forceinline__ void spec_load(SpecOps &o, int k0, int kq, int a, int b, int cbase, int R, int n,
+                                          const double *__restrict__ J0, const double *__restrict__ J2,
+                                          const double *__restrict__ omega) {
+    const int n1 = n + 1;
+    const int ks = k0 + kq, s = ks >> 1, ty = ks & 1;
+    const bool live = s < R;
+    const double *j0 = J0 + (size_t)(live ? s : 0) * n1, *j2 = J2 + (size_t)(live ? s : 0) * n1;
+    o.av = 0.0;
+    if (live && a <= n) {
+        const double w = omega[s];
+        o.av = ty == 0 ? w * (j2[a] * j0[b] + j0[a] * j2[b]) : w * (j0[a] * j0[b]);
+    }
+    const double *jb = ty == 0 ? j0 : j2;
+#pragma unroll
+    for (int q = 0; q < SPEC_CT; ++q) {
+        const int c = cbase + q * 16;
+        o.bv[q] = (live && c <= n) ? jb[c] : 0.0;
+    }
+}
 
 __global__ void __launch_bounds__(256)
 k_spectrum(const double *__restrict__ J0, const double *__restrict__ J2,
@@ -36,24 +64,18 @@ k_spectrum(const double *__restrict__ J0, const double *__restrict__ J2,
     const int row = lane & 15, kq = lane >> 4;
     const int a = a0 + row;
     const int n1 = n + 1;
+    const int cbase = cgrp * 16 + row;
     v4d acc[SPEC_CT];
 #pragma unroll
     for (int q = 0; q < SPEC_CT; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
+    SpecOps cur, nxt;
+    spec_load(cur, 0, kq, a, b, cbase, R, n, J0, J2, omega);
     for (int k0 = 0; k0 < 2 * R; k0 += 4) {
-        const int ks = k0 + kq, s = ks >> 1, ty = ks & 1;
-        double av = 0.0;
-        const double *j0 = J0 + (size_t)s * n1, *j2 = J2 + (size_t)s * n1;
-        if (s < R && a <= n) {
-            const double w = omega[s];
-            av = ty == 0 ? w * (j2[a] * j0[b] + j0[a] * j2[b]) : w * (j0[a] * j0[b]);
-        }
-        const double *jb = ty == 0 ? j0 : j2;
+        if (k0 + 4 < 2 * R) spec_load(nxt, k0 + 4, kq, a, b, cbase, R, n, J0, J2, omega);
 #pragma unroll
-        for (int q = 0; q < SPEC_CT; ++q) {
-            const int c = (cgrp + q) * 16 + row;
-            const double bv = (s < R && c <= n) ? jb[c] : 0.0;
-            acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[q], 0, 0, 0);
-        }
+        for (int q = 0; q < SPEC_CT; ++q)
+            acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur.av, cur.bv[q], acc[q], 0, 0, 0);
+        cur = nxt;
     }
 #pragma unroll
     for (int q = 0; q < SPEC_CT; ++q) {

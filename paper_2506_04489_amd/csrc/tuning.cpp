@@ -192,10 +192,10 @@ psp_status psp_autotune(psp_plan *p, int reps, void *stream, int *best_plan, int
     }
     shape_to(chosen, best_plan, best_tile);
     if (cand_ms) {
-        for (int i = 0; i < kPasses * 10; ++i) cand_ms[i] = -1.0f;
+        for (int i = 0; i < kPasses * 14; ++i) cand_ms[i] = -1.0f;
         for (int i = 0; i < kPasses; ++i)
             for (size_t c = 0; c < cand[i].size(); ++c)
-                cand_ms[i * 10 + cand[i][c].first * 5 + cand[i][c].second] = best[i][c];
+                cand_ms[i * 14 + cand[i][c].first * 7 + cand[i][c].second] = best[i][c];
     }
     return PSP_OK;
 }

@@ -119,7 +119,7 @@ def test_shape_validation_and_roundtrip():
     assert p.shape() == ([0] * 5, [2, 1, 2, 1, 1])
     for plan, tile in [([1, 0, 0, 0, 0], [0] * 5),   # no alternative plan for 2n = 64
                        ([0] * 5, [3, 0, 0, 0, 0]),   # three workgroup sizes for H1
-                       ([0] * 5, [0, 5, 0, 0, 0]),   # five tile choices for H2
+                       ([0] * 5, [0, 7, 0, 0, 0]),   # seven tile choices for H2
                        ([0] * 5, [0, 0, 0, 0, -1])]:
         with pytest.raises(B.PspError) as ei:
             p.set_shape(plan, tile)

@@ -12,7 +12,7 @@ from tests.gpu_util import announce, rel_max_err
 
 pytestmark = pytest.mark.gpu
 
-TILES = [3, 5, 5, 5, 3]
+TILES = [3, 7, 7, 7, 3]
 
 
 @pytest.fixture(autouse=True)
