@@ -157,8 +157,8 @@ psp_status psp_tuning_set(int n, psp_dtype dtype, const int *plan, const int *ti
 psp_status psp_tuning_get(int n, psp_dtype dtype, int *plan, int *tile);
 
 /* Autotuner: times every (radix plan, tile) candidate of every pass on this
- * plan's own workspace on `stream` (synthetic zero input, `reps` timed
- * solves per candidate round after one warm-up, minimum over repetitions,
+ * plan's own workspace on `stream` (a hashed pseudo-random input, `reps` timed
+ * solves per candidate round after one warm-up, median over repetitions,
  * HIP events around each launch), picks per pass the fastest candidate (the
  * default unless another is at least 1% faster), sets it as the plan's shape
  * and enters it in the tuning table.  Outputs (host arrays, each may be

@@ -40,6 +40,22 @@ static void shape_to(const Shape &s, int *plan, int *tile) {
     }
 }
 
+// a timing input with the statistics of real data: values in [-1, 1) from
+// an integer hash of the index (all-zero input draws less power and so
+// times the arithmetic-heavy candidates too kindly)
+template <typename T>
+__global__ void k_fill_hash(T *p, size_t count) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) {
+        uint32_t x = (uint32_t)i * 2654435761u + 0x9e3779b9u;
+        x ^= x >> 16;
+        x *= 0x7feb352du;
+        x ^= x >> 15;
+        x *= 0x846ca68bu;
+        x ^= x >> 16;
+        p[i] = T((double)x * (2.0 / 4294967296.0) - 1.0);
+    }
+}
+
 // candidates (radix plan, tile) of pass i for size n
 static std::vector<std::pair<int, int>> candidates(int n, int i) {
     std::vector<std::pair<int, int>> c;
@@ -123,10 +139,16 @@ psp_status psp_autotune(psp_plan *p, int reps, void *stream, int *best_plan, int
         cand[i] = candidates(n, i);
         rounds = std::max(rounds, cand[i].size());
     }
-    std::vector<std::vector<float>> best(kPasses);
-    for (int i = 0; i < kPasses; ++i) best[i].assign(cand[i].size(), FLT_MAX);
+    // every timing of every candidate; the pick uses the median
+    std::vector<std::vector<std::vector<float>>> samples(kPasses);
+    for (int i = 0; i < kPasses; ++i) samples[i].resize(cand[i].size());
     psp_status out = PSP_OK;
-    hipError_t e = hipMemsetAsync(rho, 0, bytes, st);
+    const size_t count = (size_t)n * n * n;
+    if (f32)
+        hipLaunchKernelGGL(k_fill_hash<float>, dim3(1024), dim3(256), 0, st, (float *)rho, count);
+    else
+        hipLaunchKernelGGL(k_fill_hash<double>, dim3(1024), dim3(256), 0, st, (double *)rho, count);
+    hipError_t e = hipGetLastError();
     for (int k = 0; k < nev && e == hipSuccess; ++k) e = hipEventCreate(&ev[k]);
     if (e != hipSuccess) out = hip_fail(e, "autotune set-up");
     // round r runs candidate r mod (count) of every pass at once: each pass
@@ -161,10 +183,7 @@ psp_status psp_autotune(psp_plan *p, int reps, void *stream, int *best_plan, int
                 }
                 if (ev_pass[k] >= 0 && ev_pass[k] < kPasses) pass_ms[ev_pass[k]] += ms;
             }
-            for (int i = 0; i < kPasses; ++i) {
-                float &b = best[i][r % cand[i].size()];
-                b = std::min(b, pass_ms[i]);
-            }
+            for (int i = 0; i < kPasses; ++i) samples[i][r % cand[i].size()].push_back(pass_ms[i]);
         }
     }
     if (out == PSP_OK && (e = hipStreamSynchronize(st)) != hipSuccess) out = hip_fail(e, "autotune");
@@ -173,6 +192,12 @@ psp_status psp_autotune(psp_plan *p, int reps, void *stream, int *best_plan, int
     (void)hipFree(rho);
     (void)hipFree(u);
     if (out != PSP_OK) return out;
+    std::vector<std::vector<float>> best(kPasses);
+    for (int i = 0; i < kPasses; ++i)
+        for (auto &v : samples[i]) {
+            std::sort(v.begin(), v.end());
+            best[i].push_back(v.empty() ? FLT_MAX : v[v.size() / 2]);
+        }
     Shape chosen;
     for (int i = 0; i < kPasses; ++i) {
         size_t pick = 0;   // candidate 0 is the default shape of the pass
