@@ -96,8 +96,8 @@ psp_status psp_solve_batched(int count, psp_plan *const *plans,
  * 0 (default): one launch per pass per distinct (n, shape);
  * 1: persistent kernels, one launch per pass for all solves with 2n <= 256
  *    (workgroups of 384 threads take work items from an atomic counter in
- *    the batch's device table until none is left), grouped launches for the
- *    rest.
+ *    the batch's device table until none is left) and no radix-16 plan,
+ *    grouped launches for the rest.
  * Results are bitwise the same in both modes.  PSP_EINVAL for another value. */
 psp_status psp_set_batch_mode(int mode);
 
@@ -130,9 +130,10 @@ psp_status psp_plan_set_tuning(psp_plan *p, int k3_tiles, int i1_group);
 
 /* Launch shape of the five passes H1..H5 (index 0..4), the autotuner's search
  * space, as two int[5] arrays:
- *   plan[i]: radix plan of pass i: 0 the default factorisation of 2n, 1 the
- *            alternative for 2n in {128, 256, 512, 768} (other lengths have
- *            only 0);
+ *   plan[i]: radix plan of pass i: 0 the default factorisation of 2n, 1 an
+ *            alternative for 2n in {128, 256, 512, 768}, 2 a radix-16
+ *            factorisation for 2n in {128, 192, 256, 384, 512, 768} (other
+ *            lengths have only 0);
  *   tile[i]: passes 0 and 4 (transforms along i3): workgroup size, 0: 256
  *            threads, 1: 128, 2: 512; passes 1..3 (along i2, i1, i2): 0: one
  *            128-byte row of k3 columns per workgroup (8 FP64 or 16 FP32
@@ -163,8 +164,8 @@ psp_status psp_tuning_get(int n, psp_dtype dtype, int *plan, int *tile);
  * default unless another is at least 1% faster), sets it as the plan's shape
  * and enters it in the tuning table.  Outputs (host arrays, each may be
  * NULL): best_plan[5], best_tile[5], best_ms[5] the chosen candidate and
- * that pass's time in ms; cand_ms[5 * 14]: the time of candidate
- * (plan, tile) of pass i at cand_ms[i * 14 + plan * 7 + tile], -1 where the
+ * that pass's time in ms; cand_ms[5 * 21]: the time of candidate
+ * (plan, tile) of pass i at cand_ms[i * 21 + plan * 7 + tile], -1 where the
  * candidate does not exist.  Allocates two n^3
  * buffers for the duration; synchronises `stream`.  PSP_ESTATE before
  * precompute or while profiling; PSP_EINVAL for reps outside [1, 1000]. */

@@ -2,7 +2,8 @@
 // are grouped by (n, shape) with one launch per pass per group.  In the
 // persistent batch mode, solves with padded length 2n <= 256 run through the
 // persistent pass kernels instead (one launch per pass for all of them, work
-// items from atomic counters) and only larger ones are grouped.  Each solve
+// items from atomic counters) and only larger ones (and those with a radix-16
+// plan) are grouped.  Each solve
 // has its own workspace (one chunk of all k3 tiles).  The batch image
 // (persistent header, job table, item offsets and the grouped job table) is
 // built on the host and uploaded in one copy through pinned memory.  Every
@@ -32,8 +33,12 @@ static void image_layout(const std::vector<BatchMember> &m, BatchImage *img) {
     img->persist.clear();
     img->grouped.clear();
     const bool pers = persistent_enabled();
-    for (int i = 0; i < (int)m.size(); ++i)
-        (pers && 2 * m[i].n <= PB_MAX_N ? img->persist : img->grouped).push_back(i);
+    for (int i = 0; i < (int)m.size(); ++i) {
+        // the persistent kernels size their LDS for radices up to 8
+        bool r16 = false;
+        for (int p = 0; p < kPasses; ++p) r16 |= m[i].shape.plan[p] == 2;
+        (pers && !r16 && 2 * m[i].n <= PB_MAX_N ? img->persist : img->grouped).push_back(i);
+    }
     // persistent jobs by decreasing n (the largest items are taken first);
     // grouped jobs by (n, shape) so that each group is a contiguous slice
     std::stable_sort(img->persist.begin(), img->persist.end(), [&](int a, int b) { return m[a].n > m[b].n; });

@@ -67,8 +67,7 @@ template <> struct Twiddle<double> {
             v[1] = cmul<INV>(v[1], w1);
             v[2] = cmul<INV>(v[2], w2);
             v[3] = cmul<INV>(v[3], w3);
-        } else {
-            static_assert(R == 8, "radix");
+        } else if constexpr (R == 8) {
             const double2 w2 = cmul<false>(w1, w1), w4 = cmul<false>(w2, w2);
             const double2 w3 = cmul<false>(w2, w1), w5 = cmul<false>(w4, w1);
             const double2 w6 = cmul<false>(w4, w2), w7 = cmul<false>(w4, w3);
@@ -79,6 +78,22 @@ template <> struct Twiddle<double> {
             v[5] = cmul<INV>(v[5], w5);
             v[6] = cmul<INV>(v[6], w6);
             v[7] = cmul<INV>(v[7], w7);
+        } else {
+            static_assert(R == 16, "radix");
+            // powers by a tree of depth <= 4 from w1
+            double2 w[16];
+            w[1] = w1;
+            w[2] = cmul<false>(w1, w1);
+            w[4] = cmul<false>(w[2], w[2]);
+            w[8] = cmul<false>(w[4], w[4]);
+            w[3] = cmul<false>(w[2], w1);
+            w[5] = cmul<false>(w[4], w1);
+            w[6] = cmul<false>(w[4], w[2]);
+            w[7] = cmul<false>(w[4], w[3]);
+#pragma unroll
+            for (int k = 1; k < 8; ++k) w[8 + k] = cmul<false>(w[8], w[k]);
+#pragma unroll
+            for (int k = 1; k < 16; ++k) v[k] = cmul<INV>(v[k], w[k]);
         }
     }
 };
@@ -170,10 +185,61 @@ template <bool INV, typename C> struct DFT<8, INV, C> {
     }
 };
 
+// v *= W16^E (forward W16 = exp(-2 pi i/16); inverse its conjugate) for the
+// exponents the 4 x 4 split of a length-16 DFT needs
+template <int E, bool INV, typename C> __device__ __forceinline__ C mul_w16(C a) {
+    using T = decltype(a.x);
+    const T c1 = T(0.92387953251128675612818318939678829);   // cos(pi/8)
+    const T s1 = T(0.38268343236508977172845998403039887);   // sin(pi/8)
+    const T r2 = T(0.70710678118654752440084436210484904);   // 1/sqrt(2)
+    T wr, wi;                                                // W16^E, forward
+    if constexpr (E == 0) return a;
+    else if constexpr (E == 4) return c_mul_mi<INV>(a);
+    else {
+        if constexpr (E == 1) { wr = c1; wi = -s1; }
+        else if constexpr (E == 2) { wr = r2; wi = -r2; }
+        else if constexpr (E == 3) { wr = s1; wi = -c1; }
+        else if constexpr (E == 6) { wr = -r2; wi = -r2; }
+        else { static_assert(E == 9, "exponent"); wr = -c1; wi = s1; }
+        if (INV) wi = -wi;
+        return C{fmadd(a.x, wr, -(a.y * wi)), fmadd(a.x, wi, a.y * wr)};
+    }
+}
+
+// length 16 as 4 x 4: X[k1 + 4 k2] = sum_r1 W4^(r1 k2) W16^(r1 k1)
+// sum_r2 W4^(r2 k1) x[r1 + 4 r2]
+template <bool INV, typename C> struct DFT<16, INV, C> {
+    __device__ __forceinline__ static void run(C *v) {
+        C a[4][4];
+#pragma unroll
+        for (int r1 = 0; r1 < 4; ++r1) {
+#pragma unroll
+            for (int r2 = 0; r2 < 4; ++r2) a[r1][r2] = v[r1 + 4 * r2];
+            DFT<4, INV, C>::run(a[r1]);            // a[r1][k1]
+        }
+        a[1][1] = mul_w16<1, INV>(a[1][1]);
+        a[1][2] = mul_w16<2, INV>(a[1][2]);
+        a[1][3] = mul_w16<3, INV>(a[1][3]);
+        a[2][1] = mul_w16<2, INV>(a[2][1]);
+        a[2][2] = mul_w16<4, INV>(a[2][2]);
+        a[2][3] = mul_w16<6, INV>(a[2][3]);
+        a[3][1] = mul_w16<3, INV>(a[3][1]);
+        a[3][2] = mul_w16<6, INV>(a[3][2]);
+        a[3][3] = mul_w16<9, INV>(a[3][3]);
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) {
+            C b[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
+            DFT<4, INV, C>::run(b);                 // b[k2]
+#pragma unroll
+            for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = b[k2];
+        }
+    }
+};
+
 // ------------------------------------------------------------ radix plans
 // Forward radix sequence per padded length; variant PV = 0 is the default,
-// PV = 1 an alternative ordering or factorisation that the autotuner may pick
-// (lengths without one repeat the default).  The first radix is even so that
+// PV = 1 an alternative ordering or factorisation and PV = 2 a factorisation
+// with radix 16 that the autotuner may pick (where the length has them).  The first radix is even so that
 // the zero-padded half of an input (and, in reverse, the cropped half of an
 // output) falls on whole butterfly legs.
 template <int N, int PV> struct Plan;
@@ -201,6 +267,14 @@ PSP_PLAN(128, 1, 4, 8, 4)
 PSP_PLAN(256, 1, 4, 8, 8)
 PSP_PLAN(512, 1, 8, 4, 4, 4)
 PSP_PLAN(768, 1, 8, 4, 8, 3)
+// radix-16 alternatives: one FFT stage (and LDS exchange) fewer where the
+// length allows it
+PSP_PLAN(128, 2, 16, 8)
+PSP_PLAN(192, 2, 16, 4, 3)
+PSP_PLAN(256, 2, 16, 16)
+PSP_PLAN(384, 2, 16, 8, 3)
+PSP_PLAN(512, 2, 16, 8, 4)
+PSP_PLAN(768, 2, 16, 16, 3)
 #undef PSP_PLAN
 
 template <int N, bool INV, int PV> struct Seq {

@@ -17,8 +17,9 @@ struct Job {
 
 // Launch shape of the five passes H1..H5 (index p = 0..4): the autotuner's
 // search space.
-//   plan[p]: radix plan of the pass (0: default, 1: the alternative where the
-//            padded length has one; a different rounding, same accuracy class)
+//   plan[p]: radix plan of the pass (0: default, 1: an alternative ordering,
+//            2: a radix-16 factorisation, where the padded length has them;
+//            a different rounding, same accuracy class)
 //   tile[p]: H1/H5 (p = 0, 4): workgroup size, 0: 256 threads, 1: 128, 2: 512;
 //            H2-H4 (p = 1..3): 0: one 128-byte row tile of k3 columns per
 //            workgroup (8 FP64 / 16 FP32 columns), 1: half of one, 2: one
@@ -47,11 +48,17 @@ struct Shape {
         return false;
     }
 };
-// padded lengths with an alternative radix plan
+// radix plans of a padded length: 0 the default; 1 an alternative ordering or
+// factorisation (2n in {128, 256, 512, 768}); 2 a radix-16 factorisation (2n
+// in {128, 192, 256, 384, 512, 768})
 constexpr bool alt_plan_exists(int N) { return N == 128 || N == 256 || N == 512 || N == 768; }
+constexpr bool r16_plan_exists(int N) { return N == 128 || N == 192 || N == 256 || N == 384 || N == 512 || N == 768; }
+constexpr bool plan_exists(int N, int pv) {
+    return pv == 0 || (pv == 1 && alt_plan_exists(N)) || (pv == 2 && r16_plan_exists(N));
+}
 inline bool shape_valid(int n, const Shape &s) {
     for (int p = 0; p < kPasses; ++p) {
-        if (s.plan[p] < 0 || s.plan[p] > (alt_plan_exists(2 * n) ? 1 : 0)) return false;
+        if (!plan_exists(2 * n, s.plan[p])) return false;
         if (s.tile[p] < 0 || s.tile[p] >= kTileChoices[p]) return false;
     }
     return true;

@@ -1,6 +1,6 @@
 // passes.hpp - the solve's device passes and their launch sequence, as
 // templates over the precision T and the padded length N; instantiated per
-// precision in passes_f64.hip and passes_f32.hip.
+// precision and length range in passes_{f64,f32}_{lo,hi}.hip.
 //
 // Data layout in HBM for one solve with n points per axis, N = 2n, and
 // P = round_up(n+1, 16) (pitch of the half-spectrum axis k3 = 0..n):
@@ -339,6 +339,12 @@ template <int N, typename F> inline void with_plan(int pv, F &&f) {
             return;
         }
     }
+    if constexpr (r16_plan_exists(N)) {
+        if (pv == 2) {
+            f(std::integral_constant<int, 2>{});
+            return;
+        }
+    }
     f(std::integral_constant<int, 0>{});
 }
 template <int W_, int XC_, bool HF_> struct StridedTile {
@@ -522,28 +528,20 @@ hipError_t passes_impl(const Job &one, const Job *table, int count, int P, int c
     return hipGetLastError();
 }
 
-// dispatch over the supported padded lengths
-template <typename T>
-hipError_t passes_dispatch(int N, const Job &one, const Job *table, int count, int P, int chunk_tiles, int i1_group,
-                           const Shape &sh, bool full, const void *tw_hi, const void *tw_lo, hipEvent_t *ev,
-                           int *ev_pass, int nev, hipStream_t st) {
-    switch (N) {
-#define PSP_CASE(NN)                                                                                           \
+// the pass sequence of one padded length behind a run-time switch; each
+// instantiation file covers a subset of the lengths (PSP_CASE per length)
+#define PSP_PASSES_SIGNATURE                                                                                  \
+    (int N, const Job &one, const Job *table, int count, int P, int chunk_tiles, int i1_group, const Shape &sh, \
+     bool full, const void *tw_hi, const void *tw_lo, hipEvent_t *ev, int *ev_pass, int nev, hipStream_t st)
+#define PSP_CASE(T, NN)                                                                                        \
     case NN:                                                                                                   \
         return passes_impl<T, NN>(one, table, count, P, chunk_tiles, i1_group, sh, full, tw_hi, tw_lo, ev,     \
                                   ev_pass, nev, st);
-        PSP_CASE(8) PSP_CASE(12) PSP_CASE(16) PSP_CASE(24) PSP_CASE(32) PSP_CASE(48) PSP_CASE(64)
-        PSP_CASE(96) PSP_CASE(128) PSP_CASE(192) PSP_CASE(256) PSP_CASE(384) PSP_CASE(512) PSP_CASE(768)
-#undef PSP_CASE
-        default: return hipErrorInvalidValue;
-    }
-}
 
-hipError_t passes_f64(int N, const Job &one, const Job *table, int count, int P, int chunk_tiles, int i1_group,
-                      const Shape &sh, bool full, const void *tw_hi, const void *tw_lo, hipEvent_t *ev, int *ev_pass,
-                      int nev, hipStream_t st);
-hipError_t passes_f32(int N, const Job &one, const Job *table, int count, int P, int chunk_tiles, int i1_group,
-                      const Shape &sh, bool full, const void *tw_hi, const void *tw_lo, hipEvent_t *ev, int *ev_pass,
-                      int nev, hipStream_t st);
+// padded lengths up to 192 in the *_lo files, the rest in the *_hi files
+hipError_t passes_f64_lo PSP_PASSES_SIGNATURE;
+hipError_t passes_f64_hi PSP_PASSES_SIGNATURE;
+hipError_t passes_f32_lo PSP_PASSES_SIGNATURE;
+hipError_t passes_f32_hi PSP_PASSES_SIGNATURE;
 
 }  // namespace psp

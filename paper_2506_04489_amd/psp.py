@@ -270,9 +270,9 @@ class Plan:
         time (-1: no such candidate)."""
         pa, ta = (ctypes.c_int * 5)(), (ctypes.c_int * 5)()
         ms = (ctypes.c_float * 5)()
-        cm = (ctypes.c_float * 70)()
+        cm = (ctypes.c_float * 105)()
         _check(lib().psp_autotune(self._h, int(reps), _stream_ptr(stream), pa, ta, ms, cm))
-        cand = [[round(float(cm[i * 14 + c]), 5) for c in range(14)] for i in range(5)]
+        cand = [[round(float(cm[i * 21 + c]), 5) for c in range(21)] for i in range(5)]
         return {"plan": list(pa), "tile": list(ta), "pass_ms": [float(x) for x in ms], "candidates_ms": cand}
 
     def profile_enable(self, max_solves: int):

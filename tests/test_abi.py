@@ -113,7 +113,7 @@ def test_tables_match_oracle(n, h, R):
 
 # ---------------------------------------------------------------- shapes
 def test_shape_validation_and_roundtrip():
-    p = B.Plan(32, 2 / 32, 40)                       # 2n = 64: no alternative radix plan
+    p = B.Plan(32, 2 / 32, 40)                       # 2n = 64: no alternative radix plans
     assert p.shape() == B.tuning_get(32, "f64")      # new plans start from the table
     p.set_shape([0] * 5, [2, 1, 2, 1, 1])
     assert p.shape() == ([0] * 5, [2, 1, 2, 1, 1])
@@ -124,9 +124,16 @@ def test_shape_validation_and_roundtrip():
         with pytest.raises(B.PspError) as ei:
             p.set_shape(plan, tile)
         assert B.STATUS[ei.value.status] == "PSP_EINVAL"
-    q = B.Plan(64, 2 / 64, 40)                       # 2n = 128 has an alternative
+    q = B.Plan(64, 2 / 64, 40)                       # 2n = 128 has both alternatives
     q.set_shape([1, 1, 1, 1, 1], [0] * 5)
     assert q.shape()[0] == [1] * 5
+    q.set_shape([2, 2, 2, 2, 2], [0] * 5)
+    r = B.Plan(96, 2 / 96, 40)                       # 2n = 192: radix 16 but no plan 1
+    r.set_shape([2] * 5, [0] * 5)
+    with pytest.raises(B.PspError):
+        r.set_shape([1] * 5, [0] * 5)
+    with pytest.raises(B.PspError):
+        q.set_shape([3] * 5, [0] * 5)
     with pytest.raises(ValueError):
         q.set_shape([0] * 4, [0] * 5)
 
