@@ -140,7 +140,7 @@ def bench_batched(torch, B, D, dtype, reps=5):
             "speedup_batched_vs_single": round(t_single / t_batch, 2)}
 
 
-def bench_serving(torch, B, D, count=2000, rates=(0.25, 0.5, 0.9, 1.2), budget=200 << 30, slots=64):
+def bench_serving(torch, B, D, count=2000, rates=(0.25, 0.5, 0.75, 0.9, 1.0, 1.2), budget=200 << 30, slots=64):
     """The serving stream: Poisson arrivals, n from {64..384}, 50/50 tiers and
     density families; spectra cached per (n, h, R) (warmed first).  For each
     rate (a multiple of the measured capacity) the latency percentiles from
@@ -211,11 +211,15 @@ def bench_serving(torch, B, D, count=2000, rates=(0.25, 0.5, 0.9, 1.2), budget=2
     out = {"requests": count, "capacity_req_per_s": round(cap, 1),
            "one_at_a_time_req_per_s": round(count / t_seq, 1), "rates": []}
     pts = sum(r.n ** 3 for r in reqs)
+    ns = np.array([r.n for r in reqs])
     for f in rates:
         wall, lat = run(cap * f)
+        by_n = {int(n): [round(float(np.percentile(lat[ns == n], q)), 3) for q in (50, 99)]
+                for n in sorted(set(ns.tolist()))}
         out["rates"].append({"load": f, "rate_req_per_s": round(cap * f, 1),
                              "p50_ms": round(float(np.percentile(lat, 50)), 3),
                              "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                             "p50_p99_ms_by_n": by_n,
                              "achieved_req_per_s": round(count / wall, 1),
                              "achieved_mpts_per_s": round(pts / wall / 1e6, 1)})
     st = sv.stats()
