@@ -209,8 +209,9 @@ void psp_graph_destroy(psp_graph *g);
  * A continuous-batching request loop.  Requests are admitted while their
  * device footprint (workspace plus, on a spectrum-cache miss, the multiplier
  * octant) fits `hbm_budget_bytes` and fewer than `max_slots` are in flight;
- * admitted requests are grouped per tier into batched launches on a small
- * stream pool, so new arrivals overlap work already on the device.  Spectra
+ * admitted requests are grouped per tier and size class (n <= 128 or larger)
+ * into batched launches on the least busy stream of a small pool, so new
+ * arrivals overlap work already on the device.  Spectra
  * are cached per (n, h, R) on the device in LRU order inside the budget.
  * rho_dev/u_dev stay caller-owned and must live until the request is done;
  * rho must be fully written (its producing work complete) when submitted,

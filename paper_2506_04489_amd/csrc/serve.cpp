@@ -10,11 +10,14 @@
 //      the multiplier octant (8 (n+1)^2 round_up(n+1,16) bytes).  Idle cached
 //      spectra and pooled workspaces are evicted, least recently used first,
 //      to make room; the queue head waits when nothing more can be freed;
-//   3. launches every admitted request of one tier as one batch on the next
-//      stream of a small pool and records a completion event, so requests
-//      that arrive while others run are admitted and overlap on the device.
+//   3. launches the admitted requests of one tier and size class (n <= 128 or
+//      larger) as one batch on the pool's stream with the fewest batches in
+//      flight and records a completion event, so requests that arrive while
+//      others run are admitted and overlap on the device, and a small request
+//      does not wait for a large one's completion.
 // Every solve runs the same kernels on its own workspace, so a result is
 // bitwise the same alone and in any mix.
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <tuple>
@@ -31,6 +34,11 @@ namespace psp {
 
 using Clock = std::chrono::steady_clock;
 hipError_t launch_batch(int count, const SolveArgs *args, hipStream_t st);
+
+// batch kinds per scheduler turn: tier (FP64, FP32) x size class (n <= kSmallN
+// or larger)
+constexpr int kBatchKinds = 4;
+constexpr int kSmallN = 128;
 
 struct ServeReq {
     int n = 0;
@@ -60,6 +68,7 @@ struct PooledWs {
 
 struct Batch {
     hipEvent_t ev = nullptr;
+    int stream = 0;                 // index into the server's stream pool
     std::vector<uint64_t> ids;
     std::vector<PooledWs> ws;
     std::vector<std::tuple<int, double, int>> keys;
@@ -86,7 +95,6 @@ struct psp_server {
     std::vector<PooledWs> pool;
     std::list<Batch> inflight;
     std::vector<hipStream_t> streams;
-    int next_stream = 0;
     int slots_used = 0;
     std::atomic<size_t> bytes_in_use{0}, bytes_peak{0};
     std::atomic<uint64_t> completed{0}, hits{0}, misses{0};
@@ -230,12 +238,13 @@ static void scheduler(psp_server *sv) {
                 cand.emplace_back(id, sv->reqs[id]);
             }
         }
-        // admit in order
+        // admit in order; batches per (tier, size class), so that a small
+        // request never waits for a large one's completion event
         std::vector<uint64_t> admitted;
-        std::vector<SolveArgs> args[2];
-        std::vector<uint64_t> ids[2];
-        std::vector<PooledWs> wss[2];
-        std::vector<std::tuple<int, double, int>> keys[2];
+        std::vector<SolveArgs> args[kBatchKinds];
+        std::vector<uint64_t> ids[kBatchKinds];
+        std::vector<PooledWs> wss[kBatchKinds];
+        std::vector<std::tuple<int, double, int>> keys[kBatchKinds];
         for (auto &c : cand) {
             const ServeReq &r = c.second;
             const auto key = std::make_tuple(r.n, r.h, r.R);
@@ -258,7 +267,7 @@ static void scheduler(psp_server *sv) {
             }
             (hit ? sv->hits : sv->misses)++;
             sv->specs[key].users++;
-            const int t = f32 ? 1 : 0;
+            const int t = (f32 ? 1 : 0) + (r.n > kSmallN ? 2 : 0);
             args[t].push_back(solve_args(p, w.w, r.rho, r.u));
             ids[t].push_back(c.first);
             wss[t].push_back(w);
@@ -273,11 +282,15 @@ static void scheduler(psp_server *sv) {
                         break;
                     }
         }
-        for (int t = 0; t < 2; ++t) {
+        for (int t = 0; t < kBatchKinds; ++t) {
             if (ids[t].empty()) continue;
-            hipStream_t st = sv->streams[sv->next_stream];
-            sv->next_stream = (sv->next_stream + 1) % (int)sv->streams.size();
+            // the stream with the fewest batches in flight
+            std::vector<int> load(sv->streams.size(), 0);
+            for (auto &b : sv->inflight) load[b.stream]++;
+            const int si = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            hipStream_t st = sv->streams[si];
             Batch b;
+            b.stream = si;
             hipError_t e = launch_batch((int)args[t].size(), args[t].data(), st);
             if (e == hipSuccess) e = hipEventCreateWithFlags(&b.ev, hipEventDisableTiming);
             if (e == hipSuccess) e = hipEventRecord(b.ev, st);
