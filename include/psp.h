@@ -52,7 +52,8 @@ typedef enum {
     PSP_EUNSUPPORTED = -3,  /* n odd, n < 4, n > 384, or 2n not 2^a 3^b */
     PSP_ESTATE = -4,        /* call order (solve before precompute ...) */
     PSP_EHIP = -5,          /* a HIP runtime call failed */
-    PSP_EBUSY = -6          /* server queue full */
+    PSP_EBUSY = -6,         /* server queue full; request already on the device */
+    PSP_ECANCELED = -7      /* request withdrawn by psp_serve_cancel */
 } psp_status;
 
 /* ---- plans (Algorithm 1) -------------------------------------------------
@@ -105,6 +106,15 @@ psp_status psp_set_batch_mode(int mode);
  * with side 2n, dtype of the plan. */
 psp_status psp_solve_padded_debug(psp_plan *p, const void *rho_dev, void *upad_dev,
                                   void *stream);
+
+/* Debugging of out-of-bounds writes: with enable != 0, every workspace
+ * allocated afterwards (plans, batches, graphs, the serving loop) places its
+ * two intermediates 64 KB into their allocations, between 64 KB bands filled
+ * with the byte 0xA5.  psp_plan_check_guards synchronises the device and sets
+ * *intact = 1 if every band of the plan's workspaces still holds the pattern
+ * (0 otherwise; workspaces allocated without guards are skipped). */
+psp_status psp_debug_guards(int enable);
+psp_status psp_plan_check_guards(psp_plan *p, int *intact);
 
 /* Test hook: copies the R weights w_s and exponents a_s (host arrays). */
 psp_status psp_plan_get_gs(const psp_plan *p, double *omega, double *alpha);
@@ -223,6 +233,12 @@ psp_status psp_serve_create(size_t hbm_budget_bytes, int max_slots, psp_server *
  * budget; validation errors as psp_plan_create. */
 psp_status psp_serve_submit(psp_server *sv, int n, double h, int R, psp_dtype tier,
                             const void *rho_dev, void *u_dev, uint64_t *ticket);
+
+/* Withdraw a request that is still queued: it completes at once with result
+ * PSP_ECANCELED and u is not written.  PSP_EBUSY if it has already been
+ * admitted to the device (it then completes normally), PSP_EINVAL for an
+ * unknown or finished ticket. */
+psp_status psp_serve_cancel(psp_server *sv, uint64_t ticket);
 
 /* Non-blocking status: *done = 1 once u is complete on the device; then
  * *result is the request's status and *latency_ms its submit-to-completion

@@ -1,4 +1,5 @@
 // api.cpp - libpsp's C ABI: plans, precompute, solves, test hooks, errors.
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -91,29 +92,71 @@ psp_status check_create(int n, double h, int R, double eps, double delta) {
     return PSP_OK;
 }
 
+static std::atomic<bool> g_guards{false};
+bool guards_enabled() { return g_guards.load(); }
+
+// one device buffer of `bytes`, inside pattern-filled guard bands when asked
+static hipError_t guarded_malloc(size_t bytes, bool guard, void **base, void **buf) {
+    const size_t total = guard ? bytes + 2 * kGuardBytes : bytes;
+    hipError_t e = hipMalloc(base, total);
+    if (e != hipSuccess) {
+        *base = nullptr;
+        return e;
+    }
+    *buf = guard ? (unsigned char *)*base + kGuardBytes : *base;
+    if (guard) {
+        e = hipMemset(*base, kGuardByte, kGuardBytes);
+        if (e == hipSuccess) e = hipMemset((unsigned char *)*buf + bytes, kGuardByte, kGuardBytes);
+    }
+    return e;
+}
+
 psp_status alloc_workspace(int n, bool f32, int chunk_tiles, Workspace *w, int i1_group) {
     const size_t c = f32 ? 8 : 16, P = (size_t)pitch_for(n), PA = (size_t)chunk_pitch(n, f32, chunk_tiles);
     const size_t xs = (size_t)x_slabs(n, f32, chunk_tiles, i1_group);
+    const bool guard = guards_enabled();
     w->bytes = workspace_bytes(n, f32, chunk_tiles, i1_group);
-    w->X = w->A = nullptr;
-    if (hipMalloc(&w->X, c * P * xs * n) != hipSuccess) {
+    w->X = w->A = w->X_base = w->A_base = nullptr;
+    w->X_bytes = c * P * xs * n;
+    w->A_bytes = c * PA * n * 2 * n;
+    if (guarded_malloc(w->X_bytes, guard, &w->X_base, &w->X) != hipSuccess) {
         (void)hipGetLastError();
-        w->X = nullptr;
+        free_workspace(w);
         return fail(PSP_ENOMEM, "workspace allocation of %zu bytes failed", w->bytes);
     }
-    if (hipMalloc(&w->A, c * PA * n * 2 * n) != hipSuccess) {
+    if (guarded_malloc(w->A_bytes, guard, &w->A_base, &w->A) != hipSuccess) {
         (void)hipGetLastError();
-        (void)hipFree(w->X);
-        w->X = w->A = nullptr;
+        free_workspace(w);
         return fail(PSP_ENOMEM, "workspace allocation of %zu bytes failed", w->bytes);
     }
     return PSP_OK;
 }
 
 void free_workspace(Workspace *w) {
-    if (w->X) (void)hipFree(w->X);
-    if (w->A) (void)hipFree(w->A);
-    w->X = w->A = nullptr;
+    if (w->X_base) (void)hipFree(w->X_base);
+    if (w->A_base) (void)hipFree(w->A_base);
+    w->X = w->A = w->X_base = w->A_base = nullptr;
+}
+
+psp_status check_guards(const Workspace &w, bool *intact) {
+    *intact = true;
+    std::vector<unsigned char> band(kGuardBytes);
+    const std::pair<void *, void *> bufs[2] = {{w.X_base, w.X}, {w.A_base, w.A}};
+    const size_t sizes[2] = {w.X_bytes, w.A_bytes};
+    for (int i = 0; i < 2; ++i) {
+        if (!bufs[i].first || bufs[i].first == bufs[i].second) continue;   // not guarded
+        const unsigned char *ends[2] = {(const unsigned char *)bufs[i].first,
+                                        (const unsigned char *)bufs[i].second + sizes[i]};
+        for (const unsigned char *e : ends) {
+            PSP_HIP(hipMemcpy(band.data(), e, kGuardBytes, hipMemcpyDeviceToHost), "hipMemcpy(guard)");
+            for (unsigned char b : band)
+                if (b != kGuardByte) {
+                    *intact = false;
+                    return PSP_OK;
+                }
+        }
+    }
+    return PSP_OK;
 }
 
 psp_status plan_workspace(psp_plan *p, hipStream_t st, Workspace **out) {
@@ -183,7 +226,8 @@ const char *psp_strerror(psp_status e) {
         case PSP_EUNSUPPORTED: return "unsupported size";
         case PSP_ESTATE: return "invalid call order";
         case PSP_EHIP: return "HIP runtime error";
-        case PSP_EBUSY: return "queue full";
+        case PSP_EBUSY: return "busy";
+        case PSP_ECANCELED: return "canceled";
     }
     return "unknown status";
 }
@@ -418,6 +462,26 @@ psp_status psp_plan_set_tuning(psp_plan *p, int k3_tiles, int i1_group) {
         p->chunk_tiles = k3_tiles;
         p->i1_group = i1_group;
     }
+    return PSP_OK;
+}
+
+psp_status psp_debug_guards(int enable) {
+    g_guards.store(enable != 0);
+    return PSP_OK;
+}
+
+psp_status psp_plan_check_guards(psp_plan *p, int *intact) {
+    if (!p || !intact) return fail(PSP_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(p->mu);
+    PSP_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    bool all = true;
+    for (auto &kv : p->ws) {
+        bool ok = true;
+        psp_status st = check_guards(kv.second, &ok);
+        if (st != PSP_OK) return st;
+        all = all && ok;
+    }
+    *intact = all ? 1 : 0;
     return PSP_OK;
 }
 

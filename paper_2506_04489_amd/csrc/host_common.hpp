@@ -46,7 +46,17 @@ struct Workspace {
     void *X = nullptr;
     void *A = nullptr;
     size_t bytes = 0;
+    // debug guards (psp_debug_guards): X and A sit kGuardBytes into their
+    // allocations, with pattern-filled bands of that size on both sides
+    void *X_base = nullptr, *A_base = nullptr;
+    size_t X_bytes = 0, A_bytes = 0;
 };
+constexpr size_t kGuardBytes = 64 * 1024;
+constexpr unsigned char kGuardByte = 0xA5;
+// whether workspaces allocated from now on carry guards
+bool guards_enabled();
+// the guard bands of w are intact (reads them back; synchronous)
+psp_status check_guards(const Workspace &w, bool *intact);
 
 inline int pitch_for(int n) { return ((n + 1 + 15) / 16) * 16; }
 // k3 columns of the H2-H4 chunk buffer for a chunk of `chunk_tiles` tiles

@@ -187,8 +187,8 @@ static psp_status take_ws(psp_server *sv, int n, bool f32, PooledWs *out) {
 // outcomes of this many completed requests stay available to psp_serve_poll
 constexpr size_t kKeepFinished = size_t(1) << 20;
 
-static void finish(psp_server *sv, uint64_t id, psp_status st) {
-    std::lock_guard<std::mutex> lk(sv->mu);
+// caller holds sv->mu
+static void finish_locked(psp_server *sv, uint64_t id, psp_status st) {
     auto &r = sv->reqs[id];
     r.done = true;
     r.result = st;
@@ -201,6 +201,11 @@ static void finish(psp_server *sv, uint64_t id, psp_status st) {
     sv->pending_total--;
     sv->completed++;
     sv->cv_done.notify_all();
+}
+
+static void finish(psp_server *sv, uint64_t id, psp_status st) {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    finish_locked(sv, id, st);
 }
 
 static void retire(psp_server *sv, bool wait) {
@@ -274,13 +279,31 @@ static void scheduler(psp_server *sv) {
             keys[t].push_back(key);
         }
         if (!admitted.empty()) {
-            std::lock_guard<std::mutex> lk(sv->mu);
-            for (uint64_t id : admitted)
-                for (auto it = sv->queue.begin(); it != sv->queue.end(); ++it)
-                    if (*it == id) {
+            // claim the admitted requests; one canceled since the snapshot is
+            // no longer queued (and already finished): drop it from the launch
+            std::vector<uint64_t> gone;
+            {
+                std::lock_guard<std::mutex> lk(sv->mu);
+                for (uint64_t id : admitted) {
+                    auto it = std::find(sv->queue.begin(), sv->queue.end(), id);
+                    if (it != sv->queue.end())
                         sv->queue.erase(it);
-                        break;
-                    }
+                    else
+                        gone.push_back(id);
+                }
+            }
+            for (uint64_t id : gone)
+                for (int t = 0; t < kBatchKinds; ++t)
+                    for (size_t i = 0; i < ids[t].size(); ++i)
+                        if (ids[t][i] == id) {
+                            sv->pool.push_back(wss[t][i]);
+                            sv->specs[keys[t][i]].users--;
+                            ids[t].erase(ids[t].begin() + i);
+                            wss[t].erase(wss[t].begin() + i);
+                            keys[t].erase(keys[t].begin() + i);
+                            args[t].erase(args[t].begin() + i);
+                            break;
+                        }
         }
         for (int t = 0; t < kBatchKinds; ++t) {
             if (ids[t].empty()) continue;
@@ -374,6 +397,19 @@ psp_status psp_serve_submit(psp_server *sv, int n, double h, int R, psp_dtype ti
     sv->pending_total++;
     *ticket = id;
     sv->cv_work.notify_one();
+    return PSP_OK;
+}
+
+psp_status psp_serve_cancel(psp_server *sv, uint64_t ticket) {
+    if (!sv) return fail(PSP_EINVAL, "server is NULL");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->reqs.find(ticket);
+    if (it == sv->reqs.end() || it->second.done)
+        return fail(PSP_EINVAL, "unknown or finished ticket %llu", (unsigned long long)ticket);
+    auto q = std::find(sv->queue.begin(), sv->queue.end(), ticket);
+    if (q == sv->queue.end()) return fail(PSP_EBUSY, "request %llu is on the device", (unsigned long long)ticket);
+    sv->queue.erase(q);
+    finish_locked(sv, ticket, PSP_ECANCELED);
     return PSP_OK;
 }
 

@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(HERE, "libpsp.so")
 
 PSP_F64, PSP_F32 = 0, 1
 STATUS = {0: "PSP_OK", -1: "PSP_EINVAL", -2: "PSP_ENOMEM", -3: "PSP_EUNSUPPORTED",
-          -4: "PSP_ESTATE", -5: "PSP_EHIP", -6: "PSP_EBUSY"}
+          -4: "PSP_ESTATE", -5: "PSP_EHIP", -6: "PSP_EBUSY",
+          -7: "PSP_ECANCELED"}
 
 # every entry point the header declares, with (restype, argtypes)
 _vp, _i, _d, _sz, _u64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t, ctypes.c_uint64
@@ -31,6 +32,8 @@ SIGNATURES = {
     "psp_set_batch_mode": (_i, [_i]),
     "psp_solve_padded_debug": (_i, [_vp, _vp, _vp, _vp]),
     "psp_plan_get_gs": (_i, [_vp, _P(_d), _P(_d)]),
+    "psp_debug_guards": (_i, [_i]),
+    "psp_plan_check_guards": (_i, [_vp, _P(_i)]),
     "psp_plan_get_tables": (_i, [_vp, _P(_d), _P(_d)]),
     "psp_plan_get_multiplier": (_i, [_vp, _P(_d)]),
     "psp_plan_workspace_bytes": (_i, [_vp, _P(_sz)]),
@@ -51,6 +54,7 @@ SIGNATURES = {
     "psp_serve_create": (_i, [_sz, _i, _P(_vp)]),
     "psp_serve_submit": (_i, [_vp, _i, _d, _i, _i, _vp, _vp, _P(_u64)]),
     "psp_serve_poll": (_i, [_vp, _u64, _P(_i), _P(_i), _P(_d)]),
+    "psp_serve_cancel": (_i, [_vp, _u64]),
     "psp_serve_drain": (_i, [_vp]),
     "psp_serve_stats": (_i, [_vp, _P(_sz), _P(_sz), _P(_u64), _P(_u64), _P(_u64)]),
     "psp_serve_destroy": (None, [_vp]),
@@ -120,6 +124,11 @@ def _ints5(v):
     if len(v) != 5:
         raise ValueError("a shape has 5 entries (passes H1..H5)")
     return (ctypes.c_int * 5)(*v)
+
+
+def debug_guards(enable: bool):
+    """Workspaces allocated from now on sit between pattern-filled guard bands."""
+    _check(lib().psp_debug_guards(1 if enable else 0))
 
 
 def set_batch_mode(mode: str):
@@ -256,6 +265,13 @@ class Plan:
         _check(lib().psp_plan_set_shape(self._h, pa, ta))
         return self
 
+    def guards_intact(self) -> bool:
+        """psp_plan_check_guards: the guard bands of this plan's workspaces
+        (allocated while psp_debug_guards was on) are untouched."""
+        ok = ctypes.c_int()
+        _check(lib().psp_plan_check_guards(self._h, ctypes.byref(ok)))
+        return bool(ok.value)
+
     def shape(self):
         """(plan[5], tile[5]) of this plan."""
         pa, ta = (ctypes.c_int * 5)(), (ctypes.c_int * 5)()
@@ -376,6 +392,15 @@ class Server:
         _check(lib().psp_serve_poll(self._h, ctypes.c_uint64(ticket), ctypes.byref(done), ctypes.byref(res),
                                     ctypes.byref(lat)))
         return bool(done.value), res.value, lat.value
+
+    def cancel(self, ticket: int) -> bool:
+        """Withdraw a queued request (True); False if it is already on the
+        device and will complete normally."""
+        st = lib().psp_serve_cancel(self._h, ctypes.c_uint64(ticket))
+        if st == -6:
+            return False
+        _check(st)
+        return True
 
     def drain(self):
         _check(lib().psp_serve_drain(self._h))

@@ -35,3 +35,20 @@ def sample_points(n, rng, extra=(), count=48, distinct_j3=6):
     for _ in range(count):
         pts.append((int(rng.integers(n)), int(rng.integers(n)), int(rng.choice(j3s))))
     return np.array(pts, dtype=np.int64)
+
+
+TILES = [3, 7, 7, 7, 3]          # tile choices of passes H1..H5
+
+
+def radix_plans(n):
+    """Radix plans the library has for padded length 2n."""
+    N = 2 * n
+    return [0] + ([1] if N in (128, 256, 512, 768) else []) + ([2] if N in (128, 192, 256, 384, 512, 768) else [])
+
+
+def shape_rounds(n):
+    """The autotuner's rounds: round r gives pass i its candidate r mod count,
+    so the rounds together cover every (radix plan, tile) of every pass."""
+    cands = [[(pl, tl) for pl in radix_plans(n) for tl in range(TILES[i])] for i in range(5)]
+    for r in range(max(len(c) for c in cands)):
+        yield [c[r % len(c)][0] for c in cands], [c[r % len(c)][1] for c in cands]

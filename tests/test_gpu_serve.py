@@ -101,3 +101,36 @@ def test_submit_errors():
         sv.poll(123456)
     assert B.STATUS[ei.value.status] == "PSP_EINVAL"
     sv.close()
+
+
+def test_cancel_queued_requests():
+    """With room for one n = 64 request at a time, most of a burst waits in
+    the queue: those canceled there finish with PSP_ECANCELED and leave u
+    untouched; the others (and any already admitted) complete normally."""
+    import torch
+    n, h = 64, 2.0 / 64
+    p = B.Plan(n, h, 40)
+    one = p.workspace_bytes() + p.spectrum_bytes()
+    sv = B.Server(hbm_budget_bytes=int(one * 1.5), max_slots=1)
+    rho = D.gaussian(n, h, -1.0, 0.15, xp=torch, device="cuda").contiguous()
+    torch.cuda.synchronize()
+    us = [torch.full_like(rho, 7.0) for _ in range(12)]
+    torch.cuda.synchronize()
+    tickets = [sv.submit(n, h, 40, "f64", rho, u) for u in us]
+    canceled = [t for t in tickets[4:] if sv.cancel(t)]
+    assert len(canceled) >= 1
+    _wait(sv, tickets)
+    ref = p.precompute().solve(rho)
+    torch.cuda.synchronize()
+    for t, u in zip(tickets, us):
+        done, res, _ = sv.poll(t)
+        assert done
+        if t in canceled:
+            assert B.STATUS[res] == "PSP_ECANCELED"
+            assert torch.all(u == 7.0)
+        else:
+            assert res == 0
+            assert torch.equal(u, ref)
+    with pytest.raises(B.PspError):
+        sv.cancel(tickets[0])              # finished
+    sv.close()

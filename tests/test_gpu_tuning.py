@@ -8,29 +8,14 @@ import pytest
 from oracle import psp_oracle as O
 from paper_2506_04489_amd import densities as D
 from paper_2506_04489_amd import psp as B
-from tests.gpu_util import announce, rel_max_err
+from tests.gpu_util import TILES, announce, rel_max_err, shape_rounds
 
 pytestmark = pytest.mark.gpu
-
-TILES = [3, 7, 7, 7, 3]
-
 
 @pytest.fixture(autouse=True)
 def _name(request):
     announce(request.node.nodeid)
     yield
-
-
-def _plans(n):
-    N = 2 * n
-    return [0] + ([1] if N in (128, 256, 512, 768) else []) + ([2] if N in (128, 192, 256, 384, 512, 768) else [])
-
-
-def _rounds(n):
-    """The autotuner's rounds: round r gives pass i its candidate r mod count."""
-    cands = [[(pl, tl) for pl in _plans(n) for tl in range(TILES[i])] for i in range(5)]
-    for r in range(max(len(c) for c in cands)):
-        yield [c[r % len(c)][0] for c in cands], [c[r % len(c)][1] for c in cands]
 
 
 def _density(n, seed, dtype):
@@ -61,7 +46,7 @@ def test_every_shape_matches(n, dtype):
     else:
         want = None
     tol = 1e-12 if dtype == "f64" else 1e-5
-    for plan, tile in _rounds(n):
+    for plan, tile in shape_rounds(n):
         p.set_shape(plan, tile)
         u = p.solve(rho)
         torch.cuda.synchronize()
