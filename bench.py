@@ -130,6 +130,18 @@ def bench_batched(torch, B, D, dtype, reps=5):
         t_pers = timed(lambda: B.solve_batched(ps, rhos, us))
     finally:
         B.set_batch_mode("grouped")
+    # FP32 tier: every result's error against the FP64 tier (whose parity
+    # with the oracle is 1e-12), worst per n
+    err = None
+    if dtype == "f32":
+        B.solve_batched(ps, rhos, us)
+        p64 = {n: B.Plan(n, 2.0 / n, 40).precompute() for n in plans}
+        err = {}
+        for it, r, u in zip(items, rhos, us):
+            ref = p64[it.n].solve(r.double())
+            e = float((u.double() - ref).abs().max() / ref.abs().max())
+            err[it.n] = max(err.get(it.n, 0.0), e)
+        err = {int(k): float("%.3g" % v) for k, v in sorted(err.items())}
     pts = sum(it.n ** 3 for it in items)
     return {"count": len(items), "sizes": sorted({it.n for it in items}),
             "one_at_a_time_solves_per_s": round(len(items) / t_single, 1),
@@ -137,7 +149,8 @@ def bench_batched(torch, B, D, dtype, reps=5):
             "graph_batched_solves_per_s": round(len(items) / t_graph, 1),
             "persistent_batched_solves_per_s": round(len(items) / t_pers, 1),
             "batched_mpts_per_s": round(pts / t_batch / 1e6, 1),
-            "speedup_batched_vs_single": round(t_single / t_batch, 2)}
+            "speedup_batched_vs_single": round(t_single / t_batch, 2),
+            **({"max_err_vs_f64_tier_by_n": err} if err is not None else {})}
 
 
 def bench_serving(torch, B, D, count=2000, rates=(0.25, 0.5, 0.75, 0.9, 1.0, 1.2), budget=200 << 30, slots=64):
@@ -222,6 +235,18 @@ def bench_serving(torch, B, D, count=2000, rates=(0.25, 0.5, 0.75, 0.9, 1.0, 1.2
                              "p50_p99_ms_by_n": by_n,
                              "achieved_req_per_s": round(count / wall, 1),
                              "achieved_mpts_per_s": round(pts / wall / 1e6, 1)})
+    # FP32-tier requests: error of each (n, density family) input against the
+    # FP64 tier (whose parity with the oracle is 1e-12), worst per n
+    err = {}
+    for (n, tier, kind), dens in pool.items():
+        if tier != "f32":
+            continue
+        p32, p64 = B.Plan(n, 2.0 / n, 40, dtype="f32").precompute(), B.Plan(n, 2.0 / n, 40).precompute()
+        for d in dens:
+            u32, ref = p32.solve(d), p64.solve(d.double())
+            e = float((u32.double() - ref).abs().max() / ref.abs().max())
+            err[n] = max(err.get(n, 0.0), e)
+    out["f32_max_err_vs_f64_tier_by_n"] = {int(k): float("%.3g" % v) for k, v in sorted(err.items())}
     st = sv.stats()
     out["bytes_peak_GB"] = round(st["bytes_peak"] / 2 ** 30, 2)
     out["cache_hits"], out["cache_misses"] = st["cache_hits"], st["cache_misses"]
