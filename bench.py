@@ -128,6 +128,8 @@ def bench_batched(torch, B, D, dtype, reps=5):
     B.set_batch_mode("persistent")
     try:
         t_pers = timed(lambda: B.solve_batched(ps, rhos, us))
+        B.set_batch_mode("flat")
+        t_flat = timed(lambda: B.solve_batched(ps, rhos, us))
     finally:
         B.set_batch_mode("grouped")
     # FP32 tier: every result's error against the FP64 tier (whose parity
@@ -148,6 +150,7 @@ def bench_batched(torch, B, D, dtype, reps=5):
             "batched_solves_per_s": round(len(items) / t_batch, 1),
             "graph_batched_solves_per_s": round(len(items) / t_graph, 1),
             "persistent_batched_solves_per_s": round(len(items) / t_pers, 1),
+            "flat_batched_solves_per_s": round(len(items) / t_flat, 1),
             "batched_mpts_per_s": round(pts / t_batch / 1e6, 1),
             "speedup_batched_vs_single": round(t_single / t_batch, 2),
             **({"max_err_vs_f64_tier_by_n": err} if err is not None else {})}

@@ -98,8 +98,9 @@ psp_status psp_solve_batched(int count, psp_plan *const *plans,
  * 1: persistent kernels, one launch per pass for all solves with 2n <= 256
  *    (workgroups of 384 threads take work items from an atomic counter in
  *    the batch's device table until none is left) and no radix-16 plan,
- *    grouped launches for the rest.
- * Results are bitwise the same in both modes.  PSP_EINVAL for another value. */
+ *    grouped launches for the rest;
+ * 2: as 1 with one workgroup per work item instead of persistent ones.
+ * Results are bitwise the same in every mode.  PSP_EINVAL for another value. */
 psp_status psp_set_batch_mode(int mode);
 
 /* Test hook: the uncropped (2n)^3 result of Algorithm 2 (real part), C-order

@@ -27,7 +27,7 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // grouped 27.4k solves/s, persistent 10.4k (each persistent workgroup runs
 // its items one after another and exposes every item's load latency).
 static std::atomic<int> g_batch_mode{0};
-static bool persistent_enabled() { return g_batch_mode.load() == 1; }
+static bool persistent_enabled() { return g_batch_mode.load() != 0; }
 
 static void image_layout(const std::vector<BatchMember> &m, BatchImage *img) {
     img->persist.clear();
@@ -74,6 +74,7 @@ size_t batch_image_bytes(const std::vector<BatchMember> &m) {
 void build_batch_image(const std::vector<BatchMember> &m, bool f32, unsigned char *dev_base, BatchImage *img,
                        std::vector<unsigned char> &host) {
     image_layout(m, img);
+    img->flat = g_batch_mode.load() == 2;
     host.assign(img->bytes, 0);
     const int k = (int)img->persist.size();
     PBatch hdr{};
@@ -117,7 +118,8 @@ void build_batch_image(const std::vector<BatchMember> &m, bool f32, unsigned cha
 hipError_t launch_batch_image(const std::vector<BatchMember> &m, const BatchImage &img, bool f32,
                               unsigned char *dev_base, bool reset, hipStream_t st) {
     if (!img.persist.empty()) {
-        hipError_t e = persist_launch(f32, (PBatch *)(dev_base + img.hdr_off), img.total, reset, st);
+        PBatch *hdr = (PBatch *)(dev_base + img.hdr_off);
+        hipError_t e = img.flat ? flat_launch(f32, hdr, img.total, st) : persist_launch(f32, hdr, img.total, reset, st);
         if (e != hipSuccess) return e;
     }
     const std::vector<int> &g = img.grouped;
@@ -236,7 +238,7 @@ hipError_t launch_batch(int count, const SolveArgs *args, hipStream_t st) {
 using namespace psp;
 
 extern "C" psp_status psp_set_batch_mode(int mode) {
-    if (mode != 0 && mode != 1) return fail(PSP_EINVAL, "batch mode must be 0 or 1 (got %d)", mode);
+    if (mode < 0 || mode > 2) return fail(PSP_EINVAL, "batch mode must be 0, 1 or 2 (got %d)", mode);
     g_batch_mode.store(mode);
     return PSP_OK;
 }

@@ -91,6 +91,7 @@ struct BatchImage {
     std::vector<int> grouped;     // the others, sorted by (n, shape)
     size_t hdr_off = 0, jobs_off = 0, start_off = 0, group_off = 0, bytes = 0;
     int total[kPasses] = {0, 0, 0, 0, 0};
+    bool flat = false;            // one workgroup per item instead of persistent workgroups
 };
 size_t batch_image_bytes(const std::vector<BatchMember> &m);
 // host copy of the image for the device buffer at dev_base (its pointers

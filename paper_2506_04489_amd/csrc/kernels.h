@@ -104,6 +104,8 @@ hipError_t persist_prepare();
 // the five persistent passes over the batch whose header is at d_hdr;
 // reset: clear the counters first (a kernel, so graphs may capture it)
 hipError_t persist_launch(bool f32, PBatch *d_hdr, const int *total, bool reset, hipStream_t st);
+// the same passes with one workgroup per item (grids of total[p] workgroups)
+hipError_t flat_launch(bool f32, PBatch *d_hdr, const int *total, hipStream_t st);
 
 // One solve's buffers (device pointers) and sizes.
 struct SolveArgs {

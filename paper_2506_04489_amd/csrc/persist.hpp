@@ -286,4 +286,23 @@ k_persist(PBatch *bt) {
     }
 }
 
+// The same passes with one workgroup per work item (grid = the pass's total):
+// still one launch per pass for every solve, with the hardware dispatcher
+// instead of the counter handing out items.
+template <typename T, int PASS>
+__global__ void __launch_bounds__(PB_THREADS) __attribute__((amdgpu_waves_per_eu(3)))
+k_flat(PBatch *bt) {
+    const int item = blockIdx.x;
+    const int njobs = bt->njobs;
+    const int *start = bt->start + PASS * (njobs + 1);
+    int lo = 0, hi = njobs - 1;            // last job whose first item <= item
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= item) lo = mid;
+        else hi = mid - 1;
+    }
+    const PJob *jp = bt->jobs + lo;
+    pb_dispatch<T, PASS>(jp, jp->N, jp->pv[PASS], item - start[lo]);
+}
+
 }  // namespace psp

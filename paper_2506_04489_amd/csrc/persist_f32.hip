@@ -24,4 +24,13 @@ hipError_t persist_launch_f32(PBatch *d_hdr, const int *total, const int *grid, 
     return hipGetLastError();
 }
 
+hipError_t flat_launch_f32(PBatch *d_hdr, const int *total, hipStream_t st) {
+    hipLaunchKernelGGL((k_flat<float, 0>), dim3(total[0]), dim3(PB_THREADS), 0, st, d_hdr);
+    hipLaunchKernelGGL((k_flat<float, 1>), dim3(total[1]), dim3(PB_THREADS), 0, st, d_hdr);
+    hipLaunchKernelGGL((k_flat<float, 2>), dim3(total[2]), dim3(PB_THREADS), 0, st, d_hdr);
+    hipLaunchKernelGGL((k_flat<float, 3>), dim3(total[3]), dim3(PB_THREADS), 0, st, d_hdr);
+    hipLaunchKernelGGL((k_flat<float, 4>), dim3(total[4]), dim3(PB_THREADS), 0, st, d_hdr);
+    return hipGetLastError();
+}
+
 }  // namespace psp

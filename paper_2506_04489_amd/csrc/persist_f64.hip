@@ -79,6 +79,18 @@ hipError_t persist_prepare() {
     return grids(&g);
 }
 
+hipError_t flat_launch_f32(PBatch *d_hdr, const int *total, hipStream_t st);
+
+hipError_t flat_launch(bool f32, PBatch *d_hdr, const int *total, hipStream_t st) {
+    if (f32) return flat_launch_f32(d_hdr, total, st);
+    hipLaunchKernelGGL((k_flat<double, 0>), dim3(total[0]), dim3(PB_THREADS), 0, st, d_hdr);
+    hipLaunchKernelGGL((k_flat<double, 1>), dim3(total[1]), dim3(PB_THREADS), 0, st, d_hdr);
+    hipLaunchKernelGGL((k_flat<double, 2>), dim3(total[2]), dim3(PB_THREADS), 0, st, d_hdr);
+    hipLaunchKernelGGL((k_flat<double, 3>), dim3(total[3]), dim3(PB_THREADS), 0, st, d_hdr);
+    hipLaunchKernelGGL((k_flat<double, 4>), dim3(total[4]), dim3(PB_THREADS), 0, st, d_hdr);
+    return hipGetLastError();
+}
+
 hipError_t persist_launch(bool f32, PBatch *d_hdr, const int *total, bool reset, hipStream_t st) {
     PersistGrid g;
     hipError_t e = grids(&g);

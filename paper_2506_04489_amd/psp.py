@@ -133,10 +133,11 @@ def debug_guards(enable: bool):
 
 def set_batch_mode(mode: str):
     """'grouped' (default): one launch per pass per (n, shape); 'persistent':
-    persistent kernels over every solve with 2n <= 256."""
-    codes = {"grouped": 0, "persistent": 1}
+    persistent kernels over every solve with 2n <= 256; 'flat': the same
+    kernels with one workgroup per work item."""
+    codes = {"grouped": 0, "persistent": 1, "flat": 2}
     if mode not in codes:
-        raise ValueError("mode must be 'grouped' or 'persistent'")
+        raise ValueError("mode must be 'grouped', 'persistent' or 'flat'")
     _check(lib().psp_set_batch_mode(codes[mode]))
 
 

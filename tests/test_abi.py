@@ -172,11 +172,12 @@ def test_shipped_tuning_table_is_valid():
 
 def test_batch_mode_validation():
     lib = B.lib()
-    assert lib.psp_set_batch_mode(2) == -1         # PSP_EINVAL
+    assert lib.psp_set_batch_mode(3) == -1         # PSP_EINVAL
     assert lib.psp_set_batch_mode(-1) == -1
     with pytest.raises(ValueError):
         B.set_batch_mode("fast")
     B.set_batch_mode("persistent")
+    B.set_batch_mode("flat")
     B.set_batch_mode("grouped")
 
 

@@ -29,7 +29,7 @@ def _setup(count, dtype, seed):
     return items, plans, rhos
 
 
-@pytest.fixture(params=["grouped", "persistent"])
+@pytest.fixture(params=["grouped", "persistent", "flat"])
 def batch_mode(request):
     B.set_batch_mode(request.param)
     yield request.param
@@ -129,12 +129,13 @@ def test_graph_batched_replays_match_eager(batch_mode):
     g.close()
 
 
-def test_persistent_batch_covers_every_size_and_large_members():
+@pytest.mark.parametrize("mode", ["persistent", "flat"])
+def test_persistent_batch_covers_every_size_and_large_members(mode):
     """Every padded length up to 256 (radix-2 and radix-3 plans, alternative
-    radix plans) in one persistent batch, with n = 192 members taking the
-    grouped launches in the same call."""
+    radix plans) in one persistent (or flat) batch, with n = 192 members
+    taking the grouped launches in the same call."""
     import torch
-    B.set_batch_mode("persistent")
+    B.set_batch_mode(mode)
     try:
         sizes = [4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192]
         ps, rhos = [], []
