@@ -18,29 +18,35 @@ namespace psp {
 // B[l/16][l%16], D[l/16 + 4e][l%16] for e < 4.
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-// one wave: a 16-row a-tile for one b against SPEC_CT consecutive 16-wide
-// c-tiles (six: 288 columns cover n + 1 = 257 with one partial tile); the A
-// operand of each k-step is formed once and feeds SPEC_CT MFMAs, and the
-// operands of step k + 4 are loaded before the MFMAs of step k are issued,
-// so the table loads' latency overlaps the matrix work
+// one wave: SPEC_AT 16-row a-tiles for one b against SPEC_CT consecutive
+// 16-wide c-tiles (1 x 6: 272 rows and 288 columns for n + 1 = 257); every A
+// operand of a k-step feeds SPEC_CT MFMAs and every B operand SPEC_AT, and
+// the operands of step k + 4 are loaded before the MFMAs of step k are
+// issued, so the table loads' latency overlaps the matrix work (measured on
+// MI355X at n = 256: 1 x 6 144 us; 2 x 6 171 us, its 244 registers leaving
+// two waves per SIMD)
+constexpr int SPEC_AT = 1;
 constexpr int SPEC_CT = 6;
 
 struct SpecOps {
-    double av;
+    double av[SPEC_AT];
     double bv[SPEC_CT];
 };
 
-__device__ __forceinline__ void spec_load(SpecOps &o, int k0, int kq, int a, int b, int cbase, int R, int n,
+__device__ __forceinline__ void spec_load(SpecOps &o, int k0, int kq, int abase, int b, int cbase, int R, int n,
                                           const double *__restrict__ J0, const double *__restrict__ J2,
                                           const double *__restrict__ omega) {
     const int n1 = n + 1;
     const int ks = k0 + kq, s = ks >> 1, ty = ks & 1;
     const bool live = s < R;
     const double *j0 = J0 + (size_t)(live ? s : 0) * n1, *j2 = J2 + (size_t)(live ? s : 0) * n1;
-    o.av = 0.0;
-    if (live && a <= n) {
-        const double w = omega[s];
-        o.av = ty == 0 ? w * (j2[a] * j0[b] + j0[a] * j2[b]) : w * (j0[a] * j0[b]);
+    const double w = live ? omega[s] : 0.0;
+    const double j0b = j0[b], j2b = j2[b];
+#pragma unroll
+    for (int t = 0; t < SPEC_AT; ++t) {
+        const int a = abase + t * 16;
+        o.av[t] = 0.0;
+        if (live && a <= n) o.av[t] = ty == 0 ? w * (j2[a] * j0b + j0[a] * j2b) : w * (j0[a] * j0b);
     }
     const double *jb = ty == 0 ? j0 : j2;
 #pragma unroll
@@ -55,40 +61,46 @@ k_spectrum(const double *__restrict__ J0, const double *__restrict__ J2,
            const double *__restrict__ omega, int R, int n, int P, double scale,
            double *__restrict__ mult) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int nt = (n + 1 + 15) / 16, ng = (nt + SPEC_CT - 1) / SPEC_CT;
+    const int nt = (n + 1 + 15) / 16;
+    const int na = (nt + SPEC_AT - 1) / SPEC_AT, ng = (nt + SPEC_CT - 1) / SPEC_CT;
     const long item = (long)blockIdx.x * 4 + wave;
-    if (item >= (long)(n + 1) * nt * ng) return;    // no barriers in this kernel
-    const int b = (int)(item / (nt * ng));
-    const int rem = (int)(item % (nt * ng));
-    const int a0 = (rem / ng) * 16, cgrp = (rem % ng) * SPEC_CT;
+    if (item >= (long)(n + 1) * na * ng) return;    // no barriers in this kernel
+    const int b = (int)(item / (na * ng));
+    const int rem = (int)(item % (na * ng));
+    const int a0 = (rem / ng) * 16 * SPEC_AT, cgrp = (rem % ng) * SPEC_CT;
     const int row = lane & 15, kq = lane >> 4;
-    const int a = a0 + row;
     const int n1 = n + 1;
-    const int cbase = cgrp * 16 + row;
-    v4d acc[SPEC_CT];
+    const int abase = a0 + row, cbase = cgrp * 16 + row;
+    v4d acc[SPEC_AT][SPEC_CT];
 #pragma unroll
-    for (int q = 0; q < SPEC_CT; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < SPEC_AT; ++t)
+#pragma unroll
+        for (int q = 0; q < SPEC_CT; ++q) acc[t][q] = v4d{0.0, 0.0, 0.0, 0.0};
     SpecOps cur, nxt;
-    spec_load(cur, 0, kq, a, b, cbase, R, n, J0, J2, omega);
+    spec_load(cur, 0, kq, abase, b, cbase, R, n, J0, J2, omega);
     for (int k0 = 0; k0 < 2 * R; k0 += 4) {
-        if (k0 + 4 < 2 * R) spec_load(nxt, k0 + 4, kq, a, b, cbase, R, n, J0, J2, omega);
+        if (k0 + 4 < 2 * R) spec_load(nxt, k0 + 4, kq, abase, b, cbase, R, n, J0, J2, omega);
 #pragma unroll
-        for (int q = 0; q < SPEC_CT; ++q)
-            acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur.av, cur.bv[q], acc[q], 0, 0, 0);
+        for (int t = 0; t < SPEC_AT; ++t)
+#pragma unroll
+            for (int q = 0; q < SPEC_CT; ++q)
+                acc[t][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur.av[t], cur.bv[q], acc[t][q], 0, 0, 0);
         cur = nxt;
     }
 #pragma unroll
-    for (int q = 0; q < SPEC_CT; ++q) {
-        const int cc = (cgrp + q) * 16 + row;
+    for (int t = 0; t < SPEC_AT; ++t)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int aa = a0 + kq + 4 * e;
-            if (aa <= n && cc <= n) {
-                const double k2 = (double)aa * aa + (double)b * b + (double)cc * cc;
-                mult[((size_t)(b * (P / 8) + cc / 8) * n1 + aa) * 8 + (cc & 7)] = scale * k2 * acc[q][e];
+        for (int q = 0; q < SPEC_CT; ++q) {
+            const int cc = (cgrp + q) * 16 + row;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int aa = a0 + t * 16 + kq + 4 * e;
+                if (aa <= n && cc <= n) {
+                    const double k2 = (double)aa * aa + (double)b * b + (double)cc * cc;
+                    mult[((size_t)(b * (P / 8) + cc / 8) * n1 + aa) * 8 + (cc & 7)] = scale * k2 * acc[t][q][e];
+                }
             }
         }
-    }
 }
 
 // --------------------------------------------------------------- launchers
@@ -141,8 +153,9 @@ hipError_t launch_group(int n, bool f32, const Shape &shape, const Job *table_de
 
 hipError_t launch_spectrum(const double *J0, const double *J2, const double *omega, int R, int n, int P,
                            double scale, double *mult, hipStream_t st) {
-    const int nt = (n + 1 + 15) / 16, ng = (nt + SPEC_CT - 1) / SPEC_CT;
-    const long items = (long)(n + 1) * nt * ng;
+    const int nt = (n + 1 + 15) / 16;
+    const int na = (nt + SPEC_AT - 1) / SPEC_AT, ng = (nt + SPEC_CT - 1) / SPEC_CT;
+    const long items = (long)(n + 1) * na * ng;
     hipLaunchKernelGGL(k_spectrum, dim3(ceil_div_l(items, 4)), dim3(256), 0, st, J0, J2, omega, R, n, P, scale,
                        mult);
     return hipGetLastError();
