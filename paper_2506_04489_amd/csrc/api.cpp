@@ -57,7 +57,6 @@ psp_status get_twiddles(int device, int N, const Twiddles **out) {
         return PSP_OK;
     }
     std::vector<double> w(2 * (size_t)N);
-    std::vector<float> hi(2 * (size_t)N), lo(2 * (size_t)N);
     const long double two_pi = 6.283185307179586476925286766559005768L;
     for (int m = 0; m < N; ++m) {
         // exp(-2 pi i m / N), long double evaluation rounded once
@@ -65,18 +64,10 @@ psp_status get_twiddles(int device, int N, const Twiddles **out) {
         const double c = (double)cosl(ang), s = (double)-sinl(ang);
         w[2 * m] = c;
         w[2 * m + 1] = s;
-        hi[2 * m] = (float)c;
-        hi[2 * m + 1] = (float)s;
-        lo[2 * m] = (float)(c - (double)hi[2 * m]);
-        lo[2 * m + 1] = (float)(s - (double)hi[2 * m + 1]);
     }
     Twiddles t;
     PSP_HIP(hipMalloc(&t.w64, w.size() * 8), "hipMalloc(twiddles)");
-    PSP_HIP(hipMalloc(&t.hi32, hi.size() * 4), "hipMalloc(twiddles)");
-    PSP_HIP(hipMalloc(&t.lo32, lo.size() * 4), "hipMalloc(twiddles)");
     PSP_HIP(hipMemcpy(t.w64, w.data(), w.size() * 8, hipMemcpyHostToDevice), "hipMemcpy(twiddles)");
-    PSP_HIP(hipMemcpy(t.hi32, hi.data(), hi.size() * 4, hipMemcpyHostToDevice), "hipMemcpy(twiddles)");
-    PSP_HIP(hipMemcpy(t.lo32, lo.data(), lo.size() * 4, hipMemcpyHostToDevice), "hipMemcpy(twiddles)");
     auto res = g_tw_cache.emplace(key, t);
     *out = &res.first->second;
     return PSP_OK;
@@ -187,12 +178,7 @@ SolveArgs solve_args(const psp_plan *p, const Workspace &w, const void *rho, voi
     a.i1_group = p->i1_group;
     a.shape = p->shape;
     a.mult = p->spec->mult;
-    if (a.f32) {
-        a.tw_hi = p->tw->hi32;
-        a.tw_lo = p->tw->lo32;
-    } else {
-        a.tw_hi = p->tw->w64;
-    }
+    a.tw64 = p->tw->w64;
     return a;
 }
 

@@ -103,8 +103,7 @@ void build_batch_image(const std::vector<BatchMember> &m, bool f32, unsigned cha
         pj.X = b.job.X;
         pj.A = b.job.A;
         pj.mult = b.job.mult;
-        pj.tw_hi = b.tw_hi;
-        pj.tw_lo = b.tw_lo;
+        pj.tw64 = b.tw64;
         pj.N = 2 * b.n;
         pj.P = pitch_for(b.n);
         pj.pa = ((b.n + 1 + LW - 1) / LW) * LW;   // one chunk holding all tiles
@@ -129,7 +128,7 @@ hipError_t launch_batch_image(const std::vector<BatchMember> &m, const BatchImag
         const BatchMember &b = m[g[i]];
         while (j < g.size() && m[g[j]].n == b.n && m[g[j]].shape == b.shape) ++j;
         hipError_t e = launch_group(b.n, f32, b.shape, (const Job *)(dev_base + img.group_off) + i, (int)(j - i),
-                                    b.tw_hi, b.tw_lo, st);
+                                    b.tw64, st);
         if (e != hipSuccess) return e;
         i = j;
     }
@@ -225,8 +224,7 @@ hipError_t launch_batch(int count, const SolveArgs *args, hipStream_t st) {
         m[i].job = Job{a.rho, a.u, a.X, a.A, a.mult, nullptr, nullptr};
         m[i].n = a.n;
         m[i].shape = a.shape;
-        m[i].tw_hi = a.tw_hi;
-        m[i].tw_lo = a.tw_lo;
+        m[i].tw64 = a.tw64;
     }
     std::lock_guard<std::mutex> lk(g_batch_mu);
     psp_status rs = run_batch(g_batch[{dev, st}].stage, m, args[0].f32, st);
@@ -272,8 +270,7 @@ extern "C" psp_status psp_solve_batched(int count, psp_plan *const *plans, const
         m[i].job = Job{rho_dev[i], u_dev[i], ws[i]->X, ws[i]->A, plans[i]->spec->mult, nullptr, nullptr};
         m[i].n = plans[i]->n;
         m[i].shape = plans[i]->shape;
-        m[i].tw_hi = f32 ? plans[i]->tw->hi32 : plans[i]->tw->w64;
-        m[i].tw_lo = f32 ? plans[i]->tw->lo32 : nullptr;
+        m[i].tw64 = plans[i]->tw->w64;
     }
     return run_batch(B.stage, m, f32, st);
 }

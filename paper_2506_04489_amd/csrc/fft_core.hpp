@@ -40,80 +40,54 @@ __device__ __forceinline__ double fmadd(double a, double b, double c) { return _
 __device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
 // --------------------------------------------------------------- twiddles
-// Table of W_N^m = exp(-2 pi i m / N), m < N.  FP64: one table.  FP32: the
-// value split into hi = fl32(w) and lo = fl32(w - hi), so the product a*w is
-// formed as a*hi + a*lo and the twiddle itself carries ~1e-15 error.
-template <typename T> struct Twiddle;
-template <> struct Twiddle<double> {
+// Table of W_N^m = exp(-2 pi i m / N), m < N, in FP64 for both tiers.  A
+// radix-R butterfly loads the one entry W^m and forms the powers W^{m r},
+// r = 1..R-1, by a multiplication tree of depth <= 4 (a few ulp of FP64):
+// one load instead of R-1 (wave-wide loads cost L1 return bandwidth per
+// lane).  The FP32 tier applies them in FP64 too and rounds each product
+// once to FP32: without packed FP32 instructions an FP64 multiply-add costs
+// the same issue slot as an FP32 one, and the twiddle then adds no error
+// beyond that rounding.
+__device__ __forceinline__ double2 cmul64(double2 a, double2 t) {
+    return double2{fmadd(a.x, t.x, -(a.y * t.y)), fmadd(a.x, t.y, a.y * t.x)};
+}
+template <bool INV> __device__ __forceinline__ double2 cmul64_dir(double2 a, double2 t) {
+    return cmul64(a, INV ? double2{t.x, -t.y} : t);
+}
+// p[r] = W^{m r} for r = 1..R-1 from p[1] = W^m
+template <int R> __device__ __forceinline__ void twiddle_powers(double2 *p) {
+    if constexpr (R > 2) p[2] = cmul64(p[1], p[1]);
+    if constexpr (R > 3) p[3] = cmul64(p[2], p[1]);
+    if constexpr (R > 4) {
+        p[4] = cmul64(p[2], p[2]);
+        p[5] = cmul64(p[4], p[1]);
+        p[6] = cmul64(p[4], p[2]);
+        p[7] = cmul64(p[4], p[3]);
+    }
+    if constexpr (R > 8) {
+        p[8] = cmul64(p[4], p[4]);
+#pragma unroll
+        for (int k = 1; k < 8; ++k) p[8 + k] = cmul64(p[8], p[k]);
+    }
+    static_assert(R == 2 || R == 3 || R == 4 || R == 8 || R == 16, "radix");
+}
+
+template <typename T> struct Twiddle {
     const double2 *w;
-    template <bool INV> __device__ __forceinline__ static double2 cmul(double2 a, double2 t) {
-        const double ty = INV ? -t.y : t.y;
-        return double2{fmadd(a.x, t.x, -(a.y * ty)), fmadd(a.x, ty, a.y * t.x)};
-    }
-    template <bool INV> __device__ __forceinline__ double2 mul(double2 a, int m) const { return cmul<INV>(a, w[m]); }
-    // v[r] *= W^{m r}, r = 1..R-1, from the single table entry W^m: powers
-    // by a multiplication tree of depth <= 3 (a few ulp), one load instead
-    // of R-1 (wave-wide loads cost L1 return bandwidth per lane)
-    template <int R, bool INV> __device__ __forceinline__ void apply(double2 *v, int m) const {
-        const double2 w1 = w[m];
-        if constexpr (R == 2) {
-            v[1] = cmul<INV>(v[1], w1);
-        } else if constexpr (R == 3) {
-            const double2 w2 = cmul<false>(w1, w1);
-            v[1] = cmul<INV>(v[1], w1);
-            v[2] = cmul<INV>(v[2], w2);
-        } else if constexpr (R == 4) {
-            const double2 w2 = cmul<false>(w1, w1), w3 = cmul<false>(w2, w1);
-            v[1] = cmul<INV>(v[1], w1);
-            v[2] = cmul<INV>(v[2], w2);
-            v[3] = cmul<INV>(v[3], w3);
-        } else if constexpr (R == 8) {
-            const double2 w2 = cmul<false>(w1, w1), w4 = cmul<false>(w2, w2);
-            const double2 w3 = cmul<false>(w2, w1), w5 = cmul<false>(w4, w1);
-            const double2 w6 = cmul<false>(w4, w2), w7 = cmul<false>(w4, w3);
-            v[1] = cmul<INV>(v[1], w1);
-            v[2] = cmul<INV>(v[2], w2);
-            v[3] = cmul<INV>(v[3], w3);
-            v[4] = cmul<INV>(v[4], w4);
-            v[5] = cmul<INV>(v[5], w5);
-            v[6] = cmul<INV>(v[6], w6);
-            v[7] = cmul<INV>(v[7], w7);
-        } else {
-            static_assert(R == 16, "radix");
-            // powers by a tree of depth <= 4 from w1
-            double2 w[16];
-            w[1] = w1;
-            w[2] = cmul<false>(w1, w1);
-            w[4] = cmul<false>(w[2], w[2]);
-            w[8] = cmul<false>(w[4], w[4]);
-            w[3] = cmul<false>(w[2], w1);
-            w[5] = cmul<false>(w[4], w1);
-            w[6] = cmul<false>(w[4], w[2]);
-            w[7] = cmul<false>(w[4], w[3]);
+    // v[r] *= W^{m r}, r = 1..R-1 (conjugated for the inverse transform)
+    template <int R, bool INV> __device__ __forceinline__ void apply(cplx<T> *v, int m) const {
+        double2 p[R];
+        p[1] = w[m];
+        twiddle_powers<R>(p);
 #pragma unroll
-            for (int k = 1; k < 8; ++k) w[8 + k] = cmul<false>(w[8], w[k]);
-#pragma unroll
-            for (int k = 1; k < 16; ++k) v[k] = cmul<INV>(v[k], w[k]);
+        for (int r = 1; r < R; ++r) {
+            if constexpr (sizeof(T) == 8) {
+                v[r] = cmul64_dir<INV>(v[r], p[r]);
+            } else {
+                const double2 x = cmul64_dir<INV>(double2{(double)v[r].x, (double)v[r].y}, p[r]);
+                v[r] = float2{(float)x.x, (float)x.y};
+            }
         }
-    }
-};
-template <> struct Twiddle<float> {
-    const float2 *hi;
-    const float2 *lo;
-    template <bool INV> __device__ __forceinline__ float2 mul(float2 a, int m) const {
-        float2 h = hi[m], l = lo[m];
-        float hy = INV ? -h.y : h.y;
-        float ly = INV ? -l.y : l.y;
-        // the small lo products first, then the hi products on top
-        const float rx = fmadd(-a.y, ly, a.x * l.x);
-        const float ry = fmadd(a.y, l.x, a.x * ly);
-        return float2{fmadd(a.x, h.x, fmadd(-a.y, hy, rx)), fmadd(a.x, hy, fmadd(a.y, h.x, ry))};
-    }
-    // v[r] *= W^{m r}: every power from the split table (an FP32 product
-    // of split twiddles would lose their extra precision)
-    template <int R, bool INV> __device__ __forceinline__ void apply(float2 *v, int m) const {
-#pragma unroll
-        for (int r = 1; r < R; ++r) v[r] = mul<INV>(v[r], m * r);
     }
 };
 

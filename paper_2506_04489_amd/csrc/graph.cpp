@@ -111,8 +111,7 @@ psp_status psp_graph_capture_batched(int count, psp_plan *const *plans, const vo
         m[i].job = Job{rho_dev[i], u_dev[i], g->ws[i].X, g->ws[i].A, plans[i]->spec->mult, nullptr, nullptr};
         m[i].n = plans[i]->n;
         m[i].shape = plans[i]->shape;
-        m[i].tw_hi = f32 ? plans[i]->tw->hi32 : plans[i]->tw->w64;
-        m[i].tw_lo = f32 ? plans[i]->tw->lo32 : nullptr;
+        m[i].tw64 = plans[i]->tw->w64;
     }
     if (persist_prepare() != hipSuccess) {
         (void)hipGetLastError();

@@ -37,8 +37,6 @@ struct DevSpectrum {            // the multiplier octant, shared between plans
 
 struct Twiddles {               // per (device, N), process lifetime
     void *w64 = nullptr;        // double2[N]
-    void *hi32 = nullptr;       // float2[N]
-    void *lo32 = nullptr;       // float2[N]
 };
 psp_status get_twiddles(int device, int N, const Twiddles **out);
 
@@ -83,8 +81,7 @@ struct BatchMember {
     Job job;                      // pointers; workspace of one chunk holding all tiles
     int n = 0;
     Shape shape;
-    const void *tw_hi = nullptr;  // twiddles of length 2n
-    const void *tw_lo = nullptr;
+    const void *tw64 = nullptr;  // twiddles of length 2n
 };
 struct BatchImage {
     std::vector<int> persist;     // members on the persistent path (2n <= PB_MAX_N), in table order

@@ -75,8 +75,7 @@ struct PJob {
     void *X;                 // n*n*P complex
     void *A;                 // n*N*pa complex
     const double *mult;      // blocked multiplier octant
-    const void *tw_hi;       // twiddles of length N (FP64, or FP32 hi)
-    const void *tw_lo;       // FP32 lo
+    const void *tw64;       // twiddles double2[N], both tiers
     int N;                   // padded length
     int P;                   // k3 pitch of X
     int pa;                  // k3 pitch of A
@@ -123,8 +122,7 @@ struct SolveArgs {
     void *A2 = nullptr;  // N*N*P complex, full variant only
     void *Y2 = nullptr;  // N*N*P complex, full variant only
     const double *mult = nullptr;   // blocked multiplier octant
-    const void *tw_hi = nullptr;    // twiddles: double2[N] (FP64) or float2[N] hi
-    const void *tw_lo = nullptr;    // float2[N] lo (FP32 only)
+    const void *tw64 = nullptr;    // twiddles double2[N], both tiers
     hipEvent_t *ev = nullptr;       // optional profiling events, one before each launch and one after
     int *ev_pass = nullptr;         // host array: pass (0..4) of each launch, -1 for the last event
     int nev = 0;
@@ -135,8 +133,8 @@ hipError_t launch_solve(const SolveArgs &s, hipStream_t st);
 // `count` solves of the same n and tier in one launch per pass; `table_dev`
 // is a device array of `count` jobs, each with a workspace of one chunk
 // holding all tiles (chunk_tiles = 0)
-hipError_t launch_group(int n, bool f32, const Shape &shape, const Job *table_dev, int count, const void *tw_hi,
-                        const void *tw_lo, hipStream_t st);
+hipError_t launch_group(int n, bool f32, const Shape &shape, const Job *table_dev, int count, const void *tw64,
+                        hipStream_t st);
 
 // k3 columns per 128-byte row tile of the padded intermediates (8 FP64, 16 FP32)
 inline int strided_width(bool f32) { return f32 ? 16 : 8; }

@@ -319,15 +319,9 @@ k_z_c2r(JobRef jr, int npairs, int P, Twiddle<T> tw) {
 // --------------------------------------------------------------- launchers
 inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
 
-template <typename T> static Twiddle<T> twiddle_of(const void *hi, const void *lo) {
+template <typename T> static Twiddle<T> twiddle_of(const void *w) {
     Twiddle<T> tw;
-    if constexpr (sizeof(T) == 8) {
-        (void)lo;
-        tw.w = (const double2 *)hi;
-    } else {
-        tw.hi = (const float2 *)hi;
-        tw.lo = (const float2 *)lo;
-    }
+    tw.w = (const double2 *)w;
     return tw;
 }
 
@@ -383,11 +377,11 @@ template <typename F> inline void with_threads(int tile, F &&f) {
 // ev_pass[i] receives the pass (0..4) of launch i.
 template <typename T, int N>
 hipError_t passes_impl(const Job &one, const Job *table, int count, int P, int chunk_tiles, int i1_group,
-                       const Shape &sh, bool full, const void *tw_hi, const void *tw_lo, hipEvent_t *ev,
+                       const Shape &sh, bool full, const void *tw64, hipEvent_t *ev,
                        int *ev_pass, int nev, hipStream_t st) {
     constexpr int n = N / 2;
     constexpr int LW = LayoutTile<T>::W;
-    const Twiddle<T> tw = twiddle_of<T>(tw_hi, tw_lo);
+    const Twiddle<T> tw = twiddle_of<T>(tw64);
     int launch = 0;
     auto mark = [&](int pass) {
         if (ev && launch < nev) {
@@ -532,10 +526,10 @@ hipError_t passes_impl(const Job &one, const Job *table, int count, int P, int c
 // instantiation file covers a subset of the lengths (PSP_CASE per length)
 #define PSP_PASSES_SIGNATURE                                                                                  \
     (int N, const Job &one, const Job *table, int count, int P, int chunk_tiles, int i1_group, const Shape &sh, \
-     bool full, const void *tw_hi, const void *tw_lo, hipEvent_t *ev, int *ev_pass, int nev, hipStream_t st)
+     bool full, const void *tw64, hipEvent_t *ev, int *ev_pass, int nev, hipStream_t st)
 #define PSP_CASE(T, NN)                                                                                        \
     case NN:                                                                                                   \
-        return passes_impl<T, NN>(one, table, count, P, chunk_tiles, i1_group, sh, full, tw_hi, tw_lo, ev,     \
+        return passes_impl<T, NN>(one, table, count, P, chunk_tiles, i1_group, sh, full, tw64, ev,     \
                                   ev_pass, nev, st);
 
 // padded lengths up to 192 in the *_lo files, the rest in the *_hi files

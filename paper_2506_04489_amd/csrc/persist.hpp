@@ -38,12 +38,7 @@ static __shared__ __attribute__((aligned(16))) PB_LDS_ELEM pb_lds_strided[PB_STR
 
 template <typename T> __device__ __forceinline__ Twiddle<T> pb_twiddle(const PJob &jb) {
     Twiddle<T> tw;
-    if constexpr (sizeof(T) == 8) {
-        tw.w = (const double2 *)jb.tw_hi;
-    } else {
-        tw.hi = (const float2 *)jb.tw_hi;
-        tw.lo = (const float2 *)jb.tw_lo;
-    }
+    tw.w = (const double2 *)jb.tw64;
     return tw;
 }
 

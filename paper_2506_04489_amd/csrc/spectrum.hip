@@ -107,16 +107,16 @@ k_spectrum(const double *__restrict__ J0, const double *__restrict__ J2,
 static inline int ceil_div_l(long a, long b) { return (int)((a + b - 1) / b); }
 
 hipError_t passes_f64_lo(int N, const Job &one, const Job *table, int count, int P, int chunk_tiles, int i1_group,
-                         const Shape &sh, bool full, const void *tw_hi, const void *tw_lo, hipEvent_t *ev,
+                         const Shape &sh, bool full, const void *tw64, hipEvent_t *ev,
                          int *ev_pass, int nev, hipStream_t st);
 hipError_t passes_f64_hi(int N, const Job &one, const Job *table, int count, int P, int chunk_tiles, int i1_group,
-                         const Shape &sh, bool full, const void *tw_hi, const void *tw_lo, hipEvent_t *ev,
+                         const Shape &sh, bool full, const void *tw64, hipEvent_t *ev,
                          int *ev_pass, int nev, hipStream_t st);
 hipError_t passes_f32_lo(int N, const Job &one, const Job *table, int count, int P, int chunk_tiles, int i1_group,
-                         const Shape &sh, bool full, const void *tw_hi, const void *tw_lo, hipEvent_t *ev,
+                         const Shape &sh, bool full, const void *tw64, hipEvent_t *ev,
                          int *ev_pass, int nev, hipStream_t st);
 hipError_t passes_f32_hi(int N, const Job &one, const Job *table, int count, int P, int chunk_tiles, int i1_group,
-                         const Shape &sh, bool full, const void *tw_hi, const void *tw_lo, hipEvent_t *ev,
+                         const Shape &sh, bool full, const void *tw64, hipEvent_t *ev,
                          int *ev_pass, int nev, hipStream_t st);
 
 // the instantiation holding padded length N
@@ -139,16 +139,16 @@ int solve_launches(int n, bool f32, int chunk_tiles, int i1_group) {
 hipError_t launch_solve(const SolveArgs &s, hipStream_t st) {
     const Job one{s.rho, s.u, s.X, s.A, s.mult, s.A2, s.Y2};
     auto f = passes_for(s.f32, 2 * s.n);
-    return f(2 * s.n, one, nullptr, 1, s.P, s.chunk_tiles, s.i1_group, s.shape, s.full, s.tw_hi, s.tw_lo, s.ev,
+    return f(2 * s.n, one, nullptr, 1, s.P, s.chunk_tiles, s.i1_group, s.shape, s.full, s.tw64, s.ev,
              s.ev_pass, s.nev, st);
 }
 
-hipError_t launch_group(int n, bool f32, const Shape &shape, const Job *table_dev, int count, const void *tw_hi,
-                        const void *tw_lo, hipStream_t st) {
+hipError_t launch_group(int n, bool f32, const Shape &shape, const Job *table_dev, int count, const void *tw64,
+                        hipStream_t st) {
     const Job none{};
     const int P = ((n + 1 + 15) / 16) * 16;
     auto f = passes_for(f32, 2 * n);
-    return f(2 * n, none, table_dev, count, P, 0, 0, shape, false, tw_hi, tw_lo, nullptr, nullptr, 0, st);
+    return f(2 * n, none, table_dev, count, P, 0, 0, shape, false, tw64, nullptr, nullptr, 0, st);
 }
 
 hipError_t launch_spectrum(const double *J0, const double *J2, const double *omega, int R, int n, int P,
