@@ -257,6 +257,54 @@ def bench_serving(torch, B, D, count=2000, rates=(0.25, 0.5, 0.75, 0.9, 1.0, 1.2
     return out
 
 
+EPS_TABLE3 = (7.5e-2, 2.2e-2, 5.7e-3, 1.6e-3, 4.7e-4, 2.0e-4)
+
+
+def bench_eps(torch, B, sizes=(64, 128), R=461, sigma=0.2, reps=20):
+    """Error against the exact potential as the near-field cutoff eps varies
+    (Theorem 1, Table 3): the paper's Gaussian (sigma = 0.2) on its node grid
+    of [-2, 2]^3 (N nodes per axis, both ends), S = 460 Gaussian-sum terms,
+    eps relative to the box width.  Per (N, eps): E, set-up time (plan
+    creation + precompute, i.e. Algorithm 1) and solve time; per N the slope
+    of log E against log eps over the cutoff-limited rows."""
+    import math
+    out = {"sizes": list(sizes), "R": R, "sigma": sigma, "rows": [], "slope": {}}
+    for N in sizes:
+        h = 4.0 / (N - 1)
+        x = -2.0 + h * torch.arange(N, dtype=torch.float64, device="cuda")
+        r = torch.sqrt(x[:, None, None] ** 2 + x[None, :, None] ** 2 + x[None, None, :] ** 2)
+        rho = (torch.exp(-r * r / (2 * sigma * sigma)) / ((2 * math.pi) ** 1.5 * sigma ** 3)).contiguous()
+        safe = torch.where(r > 0, r, torch.ones_like(r))
+        u_star = torch.where(r > 0, torch.special.erf(safe / (math.sqrt(2) * sigma)) / (4 * math.pi * safe),
+                             torch.full_like(r, math.sqrt(2 / math.pi) / (4 * math.pi * sigma)))
+        logs = []
+        for e in EPS_TABLE3:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            p = B.Plan(N, h, R, eps=e * 4.0, delta=math.sqrt(3.0) * N * h).precompute()
+            torch.cuda.synchronize()
+            setup_s = time.perf_counter() - t0
+            u = p.solve(rho)
+            for _ in range(3):
+                p.solve(rho, u)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                p.solve(rho, u)
+            torch.cuda.synchronize()
+            solve_ms = 1e3 * (time.perf_counter() - t0) / reps
+            E = float((u - u_star).abs().max() / u_star.abs().max())
+            out["rows"].append({"N": N, "eps": e, "E": float("%.4g" % E), "setup_s": round(setup_s, 3),
+                                "solve_ms": round(solve_ms, 4)})
+            if 4e-4 < e < 3e-2:
+                logs.append((math.log(e), math.log(E)))
+            del p
+        mx = sum(a for a, _ in logs) / len(logs)
+        my = sum(b for _, b in logs) / len(logs)
+        out["slope"][N] = round(sum((a - mx) * (b - my) for a, b in logs) / sum((a - mx) ** 2 for a, _ in logs), 3)
+    return out
+
+
 def cpu_baseline(n: int, budget_s: float = 12.0):
     """The oracle (as it stands) on a bounded sample of the same workload: its
     naive FFT on a batch of length-2n pencils, scaled to one full solve
@@ -297,6 +345,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched workload")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
     ap.add_argument("--serve-count", type=int, default=2000)
+    ap.add_argument("--no-eps", action="store_true", help="skip the near-field cutoff study")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for byte counters)")
     args = ap.parse_args()
@@ -375,6 +424,8 @@ def main():
         if loads:
             near = min(loads, key=lambda x: abs(x["load"] - 0.9))
             out["served_p50_ms"], out["served_p99_ms"] = near["p50_ms"], near["p99_ms"]
+    if not args.no_eps:
+        out["eps_study"] = bench_eps(torch, B)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(n)
     print(json.dumps(out))

@@ -163,3 +163,40 @@ def bump_radial_potential(r, radius=0.6):
         outer = quad(lambda s: s * rho(s), rc, radius, epsabs=0.0, epsrel=1e-13, limit=400)[0] if rc < radius else 0.0
         out.append(inner / rv + outer if rv > 0 else outer)
     return np.array(out)
+
+
+def gaussian_laplacian(X, Y, Z, sigma, centre=(0.0, 0.0, 0.0)):
+    """Laplacian of the normalised Gaussian of ``gaussian_pair``:
+    ``rho (r^2/sigma^4 - 3/sigma^2)``."""
+    r2 = (X - centre[0]) ** 2 + (Y - centre[1]) ** 2 + (Z - centre[2]) ** 2
+    rho = np.exp(-r2 / (2.0 * sigma * sigma)) / ((2.0 * math.pi) ** 1.5 * sigma ** 3)
+    return rho * (r2 / sigma ** 4 - 3.0 / sigma ** 2)
+
+
+def gs_cutoff_moment(omega, alpha, r_cut):
+    """Mass of the super-potential kernel's cutoff defect (Lemma 1 and its
+    proof, Section 2): ``M0 = int_{|y| < r_cut} (|y|/(8 pi) - V_GS(y)) dy``
+    with ``V_GS(r) = r^2 sum_s w_s exp(-a_s r^2)`` (eq. gs_x).
+
+    The defect lives in the ball of radius ~eps where the Gaussian sum stops
+    following 1/r; beyond it the two kernels agree to the fit error, so any
+    r_cut of a few eps gives the same M0.  For a smooth density the
+    super-potential v = V * rho is then off by ``M0 rho(x) + O(eps^6)``, and
+    since U = Lap V the potential u = Lap v is off by
+    ``u_h - u = -M0 Lap rho(x) + O(eps^6)``: the O(eps^4) law of the
+    error bound (Theorem 1).  Composite 24-point Gauss-Legendre on panels
+    split at the Gaussian widths 1/sqrt(a_s)."""
+    w = np.asarray(omega, dtype=np.float64)
+    a = np.asarray(alpha, dtype=np.float64)
+    x, wt = np.polynomial.legendre.leggauss(24)
+    widths = sorted(float(1.0 / math.sqrt(v)) for v in a if 1.0 / math.sqrt(v) < r_cut)
+    edges = [0.0] + widths + [r_cut]
+    total = 0.0
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        for k in range(4):
+            l = lo + (hi - lo) * k / 4.0
+            r = lo + (hi - lo) * (k + 1) / 4.0
+            y = 0.5 * (l + r) + 0.5 * (r - l) * x
+            vgs = y * y * (np.exp(-np.outer(y * y, a)) @ w)
+            total += 0.5 * (r - l) * float(np.sum(wt * 4.0 * math.pi * y * y * (y / (8.0 * math.pi) - vgs)))
+    return total
