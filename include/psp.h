@@ -69,10 +69,11 @@ psp_status psp_plan_create(int n, double h, int R, psp_dtype dtype, psp_plan **o
 psp_status psp_plan_create_ex(int n, double h, int R, psp_dtype dtype,
                               double eps, double delta, psp_plan **out);
 
-/* Algorithm 1 steps 2-3 on the current device: the 2 R (n+1) 1D integrals of
- * eq. Gten_sep (host FP64, Gauss-Kronrod), the kernel-spectrum multiplier
- * octant (n+1)^3 by an FP64 MFMA contraction on `stream`, FFT twiddle
- * tables.  Idempotent.  Multiplier octants are shared between plans with the
+/* Algorithm 1 steps 2-3 on the current device, on `stream`: the 2 R (n+1) 1D
+ * integrals of eq. Gten_sep (FP64 with double-double node phases: closed
+ * forms for narrow Gaussians, 15-point Gauss-Kronrod on equal panels
+ * otherwise), the kernel-spectrum multiplier octant (n+1)^3 by an FP64 MFMA
+ * contraction, FFT twiddle tables.  Idempotent.  Multiplier octants are shared between plans with the
  * same (n, h, R, eps, delta) on the same device.  Synchronises `stream`. */
 psp_status psp_kernel_precompute(psp_plan *p, void *stream);
 
@@ -120,8 +121,10 @@ psp_status psp_plan_check_guards(psp_plan *p, int *intact);
 /* Test hook: copies the R weights w_s and exponents a_s (host arrays). */
 psp_status psp_plan_get_gs(const psp_plan *p, double *omega, double *alpha);
 
-/* Test hook: copies the host 1D tables J0[s][k], J2[s][k], s < R, k <= n
- * (row-major R x (n+1) each), computing them if needed (host work only). */
+/* Test hook: computes the 1D tables J0[s][k], J2[s][k], s < R, k <= n, on
+ * the current device (the plan's device once precomputed) exactly as the
+ * precompute does and copies them to host memory (row-major R x (n+1)
+ * each).  Needs a GPU; synchronises the device's null stream. */
 psp_status psp_plan_get_tables(psp_plan *p, double *J0, double *J2);
 
 /* Test hook: copies the device multiplier octant m[a][b][c] (a,b,c <= n,

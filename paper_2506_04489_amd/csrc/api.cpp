@@ -182,12 +182,23 @@ SolveArgs solve_args(const psp_plan *p, const Workspace &w, const void *rho, voi
     return a;
 }
 
-static psp_status ensure_tables(psp_plan *p) {
-    std::lock_guard<std::mutex> lk(p->mu);
-    if (!p->tables_ready) {
-        tables_1d(p->alpha, p->n, p->L, p->J0, p->J2);
-        p->tables_ready = true;
-    }
+// S1 on the device: one allocation holding J0, J2 (R x (n+1) each), the
+// Gaussian-sum weights (R), the quadrature layout (R jobs) and the
+// trigonometric table; the tables are filled on `st`.  The caller frees
+// *buf after the stream has run, and keeps `jobs` and `trig` alive until
+// then.
+static psp_status device_tables(const psp_plan *p, const std::vector<TabJob> &jobs, const std::vector<TabTrig> &trig,
+                                hipStream_t st, double **buf) {
+    const size_t tn = (size_t)p->R * (p->n + 1);
+    double *d = nullptr;
+    PSP_HIP(hipMalloc(&d, sizeof(double) * (2 * tn + p->R) + sizeof(TabJob) * p->R + sizeof(TabTrig) * trig.size()),
+            "hipMalloc(tables)");
+    *buf = d;
+    TabJob *dj = reinterpret_cast<TabJob *>(d + 2 * tn + p->R);
+    TabTrig *dt = reinterpret_cast<TabTrig *>(dj + p->R);
+    hipError_t e = hipMemcpyAsync(d + 2 * tn, p->omega.data(), sizeof(double) * p->R, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = launch_tables(jobs, trig, p->n, p->L, d, d + tn, dj, dt, st);
+    if (e != hipSuccess) return hip_fail(e, "1D tables");
     return PSP_OK;
 }
 
@@ -272,9 +283,21 @@ psp_status psp_plan_get_gs(const psp_plan *p, double *omega, double *alpha) {
 
 psp_status psp_plan_get_tables(psp_plan *p, double *J0, double *J2) {
     if (!p || !J0 || !J2) return fail(PSP_EINVAL, "NULL argument");
-    ensure_tables(p);
-    std::memcpy(J0, p->J0.data(), sizeof(double) * p->J0.size());
-    std::memcpy(J2, p->J2.data(), sizeof(double) * p->J2.size());
+    if (p->precomputed) {
+        psp_status s = current_device_of(p);
+        if (s != PSP_OK) return s;
+    }
+    const std::vector<TabJob> jobs = table_jobs(p->alpha, p->n, p->L);
+    const std::vector<TabTrig> trig = table_trig();
+    double *d = nullptr;
+    psp_status rs = device_tables(p, jobs, trig, nullptr, &d);
+    const size_t tb = sizeof(double) * (size_t)p->R * (p->n + 1);
+    hipError_t e = hipSuccess;
+    if (rs == PSP_OK && (e = hipMemcpy(J0, d, tb, hipMemcpyDeviceToHost)) == hipSuccess)
+        e = hipMemcpy(J2, d + (size_t)p->R * (p->n + 1), tb, hipMemcpyDeviceToHost);
+    if (d) (void)hipFree(d);
+    if (rs != PSP_OK) return rs;
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(tables)");
     return PSP_OK;
 }
 
@@ -306,7 +329,6 @@ psp_status psp_kernel_precompute(psp_plan *p, void *stream) {
         if (it != g_spec_cache.end()) spec = it->second.lock();
     }
     if (!spec) {
-        ensure_tables(p);
         const int n = p->n, R = p->R, P = pitch_for(n);
         spec = std::make_shared<DevSpectrum>();
         spec->device = dev;
@@ -317,18 +339,15 @@ psp_status psp_kernel_precompute(psp_plan *p, void *stream) {
             spec->mult = nullptr;
             return fail(PSP_ENOMEM, "spectrum allocation of %zu bytes failed", spec->bytes);
         }
+        const std::vector<TabJob> jobs = table_jobs(p->alpha, n, p->L);
+        const std::vector<TabTrig> trig = table_trig();
         double *dJ = nullptr;
-        const size_t tb = sizeof(double) * (size_t)R * (n + 1);
-        PSP_HIP(hipMalloc(&dJ, 2 * tb + sizeof(double) * R), "hipMalloc(tables)");
+        psp_status out = device_tables(p, jobs, trig, st, &dJ);
         double *dJ0 = dJ, *dJ2 = dJ + (size_t)R * (n + 1), *dW = dJ + 2 * (size_t)R * (n + 1);
-        psp_status out = PSP_OK;
         do {
+            if (out != PSP_OK) break;
             hipError_t ee;
-            if ((ee = hipMemcpyAsync(dJ0, p->J0.data(), tb, hipMemcpyHostToDevice, st)) != hipSuccess ||
-                (ee = hipMemcpyAsync(dJ2, p->J2.data(), tb, hipMemcpyHostToDevice, st)) != hipSuccess ||
-                (ee = hipMemcpyAsync(dW, p->omega.data(), sizeof(double) * R, hipMemcpyHostToDevice, st)) !=
-                    hipSuccess ||
-                (ee = hipMemsetAsync(spec->mult, 0, spec->bytes, st)) != hipSuccess) {
+            if ((ee = hipMemsetAsync(spec->mult, 0, spec->bytes, st)) != hipSuccess) {
                 out = hip_fail(ee, "precompute upload");
                 break;
             }
@@ -344,7 +363,10 @@ psp_status psp_kernel_precompute(psp_plan *p, void *stream) {
                 break;
             }
         } while (0);
-        (void)hipFree(dJ);
+        if (dJ) {
+            if (out != PSP_OK) (void)hipStreamSynchronize(st);   // nothing may still read it
+            (void)hipFree(dJ);
+        }
         if (out != PSP_OK) return out;
         std::lock_guard<std::mutex> lk(g_cache_mu);
         g_spec_cache[key] = spec;

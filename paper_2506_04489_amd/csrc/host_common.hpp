@@ -12,6 +12,7 @@
 
 #include "../../include/psp.h"
 #include "kernels.h"
+#include "tables.hpp"
 
 namespace psp {
 
@@ -22,10 +23,17 @@ psp_status hip_fail(hipError_t err, const char *what);
 // ---- S0: Gaussian-sum weights and exponents (sinc quadrature) -------------
 void gs_fit(int R, double eps, double delta, std::vector<double> &omega, std::vector<double> &alpha);
 
-// ---- S1: 1D integrals of the separable kernel transform --------------------
+// ---- S1: 1D integrals of the separable kernel transform (on the device) ---
 // J0[s*(n+1)+k] = int_{-L/2}^{L/2} exp(-a_s y^2) cos(2 pi k y / L) dy, J2 with y^2.
-void tables_1d(const std::vector<double> &alpha, int n, double L, std::vector<double> &J0,
-               std::vector<double> &J2);
+// table_jobs: the per-Gaussian quadrature layout; launch_tables copies it and
+// the trigonometric table to jobs_dev (R entries) and trig_dev (`jobs` and
+// `trig` must stay alive until the stream has run) and fills J0, J2
+// (R x (n+1) device doubles each).
+std::vector<TabJob> table_jobs(const std::vector<double> &alpha, int n, double L);
+std::vector<TabTrig> table_trig();   // TAB_TRIG / 2 + 1 entries
+TabRule table_rule();
+hipError_t launch_tables(const std::vector<TabJob> &jobs, const std::vector<TabTrig> &trig, int n, double L,
+                         double *J0, double *J2, TabJob *jobs_dev, TabTrig *trig_dev, hipStream_t st);
 
 // ---- device resources ------------------------------------------------------
 struct DevSpectrum {            // the multiplier octant, shared between plans
@@ -110,8 +118,6 @@ struct psp_plan {
     int R = 0;
     psp_dtype dtype = PSP_F64;
     std::vector<double> omega, alpha;   // S0
-    std::vector<double> J0, J2;         // S1 (host)
-    bool tables_ready = false;
     int device = -1;
     std::shared_ptr<psp::DevSpectrum> spec;
     const psp::Twiddles *tw = nullptr;
