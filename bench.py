@@ -305,6 +305,71 @@ def bench_eps(torch, B, sizes=(64, 128), R=461, sigma=0.2, reps=20):
     return out
 
 
+BOX_ROWS = (("Table 4", "gauss", 0.2, ((-3, 2), (-2, 3.5), (-1, 5))),
+            ("Table 6", "bump", (2.0, 10.0), ((-3, 1), (-2, 3), (-2, 4))),
+            ("Table 8", "anis", 2.0, ((-2, 2), (-4, 4), (-4, 4))),
+            ("Table 8", "anis", 32.0, ((-2, 2), (-64, 64), (-64, 64))))
+
+
+def _box_density(torch, family, par, box, N):
+    """(rho, u*) of the paper's rectangular-box benchmarks at the box centre
+    on its node grid (N points per side including both ends), on the GPU."""
+    import math
+    hs = tuple((b - a) / (N - 1) for a, b in box)
+    ax = [a + h * torch.arange(N, dtype=torch.float64, device="cuda") - 0.5 * (a + b) for (a, b), h in zip(box, hs)]
+    X, Y, Z = ax[0][:, None, None], ax[1][None, :, None], ax[2][None, None, :]
+    if family == "gauss":
+        s = par
+        r = torch.sqrt(X * X + Y * Y + Z * Z)
+        rho = torch.exp(-r * r / (2 * s * s)) / ((2 * math.pi) ** 1.5 * s ** 3)
+        safe = torch.where(r > 0, r, torch.ones_like(r))
+        u = torch.where(r > 0, torch.special.erf(safe / (math.sqrt(2) * s)) / (4 * math.pi * safe),
+                        torch.full_like(r, math.sqrt(2 / math.pi) / (4 * math.pi * s)))
+    elif family == "bump":
+        R, d = par
+        r2 = X * X + Y * Y + Z * Z
+        inside = r2 < R * R
+        den = torch.where(inside, R * R - r2, torch.ones_like(r2))
+        u = torch.where(inside, torch.exp(-d * R * R / den), torch.zeros_like(r2))
+        rho = torch.where(inside, 2 * d * R ** 2 * (3 * R ** 4 - 2 * R ** 2 * r2 - r2 ** 2 - 2 * d * R ** 2 * r2)
+                          / den ** 4 * u, torch.zeros_like(r2))
+    else:
+        sx, sy, sz = 0.2, 0.2 * par, 0.2 * par
+        u = torch.exp(-X * X / sx ** 2 - Y * Y / sy ** 2 - Z * Z / sz ** 2)
+        rho = -(4 * X * X / sx ** 4 + 4 * Y * Y / sy ** 4 + 4 * Z * Z / sz ** 4
+                - 2 / sx ** 2 - 2 / sy ** 2 - 2 / sz ** 2) * u
+    return hs, rho.contiguous(), u
+
+
+def bench_box(torch, B, sizes=(64, 128), R=461, reps=20):
+    """The paper's rectangular-box benchmarks (Section 3, Tables 4, 6, 8):
+    E against the exact potential, set-up time (plan creation + precompute)
+    and solve time, per table row and N."""
+    out = []
+    for tab, fam, par, box in BOX_ROWS:
+        for N in sizes:
+            hs, rho, u_star = _box_density(torch, fam, par, box, N)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            p = B.Plan(N, hs, R).precompute()
+            torch.cuda.synchronize()
+            setup_s = time.perf_counter() - t0
+            u = p.solve(rho)
+            for _ in range(3):
+                p.solve(rho, u)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                p.solve(rho, u)
+            torch.cuda.synchronize()
+            E = float((u - u_star).abs().max() / u_star.abs().max())
+            out.append({"table": tab, "family": fam, "param": par, "N": N, "E": float("%.4g" % E),
+                        "setup_s": round(setup_s, 4),
+                        "solve_ms": round(1e3 * (time.perf_counter() - t0) / reps, 4)})
+            del p
+    return out
+
+
 def cpu_baseline(n: int, budget_s: float = 12.0):
     """The oracle (as it stands) on a bounded sample of the same workload: its
     naive FFT on a batch of length-2n pencils, scaled to one full solve
@@ -346,6 +411,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
     ap.add_argument("--serve-count", type=int, default=2000)
     ap.add_argument("--no-eps", action="store_true", help="skip the near-field cutoff study")
+    ap.add_argument("--no-box", action="store_true", help="skip the rectangular-box rows")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for byte counters)")
     args = ap.parse_args()
@@ -426,6 +492,8 @@ def main():
             out["served_p50_ms"], out["served_p99_ms"] = near["p50_ms"], near["p99_ms"]
     if not args.no_eps:
         out["eps_study"] = bench_eps(torch, B)
+    if not args.no_box:
+        out["box_rows"] = bench_box(torch, B)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(n)
     print(json.dumps(out))

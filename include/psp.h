@@ -69,6 +69,18 @@ psp_status psp_plan_create(int n, double h, int R, psp_dtype dtype, psp_plan **o
 psp_status psp_plan_create_ex(int n, double h, int R, psp_dtype dtype,
                               double eps, double delta, psp_plan **out);
 
+/* A rectangular box (Section 3, Tables 4, 6, 8): n points per axis with
+ * spacing h[p] along axis p (h: 3 host doubles, axis 1 = the slowest index
+ * i1 of rho[i1][i2][i3]).  The padded box has sides L_p = 2 n h_p, the
+ * kernel is truncated to it, the 1D integrals of eq. Gten_sep are taken per
+ * axis and the spectral Laplacian is -(2 pi)^2 sum_p k_p^2 / L_p^2.
+ * eps <= 0 and delta <= 0 select the defaults eps = 1e-4 max_p(L_p/2) and
+ * delta = |(L_1, L_2, L_3)|/2; otherwise 0 < eps < delta (finite).  The
+ * solve itself is the same as for a cubic box; everything else follows
+ * psp_plan_create (same errors, plus PSP_EINVAL for h == NULL). */
+psp_status psp_plan_create_box(int n, const double *h, int R, psp_dtype dtype,
+                               double eps, double delta, psp_plan **out);
+
 /* Algorithm 1 steps 2-3 on the current device, on `stream`: the 2 R (n+1) 1D
  * integrals of eq. Gten_sep (FP64 with double-double node phases: closed
  * forms for narrow Gaussians, 15-point Gauss-Kronrod on equal panels
@@ -124,7 +136,8 @@ psp_status psp_plan_get_gs(const psp_plan *p, double *omega, double *alpha);
 /* Test hook: computes the 1D tables J0[s][k], J2[s][k], s < R, k <= n, on
  * the current device (the plan's device once precomputed) exactly as the
  * precompute does and copies them to host memory (row-major R x (n+1)
- * each).  Needs a GPU; synchronises the device's null stream. */
+ * each; axis 1's tables for a rectangular box).  Needs a GPU; synchronises
+ * the device's null stream. */
 psp_status psp_plan_get_tables(psp_plan *p, double *J0, double *J2);
 
 /* Test hook: copies the device multiplier octant m[a][b][c] (a,b,c <= n,

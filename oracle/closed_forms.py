@@ -200,3 +200,27 @@ def gs_cutoff_moment(omega, alpha, r_cut):
             vgs = y * y * (np.exp(-np.outer(y * y, a)) @ w)
             total += 0.5 * (r - l) * float(np.sum(wt * 4.0 * math.pi * y * y * (y / (8.0 * math.pi) - vgs)))
     return total
+
+
+def box_grid(N: int, box):
+    """The paper's node grid on a rectangular box ((lo, hi) per axis): N
+    points per axis including both ends.  Returns (h, X, Y, Z) with h the
+    three spacings ``(hi - lo)/(N - 1)`` and X, Y, Z broadcastable."""
+    hs = tuple((hi - lo) / (N - 1) for lo, hi in box)
+    xs = [lo + h * np.arange(N) for (lo, _), h in zip(box, hs)]
+    return hs, xs[0][:, None, None], xs[1][None, :, None], xs[2][None, None, :]
+
+
+def box_pair(family: str, params: str, box, X, Y, Z):
+    """(rho, u*) of the paper's rectangular-box benchmarks at the box centre:
+    'gauss' (sigma), 'bump' ("R/d"), 'anis' (L: sigma = (0.2, 0.2 L, 0.2 L))."""
+    c = tuple(0.5 * (lo + hi) for lo, hi in box)
+    if family == "gauss":
+        return gaussian_pair(X, Y, Z, float(params), c)
+    if family == "bump":
+        R, d = (float(v) for v in params.split("/"))
+        return bump_pair(X, Y, Z, d, R, c)
+    if family == "anis":
+        L = float(params)
+        return anisotropic_pair(X, Y, Z, (0.2, 0.2 * L, 0.2 * L), c)
+    raise KeyError(family)

@@ -5,7 +5,8 @@ of the benchmark may import this module.  It shares no code with the GPU
 library: its own Gaussian-sum construction, its own Gauss-Legendre 1D
 quadrature, a plain triple loop for the kernel spectrum, its own naive
 recursive mixed-radix (2 and 3) FFT, and a direct (FFT-free) evaluation of the
-discrete convolution operator.  Everything is float64 numpy, except the\n1D integral sums, which run in extended precision (see tables_1d).
+discrete convolution operator.  Everything is float64 numpy, except the
+1D integral sums, which run in extended precision (see tables_1d).
 
 The method (Exl & Schaffer, "Near-field-free super-potential FFT method for
 the three-dimensional free-space Poisson equation"):
@@ -39,6 +40,12 @@ notes of the repository):
     100-step bisection on [1, 80].
   * ``eps = 1e-4 * L/2`` (the paper's default cutoff in units where L = 2) and
     ``delta = sqrt(3) * L/2`` (the corner of the truncation box).
+  * Rectangular domains (Section 3, Tables 4, 6, 8): n points per axis with
+    a spacing h_p per axis, so the padded box has sides ``L_p = 2 n h_p``;
+    the kernel is truncated to that box, the 1D integrals of axis p run over
+    ``[-L_p/2, L_p/2]``, the spectral Laplacian is
+    ``-(2 pi)^2 sum_p k_p^2 / L_p^2``, ``eps = 1e-4 max_p(L_p/2)`` and
+    ``delta = |(L_1, L_2, L_3)|/2``.
   * The 1D integrals run over the full truncation interval ``[-L/2, L/2]``.
   * The DFT normalisation ``1/(2n)^3`` and the factor ``-(2 pi/L)^2`` are
     folded into one real multiplier per wavenumber.
@@ -50,7 +57,7 @@ import math
 import numpy as np
 
 __all__ = [
-    "default_eps_delta", "gs_parameters", "gs_weights", "gs_biharmonic",
+    "spacings", "default_eps_delta", "gs_parameters", "gs_weights", "gs_biharmonic",
     "gauss_legendre", "tables_1d", "spectrum_octant", "multiplier_octant",
     "fft_naive", "fftn_naive", "solve", "solve_padded", "direct_operator",
     "direct_points", "Setup", "setup",
@@ -62,10 +69,21 @@ __all__ = [
 # --------------------------------------------------------------------------
 
 
-def default_eps_delta(n: int, h: float):
-    """Cutoff eps and outer radius delta for an n-point axis of spacing h."""
-    half = n * h          # L/2 with L = 2 n h
-    return 1e-4 * half, math.sqrt(3.0) * half
+def spacings(h):
+    """(h_1, h_2, h_3) from one spacing (cubic cells) or three."""
+    hs = tuple(float(v) for v in np.atleast_1d(h))
+    if len(hs) == 1:
+        return hs * 3
+    if len(hs) != 3:
+        raise ValueError("h must be one spacing or three")
+    return hs
+
+
+def default_eps_delta(n: int, h):
+    """Cutoff eps and outer radius delta for n points per axis of spacing h
+    (one value, or one per axis)."""
+    halves = [n * v for v in spacings(h)]        # L_p/2 with L_p = 2 n h_p
+    return 1e-4 * max(halves), math.sqrt(sum(v * v for v in halves))
 
 
 def _count_fn(x: float, eps: float, delta: float) -> float:
@@ -200,62 +218,85 @@ def tables_1d(alpha, n: int, L: float):
     return J0, J2
 
 
+def _per_axis(t):
+    """Three per-axis items from one shared item or a sequence of three."""
+    if isinstance(t, (list, tuple)):
+        assert len(t) == 3
+        return list(t)
+    return [t, t, t]
+
+
 def spectrum_octant(omega, J0, J2):
     """``Vhat[a,b,c] = sum_s w_s (J2_s(a) J0_s(b) J0_s(c) + J0_s(a) J2_s(b)
-    J0_s(c) + J0_s(a) J0_s(b) J2_s(c))`` for a, b, c in 0..n (eq. Gten_sep).
+    J0_s(c) + J0_s(a) J0_s(b) J2_s(c))`` for a, b, c in 0..n (eq. Gten_sep),
+    the tables of a from axis 1, of b from axis 2, of c from axis 3 (J0, J2:
+    one table pair shared by the axes, or a sequence of three).
 
     Vhat is even in every wavenumber component, so this octant of
     non-negative |k_p| holds the whole padded-grid spectrum.  A plain loop
     over the Gaussian-sum terms, one outer product per term and direction.
     """
-    n1 = J0.shape[1]
+    (x0, y0, z0), (x2, y2, z2) = _per_axis(J0), _per_axis(J2)
+    n1 = x0.shape[1]
     V = np.zeros((n1, n1, n1))
     for s in range(len(omega)):
-        j0 = J0[s]
-        j2 = J2[s]
-        V += omega[s] * (j2[:, None, None] * j0[None, :, None] * j0[None, None, :]
-                         + j0[:, None, None] * j2[None, :, None] * j0[None, None, :]
-                         + j0[:, None, None] * j0[None, :, None] * j2[None, None, :])
+        V += omega[s] * (x2[s][:, None, None] * y0[s][None, :, None] * z0[s][None, None, :]
+                         + x0[s][:, None, None] * y2[s][None, :, None] * z0[s][None, None, :]
+                         + x0[s][:, None, None] * y0[s][None, :, None] * z2[s][None, None, :])
     return V
 
 
-def multiplier_octant(V, n: int, L: float):
-    """``m[a,b,c] = -(2 pi/L)^2 (a^2+b^2+c^2) Vhat[a,b,c] / (2n)^3``.
+def multiplier_octant(V, n: int, L):
+    """``m[a,b,c] = -(2 pi)^2 (a^2/L_1^2 + b^2/L_2^2 + c^2/L_3^2) Vhat[a,b,c]
+    / (2n)^3`` (L: one period, or one per axis).
 
-    The spectral Laplacian ``-(2 pi/L)^2 |k|^2`` of eq. convtheorem times the
-    kernel spectrum, with the 1/(2n)^3 of the forward DFT (the trapezoid
-    approximation of the Fourier coefficients) folded in.
+    The spectral Laplacian ``-(2 pi/L)^2 |k|^2`` of eq. convtheorem (per axis
+    on a rectangular box) times the kernel spectrum, with the 1/(2n)^3 of
+    the forward DFT (the trapezoid approximation of the Fourier
+    coefficients) folded in.
     """
+    L1, L2, L3 = [float(v) for v in _per_axis(L)]
     a = np.arange(n + 1, dtype=np.float64)
-    k2 = a[:, None, None] ** 2 + a[None, :, None] ** 2 + a[None, None, :] ** 2
-    return -((2.0 * math.pi / L) ** 2) * k2 * V / float((2 * n) ** 3)
+    w = ((2.0 * math.pi / L1) ** 2 * a[:, None, None] ** 2 + (2.0 * math.pi / L2) ** 2 * a[None, :, None] ** 2
+         + (2.0 * math.pi / L3) ** 2 * a[None, None, :] ** 2)
+    return -w * V / float((2 * n) ** 3)
 
 
 class Setup:
-    """Everything Algorithm 1 precomputes for one (n, h, R, eps, delta).
-    The spectrum octant and the multiplier are built on first use."""
+    """Everything Algorithm 1 precomputes for one (n, h, R, eps, delta); h is
+    one spacing or one per axis (rectangular box).  The spectrum octant and
+    the multiplier are built on first use."""
 
     def __init__(self, n, h, R, eps=None, delta=None):
         d_eps, d_delta = default_eps_delta(n, h)
         self.n, self.h, self.R = n, h, R
-        self.L = 2.0 * n * h
+        self.hs = spacings(h)
+        self.Ls = tuple(2.0 * n * v for v in self.hs)
+        self.cubic = len(set(self.hs)) == 1
+        self.L = self.Ls[0] if self.cubic else self.Ls
         self.eps = d_eps if eps is None else eps
         self.delta = d_delta if delta is None else delta
         self.omega, self.alpha = gs_weights(R, self.eps, self.delta)
-        self.J0, self.J2 = tables_1d(self.alpha, n, self.L)
+        tables = {}
+        for Lp in self.Ls:
+            if Lp not in tables:
+                tables[Lp] = tables_1d(self.alpha, n, Lp)
+        self.J0s = [tables[Lp][0] for Lp in self.Ls]
+        self.J2s = [tables[Lp][1] for Lp in self.Ls]
+        self.J0, self.J2 = self.J0s[0], self.J2s[0]
         self._V = None
         self._m = None
 
     @property
     def V(self):
         if self._V is None:
-            self._V = spectrum_octant(self.omega, self.J0, self.J2)
+            self._V = spectrum_octant(self.omega, self.J0s, self.J2s)
         return self._V
 
     @property
     def m(self):
         if self._m is None:
-            self._m = multiplier_octant(self.V, self.n, self.L)
+            self._m = multiplier_octant(self.V, self.n, self.Ls)
         return self._m
 
     def full_multiplier(self):
@@ -340,9 +381,9 @@ def solve(rho, h, R, eps=None, delta=None, su: Setup | None = None):
 
 
 def _stencil_factors(su: Setup):
-    """1D stencils over offsets d = -(n-1)..(n-1) for every Gaussian-sum term:
-    ``F[f](d) = sum_{k=-n}^{n-1} f(|k|) exp(i pi k d / n)`` for
-    f in {J0, J2, k^2 J0, k^2 J2}."""
+    """1D stencils over offsets d = -(n-1)..(n-1) for every Gaussian-sum term
+    and axis p: ``F[p][f](d) = sum_{k=-n}^{n-1} f(|k|) exp(i pi k d / n)``
+    for f in {J0, J2, k^2 J0, k^2 J2} of axis p's tables."""
     n = su.n
     k = np.arange(-n, n)
     d = np.arange(-(n - 1), n)
@@ -351,25 +392,25 @@ def _stencil_factors(su: Setup):
     # whose phase exp(-i pi d) = (-1)^d is real
     phase = np.cos(math.pi * np.outer(d, k) / n)
     k2 = (ak * ak).astype(np.float64)
-    A0 = su.J0[:, ak] @ phase.T
-    A2 = su.J2[:, ak] @ phase.T
-    B0 = (su.J0[:, ak] * k2) @ phase.T
-    B2 = (su.J2[:, ak] * k2) @ phase.T
-    return A0, A2, B0, B2
+    out = []
+    for J0, J2 in zip(su.J0s, su.J2s):
+        out.append((J0[:, ak] @ phase.T, J2[:, ak] @ phase.T, (J0[:, ak] * k2) @ phase.T,
+                    (J2[:, ak] * k2) @ phase.T))
+    return out
 
 
 def _separable_terms(su: Setup):
     """Yield (s, coef, (t1, t2, t3)) for the stencil
-    ``c_d = sum coef * F_t1(d1) F_t2(d2) F_t3(d3)``: the product of
-    ``-(2 pi/L)^2/(2n)^3 (k1^2+k2^2+k3^2)`` with the three rank-one terms of
-    eq. Gten_sep, expanded into nine separable terms per Gaussian-sum term.
-    Factor types: 0 = J0, 1 = J2, 2 = k^2 J0, 3 = k^2 J2."""
-    C = -((2.0 * math.pi / su.L) ** 2) / float((2 * su.n) ** 3)
+    ``c_d = sum coef * F[0]_t1(d1) F[1]_t2(d2) F[2]_t3(d3)``: the product of
+    ``-(2 pi)^2/(2n)^3 (k1^2/L_1^2 + k2^2/L_2^2 + k3^2/L_3^2)`` with the three
+    rank-one terms of eq. Gten_sep, expanded into nine separable terms per
+    Gaussian-sum term.  Factor types: 0 = J0, 1 = J2, 2 = k^2 J0, 3 = k^2 J2."""
+    C = [-((2.0 * math.pi / Lp) ** 2) / float((2 * su.n) ** 3) for Lp in su.Ls]
     for s in range(len(su.omega)):
         for q in range(3):            # which axis carries J2
             for p2 in range(3):       # which axis carries the k^2 factor
                 ts = tuple((2 if p == p2 else 0) + (1 if p == q else 0) for p in range(3))
-                yield s, C * su.omega[s], ts
+                yield s, C[p2] * su.omega[s], ts
 
 
 def direct_operator(rho, h, R, eps=None, delta=None, su: Setup | None = None):
@@ -384,7 +425,7 @@ def direct_operator(rho, h, R, eps=None, delta=None, su: Setup | None = None):
     off = (j[:, None] - j[None, :]) + (n - 1)     # index of d = j - m
     u = np.zeros_like(rho)
     for s, coef, (t1, t2, t3) in _separable_terms(su):
-        T1, T2, T3 = F[t1][s][off], F[t2][s][off], F[t3][s][off]
+        T1, T2, T3 = F[0][t1][s][off], F[1][t2][s][off], F[2][t3][s][off]
         t = np.tensordot(rho, T3, axes=([2], [1]))          # (m1, m2, j3)
         t = np.tensordot(t, T2, axes=([1], [1]))             # (m1, j3, j2)
         t = np.tensordot(t, T1, axes=([0], [1]))             # (j3, j2, j1)
@@ -413,8 +454,8 @@ def direct_points(rho, points, h, R, eps=None, delta=None, su: Setup | None = No
         key = (s, t3)
         if key not in cache:
             cache.clear() if len(cache) > 8 else None
-            cache[key] = (rho2 @ F[t3][s][d3].T).reshape(n, n, -1)[:, :, inv3]
+            cache[key] = (rho2 @ F[2][t3][s][d3].T).reshape(n, n, -1)[:, :, inv3]
         tp = cache[key]                                        # (m1, m2, P)
-        out += coef * np.einsum("pa,pb,abp->p", F[t1][s][d1], F[t2][s][d2], tp,
+        out += coef * np.einsum("pa,pb,abp->p", F[0][t1][s][d1], F[1][t2][s][d2], tp,
                                 optimize=True)
     return out

@@ -1,4 +1,5 @@
 // api.cpp - libpsp's C ABI: plans, precompute, solves, test hooks, errors.
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <cstdarg>
@@ -44,7 +45,7 @@ DevSpectrum::~DevSpectrum() {
 
 // ---------------------------------------------------------------- caches
 static std::mutex g_cache_mu;
-using SpecKey = std::tuple<int, int, double, int, double, double>;   // device, n, h, R, eps, delta
+using SpecKey = std::tuple<int, int, double, double, double, int, double, double>;   // device, n, h[3], R, eps, delta
 static std::map<SpecKey, std::weak_ptr<DevSpectrum>> g_spec_cache;
 static std::map<std::pair<int, int>, Twiddles> g_tw_cache;            // (device, N)
 
@@ -182,23 +183,49 @@ SolveArgs solve_args(const psp_plan *p, const Workspace &w, const void *rho, voi
     return a;
 }
 
-// S1 on the device: one allocation holding J0, J2 (R x (n+1) each), the
-// Gaussian-sum weights (R), the quadrature layout (R jobs) and the
-// trigonometric table; the tables are filled on `st`.  The caller frees
-// *buf after the stream has run, and keeps `jobs` and `trig` alive until
-// then.
-static psp_status device_tables(const psp_plan *p, const std::vector<TabJob> &jobs, const std::vector<TabTrig> &trig,
-                                hipStream_t st, double **buf) {
+// S1 on the device, once per distinct axis period: one allocation holding,
+// per distinct period, J0 and J2 (R x (n+1) each), then the Gaussian-sum
+// weights (R), the quadrature layouts (R jobs per period) and the
+// trigonometric table; the tables are filled on `st`.  tb receives the table
+// pointers of axes 1..3 (shared where the periods coincide) and *omega the
+// device weights.  The caller frees *buf after the stream has run, and keeps
+// `hold` (the host copies being uploaded) alive until then.
+struct TableUpload {
+    std::vector<std::vector<TabJob>> jobs;
+    std::vector<TabTrig> trig;
+};
+static psp_status device_tables(const psp_plan *p, hipStream_t st, TableUpload &hold, double **buf, SpecTables *tb,
+                                const double **omega) {
+    std::vector<double> periods;
+    int axis_of[3];
+    for (int a = 0; a < 3; ++a) {
+        auto it = std::find(periods.begin(), periods.end(), p->Ls[a]);
+        axis_of[a] = (int)(it - periods.begin());
+        if (it == periods.end()) periods.push_back(p->Ls[a]);
+    }
+    const int nd = (int)periods.size();
     const size_t tn = (size_t)p->R * (p->n + 1);
+    hold.trig = table_trig();
+    hold.jobs.clear();
+    for (int i = 0; i < nd; ++i) hold.jobs.push_back(table_jobs(p->alpha, p->n, periods[i]));
     double *d = nullptr;
-    PSP_HIP(hipMalloc(&d, sizeof(double) * (2 * tn + p->R) + sizeof(TabJob) * p->R + sizeof(TabTrig) * trig.size()),
+    PSP_HIP(hipMalloc(&d, sizeof(double) * (2 * tn * nd + p->R) + sizeof(TabJob) * p->R * nd +
+                              sizeof(TabTrig) * hold.trig.size()),
             "hipMalloc(tables)");
     *buf = d;
-    TabJob *dj = reinterpret_cast<TabJob *>(d + 2 * tn + p->R);
-    TabTrig *dt = reinterpret_cast<TabTrig *>(dj + p->R);
-    hipError_t e = hipMemcpyAsync(d + 2 * tn, p->omega.data(), sizeof(double) * p->R, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = launch_tables(jobs, trig, p->n, p->L, d, d + tn, dj, dt, st);
+    double *dw = d + 2 * tn * nd;
+    TabJob *dj = reinterpret_cast<TabJob *>(dw + p->R);
+    TabTrig *dt = reinterpret_cast<TabTrig *>(dj + (size_t)p->R * nd);
+    hipError_t e = hipMemcpyAsync(dw, p->omega.data(), sizeof(double) * p->R, hipMemcpyHostToDevice, st);
+    for (int i = 0; i < nd && e == hipSuccess; ++i)
+        e = launch_tables(hold.jobs[i], hold.trig, p->n, periods[i], d + 2 * tn * i, d + 2 * tn * i + tn,
+                          dj + (size_t)p->R * i, dt, st);
     if (e != hipSuccess) return hip_fail(e, "1D tables");
+    for (int a = 0; a < 3; ++a) {
+        tb->J0[a] = d + 2 * tn * axis_of[a];
+        tb->J2[a] = d + 2 * tn * axis_of[a] + tn;
+    }
+    *omega = dw;
     return PSP_OK;
 }
 
@@ -231,17 +258,25 @@ const char *psp_strerror(psp_status e) {
 
 const char *psp_last_error(void) { return g_last_error.c_str(); }
 
-psp_status psp_plan_create_ex(int n, double h, int R, psp_dtype dtype, double eps, double delta, psp_plan **out) {
+// a plan for n points per axis with spacings hs[0..2] and an explicit cutoff
+static psp_status create_plan(int n, const double *hs, int R, psp_dtype dtype, double eps, double delta,
+                              psp_plan **out) {
     if (!out) return fail(PSP_EINVAL, "out is NULL");
     *out = nullptr;
     if (dtype != PSP_F64 && dtype != PSP_F32) return fail(PSP_EINVAL, "unknown dtype %d", (int)dtype);
-    psp_status st = check_create(n, h, R, eps, delta);
-    if (st != PSP_OK) return st;
+    for (int a = 0; a < 3; ++a) {
+        psp_status st = check_create(n, hs[a], R, eps, delta);
+        if (st != PSP_OK) return st;
+    }
     psp_plan *p = new (std::nothrow) psp_plan;
     if (!p) return fail(PSP_ENOMEM, "host allocation failed");
     p->n = n;
-    p->h = h;
-    p->L = 2.0 * n * h;
+    for (int a = 0; a < 3; ++a) {
+        p->hs[a] = hs[a];
+        p->Ls[a] = 2.0 * n * hs[a];
+    }
+    p->h = hs[0];
+    p->L = p->Ls[0];
     p->R = R;
     p->dtype = dtype;
     p->eps = eps;
@@ -251,6 +286,31 @@ psp_status psp_plan_create_ex(int n, double h, int R, psp_dtype dtype, double ep
     gs_fit(R, eps, delta, p->omega, p->alpha);
     *out = p;
     return PSP_OK;
+}
+
+psp_status psp_plan_create_ex(int n, double h, int R, psp_dtype dtype, double eps, double delta, psp_plan **out) {
+    const double hs[3] = {h, h, h};
+    return create_plan(n, hs, R, dtype, eps, delta, out);
+}
+
+psp_status psp_plan_create_box(int n, const double *h, int R, psp_dtype dtype, double eps, double delta,
+                               psp_plan **out) {
+    if (!out) return fail(PSP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!h) return fail(PSP_EINVAL, "h is NULL");
+    if (eps <= 0.0 && delta <= 0.0) {
+        // eps = 1e-4 max_p L_p/2 and delta = |(L_1, L_2, L_3)|/2, the corner
+        // of the kernel's truncation box (L_p = 2 n h_p)
+        double mx = 0.0, sq = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            const double half = (double)n * h[a];
+            mx = std::max(mx, half);
+            sq += half * half;
+        }
+        eps = 1e-4 * mx;
+        delta = std::sqrt(sq);
+    }
+    return create_plan(n, h, R, dtype, eps, delta, out);
 }
 
 psp_status psp_plan_create(int n, double h, int R, psp_dtype dtype, psp_plan **out) {
@@ -287,14 +347,15 @@ psp_status psp_plan_get_tables(psp_plan *p, double *J0, double *J2) {
         psp_status s = current_device_of(p);
         if (s != PSP_OK) return s;
     }
-    const std::vector<TabJob> jobs = table_jobs(p->alpha, p->n, p->L);
-    const std::vector<TabTrig> trig = table_trig();
+    TableUpload hold;
+    SpecTables tabs;
+    const double *dw = nullptr;
     double *d = nullptr;
-    psp_status rs = device_tables(p, jobs, trig, nullptr, &d);
+    psp_status rs = device_tables(p, nullptr, hold, &d, &tabs, &dw);
     const size_t tb = sizeof(double) * (size_t)p->R * (p->n + 1);
     hipError_t e = hipSuccess;
-    if (rs == PSP_OK && (e = hipMemcpy(J0, d, tb, hipMemcpyDeviceToHost)) == hipSuccess)
-        e = hipMemcpy(J2, d + (size_t)p->R * (p->n + 1), tb, hipMemcpyDeviceToHost);
+    if (rs == PSP_OK && (e = hipMemcpy(J0, tabs.J0[0], tb, hipMemcpyDeviceToHost)) == hipSuccess)
+        e = hipMemcpy(J2, tabs.J2[0], tb, hipMemcpyDeviceToHost);
     if (d) (void)hipFree(d);
     if (rs != PSP_OK) return rs;
     if (e != hipSuccess) return hip_fail(e, "hipMemcpy(tables)");
@@ -321,7 +382,7 @@ psp_status psp_kernel_precompute(psp_plan *p, void *stream) {
     PSP_HIP(hipGetDevice(&dev), "hipGetDevice");
     psp_status rs = get_twiddles(dev, 2 * p->n, &p->tw);
     if (rs != PSP_OK) return rs;
-    const SpecKey key{dev, p->n, p->h, p->R, p->eps, p->delta};
+    const SpecKey key{dev, p->n, p->hs[0], p->hs[1], p->hs[2], p->R, p->eps, p->delta};
     std::shared_ptr<DevSpectrum> spec;
     {
         std::lock_guard<std::mutex> lk(g_cache_mu);
@@ -339,11 +400,11 @@ psp_status psp_kernel_precompute(psp_plan *p, void *stream) {
             spec->mult = nullptr;
             return fail(PSP_ENOMEM, "spectrum allocation of %zu bytes failed", spec->bytes);
         }
-        const std::vector<TabJob> jobs = table_jobs(p->alpha, n, p->L);
-        const std::vector<TabTrig> trig = table_trig();
+        TableUpload hold;
+        SpecTables tabs;
+        const double *dW = nullptr;
         double *dJ = nullptr;
-        psp_status out = device_tables(p, jobs, trig, st, &dJ);
-        double *dJ0 = dJ, *dJ2 = dJ + (size_t)R * (n + 1), *dW = dJ + 2 * (size_t)R * (n + 1);
+        psp_status out = device_tables(p, st, hold, &dJ, &tabs, &dW);
         do {
             if (out != PSP_OK) break;
             hipError_t ee;
@@ -353,8 +414,10 @@ psp_status psp_kernel_precompute(psp_plan *p, void *stream) {
             }
             const double pi = 3.14159265358979323846;
             const double N = 2.0 * n;
-            const double scale = -(2.0 * pi / p->L) * (2.0 * pi / p->L) / (N * N * N);
-            if ((ee = launch_spectrum(dJ0, dJ2, dW, R, n, P, scale, spec->mult, st)) != hipSuccess) {
+            SpecScale sc;
+            for (int a = 0; a < 3; ++a) sc.w[a] = (2.0 * pi / p->Ls[a]) * (2.0 * pi / p->Ls[a]);
+            sc.scale = -1.0 / (N * N * N);
+            if ((ee = launch_spectrum(tabs, dW, R, n, P, sc, spec->mult, st)) != hipSuccess) {
                 out = hip_fail(ee, "spectrum kernel launch");
                 break;
             }

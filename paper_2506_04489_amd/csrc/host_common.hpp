@@ -114,7 +114,8 @@ inline size_t spectrum_bytes(int n) { return 8 * (size_t)(n + 1) * (n + 1) * pit
 
 struct psp_plan {
     int n = 0;
-    double h = 0, L = 0, eps = 0, delta = 0;
+    double h = 0, L = 0, eps = 0, delta = 0;   // h, L: axis 1
+    double hs[3] = {0, 0, 0}, Ls[3] = {0, 0, 0};  // per axis (rectangular box)
     int R = 0;
     psp_dtype dtype = PSP_F64;
     std::vector<double> omega, alpha;   // S0

@@ -140,8 +140,19 @@ hipError_t launch_group(int n, bool f32, const Shape &shape, const Job *table_de
 inline int strided_width(bool f32) { return f32 ? 16 : 8; }
 
 // the kernel-spectrum multiplier octant (FP64 MFMA contraction)
-hipError_t launch_spectrum(const double *J0, const double *J2, const double *omega, int R, int n, int P,
-                           double scale, double *mult, hipStream_t st);
+// S2 inputs: the 1D tables of each axis (R x (n+1) each; the same pointers
+// for every axis of a cubic box) and the epilogue's spectral-Laplacian
+// weights w_p = (2 pi / L_p)^2 and scale -1/N^3
+struct SpecTables {
+    const double *J0[3];
+    const double *J2[3];
+};
+struct SpecScale {
+    double w[3];
+    double scale;
+};
+hipError_t launch_spectrum(const SpecTables &tb, const double *omega, int R, int n, int P, const SpecScale &sc,
+                           double *mult, hipStream_t st);
 
 // kernel launches of one solve (its profiling events are one more)
 int solve_launches(int n, bool f32, int chunk_tiles, int i1_group);

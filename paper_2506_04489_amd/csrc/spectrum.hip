@@ -9,11 +9,13 @@ namespace psp {
 
 // ------------------------------------------------------------ S2: spectrum
 // Vhat[a,b,c] = sum_s w_s (J2(a)J0(b)J0(c) + J0(a)J2(b)J0(c) + J0(a)J0(b)J2(c))
+// (the tables of a, b, c from axes 1, 2, 3: the same tables on a cubic box)
 // as a GEMM over K = 2R per b: rows a, columns c,
 //   Amat[a,(s,0)] = w_s (J2(a)J0(b) + J0(a)J2(b)), Amat[a,(s,1)] = w_s J0(a)J0(b),
 //   Bmat[(s,0),c] = J0(c),                       Bmat[(s,1),c] = J2(c),
-// on v_mfma_f64_16x16x4_f64 tiles of 16 a x 16 c; the epilogue applies
-// m = scale (a^2 + b^2 + c^2) Vhat with scale = -(2 pi/L)^2 / N^3.
+// on v_mfma_f64_16x16x4_f64 tiles of 16 a x 16 c; the epilogue applies the
+// spectral Laplacian, m = scale (w1 a^2 + w2 b^2 + w3 c^2) Vhat with
+// w_p = (2 pi/L_p)^2 and scale = -1/N^3.
 // Operand layout of the 16x16x4 FP64 MFMA (lane l): A[l%16][l/16],
 // B[l/16][l%16], D[l/16 + 4e][l%16] for e < 4.
 typedef double v4d __attribute__((ext_vector_type(4)));
@@ -34,21 +36,21 @@ struct SpecOps {
 };
 
 __device__ __forceinline__ void spec_load(SpecOps &o, int k0, int kq, int abase, int b, int cbase, int R, int n,
-                                          const double *__restrict__ J0, const double *__restrict__ J2,
-                                          const double *__restrict__ omega) {
+                                          const SpecTables &tb, const double *__restrict__ omega) {
     const int n1 = n + 1;
     const int ks = k0 + kq, s = ks >> 1, ty = ks & 1;
     const bool live = s < R;
-    const double *j0 = J0 + (size_t)(live ? s : 0) * n1, *j2 = J2 + (size_t)(live ? s : 0) * n1;
+    const size_t row = (size_t)(live ? s : 0) * n1;
+    const double *j0a = tb.J0[0] + row, *j2a = tb.J2[0] + row;
     const double w = live ? omega[s] : 0.0;
-    const double j0b = j0[b], j2b = j2[b];
+    const double j0b = tb.J0[1][row + b], j2b = tb.J2[1][row + b];
 #pragma unroll
     for (int t = 0; t < SPEC_AT; ++t) {
         const int a = abase + t * 16;
         o.av[t] = 0.0;
-        if (live && a <= n) o.av[t] = ty == 0 ? w * (j2[a] * j0b + j0[a] * j2b) : w * (j0[a] * j0b);
+        if (live && a <= n) o.av[t] = ty == 0 ? w * (j2a[a] * j0b + j0a[a] * j2b) : w * (j0a[a] * j0b);
     }
-    const double *jb = ty == 0 ? j0 : j2;
+    const double *jb = (ty == 0 ? tb.J0[2] : tb.J2[2]) + row;
 #pragma unroll
     for (int q = 0; q < SPEC_CT; ++q) {
         const int c = cbase + q * 16;
@@ -57,8 +59,7 @@ __device__ __forceinline__ void spec_load(SpecOps &o, int k0, int kq, int abase,
 }
 
 __global__ void __launch_bounds__(256)
-k_spectrum(const double *__restrict__ J0, const double *__restrict__ J2,
-           const double *__restrict__ omega, int R, int n, int P, double scale,
+k_spectrum(SpecTables tb, const double *__restrict__ omega, int R, int n, int P, SpecScale sc,
            double *__restrict__ mult) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nt = (n + 1 + 15) / 16;
@@ -77,9 +78,9 @@ k_spectrum(const double *__restrict__ J0, const double *__restrict__ J2,
 #pragma unroll
         for (int q = 0; q < SPEC_CT; ++q) acc[t][q] = v4d{0.0, 0.0, 0.0, 0.0};
     SpecOps cur, nxt;
-    spec_load(cur, 0, kq, abase, b, cbase, R, n, J0, J2, omega);
+    spec_load(cur, 0, kq, abase, b, cbase, R, n, tb, omega);
     for (int k0 = 0; k0 < 2 * R; k0 += 4) {
-        if (k0 + 4 < 2 * R) spec_load(nxt, k0 + 4, kq, abase, b, cbase, R, n, J0, J2, omega);
+        if (k0 + 4 < 2 * R) spec_load(nxt, k0 + 4, kq, abase, b, cbase, R, n, tb, omega);
 #pragma unroll
         for (int t = 0; t < SPEC_AT; ++t)
 #pragma unroll
@@ -96,8 +97,8 @@ k_spectrum(const double *__restrict__ J0, const double *__restrict__ J2,
             for (int e = 0; e < 4; ++e) {
                 const int aa = a0 + t * 16 + kq + 4 * e;
                 if (aa <= n && cc <= n) {
-                    const double k2 = (double)aa * aa + (double)b * b + (double)cc * cc;
-                    mult[((size_t)(b * (P / 8) + cc / 8) * n1 + aa) * 8 + (cc & 7)] = scale * k2 * acc[t][q][e];
+                    const double k2 = sc.w[0] * ((double)aa * aa) + sc.w[1] * ((double)b * b) + sc.w[2] * ((double)cc * cc);
+                    mult[((size_t)(b * (P / 8) + cc / 8) * n1 + aa) * 8 + (cc & 7)] = sc.scale * k2 * acc[t][q][e];
                 }
             }
         }
@@ -151,13 +152,12 @@ hipError_t launch_group(int n, bool f32, const Shape &shape, const Job *table_de
     return f(2 * n, none, table_dev, count, P, 0, 0, shape, false, tw64, nullptr, nullptr, 0, st);
 }
 
-hipError_t launch_spectrum(const double *J0, const double *J2, const double *omega, int R, int n, int P,
-                           double scale, double *mult, hipStream_t st) {
+hipError_t launch_spectrum(const SpecTables &tb, const double *omega, int R, int n, int P, const SpecScale &sc,
+                           double *mult, hipStream_t st) {
     const int nt = (n + 1 + 15) / 16;
     const int na = (nt + SPEC_AT - 1) / SPEC_AT, ng = (nt + SPEC_CT - 1) / SPEC_CT;
     const long items = (long)(n + 1) * na * ng;
-    hipLaunchKernelGGL(k_spectrum, dim3(ceil_div_l(items, 4)), dim3(256), 0, st, J0, J2, omega, R, n, P, scale,
-                       mult);
+    hipLaunchKernelGGL(k_spectrum, dim3(ceil_div_l(items, 4)), dim3(256), 0, st, tb, omega, R, n, P, sc, mult);
     return hipGetLastError();
 }
 

@@ -26,6 +26,7 @@ _P = ctypes.POINTER
 SIGNATURES = {
     "psp_plan_create": (_i, [_i, _d, _i, _i, _P(_vp)]),
     "psp_plan_create_ex": (_i, [_i, _d, _i, _i, _d, _d, _P(_vp)]),
+    "psp_plan_create_box": (_i, [_i, _P(_d), _i, _i, _d, _d, _P(_vp)]),
     "psp_kernel_precompute": (_i, [_vp, _vp]),
     "psp_solve": (_i, [_vp, _vp, _vp, _vp]),
     "psp_solve_batched": (_i, [_i, _P(_vp), _P(_vp), _P(_vp), _vp]),
@@ -176,15 +177,26 @@ def _load_shipped_tuning():
 
 
 class Plan:
-    """One (n, h, R, dtype) configuration: psp_plan_create[_ex] + helpers."""
+    """One (n, h, R, dtype) configuration: psp_plan_create[_ex] + helpers.
+    h is one spacing, or three (one per axis: a rectangular box,
+    psp_plan_create_box)."""
 
-    def __init__(self, n: int, h: float, R: int, dtype="f64", eps: float = None, delta: float = None):
-        self.n, self.h, self.R = int(n), float(h), int(R)
+    def __init__(self, n: int, h, R: int, dtype="f64", eps: float = None, delta: float = None):
+        self.n, self.R = int(n), int(R)
         self.code = _dtype_code(dtype)
         handle = ctypes.c_void_p()
-        if eps is None and delta is None:
+        if np.ndim(h) > 0:
+            if len(list(h)) != 3:
+                raise ValueError("h must be one spacing or three")
+            self.h = tuple(float(v) for v in h)
+            hs = (ctypes.c_double * 3)(*self.h)
+            _check(lib().psp_plan_create_box(self.n, hs, self.R, self.code, -1.0 if eps is None else float(eps),
+                                             -1.0 if delta is None else float(delta), ctypes.byref(handle)))
+        elif eps is None and delta is None:
+            self.h = float(h)
             _check(lib().psp_plan_create(self.n, self.h, self.R, self.code, ctypes.byref(handle)))
         else:
+            self.h = float(h)
             _check(lib().psp_plan_create_ex(self.n, self.h, self.R, self.code, float(eps), float(delta),
                                             ctypes.byref(handle)))
         self._h = handle

@@ -1,0 +1,66 @@
+"""Pin the oracle on rectangular boxes (Section 3, Tables 4, 6, 8): per-axis
+spacings h_p, per-axis 1D tables over [-L_p/2, L_p/2] and the spectral
+Laplacian -(2 pi)^2 sum_p k_p^2 / L_p^2.
+
+  * the 16^3 and 32^3 rows, set by the grid, reproduce the printed digits;
+  * the FFT route equals the FFT-free Toeplitz sum on a rectangular box;
+  * permuting the axes of rho together with the spacings permutes u;
+  * three equal spacings give exactly the cubic multiplier.
+"""
+import csv
+import os
+
+import numpy as np
+import pytest
+
+from oracle import closed_forms as C
+from oracle import psp_oracle as O
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+R_PAPER = 461
+
+
+def box_rows():
+    with open(os.path.join(HERE, "golden", "paper_tables_box.csv")) as f:
+        for row in csv.reader(l for l in f if not l.startswith("#")):
+            tab, fam, par = row[:3]
+            box = [(float(row[3]), float(row[4])), (float(row[5]), float(row[6])), (float(row[7]), float(row[8]))]
+            yield tab, fam, par, box, int(row[9]), float(row[10])
+
+
+ROWS = list(box_rows())
+GRID_ROWS = [r for r in ROWS if r[4] == 16] + [r for r in ROWS if r[4] == 32 and r[2] in ("0.20", "2/10", "2", "32")]
+
+
+@pytest.mark.parametrize("tab,fam,par,box,N,E_paper", GRID_ROWS,
+                         ids=["%s-%s-%s-%d" % (r[0].replace(" ", ""), r[1], r[2], r[4]) for r in GRID_ROWS])
+def test_grid_limited_rows(tab, fam, par, box, N, E_paper):
+    h, X, Y, Z = C.box_grid(N, box)
+    rho, u_star = C.box_pair(fam, par, box, X, Y, Z)
+    u = O.solve(rho, h, R_PAPER)
+    E = C.relative_max_error(u, u_star)
+    assert abs(E - E_paper) <= 6e-4 * E_paper, (tab, E, E_paper)
+
+
+def test_fft_route_equals_direct_toeplitz_on_a_box():
+    n, hs = 8, (0.11, 0.17, 0.29)
+    rho = np.random.default_rng(5).standard_normal((n, n, n))
+    su = O.setup(n, hs, 40)
+    a = O.solve(rho, hs, 40, su=su)
+    b = O.direct_operator(rho, hs, 40, su=su)
+    assert np.max(np.abs(a - b)) <= 1e-13 * np.max(np.abs(a))
+
+
+@pytest.mark.parametrize("perm", [(1, 0, 2), (2, 1, 0), (1, 2, 0)])
+def test_axis_permutation_commutes(perm):
+    n, hs = 12, (0.1, 0.13, 0.17)
+    rho = np.random.default_rng(6).standard_normal((n, n, n))
+    u = O.solve(rho, hs, 40)
+    up = O.solve(np.transpose(rho, perm).copy(), tuple(hs[p] for p in perm), 40)
+    assert np.max(np.abs(up - np.transpose(u, perm))) <= 1e-14 * np.max(np.abs(u))
+
+
+def test_equal_spacings_are_the_cubic_case():
+    a = O.setup(10, (0.2, 0.2, 0.2), 40)
+    b = O.setup(10, 0.2, 40)
+    assert np.array_equal(a.m, b.m)
