@@ -486,7 +486,8 @@ psp_status psp_profile_enable(psp_plan *p, int max_solves) {
     p->prof_ev.resize((size_t)p->prof_nev * max_solves, nullptr);
     p->prof_pass.assign((size_t)p->prof_nev * max_solves, -1);
     for (auto &e : p->prof_ev) {
-        if (hipEventCreate(&e) != hipSuccess) {
+        // timing only: no system-scope cache writeback at every record
+        if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) {
             e = nullptr;
             profile_clear(p);
             return fail(PSP_EHIP, "hipEventCreate failed");

@@ -149,7 +149,8 @@ psp_status psp_autotune(psp_plan *p, int reps, void *stream, int *best_plan, int
     else
         hipLaunchKernelGGL(k_fill_hash<double>, dim3(1024), dim3(256), 0, st, (double *)rho, count);
     hipError_t e = hipGetLastError();
-    for (int k = 0; k < nev && e == hipSuccess; ++k) e = hipEventCreate(&ev[k]);
+    // timing only: no system-scope cache writeback at every record
+    for (int k = 0; k < nev && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&ev[k], hipEventDisableSystemFence);
     if (e != hipSuccess) out = hip_fail(e, "autotune set-up");
     // round r runs candidate r mod (count) of every pass at once: each pass
     // is timed by its own events, so one round measures five candidates
