@@ -54,6 +54,38 @@ def test_plan_create_ex_rejects_bad_cutoff():
     assert B.STATUS[ei.value.status] == "PSP_EINVAL"
 
 
+@pytest.mark.parametrize("h,eps,delta,code", [
+    ((0.1, 0.0, 0.1), None, None, "PSP_EINVAL"),             # a zero spacing
+    ((0.1, -0.2, 0.1), None, None, "PSP_EINVAL"),
+    ((0.1, float("nan"), 0.1), None, None, "PSP_EINVAL"),
+    ((0.1, 0.2, 0.3), 2.0, 1.0, "PSP_EINVAL"),                # eps > delta
+    ((0.1, 0.2, 0.3), 1e-4, float("inf"), "PSP_EINVAL"),
+])
+def test_box_plan_rejects(h, eps, delta, code):
+    with pytest.raises(B.PspError) as ei:
+        B.Plan(32, h, 40, eps=eps, delta=delta)
+    assert B.STATUS[ei.value.status] == code
+
+
+def test_box_plan_create_null_and_defaults():
+    lib = B.lib()
+    out = ctypes.c_void_p()
+    assert B.STATUS[lib.psp_plan_create_box(32, None, 40, 0, -1.0, -1.0, ctypes.byref(out))] == "PSP_EINVAL"
+    assert not out.value
+    with pytest.raises(ValueError):
+        B.Plan(32, (0.1, 0.2), 40)
+    # default cutoff: 1e-4 of the longest half side, delta the half diagonal,
+    # i.e. the oracle's; equal spacings give the cubic plan's Gaussian sum
+    hs = (0.05, 0.08, 0.11)
+    p = B.Plan(32, hs, 40)
+    eps, delta = O.default_eps_delta(32, hs)
+    wo, ao = O.gs_weights(40, eps, delta)
+    w, a = p.gs()
+    assert np.allclose(w, wo, rtol=1e-14, atol=0) and np.allclose(a, ao, rtol=1e-14, atol=0)
+    q, c = B.Plan(32, (0.1, 0.1, 0.1), 40), B.Plan(32, 0.1, 40)
+    assert all(np.array_equal(x, y) for x, y in zip(q.gs(), c.gs()))
+
+
 def test_error_strings():
     lib = B.lib()
     for code in B.STATUS:
