@@ -40,8 +40,9 @@ notes of the repository):
     100-step bisection on [1, 80].
   * ``eps = 1e-4 * L/2`` (the paper's default cutoff in units where L = 2) and
     ``delta = sqrt(3) * L/2`` (the corner of the truncation box).
-  * Rectangular domains (Section 3, Tables 4, 6, 8): n points per axis with
-    a spacing h_p per axis, so the padded box has sides ``L_p = 2 n h_p``;
+  * Rectangular domains (Section 3, Tables 4, 6, 8; Algorithm 1 takes a
+    point count and a spacing per axis): n_p points and spacing h_p on axis
+    p, so the padded box has sides ``L_p = 2 n_p h_p``;
     the kernel is truncated to that box, the 1D integrals of axis p run over
     ``[-L_p/2, L_p/2]``, the spectral Laplacian is
     ``-(2 pi)^2 sum_p k_p^2 / L_p^2``, ``eps = 1e-4 max_p(L_p/2)`` and
@@ -57,7 +58,7 @@ import math
 import numpy as np
 
 __all__ = [
-    "spacings", "default_eps_delta", "gs_parameters", "gs_weights", "gs_biharmonic",
+    "spacings", "counts", "default_eps_delta", "gs_parameters", "gs_weights", "gs_biharmonic",
     "gauss_legendre", "tables_1d", "spectrum_octant", "multiplier_octant",
     "fft_naive", "fftn_naive", "solve", "solve_padded", "direct_operator",
     "direct_points", "Setup", "setup",
@@ -79,10 +80,20 @@ def spacings(h):
     return hs
 
 
-def default_eps_delta(n: int, h):
-    """Cutoff eps and outer radius delta for n points per axis of spacing h
-    (one value, or one per axis)."""
-    halves = [n * v for v in spacings(h)]        # L_p/2 with L_p = 2 n h_p
+def counts(n):
+    """(n_1, n_2, n_3) from one point count per axis (a cube) or three."""
+    ns = tuple(int(v) for v in np.atleast_1d(n))
+    if len(ns) == 1:
+        return ns * 3
+    if len(ns) != 3:
+        raise ValueError("n must be one point count or three")
+    return ns
+
+
+def default_eps_delta(n, h):
+    """Cutoff eps and outer radius delta for n points per axis (one count,
+    or one per axis) of spacing h (one value, or one per axis)."""
+    halves = [m * v for m, v in zip(counts(n), spacings(h))]   # L_p/2 with L_p = 2 n_p h_p
     return 1e-4 * max(halves), math.sqrt(sum(v * v for v in halves))
 
 
@@ -237,8 +248,7 @@ def spectrum_octant(omega, J0, J2):
     over the Gaussian-sum terms, one outer product per term and direction.
     """
     (x0, y0, z0), (x2, y2, z2) = _per_axis(J0), _per_axis(J2)
-    n1 = x0.shape[1]
-    V = np.zeros((n1, n1, n1))
+    V = np.zeros((x0.shape[1], y0.shape[1], z0.shape[1]))
     for s in range(len(omega)):
         V += omega[s] * (x2[s][:, None, None] * y0[s][None, :, None] * z0[s][None, None, :]
                          + x0[s][:, None, None] * y2[s][None, :, None] * z0[s][None, None, :]
@@ -246,9 +256,10 @@ def spectrum_octant(omega, J0, J2):
     return V
 
 
-def multiplier_octant(V, n: int, L):
+def multiplier_octant(V, n, L):
     """``m[a,b,c] = -(2 pi)^2 (a^2/L_1^2 + b^2/L_2^2 + c^2/L_3^2) Vhat[a,b,c]
-    / (2n)^3`` (L: one period, or one per axis).
+    / (8 n_1 n_2 n_3)`` (n: one count or one per axis; L: one period, or one
+    per axis).
 
     The spectral Laplacian ``-(2 pi/L)^2 |k|^2`` of eq. convtheorem (per axis
     on a rectangular box) times the kernel spectrum, with the 1/(2n)^3 of
@@ -256,10 +267,12 @@ def multiplier_octant(V, n: int, L):
     coefficients) folded in.
     """
     L1, L2, L3 = [float(v) for v in _per_axis(L)]
-    a = np.arange(n + 1, dtype=np.float64)
-    w = ((2.0 * math.pi / L1) ** 2 * a[:, None, None] ** 2 + (2.0 * math.pi / L2) ** 2 * a[None, :, None] ** 2
-         + (2.0 * math.pi / L3) ** 2 * a[None, None, :] ** 2)
-    return -w * V / float((2 * n) ** 3)
+    n1, n2, n3 = counts(n)
+    a = np.arange(n1 + 1, dtype=np.float64)[:, None, None]
+    b = np.arange(n2 + 1, dtype=np.float64)[None, :, None]
+    c = np.arange(n3 + 1, dtype=np.float64)[None, None, :]
+    w = (2.0 * math.pi / L1) ** 2 * a ** 2 + (2.0 * math.pi / L2) ** 2 * b ** 2 + (2.0 * math.pi / L3) ** 2 * c ** 2
+    return -w * V / float(8 * n1 * n2 * n3)
 
 
 class Setup:
@@ -270,19 +283,20 @@ class Setup:
     def __init__(self, n, h, R, eps=None, delta=None):
         d_eps, d_delta = default_eps_delta(n, h)
         self.n, self.h, self.R = n, h, R
+        self.ns = counts(n)
         self.hs = spacings(h)
-        self.Ls = tuple(2.0 * n * v for v in self.hs)
-        self.cubic = len(set(self.hs)) == 1
+        self.Ls = tuple(2.0 * m * v for m, v in zip(self.ns, self.hs))
+        self.cubic = len(set(self.hs)) == 1 and len(set(self.ns)) == 1
         self.L = self.Ls[0] if self.cubic else self.Ls
         self.eps = d_eps if eps is None else eps
         self.delta = d_delta if delta is None else delta
         self.omega, self.alpha = gs_weights(R, self.eps, self.delta)
         tables = {}
-        for Lp in self.Ls:
-            if Lp not in tables:
-                tables[Lp] = tables_1d(self.alpha, n, Lp)
-        self.J0s = [tables[Lp][0] for Lp in self.Ls]
-        self.J2s = [tables[Lp][1] for Lp in self.Ls]
+        for m, Lp in zip(self.ns, self.Ls):
+            if (m, Lp) not in tables:
+                tables[(m, Lp)] = tables_1d(self.alpha, m, Lp)
+        self.J0s = [tables[key][0] for key in zip(self.ns, self.Ls)]
+        self.J2s = [tables[key][1] for key in zip(self.ns, self.Ls)]
         self.J0, self.J2 = self.J0s[0], self.J2s[0]
         self._V = None
         self._m = None
@@ -296,15 +310,17 @@ class Setup:
     @property
     def m(self):
         if self._m is None:
-            self._m = multiplier_octant(self.V, self.n, self.Ls)
+            self._m = multiplier_octant(self.V, self.ns, self.Ls)
         return self._m
 
     def full_multiplier(self):
-        """The multiplier on the whole padded (2n)^3 grid, DFT index order."""
-        n = self.n
-        idx = np.arange(2 * n)
-        a = np.minimum(idx, 2 * n - idx)     # |k| for k = idx or idx - 2n
-        return self.m[np.ix_(a, a, a)]
+        """The multiplier on the whole padded grid (2 n_p per axis), DFT index
+        order."""
+        ax = []
+        for m in self.ns:
+            idx = np.arange(2 * m)
+            ax.append(np.minimum(idx, 2 * m - idx))    # |k| for k = idx or idx - 2n
+        return self.m[np.ix_(*ax)]
 
 
 def setup(n, h, R, eps=None, delta=None) -> Setup:
@@ -355,23 +371,30 @@ def fftn_naive(x, sign: int = -1):
 
 
 def solve_padded(rho, h, R, eps=None, delta=None, su: Setup | None = None):
-    """The uncropped (2n)^3 result of Algorithm 2 (real part)."""
+    """The uncropped result of Algorithm 2 on the padded grid (2 n_p per
+    axis; real part).  rho has shape (n_1, n_2, n_3)."""
     rho = np.asarray(rho, dtype=np.float64)
-    n = rho.shape[0]
-    assert rho.shape == (n, n, n)
+    assert rho.ndim == 3
     if su is None:
-        su = setup(n, h, R, eps, delta)
-    pad = np.zeros((2 * n,) * 3, dtype=np.complex128)
-    pad[:n, :n, :n] = rho                       # zero padding, factor 2
+        su = setup(_count_of(rho), h, R, eps, delta)
+    n1, n2, n3 = rho.shape
+    pad = np.zeros((2 * n1, 2 * n2, 2 * n3), dtype=np.complex128)
+    pad[:n1, :n2, :n3] = rho                    # zero padding, factor 2
     rhohat = fftn_naive(pad, -1)                # forward DFT (1/(2n)^3 is in m)
     prod = su.full_multiplier() * rhohat        # multiply (eq. convtheorem)
     return fftn_naive(prod, +1).real            # inverse sum, real part
 
 
 def solve(rho, h, R, eps=None, delta=None, su: Setup | None = None):
-    """u on the original n^3 grid (Algorithm 2 with the crop)."""
-    n = np.asarray(rho).shape[0]
-    return solve_padded(rho, h, R, eps, delta, su)[:n, :n, :n]
+    """u on the original grid (Algorithm 2 with the crop)."""
+    n1, n2, n3 = np.asarray(rho).shape
+    return solve_padded(rho, h, R, eps, delta, su)[:n1, :n2, :n3]
+
+
+def _count_of(rho):
+    """The point count(s) of a density: one int for a cube, else three."""
+    s = tuple(np.asarray(rho).shape)
+    return s[0] if s[0] == s[1] == s[2] else s
 
 
 # --------------------------------------------------------------------------
@@ -381,19 +404,19 @@ def solve(rho, h, R, eps=None, delta=None, su: Setup | None = None):
 
 
 def _stencil_factors(su: Setup):
-    """1D stencils over offsets d = -(n-1)..(n-1) for every Gaussian-sum term
-    and axis p: ``F[p][f](d) = sum_{k=-n}^{n-1} f(|k|) exp(i pi k d / n)``
-    for f in {J0, J2, k^2 J0, k^2 J2} of axis p's tables."""
-    n = su.n
-    k = np.arange(-n, n)
-    d = np.arange(-(n - 1), n)
-    ak = np.abs(k)
-    # real because f(|k|) is even in k except for the single k = -n term,
-    # whose phase exp(-i pi d) = (-1)^d is real
-    phase = np.cos(math.pi * np.outer(d, k) / n)
-    k2 = (ak * ak).astype(np.float64)
+    """1D stencils over offsets d = -(n_p-1)..(n_p-1) for every Gaussian-sum
+    term and axis p: ``F[p][f](d) = sum_{k=-n_p}^{n_p-1} f(|k|)
+    exp(i pi k d / n_p)`` for f in {J0, J2, k^2 J0, k^2 J2} of axis p's
+    tables."""
     out = []
-    for J0, J2 in zip(su.J0s, su.J2s):
+    for n, J0, J2 in zip(su.ns, su.J0s, su.J2s):
+        k = np.arange(-n, n)
+        d = np.arange(-(n - 1), n)
+        ak = np.abs(k)
+        # real because f(|k|) is even in k except for the single k = -n
+        # term, whose phase exp(-i pi d) = (-1)^d is real
+        phase = np.cos(math.pi * np.outer(d, k) / n)
+        k2 = (ak * ak).astype(np.float64)
         out.append((J0[:, ak] @ phase.T, J2[:, ak] @ phase.T, (J0[:, ak] * k2) @ phase.T,
                     (J2[:, ak] * k2) @ phase.T))
     return out
@@ -402,10 +425,12 @@ def _stencil_factors(su: Setup):
 def _separable_terms(su: Setup):
     """Yield (s, coef, (t1, t2, t3)) for the stencil
     ``c_d = sum coef * F[0]_t1(d1) F[1]_t2(d2) F[2]_t3(d3)``: the product of
-    ``-(2 pi)^2/(2n)^3 (k1^2/L_1^2 + k2^2/L_2^2 + k3^2/L_3^2)`` with the three
-    rank-one terms of eq. Gten_sep, expanded into nine separable terms per
-    Gaussian-sum term.  Factor types: 0 = J0, 1 = J2, 2 = k^2 J0, 3 = k^2 J2."""
-    C = [-((2.0 * math.pi / Lp) ** 2) / float((2 * su.n) ** 3) for Lp in su.Ls]
+    ``-(2 pi)^2/(8 n_1 n_2 n_3) (k1^2/L_1^2 + k2^2/L_2^2 + k3^2/L_3^2)`` with
+    the three rank-one terms of eq. Gten_sep, expanded into nine separable
+    terms per Gaussian-sum term.  Factor types: 0 = J0, 1 = J2, 2 = k^2 J0,
+    3 = k^2 J2."""
+    n1, n2, n3 = su.ns
+    C = [-((2.0 * math.pi / Lp) ** 2) / float(8 * n1 * n2 * n3) for Lp in su.Ls]
     for s in range(len(su.omega)):
         for q in range(3):            # which axis carries J2
             for p2 in range(3):       # which axis carries the k^2 factor
@@ -417,15 +442,16 @@ def direct_operator(rho, h, R, eps=None, delta=None, su: Setup | None = None):
     """u_j = sum_m c_{j-m} rho_m over the whole grid, no FFT.  Cost
     O(R n^4) through the separable stencil; intended for n <= 32."""
     rho = np.asarray(rho, dtype=np.float64)
-    n = rho.shape[0]
     if su is None:
-        su = setup(n, h, R, eps, delta)
+        su = setup(_count_of(rho), h, R, eps, delta)
     F = _stencil_factors(su)
-    j = np.arange(n)
-    off = (j[:, None] - j[None, :]) + (n - 1)     # index of d = j - m
+    off = []
+    for n in rho.shape:
+        j = np.arange(n)
+        off.append((j[:, None] - j[None, :]) + (n - 1))     # index of d = j - m
     u = np.zeros_like(rho)
     for s, coef, (t1, t2, t3) in _separable_terms(su):
-        T1, T2, T3 = F[0][t1][s][off], F[1][t2][s][off], F[2][t3][s][off]
+        T1, T2, T3 = F[0][t1][s][off[0]], F[1][t2][s][off[1]], F[2][t3][s][off[2]]
         t = np.tensordot(rho, T3, axes=([2], [1]))          # (m1, m2, j3)
         t = np.tensordot(t, T2, axes=([1], [1]))             # (m1, j3, j2)
         t = np.tensordot(t, T1, axes=([0], [1]))             # (j3, j2, j1)
@@ -437,24 +463,23 @@ def direct_points(rho, points, h, R, eps=None, delta=None, su: Setup | None = No
     """u at selected grid indices ``points`` (array of shape (P, 3)) by the
     same FFT-free Toeplitz sum; usable at any n."""
     rho = np.asarray(rho, dtype=np.float64)
-    n = rho.shape[0]
     if su is None:
-        su = setup(n, h, R, eps, delta)
+        su = setup(_count_of(rho), h, R, eps, delta)
+    n1, n2, n3 = rho.shape
     F = _stencil_factors(su)
     pts = np.asarray(points, dtype=np.int64).reshape(-1, 3)
-    m = np.arange(n)
     j3s, inv3 = np.unique(pts[:, 2], return_inverse=True)
     out = np.zeros(pts.shape[0])
-    rho2 = rho.reshape(n * n, n)
-    d3 = (j3s[:, None] - m[None, :]) + (n - 1)
-    d1 = (pts[:, 0][:, None] - m[None, :]) + (n - 1)
-    d2 = (pts[:, 1][:, None] - m[None, :]) + (n - 1)
+    rho2 = rho.reshape(n1 * n2, n3)
+    d3 = (j3s[:, None] - np.arange(n3)[None, :]) + (n3 - 1)
+    d1 = (pts[:, 0][:, None] - np.arange(n1)[None, :]) + (n1 - 1)
+    d2 = (pts[:, 1][:, None] - np.arange(n2)[None, :]) + (n2 - 1)
     cache = {}
     for s, coef, (t1, t2, t3) in _separable_terms(su):
         key = (s, t3)
         if key not in cache:
             cache.clear() if len(cache) > 8 else None
-            cache[key] = (rho2 @ F[2][t3][s][d3].T).reshape(n, n, -1)[:, :, inv3]
+            cache[key] = (rho2 @ F[2][t3][s][d3].T).reshape(n1, n2, -1)[:, :, inv3]
         tp = cache[key]                                        # (m1, m2, P)
         out += coef * np.einsum("pa,pb,abp->p", F[0][t1][s][d1], F[1][t2][s][d2], tp,
                                 optimize=True)
