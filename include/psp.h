@@ -49,7 +49,7 @@ typedef enum {
     PSP_OK = 0,
     PSP_EINVAL = -1,        /* bad argument (h <= 0, R < 1, NULL pointer ...) */
     PSP_ENOMEM = -2,        /* device or host allocation failed, or over budget */
-    PSP_EUNSUPPORTED = -3,  /* n odd, n < 4, n > 384, or 2n not 2^a 3^b */
+    PSP_EUNSUPPORTED = -3,  /* n not one of the built sizes (see psp_plan_create) */
     PSP_ESTATE = -4,        /* call order (solve before precompute ...) */
     PSP_EHIP = -5,          /* a HIP runtime call failed */
     PSP_EBUSY = -6,         /* server queue full; request already on the device */
@@ -61,7 +61,9 @@ typedef enum {
  * weights and exponents on the host (Section 2, eq. sin_1_x: sinc quadrature
  * of 1/(8 pi r) on (eps, delta] with eps = 1e-4 * n h and
  * delta = sqrt(3) * n h).  Host work only; no device memory is touched.
- * n: points per axis (even, 4..384, 2n = 2^a 3^b); h > 0 finite; 1 <= R <= 2048.
+ * n: points per axis, one of 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192,
+ * 256, 384 (padded lengths 2n = 2^a or 3 * 2^a, the lengths whose FFT
+ * kernels are built); h > 0 finite; 1 <= R <= 2048.
  * *out receives the plan (NULL on failure). */
 psp_status psp_plan_create(int n, double h, int R, psp_dtype dtype, psp_plan **out);
 
@@ -80,6 +82,20 @@ psp_status psp_plan_create_ex(int n, double h, int R, psp_dtype dtype,
  * psp_plan_create (same errors, plus PSP_EINVAL for h == NULL). */
 psp_status psp_plan_create_box(int n, const double *h, int R, psp_dtype dtype,
                                double eps, double delta, psp_plan **out);
+
+/* The general grid (Algorithm 1 takes a point count and a spacing per
+ * axis): n[p] points and spacing h[p] along axis p (n, h: 3 host values;
+ * each n[p] as for psp_plan_create).  rho and u are n[0] x n[1] x n[2],
+ * C-order.  Defaults as for psp_plan_create_box, with L_p = 2 n_p h_p.
+ * With unequal counts every pass runs at its own axis's padded length and
+ * takes the tuned shape of a cube of that size; such plans solve singly
+ * (psp_solve, psp_graph_capture); psp_solve_batched,
+ * psp_graph_capture_batched, psp_solve_padded_debug, psp_autotune,
+ * psp_plan_set_shape, psp_profile_enable and k3 chunks / i1 groups return
+ * PSP_EUNSUPPORTED for them.  Equal counts give the psp_plan_create_box
+ * plan. */
+psp_status psp_plan_create_grid(const int *n, const double *h, int R, psp_dtype dtype,
+                                double eps, double delta, psp_plan **out);
 
 /* Algorithm 1 steps 2-3 on the current device, on `stream`: the 2 R (n+1) 1D
  * integrals of eq. Gten_sep (FP64 with double-double node phases: closed
@@ -140,8 +156,9 @@ psp_status psp_plan_get_gs(const psp_plan *p, double *omega, double *alpha);
  * the device's null stream. */
 psp_status psp_plan_get_tables(psp_plan *p, double *J0, double *J2);
 
-/* Test hook: copies the device multiplier octant m[a][b][c] (a,b,c <= n,
- * row-major (n+1)^3 doubles) to host memory.  Needs precompute; syncs. */
+/* Test hook: copies the device multiplier octant m[a][b][c] (a <= n1,
+ * b <= n2, c <= n3; row-major (n1+1)(n2+1)(n3+1) doubles, (n+1)^3 for a
+ * cube) to host memory.  Needs precompute; syncs. */
 psp_status psp_plan_get_multiplier(psp_plan *p, double *m_host);
 
 /* Tuning of single solves (batched solves and graphs use the defaults).

@@ -45,7 +45,8 @@ DevSpectrum::~DevSpectrum() {
 
 // ---------------------------------------------------------------- caches
 static std::mutex g_cache_mu;
-using SpecKey = std::tuple<int, int, double, double, double, int, double, double>;   // device, n, h[3], R, eps, delta
+// device, n[3], h[3], R, eps, delta
+using SpecKey = std::tuple<int, int, int, int, double, double, double, int, double, double>;
 static std::map<SpecKey, std::weak_ptr<DevSpectrum>> g_spec_cache;
 static std::map<std::pair<int, int>, Twiddles> g_tw_cache;            // (device, N)
 
@@ -80,7 +81,9 @@ psp_status check_create(int n, double h, int R, double eps, double delta) {
     if (!(eps > 0.0) || !(delta > eps) || !std::isfinite(delta))
         return fail(PSP_EINVAL, "need 0 < eps < delta finite (got %g, %g)", eps, delta);
     if (n < 4 || n > 384 || (n & 1)) return fail(PSP_EUNSUPPORTED, "n must be even and in [4, 384] (got %d)", n);
-    if (!supported_length(2 * n)) return fail(PSP_EUNSUPPORTED, "2n = %d is not of the form 2^a 3^b", 2 * n);
+    if (!supported_length(2 * n))
+        return fail(PSP_EUNSUPPORTED,
+                    "n = %d is not one of the built sizes 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384", n);
     return PSP_OK;
 }
 
@@ -124,6 +127,22 @@ psp_status alloc_workspace(int n, bool f32, int chunk_tiles, Workspace *w, int i
     return PSP_OK;
 }
 
+psp_status alloc_workspace_dims(const Dims &d, bool f32, Workspace *w) {
+    const size_t c = f32 ? 8 : 16, P = (size_t)pitch_for(d.n3), PA = (size_t)chunk_pitch(d.n3, f32, 0);
+    const bool guard = guards_enabled();
+    w->bytes = workspace_bytes_dims(d, f32);
+    w->X = w->A = w->X_base = w->A_base = nullptr;
+    w->X_bytes = c * P * (size_t)d.n1 * d.n2;
+    w->A_bytes = c * PA * (size_t)d.n1 * 2 * d.n2;
+    if (guarded_malloc(w->X_bytes, guard, &w->X_base, &w->X) != hipSuccess ||
+        guarded_malloc(w->A_bytes, guard, &w->A_base, &w->A) != hipSuccess) {
+        (void)hipGetLastError();
+        free_workspace(w);
+        return fail(PSP_ENOMEM, "workspace allocation of %zu bytes failed", w->bytes);
+    }
+    return PSP_OK;
+}
+
 void free_workspace(Workspace *w) {
     if (w->X_base) (void)hipFree(w->X_base);
     if (w->A_base) (void)hipFree(w->A_base);
@@ -159,7 +178,8 @@ psp_status plan_workspace(psp_plan *p, hipStream_t st, Workspace **out) {
         return PSP_OK;
     }
     Workspace w;
-    psp_status rs = alloc_workspace(p->n, p->dtype == PSP_F32, p->chunk_tiles, &w, p->i1_group);
+    psp_status rs = p->grid ? alloc_workspace_dims(Dims{p->ns[0], p->ns[1], p->ns[2]}, p->dtype == PSP_F32, &w)
+                            : alloc_workspace(p->n, p->dtype == PSP_F32, p->chunk_tiles, &w, p->i1_group);
     if (rs != PSP_OK) return rs;
     auto res = p->ws.emplace(st, w);
     *out = &res.first->second;
@@ -180,6 +200,13 @@ SolveArgs solve_args(const psp_plan *p, const Workspace &w, const void *rho, voi
     a.shape = p->shape;
     a.mult = p->spec->mult;
     a.tw64 = p->tw->w64;
+    if (p->grid) {
+        a.P = pitch_for(p->ns[2]);
+        for (int i = 0; i < 3; ++i) {
+            a.ns[i] = p->ns[i];
+            a.tw_axis[i] = p->tws[i]->w64;
+        }
+    }
     return a;
 }
 
@@ -196,34 +223,40 @@ struct TableUpload {
 };
 static psp_status device_tables(const psp_plan *p, hipStream_t st, TableUpload &hold, double **buf, SpecTables *tb,
                                 const double **omega) {
-    std::vector<double> periods;
+    std::vector<std::pair<int, double>> axes;   // distinct (points, period)
     int axis_of[3];
     for (int a = 0; a < 3; ++a) {
-        auto it = std::find(periods.begin(), periods.end(), p->Ls[a]);
-        axis_of[a] = (int)(it - periods.begin());
-        if (it == periods.end()) periods.push_back(p->Ls[a]);
+        const std::pair<int, double> key{p->ns[a], p->Ls[a]};
+        auto it = std::find(axes.begin(), axes.end(), key);
+        axis_of[a] = (int)(it - axes.begin());
+        if (it == axes.end()) axes.push_back(key);
     }
-    const int nd = (int)periods.size();
-    const size_t tn = (size_t)p->R * (p->n + 1);
+    const int nd = (int)axes.size();
+    std::vector<size_t> off(nd + 1, 0);           // doubles before distinct axis i
+    for (int i = 0; i < nd; ++i) off[i + 1] = off[i] + 2 * (size_t)p->R * (axes[i].first + 1);
     hold.trig = table_trig();
     hold.jobs.clear();
-    for (int i = 0; i < nd; ++i) hold.jobs.push_back(table_jobs(p->alpha, p->n, periods[i]));
+    for (int i = 0; i < nd; ++i) hold.jobs.push_back(table_jobs(p->alpha, axes[i].first, axes[i].second));
     double *d = nullptr;
-    PSP_HIP(hipMalloc(&d, sizeof(double) * (2 * tn * nd + p->R) + sizeof(TabJob) * p->R * nd +
+    PSP_HIP(hipMalloc(&d, sizeof(double) * (off[nd] + p->R) + sizeof(TabJob) * p->R * nd +
                               sizeof(TabTrig) * hold.trig.size()),
             "hipMalloc(tables)");
     *buf = d;
-    double *dw = d + 2 * tn * nd;
+    double *dw = d + off[nd];
     TabJob *dj = reinterpret_cast<TabJob *>(dw + p->R);
     TabTrig *dt = reinterpret_cast<TabTrig *>(dj + (size_t)p->R * nd);
     hipError_t e = hipMemcpyAsync(dw, p->omega.data(), sizeof(double) * p->R, hipMemcpyHostToDevice, st);
-    for (int i = 0; i < nd && e == hipSuccess; ++i)
-        e = launch_tables(hold.jobs[i], hold.trig, p->n, periods[i], d + 2 * tn * i, d + 2 * tn * i + tn,
+    for (int i = 0; i < nd && e == hipSuccess; ++i) {
+        const size_t tn = (size_t)p->R * (axes[i].first + 1);
+        e = launch_tables(hold.jobs[i], hold.trig, axes[i].first, axes[i].second, d + off[i], d + off[i] + tn,
                           dj + (size_t)p->R * i, dt, st);
+    }
     if (e != hipSuccess) return hip_fail(e, "1D tables");
     for (int a = 0; a < 3; ++a) {
-        tb->J0[a] = d + 2 * tn * axis_of[a];
-        tb->J2[a] = d + 2 * tn * axis_of[a] + tn;
+        const int i = axis_of[a];
+        tb->J0[a] = d + off[i];
+        tb->J2[a] = d + off[i] + (size_t)p->R * (axes[i].first + 1);
+        tb->n[a] = p->ns[a];
     }
     *omega = dw;
     return PSP_OK;
@@ -258,22 +291,25 @@ const char *psp_strerror(psp_status e) {
 
 const char *psp_last_error(void) { return g_last_error.c_str(); }
 
-// a plan for n points per axis with spacings hs[0..2] and an explicit cutoff
-static psp_status create_plan(int n, const double *hs, int R, psp_dtype dtype, double eps, double delta,
+// a plan for ns[p] points and spacing hs[p] along axis p, explicit cutoff
+static psp_status create_plan(const int *ns, const double *hs, int R, psp_dtype dtype, double eps, double delta,
                               psp_plan **out) {
     if (!out) return fail(PSP_EINVAL, "out is NULL");
     *out = nullptr;
     if (dtype != PSP_F64 && dtype != PSP_F32) return fail(PSP_EINVAL, "unknown dtype %d", (int)dtype);
     for (int a = 0; a < 3; ++a) {
-        psp_status st = check_create(n, hs[a], R, eps, delta);
+        psp_status st = check_create(ns[a], hs[a], R, eps, delta);
         if (st != PSP_OK) return st;
     }
     psp_plan *p = new (std::nothrow) psp_plan;
     if (!p) return fail(PSP_ENOMEM, "host allocation failed");
+    const int n = ns[0];
     p->n = n;
+    p->grid = !(ns[0] == ns[1] && ns[1] == ns[2]);
     for (int a = 0; a < 3; ++a) {
+        p->ns[a] = ns[a];
         p->hs[a] = hs[a];
-        p->Ls[a] = 2.0 * n * hs[a];
+        p->Ls[a] = 2.0 * ns[a] * hs[a];
     }
     p->h = hs[0];
     p->L = p->Ls[0];
@@ -283,27 +319,37 @@ static psp_status create_plan(int n, const double *hs, int R, psp_dtype dtype, d
     p->delta = delta;
     p->chunk_tiles = 0;   // one chunk: fastest for a single solve
     p->shape = tuned_shape(n, dtype == PSP_F32);
+    if (p->grid) {
+        // each pass takes the tuned shape of its own axis's length
+        static const int axis_of_pass[kPasses] = {2, 1, 0, 1, 2};
+        for (int q = 0; q < kPasses; ++q) {
+            const Shape s = tuned_shape(ns[axis_of_pass[q]], dtype == PSP_F32);
+            p->shape.plan[q] = s.plan[q];
+            p->shape.tile[q] = s.tile[q];
+        }
+    }
     gs_fit(R, eps, delta, p->omega, p->alpha);
     *out = p;
     return PSP_OK;
 }
 
 psp_status psp_plan_create_ex(int n, double h, int R, psp_dtype dtype, double eps, double delta, psp_plan **out) {
+    const int ns[3] = {n, n, n};
     const double hs[3] = {h, h, h};
-    return create_plan(n, hs, R, dtype, eps, delta, out);
+    return create_plan(ns, hs, R, dtype, eps, delta, out);
 }
 
-psp_status psp_plan_create_box(int n, const double *h, int R, psp_dtype dtype, double eps, double delta,
-                               psp_plan **out) {
+psp_status psp_plan_create_grid(const int *n, const double *h, int R, psp_dtype dtype, double eps, double delta,
+                                psp_plan **out) {
     if (!out) return fail(PSP_EINVAL, "out is NULL");
     *out = nullptr;
-    if (!h) return fail(PSP_EINVAL, "h is NULL");
+    if (!n || !h) return fail(PSP_EINVAL, "n or h is NULL");
     if (eps <= 0.0 && delta <= 0.0) {
         // eps = 1e-4 max_p L_p/2 and delta = |(L_1, L_2, L_3)|/2, the corner
-        // of the kernel's truncation box (L_p = 2 n h_p)
+        // of the kernel's truncation box (L_p = 2 n_p h_p)
         double mx = 0.0, sq = 0.0;
         for (int a = 0; a < 3; ++a) {
-            const double half = (double)n * h[a];
+            const double half = (double)n[a] * h[a];
             mx = std::max(mx, half);
             sq += half * half;
         }
@@ -311,6 +357,12 @@ psp_status psp_plan_create_box(int n, const double *h, int R, psp_dtype dtype, d
         delta = std::sqrt(sq);
     }
     return create_plan(n, h, R, dtype, eps, delta, out);
+}
+
+psp_status psp_plan_create_box(int n, const double *h, int R, psp_dtype dtype, double eps, double delta,
+                               psp_plan **out) {
+    const int ns[3] = {n, n, n};
+    return psp_plan_create_grid(ns, h, R, dtype, eps, delta, out);
 }
 
 psp_status psp_plan_create(int n, double h, int R, psp_dtype dtype, psp_plan **out) {
@@ -364,13 +416,14 @@ psp_status psp_plan_get_tables(psp_plan *p, double *J0, double *J2) {
 
 psp_status psp_plan_workspace_bytes(const psp_plan *p, size_t *bytes) {
     if (!p || !bytes) return fail(PSP_EINVAL, "NULL argument");
-    *bytes = workspace_bytes(p->n, p->dtype == PSP_F32, p->chunk_tiles, p->i1_group);
+    *bytes = p->grid ? workspace_bytes_dims(Dims{p->ns[0], p->ns[1], p->ns[2]}, p->dtype == PSP_F32)
+                     : workspace_bytes(p->n, p->dtype == PSP_F32, p->chunk_tiles, p->i1_group);
     return PSP_OK;
 }
 
 psp_status psp_plan_spectrum_bytes(const psp_plan *p, size_t *bytes) {
     if (!p || !bytes) return fail(PSP_EINVAL, "NULL argument");
-    *bytes = spectrum_bytes(p->n);
+    *bytes = p->grid ? spectrum_bytes_dims(Dims{p->ns[0], p->ns[1], p->ns[2]}) : spectrum_bytes(p->n);
     return PSP_OK;
 }
 
@@ -380,9 +433,12 @@ psp_status psp_kernel_precompute(psp_plan *p, void *stream) {
     if (p->precomputed) return current_device_of(p);
     int dev = -1;
     PSP_HIP(hipGetDevice(&dev), "hipGetDevice");
-    psp_status rs = get_twiddles(dev, 2 * p->n, &p->tw);
-    if (rs != PSP_OK) return rs;
-    const SpecKey key{dev, p->n, p->hs[0], p->hs[1], p->hs[2], p->R, p->eps, p->delta};
+    for (int a = 0; a < 3; ++a) {
+        psp_status rs = get_twiddles(dev, 2 * p->ns[a], &p->tws[a]);
+        if (rs != PSP_OK) return rs;
+    }
+    p->tw = p->tws[0];
+    const SpecKey key{dev, p->ns[0], p->ns[1], p->ns[2], p->hs[0], p->hs[1], p->hs[2], p->R, p->eps, p->delta};
     std::shared_ptr<DevSpectrum> spec;
     {
         std::lock_guard<std::mutex> lk(g_cache_mu);
@@ -390,10 +446,10 @@ psp_status psp_kernel_precompute(psp_plan *p, void *stream) {
         if (it != g_spec_cache.end()) spec = it->second.lock();
     }
     if (!spec) {
-        const int n = p->n, R = p->R, P = pitch_for(n);
+        const int R = p->R, P = pitch_for(p->ns[2]);
         spec = std::make_shared<DevSpectrum>();
         spec->device = dev;
-        spec->bytes = spectrum_bytes(n);
+        spec->bytes = spectrum_bytes_dims(Dims{p->ns[0], p->ns[1], p->ns[2]});
         hipError_t e = hipMalloc(&spec->mult, spec->bytes);
         if (e != hipSuccess) {
             (void)hipGetLastError();
@@ -413,11 +469,10 @@ psp_status psp_kernel_precompute(psp_plan *p, void *stream) {
                 break;
             }
             const double pi = 3.14159265358979323846;
-            const double N = 2.0 * n;
             SpecScale sc;
             for (int a = 0; a < 3; ++a) sc.w[a] = (2.0 * pi / p->Ls[a]) * (2.0 * pi / p->Ls[a]);
-            sc.scale = -1.0 / (N * N * N);
-            if ((ee = launch_spectrum(tabs, dW, R, n, P, sc, spec->mult, st)) != hipSuccess) {
+            sc.scale = -1.0 / ((2.0 * p->ns[0]) * (2.0 * p->ns[1]) * (2.0 * p->ns[2]));
+            if ((ee = launch_spectrum(tabs, dW, R, P, sc, spec->mult, st)) != hipSuccess) {
                 out = hip_fail(ee, "spectrum kernel launch");
                 break;
             }
@@ -443,14 +498,16 @@ psp_status psp_kernel_precompute(psp_plan *p, void *stream) {
 psp_status psp_plan_get_multiplier(psp_plan *p, double *m_host) {
     if (!p || !m_host) return fail(PSP_EINVAL, "NULL argument");
     if (!p->precomputed) return fail(PSP_ESTATE, "multiplier requested before psp_kernel_precompute");
-    const int n = p->n, P = pitch_for(n);
-    std::vector<double> blk(spectrum_bytes(n) / 8);
-    PSP_HIP(hipMemcpy(blk.data(), p->spec->mult, spectrum_bytes(n), hipMemcpyDeviceToHost), "hipMemcpy(mult)");
-    const size_t n1 = (size_t)n + 1;
-    for (size_t a = 0; a < n1; ++a)
-        for (size_t b = 0; b < n1; ++b)
-            for (size_t c = 0; c < n1; ++c)
-                m_host[(a * n1 + b) * n1 + c] = blk[((b * (P / 8) + c / 8) * n1 + a) * 8 + (c & 7)];
+    const Dims d{p->ns[0], p->ns[1], p->ns[2]};
+    const int P = pitch_for(d.n3);
+    const size_t bytes = spectrum_bytes_dims(d);
+    std::vector<double> blk(bytes / 8);
+    PSP_HIP(hipMemcpy(blk.data(), p->spec->mult, bytes, hipMemcpyDeviceToHost), "hipMemcpy(mult)");
+    const size_t na = (size_t)d.n1 + 1, nb = (size_t)d.n2 + 1, nc = (size_t)d.n3 + 1;
+    for (size_t a = 0; a < na; ++a)
+        for (size_t b = 0; b < nb; ++b)
+            for (size_t c = 0; c < nc; ++c)
+                m_host[(a * nb + b) * nc + c] = blk[((b * (P / 8) + c / 8) * na + a) * 8 + (c & 7)];
     return PSP_OK;
 }
 
@@ -480,6 +537,7 @@ psp_status psp_solve(psp_plan *p, const void *rho_dev, void *u_dev, void *stream
 
 psp_status psp_profile_enable(psp_plan *p, int max_solves) {
     if (!p || max_solves < 0 || max_solves > 100000) return fail(PSP_EINVAL, "bad profile arguments");
+    if (p->grid) return fail(PSP_EUNSUPPORTED, "per-pass profiling needs equal point counts per axis");
     std::lock_guard<std::mutex> lk(p->mu);
     profile_clear(p);
     p->prof_nev = solve_launches(p->n, p->dtype == PSP_F32, p->chunk_tiles, p->i1_group) + 1;
@@ -524,6 +582,8 @@ psp_status psp_profile_read(psp_plan *p, int *count, double *pass_ms) {
 
 psp_status psp_plan_set_tuning(psp_plan *p, int k3_tiles, int i1_group) {
     if (!p || k3_tiles < 0 || i1_group < 0) return fail(PSP_EINVAL, "bad tuning arguments");
+    if (p->grid && (k3_tiles != 0 || i1_group != 0))
+        return fail(PSP_EUNSUPPORTED, "k3 chunks and i1 groups need equal point counts per axis");
     std::lock_guard<std::mutex> lk(p->mu);
     if (p->prof_cap > 0) return fail(PSP_ESTATE, "cannot change the tuning while profiling");
     if (k3_tiles != p->chunk_tiles || i1_group != p->i1_group) {
@@ -560,6 +620,7 @@ psp_status psp_plan_check_guards(psp_plan *p, int *intact) {
 psp_status psp_solve_padded_debug(psp_plan *p, const void *rho_dev, void *upad_dev, void *stream) {
     if (!p || !rho_dev || !upad_dev) return fail(PSP_EINVAL, "NULL argument");
     if (!p->precomputed) return fail(PSP_ESTATE, "psp_solve_padded_debug before psp_kernel_precompute");
+    if (p->grid) return fail(PSP_EUNSUPPORTED, "the uncropped output needs equal point counts per axis");
     psp_status st = current_device_of(p);
     if (st != PSP_OK) return st;
     hipStream_t s = (hipStream_t)stream;

@@ -251,6 +251,7 @@ extern "C" psp_status psp_solve_batched(int count, psp_plan *const *plans, const
         if (!plans[i]->precomputed) return fail(PSP_ESTATE, "batch entry %d not precomputed", i);
         if (plans[i]->dtype != plans[0]->dtype) return fail(PSP_EINVAL, "batch mixes dtypes");
         if (plans[i]->device != plans[0]->device) return fail(PSP_EINVAL, "batch mixes devices");
+        if (plans[i]->grid) return fail(PSP_EUNSUPPORTED, "batch entry %d has unequal point counts per axis", i);
         if (rho_dev[i] == u_dev[i]) return fail(PSP_EINVAL, "entry %d: rho and u must not alias", i);
     }
     int dev = -1;

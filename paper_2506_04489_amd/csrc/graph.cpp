@@ -68,7 +68,8 @@ psp_status psp_graph_capture(psp_plan *p, const void *rho_dev, void *u_dev, void
     if (!g) return fail(PSP_ENOMEM, "host allocation failed");
     g->device = p->device;
     g->ws.resize(1);
-    psp_status rs = alloc_workspace(p->n, p->dtype == PSP_F32, 0, &g->ws[0]);
+    psp_status rs = p->grid ? alloc_workspace_dims(Dims{p->ns[0], p->ns[1], p->ns[2]}, p->dtype == PSP_F32, &g->ws[0])
+                            : alloc_workspace(p->n, p->dtype == PSP_F32, 0, &g->ws[0]);
     if (rs != PSP_OK) {
         g->ws.clear();
         graph_free(g);
@@ -94,6 +95,7 @@ psp_status psp_graph_capture_batched(int count, psp_plan *const *plans, const vo
         if (!plans[i] || !rho_dev[i] || !u_dev[i]) return fail(PSP_EINVAL, "NULL entry %d in batch", i);
         if (!plans[i]->precomputed) return fail(PSP_ESTATE, "batch entry %d not precomputed", i);
         if (plans[i]->dtype != plans[0]->dtype) return fail(PSP_EINVAL, "batch mixes dtypes");
+        if (plans[i]->grid) return fail(PSP_EUNSUPPORTED, "batch entry %d has unequal point counts per axis", i);
     }
     const bool f32 = plans[0]->dtype == PSP_F32;
     psp_graph *g = new (std::nothrow) psp_graph;

@@ -83,6 +83,14 @@ inline size_t workspace_bytes(int n, bool f32, int chunk_tiles, int i1_group = 0
     return c * (P * (size_t)x_slabs(n, f32, chunk_tiles, i1_group) * n + PA * (size_t)n * 2 * n);
 }
 psp_status alloc_workspace(int n, bool f32, int chunk_tiles, Workspace *w, int i1_group = 0);
+// unequal point counts per axis: X holds n1 x n2 rows of pitch P(n3), A the
+// one chunk n1 x 2 n2 x pitch(n3)
+inline size_t workspace_bytes_dims(const Dims &d, bool f32) {
+    const size_t c = f32 ? 8 : 16;
+    const size_t P = (size_t)pitch_for(d.n3), PA = (size_t)chunk_pitch(d.n3, f32, 0);
+    return c * (P * (size_t)d.n1 * d.n2 + PA * (size_t)d.n1 * 2 * d.n2);
+}
+psp_status alloc_workspace_dims(const Dims &d, bool f32, Workspace *w);
 
 // ---- batches: the device image of a batch -----------------------------------
 struct BatchMember {
@@ -109,6 +117,8 @@ hipError_t launch_batch_image(const std::vector<BatchMember> &m, const BatchImag
                               unsigned char *dev_base, bool reset, hipStream_t st);
 void free_workspace(Workspace *w);
 inline size_t spectrum_bytes(int n) { return 8 * (size_t)(n + 1) * (n + 1) * pitch_for(n); }
+// the multiplier octant of a grid: (n2 + 1) x pitch(n3) x (n1 + 1) doubles
+inline size_t spectrum_bytes_dims(const Dims &d) { return 8 * (size_t)(d.n1 + 1) * (d.n2 + 1) * pitch_for(d.n3); }
 
 }  // namespace psp
 
@@ -116,6 +126,9 @@ struct psp_plan {
     int n = 0;
     double h = 0, L = 0, eps = 0, delta = 0;   // h, L: axis 1
     double hs[3] = {0, 0, 0}, Ls[3] = {0, 0, 0};  // per axis (rectangular box)
+    int ns[3] = {0, 0, 0};                         // points per axis
+    bool grid = false;                             // unequal point counts per axis
+    const psp::Twiddles *tws[3] = {nullptr, nullptr, nullptr};   // per axis (grid)
     int R = 0;
     psp_dtype dtype = PSP_F64;
     std::vector<double> omega, alpha;   // S0

@@ -32,6 +32,11 @@ struct Job {
 // tile choice.
 constexpr int kPasses = 5;
 constexpr int kTileChoices[kPasses] = {3, 7, 7, 7, 3};
+// points along i1, i2, i3 (the slowest to the contiguous axis of rho)
+struct Dims {
+    int n1, n2, n3;
+};
+
 struct Shape {
     int plan[kPasses] = {0, 0, 0, 0, 0};
     int tile[kPasses] = {0, 0, 0, 0, 0};
@@ -126,6 +131,11 @@ struct SolveArgs {
     hipEvent_t *ev = nullptr;       // optional profiling events, one before each launch and one after
     int *ev_pass = nullptr;         // host array: pass (0..4) of each launch, -1 for the last event
     int nev = 0;
+    // unequal point counts per axis (ns[0] == 0: all n): each pass runs at
+    // the padded length of its axis with that axis's twiddles tw_axis[]; no
+    // chunking, grouping, uncropped output or profiling events
+    int ns[3] = {0, 0, 0};
+    const void *tw_axis[3] = {nullptr, nullptr, nullptr};
 };
 
 hipError_t launch_solve(const SolveArgs &s, hipStream_t st);
@@ -142,16 +152,17 @@ inline int strided_width(bool f32) { return f32 ? 16 : 8; }
 // the kernel-spectrum multiplier octant (FP64 MFMA contraction)
 // S2 inputs: the 1D tables of each axis (R x (n+1) each; the same pointers
 // for every axis of a cubic box) and the epilogue's spectral-Laplacian
-// weights w_p = (2 pi / L_p)^2 and scale -1/N^3
+// weights w_p = (2 pi / L_p)^2 and scale -1/(N1 N2 N3)
 struct SpecTables {
     const double *J0[3];
     const double *J2[3];
+    int n[3];   // points per axis: tables of axis p have n[p] + 1 columns
 };
 struct SpecScale {
     double w[3];
     double scale;
 };
-hipError_t launch_spectrum(const SpecTables &tb, const double *omega, int R, int n, int P, const SpecScale &sc,
+hipError_t launch_spectrum(const SpecTables &tb, const double *omega, int R, int P, const SpecScale &sc,
                            double *mult, hipStream_t st);
 
 // kernel launches of one solve (its profiling events are one more)

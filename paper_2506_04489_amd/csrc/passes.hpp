@@ -140,6 +140,8 @@ struct Chunk {
     int tile0;      // first row tile of the chunk
     int ntile;      // row tiles in the chunk
     int pa;         // k3 pitch of the chunk buffer A
+    int n2;         // points along i2 (rows k2 of A: 2 n2)
+    int n3;         // points along i3 (columns k3 <= n3 are valid)
 };
 
 template <int N>
@@ -161,7 +163,7 @@ k_y_fwd(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
     const int col = threadIdx.x % W, t = threadIdx.x / W;
     const int i1 = blockIdx.x / nsub, c = (blockIdx.x % nsub) * W + col;
     const int cg = ck.tile0 * LayoutTile<T>::W + c;
-    const bool valid = cg <= n;
+    const bool valid = cg <= ck.n3;
     const C *src = (const C *)jb.X + (size_t)i1 * n * P + cg;      // rows i2 of X
     C *dst = (C *)jb.A + a_index<N>(ck.pa, c, 0, i1);              // rows k2 of A
     C v[E::V];
@@ -191,17 +193,17 @@ k_x_fused(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
     const int nsub = ck.ntile * Cfg::SUB;
     const int g = blockIdx.x;
     const int pi = (g / 16) * 8 + (g % 8), side = (g % 16) / 8;
-    if (pi >= (n + 1) * nsub) return;               // uniform over the workgroup
+    if (pi >= (ck.n2 + 1) * nsub) return;           // uniform over the workgroup
     const int b = pi / nsub, sub = pi % nsub;
-    if (side && (b == 0 || b == n)) return;
+    if (side && (b == 0 || b == ck.n2)) return;
     const Job jb = jr.get();
-    const int k2 = side ? N - b : b;
+    const int k2 = side ? 2 * ck.n2 - b : b;        // rows k2 < 2 n2 of A per i1
     const int col = threadIdx.x % W, t = threadIdx.x / W;
     const int c = sub * W + col;
     const int cg = ck.tile0 * LayoutTile<T>::W + c;
-    const bool valid = cg <= n;
-    const C *src = (const C *)jb.A + a_index<N>(ck.pa, c, k2, 0);   // rows i1
-    const size_t step = (size_t)N * ck.pa;
+    const bool valid = cg <= ck.n3;
+    const C *src = (const C *)jb.A + (size_t)k2 * ck.pa + c;        // rows i1
+    const size_t step = (size_t)(2 * ck.n2) * ck.pa;
     const double *mrow = jb.mult + ((size_t)(b * (P / 8) + cg / 8) * (n + 1)) * 8 + (cg & 7);
     C v[EF::V];
     EF::for_inputs(v, t, [&](int pos, int r) -> C {
@@ -216,7 +218,7 @@ k_x_fused(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
     });
     strided_stages<EI, Cfg, W>(v, lds, t, col, tw);
     if constexpr (!FULL) {
-        C *dst = (C *)jb.A + a_index<N>(ck.pa, c, k2, 0);
+        C *dst = (C *)jb.A + (size_t)k2 * ck.pa + c;
         EI::for_outputs(v, t, [&](int pos, int r, C &val) {
             if (valid && r < EI::R(EI::S - 1) / 2) dst[pos * step] = val;
         });
@@ -244,7 +246,7 @@ k_y_inv(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
     const int col = threadIdx.x % W, t = threadIdx.x / W;
     const int i1 = blockIdx.x / nsub, c = (blockIdx.x % nsub) * W + col;
     const int cg = ck.tile0 * LayoutTile<T>::W + c;
-    const bool valid = cg <= n;
+    const bool valid = cg <= ck.n3;
     C v[E::V];
     if constexpr (!FULL) {
         const C *src = (const C *)jb.A + a_index<N>(ck.pa, c, 0, i1);   // rows k2
@@ -375,10 +377,14 @@ template <typename F> inline void with_threads(int tile, F &&f) {
 //   written and read back while it can still sit in the last-level cache.
 // Profiling: event i is recorded before launch i (and one after the last);
 // ev_pass[i] receives the pass (0..4) of launch i.
+// dm: points along i1, i2, i3; only the passes in `mask` (bit p: pass p)
+// run, each of them a transform of length N (a cube runs all five at one
+// N; otherwise each pass is launched at the length of its own axis: H1, H5
+// along i3, H2, H4 along i2, H3 along i1).
 template <typename T, int N>
 hipError_t passes_impl(const Job &one, const Job *table, int count, int P, int chunk_tiles, int i1_group,
                        const Shape &sh, bool full, const void *tw64, hipEvent_t *ev,
-                       int *ev_pass, int nev, hipStream_t st) {
+                       int *ev_pass, int nev, const Dims &dm, int mask, hipStream_t st) {
     constexpr int n = N / 2;
     constexpr int LW = LayoutTile<T>::W;
     const Twiddle<T> tw = twiddle_of<T>(tw64);
@@ -390,7 +396,7 @@ hipError_t passes_impl(const Job &one, const Job *table, int count, int P, int c
         }
         ++launch;
     };
-    const int ntile = ceil_div(n + 1, LW);
+    const int ntile = ceil_div(dm.n3 + 1, LW);
     const int y = count;
     if (full) {
         // uncropped variant (one chunk, default shape): A2 and Y2 (N x N x P,
@@ -398,7 +404,7 @@ hipError_t passes_impl(const Job &one, const Job *table, int count, int P, int c
         using SC = StridedCfg<T, N, 0, LW, 0, false>;
         using LC = LineCfg<T, N, 0, 256>;
         const JobRef jr{one, table};
-        const Chunk ck{0, ntile, ntile * LW};
+        const Chunk ck{0, ntile, ntile * LW, n, n};
         hipLaunchKernelGGL((k_z_r2c<T, N, 0, 256>), dim3(ceil_div(n * n / 2, LC::Q), y), dim3(LC::THREADS), 0, st,
                            jr, n * n / 2, P, tw);
         hipLaunchKernelGGL((k_y_fwd<T, N, 0, LW, 0, false>), dim3(n * ntile, y), dim3(SC::THREADS), 0, st, jr, ck, P, tw);
@@ -440,7 +446,7 @@ hipError_t passes_impl(const Job &one, const Job *table, int count, int P, int c
                 constexpr bool HF = decltype(w)::HF;
                 using SC = StridedCfg<T, N, PV, W, XC, HF>;
                 hipLaunchKernelGGL((k_x_fused<T, N, PV, W, XC, HF, false>),
-                                   dim3(ceil_div((long)(n + 1) * ck.ntile * SC::SUB, 8) * 16, y), dim3(SC::THREADS),
+                                   dim3(ceil_div((long)(ck.n2 + 1) * ck.ntile * SC::SUB, 8) * 16, y), dim3(SC::THREADS),
                                    0, st, jr, ck, P, tw);
             });
         });
@@ -469,54 +475,62 @@ hipError_t passes_impl(const Job &one, const Job *table, int count, int P, int c
     };
     const int ct = chunk_tiles > 0 ? std::min(chunk_tiles, ntile) : ntile;
     const int nchunks = ceil_div(ntile, ct);
-    const int G = (table == nullptr && nchunks == 1 && i1_group > 0 && i1_group < n) ? i1_group : n;
+    const int n1 = dm.n1, n2 = dm.n2, n3 = dm.n3;
+    const int G = (table == nullptr && nchunks == 1 && i1_group > 0 && i1_group < n1) ? i1_group : n1;
     const int PA = ct * LW;
+    auto on = [&](int pass) { return (mask >> pass) & 1; };
     // H1 (+ H2 when grouped) per i1 group
-    for (int g0 = 0; g0 < n; g0 += G) {
-        const int gs = std::min(G, n - g0);
+    for (int g0 = 0; g0 < n1 && (on(0) || (G < n1 && on(1))); g0 += G) {
+        const int gs = std::min(G, n1 - g0);
         Job j = one;
         if (!table) {
-            j.rho = (const T *)one.rho + (size_t)g0 * n * n;
-            j.A = (cplx<T> *)one.A + (size_t)g0 * N * PA;
+            j.rho = (const T *)one.rho + (size_t)g0 * n2 * n3;
+            j.A = (cplx<T> *)one.A + (size_t)g0 * (2 * n2) * PA;
         }
         const JobRef jr{j, table};
-        mark(0);
-        h1(jr, gs * n / 2);
-        if (G < n) {
+        if (on(0)) {
+            mark(0);
+            h1(jr, gs * n2 / 2);
+        }
+        if (G < n1 && on(1)) {
             mark(1);
-            h2(jr, Chunk{0, ntile, PA}, gs);
+            h2(jr, Chunk{0, ntile, PA, n2, n3}, gs);
         }
     }
     const JobRef jr{one, table};
     for (int ch = 0; ch < nchunks; ++ch) {
         const int t0 = ch * ct, nt = std::min(ct, ntile - t0);
-        const Chunk ck{t0, nt, PA};
-        if (G == n) {
+        const Chunk ck{t0, nt, PA, n2, n3};
+        if (G == n1 && on(1)) {
             mark(1);
-            h2(jr, ck, n);
+            h2(jr, ck, n1);
         }
-        mark(2);
-        h3(jr, ck);
-        if (G == n) {
+        if (on(2)) {
+            mark(2);
+            h3(jr, ck);
+        }
+        if (G == n1 && on(3)) {
             mark(3);
-            h4(jr, ck, n);
+            h4(jr, ck, n1);
         }
     }
     // (H4 +) H5 per i1 group
-    for (int g0 = 0; g0 < n; g0 += G) {
-        const int gs = std::min(G, n - g0);
+    for (int g0 = 0; g0 < n1 && (on(4) || (G < n1 && on(3))); g0 += G) {
+        const int gs = std::min(G, n1 - g0);
         Job j = one;
         if (!table) {
-            j.u = (T *)one.u + (size_t)g0 * n * n;
-            j.A = (cplx<T> *)one.A + (size_t)g0 * N * PA;
+            j.u = (T *)one.u + (size_t)g0 * n2 * n3;
+            j.A = (cplx<T> *)one.A + (size_t)g0 * (2 * n2) * PA;
         }
         const JobRef jrg{j, table};
-        if (G < n) {
+        if (G < n1 && on(3)) {
             mark(3);
-            h4(jrg, Chunk{0, ntile, PA}, gs);
+            h4(jrg, Chunk{0, ntile, PA, n2, n3}, gs);
         }
-        mark(4);
-        h5(jrg, gs * n / 2);
+        if (on(4)) {
+            mark(4);
+            h5(jrg, gs * n2 / 2);
+        }
     }
     mark(-1);
     return hipGetLastError();
@@ -526,11 +540,11 @@ hipError_t passes_impl(const Job &one, const Job *table, int count, int P, int c
 // instantiation file covers a subset of the lengths (PSP_CASE per length)
 #define PSP_PASSES_SIGNATURE                                                                                  \
     (int N, const Job &one, const Job *table, int count, int P, int chunk_tiles, int i1_group, const Shape &sh, \
-     bool full, const void *tw64, hipEvent_t *ev, int *ev_pass, int nev, hipStream_t st)
+     bool full, const void *tw64, hipEvent_t *ev, int *ev_pass, int nev, const Dims &dm, int mask, hipStream_t st)
 #define PSP_CASE(T, NN)                                                                                        \
     case NN:                                                                                                   \
         return passes_impl<T, NN>(one, table, count, P, chunk_tiles, i1_group, sh, full, tw64, ev,     \
-                                  ev_pass, nev, st);
+                                  ev_pass, nev, dm, mask, st);
 
 // padded lengths up to 192 in the *_lo files, the rest in the *_hi files
 hipError_t passes_f64_lo PSP_PASSES_SIGNATURE;

@@ -15,7 +15,8 @@ namespace psp {
 //   Bmat[(s,0),c] = J0(c),                       Bmat[(s,1),c] = J2(c),
 // on v_mfma_f64_16x16x4_f64 tiles of 16 a x 16 c; the epilogue applies the
 // spectral Laplacian, m = scale (w1 a^2 + w2 b^2 + w3 c^2) Vhat with
-// w_p = (2 pi/L_p)^2 and scale = -1/N^3.
+// w_p = (2 pi/L_p)^2 and scale = -1/(N1 N2 N3).  Octant a <= n1, b <= n2,
+// c <= n3 in the layout [b][c/8][a][c%8] (P: the pitch of c).
 // Operand layout of the 16x16x4 FP64 MFMA (lane l): A[l%16][l/16],
 // B[l/16][l%16], D[l/16 + 4e][l%16] for e < 4.
 typedef double v4d __attribute__((ext_vector_type(4)));
@@ -35,22 +36,23 @@ struct SpecOps {
     double bv[SPEC_CT];
 };
 
-__device__ __forceinline__ void spec_load(SpecOps &o, int k0, int kq, int abase, int b, int cbase, int R, int n,
+__device__ __forceinline__ void spec_load(SpecOps &o, int k0, int kq, int abase, int b, int cbase, int R,
                                           const SpecTables &tb, const double *__restrict__ omega) {
-    const int n1 = n + 1;
     const int ks = k0 + kq, s = ks >> 1, ty = ks & 1;
     const bool live = s < R;
-    const size_t row = (size_t)(live ? s : 0) * n1;
-    const double *j0a = tb.J0[0] + row, *j2a = tb.J2[0] + row;
+    const size_t sr = (size_t)(live ? s : 0);
+    const double *j0a = tb.J0[0] + sr * (tb.n[0] + 1), *j2a = tb.J2[0] + sr * (tb.n[0] + 1);
     const double w = live ? omega[s] : 0.0;
-    const double j0b = tb.J0[1][row + b], j2b = tb.J2[1][row + b];
+    const size_t rb = sr * (tb.n[1] + 1) + b;
+    const double j0b = tb.J0[1][rb], j2b = tb.J2[1][rb];
 #pragma unroll
     for (int t = 0; t < SPEC_AT; ++t) {
         const int a = abase + t * 16;
         o.av[t] = 0.0;
-        if (live && a <= n) o.av[t] = ty == 0 ? w * (j2a[a] * j0b + j0a[a] * j2b) : w * (j0a[a] * j0b);
+        if (live && a <= tb.n[0]) o.av[t] = ty == 0 ? w * (j2a[a] * j0b + j0a[a] * j2b) : w * (j0a[a] * j0b);
     }
-    const double *jb = (ty == 0 ? tb.J0[2] : tb.J2[2]) + row;
+    const int n = tb.n[2];
+    const double *jb = (ty == 0 ? tb.J0[2] : tb.J2[2]) + sr * (n + 1);
 #pragma unroll
     for (int q = 0; q < SPEC_CT; ++q) {
         const int c = cbase + q * 16;
@@ -59,18 +61,18 @@ __device__ __forceinline__ void spec_load(SpecOps &o, int k0, int kq, int abase,
 }
 
 __global__ void __launch_bounds__(256)
-k_spectrum(SpecTables tb, const double *__restrict__ omega, int R, int n, int P, SpecScale sc,
+k_spectrum(SpecTables tb, const double *__restrict__ omega, int R, int P, SpecScale sc,
            double *__restrict__ mult) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int nt = (n + 1 + 15) / 16;
-    const int na = (nt + SPEC_AT - 1) / SPEC_AT, ng = (nt + SPEC_CT - 1) / SPEC_CT;
+    const int nA = tb.n[0], nB = tb.n[1], nC = tb.n[2];
+    const int na = ((nA + 1 + 15) / 16 + SPEC_AT - 1) / SPEC_AT, ng = ((nC + 1 + 15) / 16 + SPEC_CT - 1) / SPEC_CT;
     const long item = (long)blockIdx.x * 4 + wave;
-    if (item >= (long)(n + 1) * na * ng) return;    // no barriers in this kernel
+    if (item >= (long)(nB + 1) * na * ng) return;   // no barriers in this kernel
     const int b = (int)(item / (na * ng));
     const int rem = (int)(item % (na * ng));
     const int a0 = (rem / ng) * 16 * SPEC_AT, cgrp = (rem % ng) * SPEC_CT;
     const int row = lane & 15, kq = lane >> 4;
-    const int n1 = n + 1;
+    const int n1 = nA + 1;
     const int abase = a0 + row, cbase = cgrp * 16 + row;
     v4d acc[SPEC_AT][SPEC_CT];
 #pragma unroll
@@ -78,9 +80,9 @@ k_spectrum(SpecTables tb, const double *__restrict__ omega, int R, int n, int P,
 #pragma unroll
         for (int q = 0; q < SPEC_CT; ++q) acc[t][q] = v4d{0.0, 0.0, 0.0, 0.0};
     SpecOps cur, nxt;
-    spec_load(cur, 0, kq, abase, b, cbase, R, n, tb, omega);
+    spec_load(cur, 0, kq, abase, b, cbase, R, tb, omega);
     for (int k0 = 0; k0 < 2 * R; k0 += 4) {
-        if (k0 + 4 < 2 * R) spec_load(nxt, k0 + 4, kq, abase, b, cbase, R, n, tb, omega);
+        if (k0 + 4 < 2 * R) spec_load(nxt, k0 + 4, kq, abase, b, cbase, R, tb, omega);
 #pragma unroll
         for (int t = 0; t < SPEC_AT; ++t)
 #pragma unroll
@@ -96,7 +98,7 @@ k_spectrum(SpecTables tb, const double *__restrict__ omega, int R, int n, int P,
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int aa = a0 + t * 16 + kq + 4 * e;
-                if (aa <= n && cc <= n) {
+                if (aa <= nA && cc <= nC) {
                     const double k2 = sc.w[0] * ((double)aa * aa) + sc.w[1] * ((double)b * b) + sc.w[2] * ((double)cc * cc);
                     mult[((size_t)(b * (P / 8) + cc / 8) * n1 + aa) * 8 + (cc & 7)] = sc.scale * k2 * acc[t][q][e];
                 }
@@ -109,16 +111,16 @@ static inline int ceil_div_l(long a, long b) { return (int)((a + b - 1) / b); }
 
 hipError_t passes_f64_lo(int N, const Job &one, const Job *table, int count, int P, int chunk_tiles, int i1_group,
                          const Shape &sh, bool full, const void *tw64, hipEvent_t *ev,
-                         int *ev_pass, int nev, hipStream_t st);
+                         int *ev_pass, int nev, const Dims &dm, int mask, hipStream_t st);
 hipError_t passes_f64_hi(int N, const Job &one, const Job *table, int count, int P, int chunk_tiles, int i1_group,
                          const Shape &sh, bool full, const void *tw64, hipEvent_t *ev,
-                         int *ev_pass, int nev, hipStream_t st);
+                         int *ev_pass, int nev, const Dims &dm, int mask, hipStream_t st);
 hipError_t passes_f32_lo(int N, const Job &one, const Job *table, int count, int P, int chunk_tiles, int i1_group,
                          const Shape &sh, bool full, const void *tw64, hipEvent_t *ev,
-                         int *ev_pass, int nev, hipStream_t st);
+                         int *ev_pass, int nev, const Dims &dm, int mask, hipStream_t st);
 hipError_t passes_f32_hi(int N, const Job &one, const Job *table, int count, int P, int chunk_tiles, int i1_group,
                          const Shape &sh, bool full, const void *tw64, hipEvent_t *ev,
-                         int *ev_pass, int nev, hipStream_t st);
+                         int *ev_pass, int nev, const Dims &dm, int mask, hipStream_t st);
 
 // the instantiation holding padded length N
 static auto passes_for(bool f32, int N) {
@@ -139,9 +141,22 @@ int solve_launches(int n, bool f32, int chunk_tiles, int i1_group) {
 
 hipError_t launch_solve(const SolveArgs &s, hipStream_t st) {
     const Job one{s.rho, s.u, s.X, s.A, s.mult, s.A2, s.Y2};
-    auto f = passes_for(s.f32, 2 * s.n);
-    return f(2 * s.n, one, nullptr, 1, s.P, s.chunk_tiles, s.i1_group, s.shape, s.full, s.tw64, s.ev,
-             s.ev_pass, s.nev, st);
+    if (s.ns[0] == 0) {
+        auto f = passes_for(s.f32, 2 * s.n);
+        return f(2 * s.n, one, nullptr, 1, s.P, s.chunk_tiles, s.i1_group, s.shape, s.full, s.tw64, s.ev,
+                 s.ev_pass, s.nev, Dims{s.n, s.n, s.n}, 0x1f, st);
+    }
+    // one pass at a time at the padded length of its axis
+    static const int axis_of_pass[5] = {2, 1, 0, 1, 2};
+    const Dims dm{s.ns[0], s.ns[1], s.ns[2]};
+    for (int p = 0; p < 5; ++p) {
+        const int a = axis_of_pass[p], N = 2 * s.ns[a];
+        auto f = passes_for(s.f32, N);
+        const hipError_t e =
+            f(N, one, nullptr, 1, s.P, 0, 0, s.shape, false, s.tw_axis[a], nullptr, nullptr, 0, dm, 1 << p, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_group(int n, bool f32, const Shape &shape, const Job *table_dev, int count, const void *tw64,
@@ -149,15 +164,16 @@ hipError_t launch_group(int n, bool f32, const Shape &shape, const Job *table_de
     const Job none{};
     const int P = ((n + 1 + 15) / 16) * 16;
     auto f = passes_for(f32, 2 * n);
-    return f(2 * n, none, table_dev, count, P, 0, 0, shape, false, tw64, nullptr, nullptr, 0, st);
+    return f(2 * n, none, table_dev, count, P, 0, 0, shape, false, tw64, nullptr, nullptr, 0, Dims{n, n, n}, 0x1f,
+             st);
 }
 
-hipError_t launch_spectrum(const SpecTables &tb, const double *omega, int R, int n, int P, const SpecScale &sc,
+hipError_t launch_spectrum(const SpecTables &tb, const double *omega, int R, int P, const SpecScale &sc,
                            double *mult, hipStream_t st) {
-    const int nt = (n + 1 + 15) / 16;
-    const int na = (nt + SPEC_AT - 1) / SPEC_AT, ng = (nt + SPEC_CT - 1) / SPEC_CT;
-    const long items = (long)(n + 1) * na * ng;
-    hipLaunchKernelGGL(k_spectrum, dim3(ceil_div_l(items, 4)), dim3(256), 0, st, tb, omega, R, n, P, sc, mult);
+    const int na = ((tb.n[0] + 1 + 15) / 16 + SPEC_AT - 1) / SPEC_AT;
+    const int ng = ((tb.n[2] + 1 + 15) / 16 + SPEC_CT - 1) / SPEC_CT;
+    const long items = (long)(tb.n[1] + 1) * na * ng;
+    hipLaunchKernelGGL(k_spectrum, dim3(ceil_div_l(items, 4)), dim3(256), 0, st, tb, omega, R, P, sc, mult);
     return hipGetLastError();
 }
 

@@ -73,6 +73,7 @@ extern "C" {
 
 psp_status psp_plan_set_shape(psp_plan *p, const int *plan, const int *tile) {
     if (!p) return fail(PSP_EINVAL, "plan is NULL");
+    if (p->grid) return fail(PSP_EUNSUPPORTED, "launch shapes of a plan with unequal point counts come from the table");
     Shape s;
     psp_status rs = shape_from(p->n, plan, tile, &s);
     if (rs != PSP_OK) return rs;
@@ -110,6 +111,7 @@ psp_status psp_autotune(psp_plan *p, int reps, void *stream, int *best_plan, int
     if (!p) return fail(PSP_EINVAL, "plan is NULL");
     if (reps < 1 || reps > 1000) return fail(PSP_EINVAL, "reps must be in [1, 1000] (got %d)", reps);
     if (!p->precomputed) return fail(PSP_ESTATE, "autotune before psp_kernel_precompute");
+    if (p->grid) return fail(PSP_EUNSUPPORTED, "autotune a cube of each axis's size instead");
     {
         std::lock_guard<std::mutex> lk(p->mu);
         if (p->prof_cap > 0) return fail(PSP_ESTATE, "autotune while profiling");

@@ -27,6 +27,7 @@ SIGNATURES = {
     "psp_plan_create": (_i, [_i, _d, _i, _i, _P(_vp)]),
     "psp_plan_create_ex": (_i, [_i, _d, _i, _i, _d, _d, _P(_vp)]),
     "psp_plan_create_box": (_i, [_i, _P(_d), _i, _i, _d, _d, _P(_vp)]),
+    "psp_plan_create_grid": (_i, [_P(_i), _P(_d), _i, _i, _d, _d, _P(_vp)]),
     "psp_kernel_precompute": (_i, [_vp, _vp]),
     "psp_solve": (_i, [_vp, _vp, _vp, _vp]),
     "psp_solve_batched": (_i, [_i, _P(_vp), _P(_vp), _P(_vp), _vp]),
@@ -179,12 +180,31 @@ def _load_shipped_tuning():
 class Plan:
     """One (n, h, R, dtype) configuration: psp_plan_create[_ex] + helpers.
     h is one spacing, or three (one per axis: a rectangular box,
-    psp_plan_create_box)."""
+    psp_plan_create_box); n is one point count, or three (one per axis,
+    psp_plan_create_grid; rho is then n[0] x n[1] x n[2] and ``n`` holds
+    n[0])."""
 
-    def __init__(self, n: int, h, R: int, dtype="f64", eps: float = None, delta: float = None):
-        self.n, self.R = int(n), int(R)
+    def __init__(self, n, h, R: int, dtype="f64", eps: float = None, delta: float = None):
+        self.R = int(R)
         self.code = _dtype_code(dtype)
         handle = ctypes.c_void_p()
+        if np.ndim(n) > 0:
+            if len(list(n)) != 3:
+                raise ValueError("n must be one point count or three")
+            self.shape3 = tuple(int(v) for v in n)
+            self.n = self.shape3[0]
+            hl = [float(v) for v in (h if np.ndim(h) > 0 else (h, h, h))]
+            if len(hl) != 3:
+                raise ValueError("h must be one spacing or three")
+            self.h = tuple(hl)
+            ns = (ctypes.c_int * 3)(*self.shape3)
+            hs = (ctypes.c_double * 3)(*self.h)
+            _check(lib().psp_plan_create_grid(ns, hs, self.R, self.code, -1.0 if eps is None else float(eps),
+                                              -1.0 if delta is None else float(delta), ctypes.byref(handle)))
+            self._h = handle
+            return
+        self.n = int(n)
+        self.shape3 = (self.n,) * 3
         if np.ndim(h) > 0:
             if len(list(h)) != 3:
                 raise ValueError("h must be one spacing or three")
@@ -235,19 +255,17 @@ class Plan:
 
     def solve(self, rho, u=None, stream=None):
         import torch
-        n = self.n
-        self._check_tensor(rho, (n, n, n))
+        self._check_tensor(rho, self.shape3)
         if u is None:
             u = torch.empty_like(rho)
-        self._check_tensor(u, (n, n, n))
+        self._check_tensor(u, self.shape3)
         _check(lib().psp_solve(self._h, rho.data_ptr(), u.data_ptr(), _stream_ptr(stream)))
         return u
 
     def solve_padded_debug(self, rho, stream=None):
         import torch
-        n = self.n
-        self._check_tensor(rho, (n, n, n))
-        up = torch.empty((2 * n,) * 3, dtype=rho.dtype, device=rho.device)
+        self._check_tensor(rho, self.shape3)
+        up = torch.empty(tuple(2 * v for v in self.shape3), dtype=rho.dtype, device=rho.device)
         _check(lib().psp_solve_padded_debug(self._h, rho.data_ptr(), up.data_ptr(), _stream_ptr(stream)))
         return up
 
@@ -264,7 +282,7 @@ class Plan:
         return J0, J2
 
     def multiplier(self):
-        m = np.empty((self.n + 1,) * 3)
+        m = np.empty(tuple(v + 1 for v in self.shape3))
         _check(lib().psp_plan_get_multiplier(self._h, m.ctypes.data_as(_P(_d))))
         return m
 
@@ -331,8 +349,8 @@ def solve_batched(plans: Sequence[Plan], rhos, us, stream=None):
     if not (len(rhos) == k and len(us) == k):
         raise ValueError("plans, rhos and us must have the same length")
     for p, r, u in zip(plans, rhos, us):
-        p._check_tensor(r, (p.n,) * 3)
-        p._check_tensor(u, (p.n,) * 3)
+        p._check_tensor(r, p.shape3)
+        p._check_tensor(u, p.shape3)
     ph = (ctypes.c_void_p * k)(*[p.handle.value for p in plans])
     rp = (ctypes.c_void_p * k)(*[r.data_ptr() for r in rhos])
     up = (ctypes.c_void_p * k)(*[u.data_ptr() for u in us])
@@ -349,8 +367,8 @@ class Graph:
 
     @classmethod
     def capture(cls, plan: "Plan", rho, u, stream=None):
-        plan._check_tensor(rho, (plan.n,) * 3)
-        plan._check_tensor(u, (plan.n,) * 3)
+        plan._check_tensor(rho, plan.shape3)
+        plan._check_tensor(u, plan.shape3)
         h = ctypes.c_void_p()
         _check(lib().psp_graph_capture(plan.handle, rho.data_ptr(), u.data_ptr(), _stream_ptr(stream),
                                        ctypes.byref(h)))
@@ -360,8 +378,8 @@ class Graph:
     def capture_batched(cls, plans, rhos, us, stream=None):
         k = len(plans)
         for p, r, u in zip(plans, rhos, us):
-            p._check_tensor(r, (p.n,) * 3)
-            p._check_tensor(u, (p.n,) * 3)
+            p._check_tensor(r, p.shape3)
+            p._check_tensor(u, p.shape3)
         ph = (ctypes.c_void_p * k)(*[p.handle.value for p in plans])
         rp = (ctypes.c_void_p * k)(*[r.data_ptr() for r in rhos])
         up = (ctypes.c_void_p * k)(*[u.data_ptr() for u in us])

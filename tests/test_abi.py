@@ -86,6 +86,41 @@ def test_box_plan_create_null_and_defaults():
     assert all(np.array_equal(x, y) for x, y in zip(q.gs(), c.gs()))
 
 
+def test_grid_plan_create_validation_and_layout():
+    lib = B.lib()
+    out = ctypes.c_void_p()
+    h3 = (ctypes.c_double * 3)(0.1, 0.1, 0.1)
+    assert B.STATUS[lib.psp_plan_create_grid(None, h3, 40, 0, -1.0, -1.0, ctypes.byref(out))] == "PSP_EINVAL"
+    for bad in [(32, 31, 32), (32, 10, 32), (32, 32, 512), (2, 32, 32)]:
+        with pytest.raises(B.PspError) as ei:
+            B.Plan(bad, 0.1, 40)
+        assert B.STATUS[ei.value.status] == "PSP_EUNSUPPORTED", bad
+    ns, hs = (16, 24, 32), (0.1, 0.2, 0.3)
+    p = B.Plan(ns, hs, 40)
+    assert p.shape3 == ns and p.n == 16
+    eps, delta = O.default_eps_delta(ns, hs)
+    wo, ao = O.gs_weights(40, eps, delta)
+    w, a = p.gs()
+    assert np.allclose(w, wo, rtol=1e-14, atol=0) and np.allclose(a, ao, rtol=1e-14, atol=0)
+    # every pass takes the tuned shape of a cube of its own axis's size
+    plan, tile = p.shape()
+    for q, m in enumerate((32, 24, 16, 24, 32)):
+        tp, tt = B.tuning_get(m, "f64")
+        assert (plan[q], tile[q]) == (tp[q], tt[q]), q
+    pitch = lambda m: ((m + 1 + 15) // 16) * 16
+    cols = lambda m: ((m + 1 + 7) // 8) * 8
+    assert p.workspace_bytes() == 16 * (pitch(32) * 16 * 24 + cols(32) * 16 * 2 * 24)
+    assert p.spectrum_bytes() == 8 * 17 * 25 * pitch(32)
+    # equal counts: the box plan
+    q, c = B.Plan((16, 16, 16), hs, 40), B.Plan(16, hs, 40)
+    assert all(np.array_equal(x, y) for x, y in zip(q.gs(), c.gs()))
+    assert q.shape() == c.shape()
+    for call in (lambda: p.set_shape([0] * 5, [0] * 5), lambda: p.set_tuning(2, 0), lambda: p.profile_enable(1)):
+        with pytest.raises(B.PspError) as ei:
+            call()
+        assert B.STATUS[ei.value.status] == "PSP_EUNSUPPORTED"
+
+
 def test_error_strings():
     lib = B.lib()
     for code in B.STATUS:
