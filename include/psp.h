@@ -15,8 +15,9 @@
  *   The operator is translation invariant, so no grid origin is needed.
  *
  * Conventions shared by every entry point:
- *   - Arrays rho and u are C-ordered n*n*n, element [i1][i2][i3] at
- *     (i1*n + i2)*n + i3, i3 contiguous, in the plan's dtype (double for
+ *   - Arrays rho and u are C-ordered n*n*n (n1*n2*n3 for a plan from
+ *     psp_plan_create_grid), element [i1][i2][i3] at (i1*n2 + i2)*n3 + i3,
+ *     i3 contiguous, in the plan's dtype (double for
  *     PSP_F64, float for PSP_F32), in device memory of the current HIP
  *     device, at least 16-byte aligned.  The caller owns them.
  *   - `stream` is a hipStream_t passed as void*; NULL means the null stream.
