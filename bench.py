@@ -352,10 +352,13 @@ BOX_ROWS = (("Table 4", "gauss", 0.2, ((-3, 2), (-2, 3.5), (-1, 5))),
 
 def _box_density(torch, family, par, box, N):
     """(rho, u*) of the paper's rectangular-box benchmarks at the box centre
-    on its node grid (N points per side including both ends), on the GPU."""
+    on its node grid (N points per side including both ends; N: one count or
+    one per axis), on the GPU."""
     import math
-    hs = tuple((b - a) / (N - 1) for a, b in box)
-    ax = [a + h * torch.arange(N, dtype=torch.float64, device="cuda") - 0.5 * (a + b) for (a, b), h in zip(box, hs)]
+    Ns = tuple(N) if isinstance(N, (tuple, list)) else (N, N, N)
+    hs = tuple((b - a) / (m - 1) for (a, b), m in zip(box, Ns))
+    ax = [a + h * torch.arange(m, dtype=torch.float64, device="cuda") - 0.5 * (a + b)
+          for (a, b), h, m in zip(box, hs, Ns)]
     X, Y, Z = ax[0][:, None, None], ax[1][None, :, None], ax[2][None, None, :]
     if family == "gauss":
         s = par
@@ -380,32 +383,37 @@ def _box_density(torch, family, par, box, N):
     return hs, rho.contiguous(), u
 
 
+GRID_ROWS = (("grid", "gauss", 0.2, ((-2, 2), (-2, 2), (-2, 2)), (64, 96, 128)),
+             ("grid", "gauss", 0.2, ((-2, 2), (-2, 2), (-2, 2)), (128, 192, 256)))
+
+
 def bench_box(torch, B, sizes=(64, 128), R=461, reps=20):
     """The paper's rectangular-box benchmarks (Section 3, Tables 4, 6, 8):
     E against the exact potential, set-up time (plan creation + precompute)
-    and solve time, per table row and N."""
+    and solve time, per table row and N; then the Gaussian on grids with a
+    different point count per axis."""
     out = []
-    for tab, fam, par, box in BOX_ROWS:
-        for N in sizes:
-            hs, rho, u_star = _box_density(torch, fam, par, box, N)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            p = B.Plan(N, hs, R).precompute()
-            torch.cuda.synchronize()
-            setup_s = time.perf_counter() - t0
-            u = p.solve(rho)
-            for _ in range(3):
-                p.solve(rho, u)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(reps):
-                p.solve(rho, u)
-            torch.cuda.synchronize()
-            E = float((u - u_star).abs().max() / u_star.abs().max())
-            out.append({"table": tab, "family": fam, "param": par, "N": N, "E": float("%.4g" % E),
-                        "setup_s": round(setup_s, 4),
-                        "solve_ms": round(1e3 * (time.perf_counter() - t0) / reps, 4)})
-            del p
+    rows = [(t, f, p, b, N) for t, f, p, b in BOX_ROWS for N in sizes] + list(GRID_ROWS)
+    for tab, fam, par, box, N in rows:
+        hs, rho, u_star = _box_density(torch, fam, par, box, N)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p = B.Plan(N, hs, R).precompute()
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t0
+        u = p.solve(rho)
+        for _ in range(3):
+            p.solve(rho, u)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            p.solve(rho, u)
+        torch.cuda.synchronize()
+        E = float((u - u_star).abs().max() / u_star.abs().max())
+        out.append({"table": tab, "family": fam, "param": par, "N": N, "E": float("%.4g" % E),
+                    "setup_s": round(setup_s, 4),
+                    "solve_ms": round(1e3 * (time.perf_counter() - t0) / reps, 4)})
+        del p
     return out
 
 
