@@ -517,6 +517,10 @@ def main():
         "paper_context": "MATLAB on i7-8565U, FP64, 128^3: 0.536 s/solve (Table 1); no 256^3 or GPU number",
     }
     out["latency"] = solve_latency(torch, B, res["plan"], res["rho"], res["u"].clone(), res["stream"])
+    pk = B.device_peaks()
+    out["peaks"] = {"hbm_spec_GBps": HBM_PEAK_GBS, "copy_measured_GBps": round(pk["copy_GBps"], 1),
+                    "fp64_mfma_spec_TFLOPs": 78.6, "fp64_mfma_measured_TFLOPs": round(pk["fp64_mfma_TFLOPs"], 1)}
+    out["roofline"]["frac_of_measured_copy"] = round(achieved / pk["copy_GBps"], 4)
     tr = measured_traffic() if n == 256 else None
     if tr is not None and PASS_NAMES[dom] in tr.get("passes", {}):
         out["roofline"]["traffic"] = tr["passes"][PASS_NAMES[dom]]["bytes"]

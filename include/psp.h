@@ -233,6 +233,15 @@ psp_status psp_plan_spectrum_bytes(const psp_plan *p, size_t *bytes);
 psp_status psp_profile_enable(psp_plan *p, int max_solves);
 psp_status psp_profile_read(psp_plan *p, int *count, double *pass_ms);
 
+/* Measured ceilings of the current device, for rooflines: the rate of a
+ * streaming copy from buf_a to buf_b (bytes each, device memory owned by
+ * the caller, >= 1 MiB, a multiple of 16; counts bytes read plus written)
+ * in GB/s, and the FP64 matrix-core rate of back-to-back independent
+ * 16x16x4 FP64 MFMA instructions in TFLOP/s; best of 5 timed runs each on
+ * `stream`.  Allocates nothing; synchronises `stream`; overwrites buf_b. */
+psp_status psp_device_peaks(void *buf_a, void *buf_b, size_t bytes, void *stream,
+                            double *copy_gbps, double *fp64_mfma_tflops);
+
 void psp_plan_destroy(psp_plan *p);
 
 /* ---- captured solves (hipGraph) -------------------------------------------

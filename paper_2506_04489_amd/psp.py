@@ -28,6 +28,7 @@ SIGNATURES = {
     "psp_plan_create_ex": (_i, [_i, _d, _i, _i, _d, _d, _P(_vp)]),
     "psp_plan_create_box": (_i, [_i, _P(_d), _i, _i, _d, _d, _P(_vp)]),
     "psp_plan_create_grid": (_i, [_P(_i), _P(_d), _i, _i, _d, _d, _P(_vp)]),
+    "psp_device_peaks": (_i, [_vp, _vp, _sz, _vp, _P(_d), _P(_d)]),
     "psp_kernel_precompute": (_i, [_vp, _vp]),
     "psp_solve": (_i, [_vp, _vp, _vp, _vp]),
     "psp_solve_batched": (_i, [_i, _P(_vp), _P(_vp), _P(_vp), _vp]),
@@ -126,6 +127,20 @@ def _ints5(v):
     if len(v) != 5:
         raise ValueError("a shape has 5 entries (passes H1..H5)")
     return (ctypes.c_int * 5)(*v)
+
+
+def device_peaks(nbytes: int = 1 << 30, stream=None):
+    """psp_device_peaks on two scratch tensors of nbytes each: the measured
+    streaming-copy rate (GB/s, read plus write) and FP64 MFMA rate
+    (TFLOP/s) of the current device."""
+    import torch
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    gbps, tflops = ctypes.c_double(), ctypes.c_double()
+    torch.cuda.synchronize()
+    _check(lib().psp_device_peaks(a.data_ptr(), b.data_ptr(), nbytes, _stream_ptr(stream), ctypes.byref(gbps),
+                                  ctypes.byref(tflops)))
+    return {"copy_GBps": gbps.value, "fp64_mfma_TFLOPs": tflops.value}
 
 
 def debug_guards(enable: bool):
