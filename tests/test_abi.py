@@ -265,3 +265,11 @@ def test_gauss_kronrod_constants_are_exact():
     # degree 24 is not integrated exactly (the rule is not of higher degree)
     got = mp.fsum(wi * xi ** 24 for wi, xi in zip(wts, nodes))
     assert abs(got - mp.mpf(2) / 25) > mp.mpf("1e-12")
+
+
+def test_device_peaks_rejects_bad_arguments():
+    lib = B.lib()
+    g, t = ctypes.c_double(), ctypes.c_double()
+    assert B.STATUS[lib.psp_device_peaks(None, None, 1 << 20, None, ctypes.byref(g), ctypes.byref(t))] == "PSP_EINVAL"
+    buf = ctypes.c_void_p(4096)          # never dereferenced: the size check comes first
+    assert B.STATUS[lib.psp_device_peaks(buf, buf, 1000, None, ctypes.byref(g), ctypes.byref(t))] == "PSP_EINVAL"

@@ -104,3 +104,10 @@ def test_tables_deterministic_and_precompute_consistent():
     p.precompute()
     c0, c2 = p.tables()
     assert np.array_equal(a0, c0) and np.array_equal(a2, c2)
+
+
+def test_device_peaks_are_plausible():
+    pk = B.device_peaks(1 << 28)
+    print("measured peaks", pk)
+    assert 500 < pk["copy_GBps"] < 8000          # below the 8 TB/s HBM3E spec
+    assert 5 < pk["fp64_mfma_TFLOPs"] < 78.6     # below the FP64 MFMA spec
