@@ -34,7 +34,10 @@ def test_grid_multiplier(ns):
 
 @pytest.mark.parametrize("ns,dtype,tol", [((16, 24, 32), "f64", 1e-12), ((32, 12, 8), "f64", 1e-12),
                                           ((6, 48, 16), "f64", 1e-12), ((48, 32, 64), "f64", 1e-12),
-                                          ((16, 24, 32), "f32", 1e-5)])
+                                          ((16, 24, 32), "f32", 1e-5),
+                                          # extreme aspect ratios: the smallest and largest counts together
+                                          ((4, 8, 384), "f64", 1e-12), ((384, 4, 6), "f64", 1e-12),
+                                          ((8, 384, 4), "f32", 1e-5)])
 def test_grid_random_density_parity(ns, dtype, tol):
     import torch
     rho = np.random.default_rng(sum(ns)).standard_normal(ns)
