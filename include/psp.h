@@ -12,6 +12,10 @@
  *   of the biharmonic kernel |y|/(8 pi) over the box [-L/2, L/2]^3
  *   (eq. gs_x, Gten0, Gten_sep); an inverse DFT (no scaling) follows and
  *   the first n points of every axis are returned as u.
+ *   On a rectangular box or grid (psp_plan_create_box, psp_plan_create_grid)
+ *   axis p has its own n_p, h_p and L_p = 2 n_p h_p: |k|^2 / L^2 becomes
+ *   sum_p k_p^2 / L_p^2, (2n)^3 becomes 8 n_1 n_2 n_3, and the kernel is
+ *   truncated to the box of sides L_p.
  *   The operator is translation invariant, so no grid origin is needed.
  *
  * Conventions shared by every entry point:
@@ -50,7 +54,8 @@ typedef enum {
     PSP_OK = 0,
     PSP_EINVAL = -1,        /* bad argument (h <= 0, R < 1, NULL pointer ...) */
     PSP_ENOMEM = -2,        /* device or host allocation failed, or over budget */
-    PSP_EUNSUPPORTED = -3,  /* n not one of the built sizes (see psp_plan_create) */
+    PSP_EUNSUPPORTED = -3,  /* n not one of the built sizes (see psp_plan_create),
+                               or an entry point a grid plan cannot use */
     PSP_ESTATE = -4,        /* call order (solve before precompute ...) */
     PSP_EHIP = -5,          /* a HIP runtime call failed */
     PSP_EBUSY = -6,         /* server queue full; request already on the device */
