@@ -437,11 +437,21 @@ def cpu_baseline(n: int, budget_s: float = 12.0):
             break
     per_pencil = el / (calls * batch)
     solve_s = per_pencil * 6 * N * N
+    # beside it, one whole oracle solve of the small configuration (n = 32
+    # Gaussian, R = 40: set-up and solve), timed end to end
+    h32 = 2.0 / 32
+    xs = -1.0 + h32 * np.arange(32)
+    r2 = xs[:, None, None] ** 2 + xs[None, :, None] ** 2 + xs[None, None, :] ** 2
+    t0 = time.perf_counter()
+    O.solve(np.exp(-r2 / 0.15 ** 2), h32, 40)
+    n32_s = time.perf_counter() - t0
     return {"value": 1.0 / solve_s, "unit": "solves/s", "cores": 1, "kind": "oracle",
             "sample": "%d calls of the oracle's naive radix-2/3 FFT on %d length-%d pencils (%.1f s); "
                       "one n=%d solve needs 6*%d^2 such pencil transforms; pad/multiply/crop not timed"
                       % (calls, batch, N, el, n, N),
-            "est_solve_s": solve_s}
+            "est_solve_s": solve_s, "n32_whole_solve_s": round(n32_s, 3),
+            "host_cpus": os.cpu_count(),
+            "threads_note": "the oracle's FFT is a Python recursion over numpy vector operations on one core"}
 
 
 def main():
