@@ -46,8 +46,8 @@ typedef struct psp_plan psp_plan;       /* opaque, library owned */
 typedef struct psp_server psp_server;   /* opaque, library owned */
 
 /* Precision tier.  PSP_F32 keeps the kernel spectrum, Gaussian-sum data and
- * the multiply in FP64 and runs the FFT passes on FP32 data; each twiddle
- * product is formed in FP64 and rounded to FP32. */
+ * the multiply in FP64 and runs the FFT passes in FP32 (twiddles formed in
+ * FP64 and rounded once to FP32). */
 typedef enum { PSP_F64 = 0, PSP_F32 = 1 } psp_dtype;
 
 typedef enum {

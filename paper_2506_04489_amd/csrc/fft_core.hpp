@@ -44,10 +44,9 @@ __device__ __forceinline__ float fmadd(float a, float b, float c) { return __bui
 // radix-R butterfly loads the one entry W^m and forms the powers W^{m r},
 // r = 1..R-1, by a multiplication tree of depth <= 4 (a few ulp of FP64):
 // one load instead of R-1 (wave-wide loads cost L1 return bandwidth per
-// lane).  The FP32 tier applies them in FP64 too and rounds each product
-// once to FP32: without packed FP32 instructions an FP64 multiply-add costs
-// the same issue slot as an FP32 one, and the twiddle then adds no error
-// beyond that rounding.
+// lane).  The FP32 tier forms the powers in FP64 too (an FP32 tree would
+// add its own rounding at every level), rounds each once to FP32 and
+// multiplies in FP32.
 __device__ __forceinline__ double2 cmul64(double2 a, double2 t) {
     return double2{fmadd(a.x, t.x, -(a.y * t.y)), fmadd(a.x, t.y, a.y * t.x)};
 }
@@ -84,8 +83,8 @@ template <typename T> struct Twiddle {
             if constexpr (sizeof(T) == 8) {
                 v[r] = cmul64_dir<INV>(v[r], p[r]);
             } else {
-                const double2 x = cmul64_dir<INV>(double2{(double)v[r].x, (double)v[r].y}, p[r]);
-                v[r] = float2{(float)x.x, (float)x.y};
+                const float tx = (float)p[r].x, ty = INV ? -(float)p[r].y : (float)p[r].y;
+                v[r] = float2{fmadd(v[r].x, tx, -(v[r].y * ty)), fmadd(v[r].x, ty, v[r].y * tx)};
             }
         }
     }
