@@ -139,7 +139,8 @@ psp_status psp_solve_batched(int count, psp_plan *const *plans,
 psp_status psp_set_batch_mode(int mode);
 
 /* Test hook: the uncropped (2n)^3 result of Algorithm 2 (real part), C-order
- * with side 2n, dtype of the plan. */
+ * with side 2n, dtype of the plan.  PSP_EUNSUPPORTED for grids with unequal
+ * counts and for plans whose workspace psp_plan_set_tuning shrank. */
 psp_status psp_solve_padded_debug(psp_plan *p, const void *rho_dev, void *upad_dev,
                                   void *stream);
 

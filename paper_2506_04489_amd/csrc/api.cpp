@@ -107,13 +107,14 @@ static hipError_t guarded_malloc(size_t bytes, bool guard, void **base, void **b
 }
 
 psp_status alloc_workspace(int n, bool f32, int chunk_tiles, Workspace *w, int i1_group) {
-    const size_t c = f32 ? 8 : 16, P = (size_t)pitch_for(n), PA = (size_t)chunk_pitch(n, f32, chunk_tiles);
+    const size_t c = f32 ? 8 : 16, P = (size_t)pitch_for(n);
+    const size_t plane = a_plane(n, n, chunk_pitch(n, f32, chunk_tiles), (int)c);
     const size_t xs = (size_t)x_slabs(n, f32, chunk_tiles, i1_group);
     const bool guard = guards_enabled();
     w->bytes = workspace_bytes(n, f32, chunk_tiles, i1_group);
     w->X = w->A = w->X_base = w->A_base = nullptr;
     w->X_bytes = c * P * xs * n;
-    w->A_bytes = c * PA * n * 2 * n;
+    w->A_bytes = c * plane * n;
     if (guarded_malloc(w->X_bytes, guard, &w->X_base, &w->X) != hipSuccess) {
         (void)hipGetLastError();
         free_workspace(w);
@@ -128,12 +129,13 @@ psp_status alloc_workspace(int n, bool f32, int chunk_tiles, Workspace *w, int i
 }
 
 psp_status alloc_workspace_dims(const Dims &d, bool f32, Workspace *w) {
-    const size_t c = f32 ? 8 : 16, P = (size_t)pitch_for(d.n3), PA = (size_t)chunk_pitch(d.n3, f32, 0);
+    const size_t c = f32 ? 8 : 16, P = (size_t)pitch_for(d.n3);
+    const size_t plane = a_plane(d.n1, d.n2, chunk_pitch(d.n3, f32, 0), (int)c);
     const bool guard = guards_enabled();
     w->bytes = workspace_bytes_dims(d, f32);
     w->X = w->A = w->X_base = w->A_base = nullptr;
     w->X_bytes = c * P * (size_t)d.n1 * d.n2;
-    w->A_bytes = c * PA * (size_t)d.n1 * 2 * d.n2;
+    w->A_bytes = c * plane * (size_t)d.n1;
     if (guarded_malloc(w->X_bytes, guard, &w->X_base, &w->X) != hipSuccess ||
         guarded_malloc(w->A_bytes, guard, &w->A_base, &w->A) != hipSuccess) {
         (void)hipGetLastError();
@@ -621,6 +623,10 @@ psp_status psp_solve_padded_debug(psp_plan *p, const void *rho_dev, void *upad_d
     if (!p || !rho_dev || !upad_dev) return fail(PSP_EINVAL, "NULL argument");
     if (!p->precomputed) return fail(PSP_ESTATE, "psp_solve_padded_debug before psp_kernel_precompute");
     if (p->grid) return fail(PSP_EUNSUPPORTED, "the uncropped output needs equal point counts per axis");
+    // the uncropped passes run over one chunk of all k3 tiles and every i1
+    // slab, which a workspace shrunk by psp_plan_set_tuning cannot hold
+    if (p->chunk_tiles != 0 || p->i1_group != 0)
+        return fail(PSP_EUNSUPPORTED, "the uncropped output needs the default tuning (no k3 chunks, no i1 groups)");
     psp_status st = current_device_of(p);
     if (st != PSP_OK) return st;
     hipStream_t s = (hipStream_t)stream;

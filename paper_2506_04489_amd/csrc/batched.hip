@@ -107,6 +107,7 @@ void build_batch_image(const std::vector<BatchMember> &m, bool f32, unsigned cha
         pj.N = 2 * b.n;
         pj.P = pitch_for(b.n);
         pj.pa = ((b.n + 1 + LW - 1) / LW) * LW;   // one chunk holding all tiles
+        pj.plane = (long long)a_plane(b.n, b.n, pj.pa, f32 ? 8 : 16);
         for (int p = 0; p < kPasses; ++p) pj.pv[p] = b.shape.plan[p];
     }
     std::memcpy(host.data() + img->hdr_off, &hdr, sizeof(hdr));

@@ -79,16 +79,18 @@ inline int x_slabs(int n, bool f32, int chunk_tiles, int i1_group) {
 }
 inline size_t workspace_bytes(int n, bool f32, int chunk_tiles, int i1_group = 0) {
     const size_t c = f32 ? 8 : 16;
-    const size_t P = (size_t)pitch_for(n), PA = (size_t)chunk_pitch(n, f32, chunk_tiles);
-    return c * (P * (size_t)x_slabs(n, f32, chunk_tiles, i1_group) * n + PA * (size_t)n * 2 * n);
+    const size_t P = (size_t)pitch_for(n);
+    const size_t plane = a_plane(n, n, chunk_pitch(n, f32, chunk_tiles), (int)c);
+    return c * (P * (size_t)x_slabs(n, f32, chunk_tiles, i1_group) * n + plane * (size_t)n);
 }
 psp_status alloc_workspace(int n, bool f32, int chunk_tiles, Workspace *w, int i1_group = 0);
 // unequal point counts per axis: X holds n1 x n2 rows of pitch P(n3), A the
-// one chunk n1 x 2 n2 x pitch(n3)
+// one chunk: n1 planes of 2 n2 rows of round_up(n3 + 1, tile) columns
 inline size_t workspace_bytes_dims(const Dims &d, bool f32) {
     const size_t c = f32 ? 8 : 16;
-    const size_t P = (size_t)pitch_for(d.n3), PA = (size_t)chunk_pitch(d.n3, f32, 0);
-    return c * (P * (size_t)d.n1 * d.n2 + PA * (size_t)d.n1 * 2 * d.n2);
+    const size_t P = (size_t)pitch_for(d.n3);
+    const size_t plane = a_plane(d.n1, d.n2, chunk_pitch(d.n3, f32, 0), (int)c);
+    return c * (P * (size_t)d.n1 * d.n2 + plane * (size_t)d.n1);
 }
 psp_status alloc_workspace_dims(const Dims &d, bool f32, Workspace *w);
 

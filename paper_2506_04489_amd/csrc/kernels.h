@@ -37,6 +37,20 @@ struct Dims {
     int n1, n2, n3;
 };
 
+// i1 pitch, in elements of `elem` bytes, of the padded intermediate A of n1
+// planes whose 2 n2 rows k2 hold `pa` columns (pa * elem a multiple of 128
+// bytes).  The fused i1 pass reads each column at this stride; at a multiple
+// of 4 KB those reads fall on too few HBM channels (measured: the pass's
+// access pattern at n = 256 streams 10% faster at 15 mod 32 lines of 128
+// bytes than at 0 mod 32).  So a buffer larger than 128 MiB gets its pitch
+// rounded up to 15 mod 32 lines; a smaller one is mostly served by the
+// last-level cache and keeps 2 n2 pa (padding measured no faster there).
+__host__ __device__ constexpr size_t a_plane(int n1, int n2, int pa, int elem) {
+    const size_t lines = (size_t)2 * n2 * pa * elem / 128;
+    if (lines * 128 * (size_t)n1 <= ((size_t)128 << 20)) return lines * 128 / elem;
+    return (lines + (47 - lines % 32) % 32) * 128 / elem;
+}
+
 struct Shape {
     int plan[kPasses] = {0, 0, 0, 0, 0};
     int tile[kPasses] = {0, 0, 0, 0, 0};
@@ -78,13 +92,14 @@ struct PJob {
     const void *rho;
     void *u;
     void *X;                 // n*n*P complex
-    void *A;                 // n*N*pa complex
+    void *A;                 // n planes of `plane` complex, rows of pa
     const double *mult;      // blocked multiplier octant
     const void *tw64;       // twiddles double2[N], both tiers
     int N;                   // padded length
     int P;                   // k3 pitch of X
     int pa;                  // k3 pitch of A
     int pv[kPasses];         // radix plan of each pass
+    long long plane;         // i1 pitch of A (a_plane)
 };
 
 // Batch header in device memory.  counter[p] must be zero when pass p

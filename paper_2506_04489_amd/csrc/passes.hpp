@@ -6,8 +6,9 @@
 // P = round_up(n+1, 16) (pitch of the half-spectrum axis k3 = 0..n):
 //   rho, u : n*n*n real, [i1][i2][i3]
 //   X      : n*n*P complex, [i1][i2][k3]   after H1; reused as Y after H4
-//   A      : n*N*pa complex, [i1][k2][k3]  after H2; H3 updates it in place
-//            (pa = the k3 columns of one chunk, a multiple of the row tile)
+//   A      : n planes of N rows of pa complex, [i1][k2][k3] after H2; H3
+//            updates it in place (pa = the k3 columns of one chunk, a
+//            multiple of the row tile; plane pitch a_plane(n, n, pa) >= N pa)
 //   mult   : (n+1)*P*(n+1) FP64, blocked [b][c/8][a][c%8] holding the
 //            multiplier m(|k1| = a, |k2| = b, k3 = c), zero for c > n
 // Passes (Algorithm 2):
@@ -142,11 +143,11 @@ struct Chunk {
     int pa;         // k3 pitch of the chunk buffer A
     int n2;         // points along i2 (rows k2 of A: 2 n2)
     int n3;         // points along i3 (columns k3 <= n3 are valid)
+    long long plane;    // i1 pitch of A: a_plane(n1, n2, pa)
 };
 
-template <int N>
-__device__ __forceinline__ size_t a_index(int pa, int c, int k2, int i1) {
-    return ((size_t)i1 * N + k2) * pa + c;
+__device__ __forceinline__ size_t a_index(const Chunk &ck, int c, int k2, int i1) {
+    return (size_t)i1 * ck.plane + (size_t)k2 * ck.pa + c;
 }
 
 // ------------------------------------------------------------------- H2
@@ -165,7 +166,7 @@ k_y_fwd(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
     const int cg = ck.tile0 * LayoutTile<T>::W + c;
     const bool valid = cg <= ck.n3;
     const C *src = (const C *)jb.X + (size_t)i1 * n * P + cg;      // rows i2 of X
-    C *dst = (C *)jb.A + a_index<N>(ck.pa, c, 0, i1);              // rows k2 of A
+    C *dst = (C *)jb.A + a_index(ck, c, 0, i1);                    // rows k2 of A
     C v[E::V];
     E::for_inputs(v, t, [&](int pos, int r) -> C {
         if (r < E::R(0) / 2 && valid) return src[(size_t)pos * P];
@@ -203,7 +204,7 @@ k_x_fused(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
     const int cg = ck.tile0 * LayoutTile<T>::W + c;
     const bool valid = cg <= ck.n3;
     const C *src = (const C *)jb.A + (size_t)k2 * ck.pa + c;        // rows i1
-    const size_t step = (size_t)(2 * ck.n2) * ck.pa;
+    const size_t step = (size_t)ck.plane;
     const double *mrow = jb.mult + ((size_t)(b * (P / 8) + cg / 8) * (n + 1)) * 8 + (cg & 7);
     C v[EF::V];
     EF::for_inputs(v, t, [&](int pos, int r) -> C {
@@ -249,7 +250,7 @@ k_y_inv(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
     const bool valid = cg <= ck.n3;
     C v[E::V];
     if constexpr (!FULL) {
-        const C *src = (const C *)jb.A + a_index<N>(ck.pa, c, 0, i1);   // rows k2
+        const C *src = (const C *)jb.A + a_index(ck, c, 0, i1);         // rows k2
         E::for_inputs(v, t, [&](int pos, int) -> C {
             if (valid) return src[(size_t)pos * ck.pa];
             return c_zero<C>();
@@ -404,7 +405,7 @@ hipError_t passes_impl(const Job &one, const Job *table, int count, int P, int c
         using SC = StridedCfg<T, N, 0, LW, 0, false>;
         using LC = LineCfg<T, N, 0, 256>;
         const JobRef jr{one, table};
-        const Chunk ck{0, ntile, ntile * LW, n, n};
+        const Chunk ck{0, ntile, ntile * LW, n, n, (long long)a_plane(n, n, ntile * LW, sizeof(cplx<T>))};
         hipLaunchKernelGGL((k_z_r2c<T, N, 0, 256>), dim3(ceil_div(n * n / 2, LC::Q), y), dim3(LC::THREADS), 0, st,
                            jr, n * n / 2, P, tw);
         hipLaunchKernelGGL((k_y_fwd<T, N, 0, LW, 0, false>), dim3(n * ntile, y), dim3(SC::THREADS), 0, st, jr, ck, P, tw);
@@ -478,6 +479,7 @@ hipError_t passes_impl(const Job &one, const Job *table, int count, int P, int c
     const int n1 = dm.n1, n2 = dm.n2, n3 = dm.n3;
     const int G = (table == nullptr && nchunks == 1 && i1_group > 0 && i1_group < n1) ? i1_group : n1;
     const int PA = ct * LW;
+    const long long plane = (long long)a_plane(n1, n2, PA, sizeof(cplx<T>));
     auto on = [&](int pass) { return (mask >> pass) & 1; };
     // H1 (+ H2 when grouped) per i1 group
     for (int g0 = 0; g0 < n1 && (on(0) || (G < n1 && on(1))); g0 += G) {
@@ -485,7 +487,7 @@ hipError_t passes_impl(const Job &one, const Job *table, int count, int P, int c
         Job j = one;
         if (!table) {
             j.rho = (const T *)one.rho + (size_t)g0 * n2 * n3;
-            j.A = (cplx<T> *)one.A + (size_t)g0 * (2 * n2) * PA;
+            j.A = (cplx<T> *)one.A + (size_t)g0 * plane;
         }
         const JobRef jr{j, table};
         if (on(0)) {
@@ -494,13 +496,13 @@ hipError_t passes_impl(const Job &one, const Job *table, int count, int P, int c
         }
         if (G < n1 && on(1)) {
             mark(1);
-            h2(jr, Chunk{0, ntile, PA, n2, n3}, gs);
+            h2(jr, Chunk{0, ntile, PA, n2, n3, plane}, gs);
         }
     }
     const JobRef jr{one, table};
     for (int ch = 0; ch < nchunks; ++ch) {
         const int t0 = ch * ct, nt = std::min(ct, ntile - t0);
-        const Chunk ck{t0, nt, PA, n2, n3};
+        const Chunk ck{t0, nt, PA, n2, n3, plane};
         if (G == n1 && on(1)) {
             mark(1);
             h2(jr, ck, n1);
@@ -520,12 +522,12 @@ hipError_t passes_impl(const Job &one, const Job *table, int count, int P, int c
         Job j = one;
         if (!table) {
             j.u = (T *)one.u + (size_t)g0 * n2 * n3;
-            j.A = (cplx<T> *)one.A + (size_t)g0 * (2 * n2) * PA;
+            j.A = (cplx<T> *)one.A + (size_t)g0 * plane;
         }
         const JobRef jrg{j, table};
         if (G < n1 && on(3)) {
             mark(3);
-            h4(jrg, Chunk{0, ntile, PA, n2, n3}, gs);
+            h4(jrg, Chunk{0, ntile, PA, n2, n3, plane}, gs);
         }
         if (on(4)) {
             mark(4);

@@ -95,7 +95,7 @@ __device__ __noinline__ void pb_y_fwd(const PJob *jp, int item) {
     const int i1 = f / (n + 1), c = f % (n + 1);
     const bool valid = i1 < n;
     const C *src = (const C *)jb.X + (size_t)i1 * n * jb.P + c;
-    C *dst = (C *)jb.A + (size_t)i1 * N * jb.pa + c;
+    C *dst = (C *)jb.A + (size_t)i1 * jb.plane + c;
     C v[E::V];
     E::for_inputs(v, t, [&](int pos, int r) -> C {
         if (r < E::R(0) / 2 && valid) return src[(size_t)pos * jb.P];
@@ -125,7 +125,7 @@ __device__ __noinline__ void pb_x_fused(const PJob *jp, int item) {
     const bool valid = k2 < N;
     const int b = !valid ? 0 : (k2 <= n ? k2 : N - k2);
     const C *src = (const C *)jb.A + (size_t)k2 * jb.pa + c;      // rows i1
-    const size_t step = (size_t)N * jb.pa;
+    const size_t step = (size_t)jb.plane;
     const double *mrow = jb.mult + ((size_t)(b * (jb.P / 8) + c / 8) * (n + 1)) * 8 + (c & 7);
     C v[EF::V];
     EF::for_inputs(v, t, [&](int pos, int r) -> C {
@@ -160,7 +160,7 @@ __device__ __noinline__ void pb_y_inv(const PJob *jp, int item) {
     const int f = item * W + col;
     const int i1 = f / (n + 1), c = f % (n + 1);
     const bool valid = i1 < n;
-    const C *src = (const C *)jb.A + (size_t)i1 * N * jb.pa + c;   // rows k2
+    const C *src = (const C *)jb.A + (size_t)i1 * jb.plane + c;   // rows k2
     C v[E::V];
     E::for_inputs(v, t, [&](int pos, int) -> C {
         if (valid) return src[(size_t)pos * jb.pa];

@@ -109,7 +109,7 @@ def test_grid_plan_create_validation_and_layout():
         assert (plan[q], tile[q]) == (tp[q], tt[q]), q
     pitch = lambda m: ((m + 1 + 15) // 16) * 16
     cols = lambda m: ((m + 1 + 7) // 8) * 8
-    assert p.workspace_bytes() == 16 * (pitch(32) * 16 * 24 + cols(32) * 16 * 2 * 24)
+    assert p.workspace_bytes() == 16 * (pitch(32) * 16 * 24 + 16 * a_plane(16, 24, cols(32), 16))
     assert p.spectrum_bytes() == 8 * 17 * 25 * pitch(32)
     # equal counts: the box plan
     q, c = B.Plan((16, 16, 16), hs, 40), B.Plan(16, hs, 40)
@@ -149,17 +149,41 @@ def test_gs_weights_match_oracle(n, h, R):
     assert np.max(np.abs(al / al_o - 1)) < 1e-14 * max(1, R / 40)
 
 
+def a_plane(n1, n2, pa, elem):
+    """i1 pitch (elements) of a chunk buffer of n1 planes of 2 n2 rows of pa
+    columns: above 128 MiB the smallest whole number of 128-byte lines that
+    holds a plane and is 15 mod 32 lines (so that the fused i1 pass's column
+    reads spread over the HBM channels), else the plane itself."""
+    need = 2 * n2 * pa * elem
+    assert need % 128 == 0
+    lines = need // 128
+    if need * n1 > 128 << 20:
+        while lines % 32 != 15:
+            lines += 1
+    return lines * 128 // elem
+
+
+def test_chunk_plane_pitch():
+    assert a_plane(256, 256, 264, 16) == 256 * 2 * 264 + 15 * 8   # n = 256 FP64: 15 lines of pad
+    assert a_plane(128, 128, 136, 16) == 256 * 136                # 71 MB: no pad
+    for n in (2, 3, 12, 24, 96, 128, 192, 256, 384):
+        for pa, elem in ((8, 16), (16, 8), (264, 16), (272, 8), (392, 16)):
+            pl = a_plane(n, n, pa, elem)
+            assert 2 * n * pa <= pl < 2 * n * pa + 32 * 128 // elem
+
+
 def test_workspace_and_spectrum_sizes():
-    # X: n*n*P complex; chunk buffer: n*2n*(tiles*W) complex with W = 8 (FP64)
-    # or 16 (FP32) k3 bins per tile; by default one chunk of all tiles
+    # X: n*n*P complex; chunk buffer: n planes of 2n rows of tiles*W complex
+    # (W = 8 FP64 or 16 FP32 k3 bins per tile; by default one chunk of all
+    # tiles), the plane pitch padded as a_plane says
     p = B.Plan(256, 2 / 256, 40)
     P = 272
-    assert p.workspace_bytes() == 16 * (P * 256 * 256 + 264 * 256 * 512)
+    assert p.workspace_bytes() == 16 * (P * 256 * 256 + 256 * a_plane(256, 256, 264, 16))
     assert p.spectrum_bytes() == 8 * 257 * 257 * P
     q = B.Plan(256, 2 / 256, 40, dtype="f32")
-    assert q.workspace_bytes() == 8 * (P * 256 * 256 + 272 * 256 * 512)
+    assert q.workspace_bytes() == 8 * (P * 256 * 256 + 256 * a_plane(256, 256, 272, 8))
     p.set_tuning(4, 0)
-    assert p.workspace_bytes() == 16 * (P * 256 * 256 + 32 * 256 * 512)
+    assert p.workspace_bytes() == 16 * (P * 256 * 256 + 256 * a_plane(256, 256, 32, 16))
 
 
 # ---------------------------------------------------------------- shapes

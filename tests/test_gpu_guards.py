@@ -31,11 +31,17 @@ def test_passes_stay_inside_their_workspace(n, dtype):
         torch.cuda.synchronize()
         assert p.guards_intact(), "shapes"
         p.set_shape([0] * 5, [0] * 5)
+        if n <= 128:
+            p.solve_padded_debug(rho)            # the uncropped passes, same workspace
+            assert p.guards_intact(), "uncropped"
         for k3_tiles, group in ((3, 0), (0, max(1, n // 3))):
             p.set_tuning(k3_tiles, group)        # new (guarded) workspaces
             p.solve(rho)
             torch.cuda.synchronize()
             assert p.guards_intact(), (k3_tiles, group)
+            # a shrunk workspace cannot hold the uncropped passes
+            with pytest.raises(B.PspError, match="default tuning"):
+                p.solve_padded_debug(rho)
         p.set_tuning(0, 0)
     finally:
         B.debug_guards(False)
