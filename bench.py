@@ -473,7 +473,7 @@ def main():
                     help="first run a plain 1 GiB device copy (reference for byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        sys.stderr.write("bench.py measures one GPU: this build has no multi-GPU path "
+        sys.stderr.write("bench.py measures one GPU: the library has no multi-GPU path "
                          "(requested --gpus %d)\n" % args.gpus)
         sys.exit(2)
 

@@ -94,11 +94,12 @@ psp_status psp_plan_create_box(int n, const double *h, int R, psp_dtype dtype,
  * each n[p] as for psp_plan_create).  rho and u are n[0] x n[1] x n[2],
  * C-order.  Defaults as for psp_plan_create_box, with L_p = 2 n_p h_p.
  * With unequal counts every pass runs at its own axis's padded length and
- * takes the tuned shape of a cube of that size; such plans solve singly
- * (psp_solve, psp_graph_capture); psp_solve_batched,
- * psp_graph_capture_batched, psp_solve_padded_debug, psp_autotune,
- * psp_plan_set_shape, psp_profile_enable and k3 chunks / i1 groups return
- * PSP_EUNSUPPORTED for them.  Equal counts give the psp_plan_create_box
+ * takes the tuned shape of a cube of that size.  Such plans solve through
+ * psp_solve, psp_graph_capture and, beside cubic plans, psp_solve_batched
+ * and psp_graph_capture_batched (each grid with its own launch sequence);
+ * psp_solve_padded_debug, psp_autotune, psp_plan_set_shape,
+ * psp_profile_enable and k3 chunks / i1 groups return PSP_EUNSUPPORTED for
+ * them.  Equal counts give the psp_plan_create_box
  * plan. */
 psp_status psp_plan_create_grid(const int *n, const double *h, int R, psp_dtype dtype,
                                 double eps, double delta, psp_plan **out);
@@ -120,8 +121,10 @@ psp_status psp_solve(psp_plan *p, const void *rho_dev, void *u_dev, void *stream
  * distinct n in the batch (the pass kernels read each solve's pointers from
  * a device job table).  plans may differ in n (and h, R) but must share one
  * dtype and device and all be precomputed; rho_dev[i] and u_dev[i] follow
- * plans[i].  Results are bitwise equal to psp_solve of the same plan and rho.
- * Workspaces (one per solve of the batch) are library-owned, bound to the
+ * plans[i].  Grid plans with unequal counts per axis run after the cubic
+ * ones, each with its own per-axis launch sequence.  Results are bitwise
+ * equal to psp_solve of the same plan and rho.  Workspaces (one per cubic
+ * solve of the batch, one per distinct grid) are library-owned, bound to the
  * stream and reused by later batches on it. */
 psp_status psp_solve_batched(int count, psp_plan *const *plans,
                              const void *const *rho_dev, void *const *u_dev,

@@ -6,9 +6,11 @@
 // plan) are grouped.  Each solve
 // has its own workspace (one chunk of all k3 tiles).  The batch image
 // (persistent header, job table, item offsets and the grouped job table) is
-// built on the host and uploaded in one copy through pinned memory.  Every
-// solve runs the same arithmetic as a single psp_solve, so the results are
-// bitwise equal.
+// built on the host and uploaded in one copy through pinned memory.  Grids
+// with unequal point counts per axis run after the cubes, each with its own
+// per-axis launch sequence, one workspace per distinct grid.  Every solve
+// runs the same arithmetic as a single psp_solve, so the results are bitwise
+// equal.
 #include <algorithm>
 #include <atomic>
 #include <cstring>
@@ -146,6 +148,9 @@ struct Staging {
 struct StreamBatch {
     Staging stage;
     std::map<std::pair<int, bool>, std::vector<Workspace>> ws;   // (n, f32) -> pool
+    // grids: one workspace per (n1, n2, n3, f32); their solves run one after
+    // another on the stream, so they can share it
+    std::map<std::pair<std::vector<int>, bool>, Workspace> grid_ws;
 };
 
 static std::mutex g_batch_mu;
@@ -252,7 +257,6 @@ extern "C" psp_status psp_solve_batched(int count, psp_plan *const *plans, const
         if (!plans[i]->precomputed) return fail(PSP_ESTATE, "batch entry %d not precomputed", i);
         if (plans[i]->dtype != plans[0]->dtype) return fail(PSP_EINVAL, "batch mixes dtypes");
         if (plans[i]->device != plans[0]->device) return fail(PSP_EINVAL, "batch mixes devices");
-        if (plans[i]->grid) return fail(PSP_EUNSUPPORTED, "batch entry %d has unequal point counts per axis", i);
         if (rho_dev[i] == u_dev[i]) return fail(PSP_EINVAL, "entry %d: rho and u must not alias", i);
     }
     int dev = -1;
@@ -260,19 +264,45 @@ extern "C" psp_status psp_solve_batched(int count, psp_plan *const *plans, const
         return fail(PSP_EINVAL, "plans were precomputed on device %d, current is %d", plans[0]->device, dev);
     hipStream_t st = (hipStream_t)stream;
     const bool f32 = plans[0]->dtype == PSP_F32;
-    std::vector<int> ns(count);
-    for (int i = 0; i < count; ++i) ns[i] = plans[i]->n;
+    std::vector<int> cube, grid;
+    for (int i = 0; i < count; ++i) (plans[i]->grid ? grid : cube).push_back(i);
     std::lock_guard<std::mutex> lk(g_batch_mu);
     StreamBatch &B = g_batch[{dev, st}];
-    std::vector<Workspace *> ws;
-    psp_status rs = batch_workspaces(B, ns, f32, ws);
-    if (rs != PSP_OK) return rs;
-    std::vector<BatchMember> m(count);
-    for (int i = 0; i < count; ++i) {
-        m[i].job = Job{rho_dev[i], u_dev[i], ws[i]->X, ws[i]->A, plans[i]->spec->mult, nullptr, nullptr};
-        m[i].n = plans[i]->n;
-        m[i].shape = plans[i]->shape;
-        m[i].tw64 = plans[i]->tw->w64;
+    // grid workspaces first: an allocation failure leaves nothing enqueued
+    std::vector<Workspace *> gws;
+    for (int i : grid) {
+        const psp_plan *p = plans[i];
+        auto key = std::make_pair(std::vector<int>{p->ns[0], p->ns[1], p->ns[2]}, f32);
+        auto it = B.grid_ws.find(key);
+        if (it == B.grid_ws.end()) {
+            Workspace w;
+            psp_status rs = alloc_workspace_dims(Dims{p->ns[0], p->ns[1], p->ns[2]}, f32, &w);
+            if (rs != PSP_OK) return rs;
+            it = B.grid_ws.emplace(key, w).first;
+        }
+        gws.push_back(&it->second);
     }
-    return run_batch(B.stage, m, f32, st);
+    if (!cube.empty()) {
+        std::vector<int> ns;
+        for (int i : cube) ns.push_back(plans[i]->n);
+        std::vector<Workspace *> ws;
+        psp_status rs = batch_workspaces(B, ns, f32, ws);
+        if (rs != PSP_OK) return rs;
+        std::vector<BatchMember> m(cube.size());
+        for (size_t j = 0; j < cube.size(); ++j) {
+            const int i = cube[j];
+            m[j].job = Job{rho_dev[i], u_dev[i], ws[j]->X, ws[j]->A, plans[i]->spec->mult, nullptr, nullptr};
+            m[j].n = plans[i]->n;
+            m[j].shape = plans[i]->shape;
+            m[j].tw64 = plans[i]->tw->w64;
+        }
+        rs = run_batch(B.stage, m, f32, st);
+        if (rs != PSP_OK) return rs;
+    }
+    for (size_t j = 0; j < grid.size(); ++j) {
+        const int i = grid[j];
+        const hipError_t e = launch_solve(solve_args(plans[i], *gws[j], rho_dev[i], u_dev[i]), st);
+        if (e != hipSuccess) return hip_fail(e, "batched grid solve");
+    }
+    return PSP_OK;
 }

@@ -95,49 +95,66 @@ psp_status psp_graph_capture_batched(int count, psp_plan *const *plans, const vo
         if (!plans[i] || !rho_dev[i] || !u_dev[i]) return fail(PSP_EINVAL, "NULL entry %d in batch", i);
         if (!plans[i]->precomputed) return fail(PSP_ESTATE, "batch entry %d not precomputed", i);
         if (plans[i]->dtype != plans[0]->dtype) return fail(PSP_EINVAL, "batch mixes dtypes");
-        if (plans[i]->grid) return fail(PSP_EUNSUPPORTED, "batch entry %d has unequal point counts per axis", i);
     }
     const bool f32 = plans[0]->dtype == PSP_F32;
     psp_graph *g = new (std::nothrow) psp_graph;
     if (!g) return fail(PSP_ENOMEM, "host allocation failed");
     g->device = plans[0]->device;
     g->ws.resize(count);
-    std::vector<BatchMember> m(count);
+    // cubes go through the batch image; grids with unequal counts follow,
+    // each with its own per-axis launch sequence
+    std::vector<BatchMember> m;
+    std::vector<SolveArgs> grid_args;
     for (int i = 0; i < count; ++i) {
-        psp_status rs = alloc_workspace(plans[i]->n, f32, 0, &g->ws[i]);
+        const psp_plan *p = plans[i];
+        psp_status rs = p->grid ? alloc_workspace_dims(Dims{p->ns[0], p->ns[1], p->ns[2]}, f32, &g->ws[i])
+                                : alloc_workspace(p->n, f32, 0, &g->ws[i]);
         if (rs != PSP_OK) {
             g->ws.resize(i);
             graph_free(g);
             return rs;
         }
-        m[i].job = Job{rho_dev[i], u_dev[i], g->ws[i].X, g->ws[i].A, plans[i]->spec->mult, nullptr, nullptr};
-        m[i].n = plans[i]->n;
-        m[i].shape = plans[i]->shape;
-        m[i].tw64 = plans[i]->tw->w64;
-    }
-    if (persist_prepare() != hipSuccess) {
-        (void)hipGetLastError();
-        graph_free(g);
-        return fail(PSP_EHIP, "occupancy query failed");
+        if (p->grid) {
+            grid_args.push_back(solve_args(p, g->ws[i], rho_dev[i], u_dev[i]));
+            continue;
+        }
+        BatchMember b;
+        b.job = Job{rho_dev[i], u_dev[i], g->ws[i].X, g->ws[i].A, p->spec->mult, nullptr, nullptr};
+        b.n = p->n;
+        b.shape = p->shape;
+        b.tw64 = p->tw->w64;
+        m.push_back(b);
     }
     // the batch image is written once, before capture; each replay clears
     // the persistent counters with a kernel (no memset node in the graph)
     BatchImage img;
-    std::vector<unsigned char> host;
-    if (hipMalloc((void **)&g->table, batch_image_bytes(m)) != hipSuccess) {
-        (void)hipGetLastError();
-        g->table = nullptr;
-        graph_free(g);
-        return fail(PSP_ENOMEM, "graph batch table allocation failed");
-    }
-    build_batch_image(m, f32, g->table, &img, host);
-    if (hipMemcpy(g->table, host.data(), img.bytes, hipMemcpyHostToDevice) != hipSuccess) {
-        (void)hipGetLastError();
-        graph_free(g);
-        return fail(PSP_EHIP, "graph batch table upload failed");
+    if (!m.empty()) {
+        if (persist_prepare() != hipSuccess) {
+            (void)hipGetLastError();
+            graph_free(g);
+            return fail(PSP_EHIP, "occupancy query failed");
+        }
+        std::vector<unsigned char> host;
+        if (hipMalloc((void **)&g->table, batch_image_bytes(m)) != hipSuccess) {
+            (void)hipGetLastError();
+            g->table = nullptr;
+            graph_free(g);
+            return fail(PSP_ENOMEM, "graph batch table allocation failed");
+        }
+        build_batch_image(m, f32, g->table, &img, host);
+        if (hipMemcpy(g->table, host.data(), img.bytes, hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipGetLastError();
+            graph_free(g);
+            return fail(PSP_EHIP, "graph batch table upload failed");
+        }
     }
     psp_status rs = capture(g, (hipStream_t)stream, [&](hipStream_t cs) -> hipError_t {
-        return launch_batch_image(m, img, f32, g->table, true, cs);
+        hipError_t e = m.empty() ? hipSuccess : launch_batch_image(m, img, f32, g->table, true, cs);
+        for (const SolveArgs &a : grid_args) {
+            if (e != hipSuccess) break;
+            e = launch_solve(a, cs);
+        }
+        return e;
     });
     if (rs != PSP_OK) {
         graph_free(g);

@@ -1,7 +1,7 @@
 """Unequal point counts per axis on the GPU (psp_plan_create_grid): every
 pass at its own axis's padded length, the per-axis multiplier octant, and
-the solve against the oracle; graph capture; entry points that need equal
-counts refuse such plans."""
+the solve against the oracle; graph capture; batches mixing grids and
+cubes; entry points that need equal counts refuse such plans."""
 import numpy as np
 import pytest
 
@@ -78,10 +78,48 @@ def test_grid_graph_and_refusals():
     torch.cuda.synchronize()
     assert torch.equal(u, ug)
     g.close()
-    q = B.Plan(16, 0.1, 40).precompute()
-    for call in (lambda: B.solve_batched([q, p], [to_dev(np.zeros((16,) * 3)), rho],
-                                         [torch.empty((16,) * 3, dtype=torch.float64, device="cuda"), ug]),
-                 lambda: p.solve_padded_debug(rho), lambda: p.autotune(reps=1)):
+    for call in (lambda: p.solve_padded_debug(rho), lambda: p.autotune(reps=1)):
         with pytest.raises(B.PspError) as ei:
             call()
         assert B.STATUS[ei.value.status] == "PSP_EUNSUPPORTED"
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_grid_batches_match_single_solves(dtype):
+    """Grids beside cubes in psp_solve_batched and psp_graph_capture_batched:
+    bitwise the single solves (two grids share a shape, so their workspace is
+    shared and reused), also on a second batch and on graph replays between
+    eager work; the grids alone in a batch too."""
+    import torch
+    td = torch.float64 if dtype == "f64" else torch.float32
+    rng = np.random.default_rng(7)
+    shapes = [(16, 24, 32), 24, (32, 12, 8), 16, (16, 24, 32), (6, 48, 16)]
+    plans = [B.Plan(s, HS if isinstance(s, tuple) else 0.1, 40, dtype=dtype).precompute() for s in shapes]
+    rhos = [to_dev(rng.standard_normal(p.shape3), td) for p in plans]
+    want = [p.solve(r).clone() for p, r in zip(plans, rhos)]
+    torch.cuda.synchronize()
+    for rep in range(2):
+        us = [torch.full_like(r, float("nan")) for r in rhos]
+        B.solve_batched(plans, rhos, us)
+        torch.cuda.synchronize()
+        for i, (u, w) in enumerate(zip(us, want)):
+            assert torch.equal(u, w), (rep, i, shapes[i])
+    grids = [i for i, s in enumerate(shapes) if isinstance(s, tuple)]
+    us = [torch.full_like(rhos[i], float("nan")) for i in grids]
+    B.solve_batched([plans[i] for i in grids], [rhos[i] for i in grids], us)
+    torch.cuda.synchronize()
+    for u, i in zip(us, grids):
+        assert torch.equal(u, want[i]), ("grids only", i)
+    for members in (list(range(len(shapes))), grids):
+        ug = [torch.empty_like(rhos[i]) for i in members]
+        g = B.Graph.capture_batched([plans[i] for i in members], [rhos[i] for i in members], ug)
+        for rep in range(3):
+            for u in ug:
+                u.fill_(float("nan"))
+            plans[1].solve(rhos[1])               # eager work between replays
+            torch.cuda.synchronize()
+            g.launch()
+            torch.cuda.synchronize()
+            for u, i in zip(ug, members):
+                assert torch.equal(u, want[i]), ("graph", rep, i)
+        g.close()
