@@ -196,9 +196,12 @@ psp_status psp_plan_set_tuning(psp_plan *p, int k3_tiles, int i1_group);
  *            3: one row with half the threads per column (two butterflies
  *            per thread and stage), 4: 2 and 3 together, 5: one row with the
  *            exchanges through half-size LDS buffers by column half, 6: 5 and
- *            3 together.
- * A tile choice changes only which workgroup transforms which column and how
- * values move between stages: the results are bitwise the same.  A radix plan changes the rounding, not the
+ *            3 together; pass 2 also 7..13: 0..6 with nontemporal stores of
+ *            the intermediate, 14..20: 0..6 with nontemporal loads and
+ *            stores.
+ * A tile choice changes only which workgroup transforms which column, how
+ * values move between stages and the accesses' cache policy: the results
+ * are bitwise the same.  A radix plan changes the rounding, not the
  * accuracy class.  Batched solves and graphs group their members by (n,
  * shape).  Set: PSP_EINVAL for a value out of range; call it while no solve
  * of this plan is in flight.  Get: copies the plan's current shape. */
@@ -218,8 +221,8 @@ psp_status psp_tuning_get(int n, psp_dtype dtype, int *plan, int *tile);
  * default unless another is at least 1% faster), sets it as the plan's shape
  * and enters it in the tuning table.  Outputs (host arrays, each may be
  * NULL): best_plan[5], best_tile[5], best_ms[5] the chosen candidate and
- * that pass's time in ms; cand_ms[5 * 21]: the time of candidate
- * (plan, tile) of pass i at cand_ms[i * 21 + plan * 7 + tile], -1 where the
+ * that pass's time in ms; cand_ms[5 * 63]: the time of candidate
+ * (plan, tile) of pass i at cand_ms[i * 63 + plan * 21 + tile], -1 where the
  * candidate does not exist.  Allocates two n^3
  * buffers for the duration; synchronises `stream`.  PSP_ESTATE before
  * precompute or while profiling; PSP_EINVAL for reps outside [1, 1000]. */

@@ -46,7 +46,7 @@ def main(argv=None) -> int:
                 n, dt, res["plan"], res["tile"], ["%.4f" % x for x in res["pass_ms"]], time.time() - t0),
                 flush=True)
             for i, row in enumerate(res["candidates_ms"]):
-                print("    H%d candidates (plan*7+tile): %s" % (i + 1, [x for x in row if x >= 0]), flush=True)
+                print("    H%d candidates (plan*21+tile): %s" % (i + 1, [x for x in row if x >= 0]), flush=True)
             del p
     doc = {"device": torch.cuda.get_device_name(0), "reps": args.reps, "entries": entries}
     with open(args.out, "w") as f:

@@ -26,12 +26,16 @@ struct Job {
 //            tile with exchanges through half-size LDS buffers by position
 //            half, 3: one tile with half the threads per column (two
 //            butterflies each), 4: 2 and 3, 5: one tile with exchanges
-//            through half-size LDS buffers by column half, 6: 5 and 3
-// A tile choice only changes which workgroup transforms which column and how
-// values move between stages, so results are bitwise the same under every
-// tile choice.
+//            through half-size LDS buffers by column half, 6: 5 and 3;
+//            H3 (p = 2) also 7-13: 0-6 with nontemporal stores of the
+//            intermediate, 14-20: 0-6 with nontemporal loads and stores
+// A tile choice only changes which workgroup transforms which column, how
+// values move between stages and the cache policy of the accesses, so
+// results are bitwise the same under every tile choice.
 constexpr int kPasses = 5;
-constexpr int kTileChoices[kPasses] = {3, 7, 7, 7, 3};
+constexpr int kTileChoices[kPasses] = {3, 7, 21, 7, 3};
+constexpr int kMaxTiles = 21;     // the largest of kTileChoices
+constexpr int kMaxPlans = 3;      // radix plans 0..2
 // points along i1, i2, i3 (the slowest to the contiguous axis of rho)
 struct Dims {
     int n1, n2, n3;

@@ -177,12 +177,41 @@ k_y_fwd(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
 }
 
 // ------------------------------------------------------------------- H3
+// Cache policy CP of H3's accesses to the intermediate: 0 ordinary, 1
+// nontemporal stores, 2 nontemporal loads and stores (streaming hints that
+// keep the stream of A from displacing the multiplier blocks the paired
+// workgroups share in L2; which one pays depends on the size and tier, so
+// it is a tuning choice).  The pointers are global memory.
+template <typename C> struct VecOf;
+template <> struct VecOf<double2> { typedef double type __attribute__((ext_vector_type(2))); };
+template <> struct VecOf<float2> { typedef float type __attribute__((ext_vector_type(2))); };
+template <int CP, typename C> __device__ __forceinline__ C a_load(const C *p) {
+    if constexpr (CP == 2) {
+        typedef const __attribute__((address_space(1))) typename VecOf<C>::type *G;
+        const auto t = __builtin_nontemporal_load((G)p);
+        return C{t.x, t.y};
+    } else {
+        return *p;
+    }
+}
+template <int CP, typename C> __device__ __forceinline__ void a_store(C *p, const C &v) {
+    if constexpr (CP >= 1) {
+        typedef __attribute__((address_space(1))) typename VecOf<C>::type *G;
+        typename VecOf<C>::type t;
+        t.x = v.x;
+        t.y = v.y;
+        __builtin_nontemporal_store(t, (G)p);
+    } else {
+        *p = v;
+    }
+}
+
 // Work item (b, sub-tile, side): column k2 = b (side 0) or N - b (side 1),
 // both reading the same multiplier block.  Items (b, ., 0) and (b, ., 1) go
 // to workgroups g and g + 8, which the dispatcher places on the same XCD at
 // nearly the same time, so the second read of the block hits that XCD's L2.
 // FULL (test hook): all N outputs of the inverse go to A2[i1][k2][k3] (pitch P).
-template <typename T, int N, int PV, int W, int XC, bool HF, bool FULL>
+template <typename T, int N, int PV, int W, int XC, bool HF, bool FULL, int CP>
 __global__ void __launch_bounds__((StridedCfg<T, N, PV, W, XC, HF>::THREADS))
 k_x_fused(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
     using C = cplx<T>;
@@ -208,7 +237,7 @@ k_x_fused(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
     const double *mrow = jb.mult + ((size_t)(b * (P / 8) + cg / 8) * (n + 1)) * 8 + (cg & 7);
     C v[EF::V];
     EF::for_inputs(v, t, [&](int pos, int r) -> C {
-        if (r < EF::R(0) / 2 && valid) return src[pos * step];
+        if (r < EF::R(0) / 2 && valid) return a_load<CP>(&src[pos * step]);
         return c_zero<C>();
     });
     strided_stages<EF, Cfg, W>(v, lds, t, col, tw);
@@ -221,7 +250,7 @@ k_x_fused(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
     if constexpr (!FULL) {
         C *dst = (C *)jb.A + (size_t)k2 * ck.pa + c;
         EI::for_outputs(v, t, [&](int pos, int r, C &val) {
-            if (valid && r < EI::R(EI::S - 1) / 2) dst[pos * step] = val;
+            if (valid && r < EI::R(EI::S - 1) / 2) a_store<CP>(&dst[pos * step], val);
         });
     } else {
         C *dst = (C *)jb.A2 + (size_t)k2 * P + cg;
@@ -361,6 +390,17 @@ template <typename T, typename F> inline void with_cols(int tile, F &&f) {
         default: f(StridedTile<LW, 0, false>{}); break;
     }
 }
+// H3's tile choice: the strided tile (tile mod 7) and the cache policy
+// (tile / 7)
+template <typename T, typename F> inline void with_h3_tile(int tile, F &&f) {
+    with_cols<T>(tile % 7, [&](auto w) {
+        switch (tile / 7) {
+            case 1: f(w, std::integral_constant<int, 1>{}); break;
+            case 2: f(w, std::integral_constant<int, 2>{}); break;
+            default: f(w, std::integral_constant<int, 0>{}); break;
+        }
+    });
+}
 template <typename F> inline void with_threads(int tile, F &&f) {
     if (tile == 1)
         f(std::integral_constant<int, 128>{});
@@ -409,7 +449,7 @@ hipError_t passes_impl(const Job &one, const Job *table, int count, int P, int c
         hipLaunchKernelGGL((k_z_r2c<T, N, 0, 256>), dim3(ceil_div(n * n / 2, LC::Q), y), dim3(LC::THREADS), 0, st,
                            jr, n * n / 2, P, tw);
         hipLaunchKernelGGL((k_y_fwd<T, N, 0, LW, 0, false>), dim3(n * ntile, y), dim3(SC::THREADS), 0, st, jr, ck, P, tw);
-        hipLaunchKernelGGL((k_x_fused<T, N, 0, LW, 0, false, true>), dim3(ceil_div((long)(n + 1) * ntile, 8) * 16, y),
+        hipLaunchKernelGGL((k_x_fused<T, N, 0, LW, 0, false, true, 0>), dim3(ceil_div((long)(n + 1) * ntile, 8) * 16, y),
                            dim3(SC::THREADS), 0, st, jr, ck, P, tw);
         hipLaunchKernelGGL((k_y_inv<T, N, 0, LW, 0, false, true>), dim3(N * ntile, y), dim3(SC::THREADS), 0, st, jr, ck, P,
                            tw);
@@ -441,12 +481,13 @@ hipError_t passes_impl(const Job &one, const Job *table, int count, int P, int c
     };
     auto h3 = [&](const JobRef &jr, const Chunk &ck) {
         with_plan<N>(sh.plan[2], [&](auto pv) {
-            with_cols<T>(sh.tile[2], [&](auto w) {
+            with_h3_tile<T>(sh.tile[2], [&](auto w, auto cp) {
                 constexpr int PV = decltype(pv)::value, W = decltype(w)::W;
                 constexpr int XC = decltype(w)::XC;
                 constexpr bool HF = decltype(w)::HF;
+                constexpr int CP = decltype(cp)::value;
                 using SC = StridedCfg<T, N, PV, W, XC, HF>;
-                hipLaunchKernelGGL((k_x_fused<T, N, PV, W, XC, HF, false>),
+                hipLaunchKernelGGL((k_x_fused<T, N, PV, W, XC, HF, false, CP>),
                                    dim3(ceil_div((long)(ck.n2 + 1) * ck.ntile * SC::SUB, 8) * 16, y), dim3(SC::THREADS),
                                    0, st, jr, ck, P, tw);
             });

@@ -59,7 +59,7 @@ __global__ void k_fill_hash(T *p, size_t count) {
 // candidates (radix plan, tile) of pass i for size n
 static std::vector<std::pair<int, int>> candidates(int n, int i) {
     std::vector<std::pair<int, int>> c;
-    for (int pl = 0; pl < 3; ++pl)
+    for (int pl = 0; pl < kMaxPlans; ++pl)
         if (plan_exists(2 * n, pl))
             for (int tl = 0; tl < kTileChoices[i]; ++tl) c.push_back({pl, tl});
     return c;
@@ -220,10 +220,11 @@ psp_status psp_autotune(psp_plan *p, int reps, void *stream, int *best_plan, int
     }
     shape_to(chosen, best_plan, best_tile);
     if (cand_ms) {
-        for (int i = 0; i < kPasses * 21; ++i) cand_ms[i] = -1.0f;
+        constexpr int stride = kMaxPlans * kMaxTiles;
+        for (int i = 0; i < kPasses * stride; ++i) cand_ms[i] = -1.0f;
         for (int i = 0; i < kPasses; ++i)
             for (size_t c = 0; c < cand[i].size(); ++c)
-                cand_ms[i * 21 + cand[i][c].first * 7 + cand[i][c].second] = best[i][c];
+                cand_ms[i * stride + cand[i][c].first * kMaxTiles + cand[i][c].second] = best[i][c];
     }
     return PSP_OK;
 }

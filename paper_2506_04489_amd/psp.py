@@ -328,13 +328,13 @@ class Plan:
         """Time every candidate shape of every pass (psp_autotune); the plan
         and the process-wide tuning table take the fastest.  Returns
         {"plan": [...], "tile": [...], "pass_ms": [...], "candidates_ms": [[...] x 5]}
-        where candidates_ms[i][plan * 7 + tile] is each candidate's
+        where candidates_ms[i][plan * 21 + tile] is each candidate's
         time (-1: no such candidate)."""
         pa, ta = (ctypes.c_int * 5)(), (ctypes.c_int * 5)()
         ms = (ctypes.c_float * 5)()
-        cm = (ctypes.c_float * 105)()
+        cm = (ctypes.c_float * 315)()
         _check(lib().psp_autotune(self._h, int(reps), _stream_ptr(stream), pa, ta, ms, cm))
-        cand = [[round(float(cm[i * 21 + c]), 5) for c in range(21)] for i in range(5)]
+        cand = [[round(float(cm[i * 63 + c]), 5) for c in range(63)] for i in range(5)]
         return {"plan": list(pa), "tile": list(ta), "pass_ms": [float(x) for x in ms], "candidates_ms": cand}
 
     def profile_enable(self, max_solves: int):

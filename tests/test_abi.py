@@ -192,9 +192,12 @@ def test_shape_validation_and_roundtrip():
     assert p.shape() == B.tuning_get(32, "f64")      # new plans start from the table
     p.set_shape([0] * 5, [2, 1, 2, 1, 1])
     assert p.shape() == ([0] * 5, [2, 1, 2, 1, 1])
+    p.set_shape([0] * 5, [0, 0, 20, 0, 0])           # H3: tile 6 with nontemporal loads and stores
+    assert p.shape() == ([0] * 5, [0, 0, 20, 0, 0])
     for plan, tile in [([1, 0, 0, 0, 0], [0] * 5),   # no alternative plan for 2n = 64
                        ([0] * 5, [3, 0, 0, 0, 0]),   # three workgroup sizes for H1
                        ([0] * 5, [0, 7, 0, 0, 0]),   # seven tile choices for H2
+                       ([0] * 5, [0, 0, 21, 0, 0]),  # twenty-one for H3 (three cache policies)
                        ([0] * 5, [0, 0, 0, 0, -1])]:
         with pytest.raises(B.PspError) as ei:
             p.set_shape(plan, tile)
