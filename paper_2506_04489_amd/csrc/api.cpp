@@ -19,7 +19,10 @@ psp_status fail(psp_status e, const char *fmt, ...) {
     va_start(ap, fmt);
     vsnprintf(buf, sizeof(buf), fmt, ap);
     va_end(ap);
-    g_last_error = buf;
+    try {
+        g_last_error = buf;
+    } catch (...) {   // out of host memory: keep the previous detail
+    }
     return e;
 }
 
@@ -336,42 +339,50 @@ static psp_status create_plan(const int *ns, const double *hs, int R, psp_dtype 
 }
 
 psp_status psp_plan_create_ex(int n, double h, int R, psp_dtype dtype, double eps, double delta, psp_plan **out) {
-    const int ns[3] = {n, n, n};
-    const double hs[3] = {h, h, h};
-    return create_plan(ns, hs, R, dtype, eps, delta, out);
+    return guarded([&]() -> psp_status {
+        const int ns[3] = {n, n, n};
+        const double hs[3] = {h, h, h};
+        return create_plan(ns, hs, R, dtype, eps, delta, out);
+    });
 }
 
 psp_status psp_plan_create_grid(const int *n, const double *h, int R, psp_dtype dtype, double eps, double delta,
                                 psp_plan **out) {
-    if (!out) return fail(PSP_EINVAL, "out is NULL");
-    *out = nullptr;
-    if (!n || !h) return fail(PSP_EINVAL, "n or h is NULL");
-    if (eps <= 0.0 && delta <= 0.0) {
-        // eps = 1e-4 max_p L_p/2 and delta = |(L_1, L_2, L_3)|/2, the corner
-        // of the kernel's truncation box (L_p = 2 n_p h_p)
-        double mx = 0.0, sq = 0.0;
-        for (int a = 0; a < 3; ++a) {
-            const double half = (double)n[a] * h[a];
-            mx = std::max(mx, half);
-            sq += half * half;
+    return guarded([&]() -> psp_status {
+        if (!out) return fail(PSP_EINVAL, "out is NULL");
+        *out = nullptr;
+        if (!n || !h) return fail(PSP_EINVAL, "n or h is NULL");
+        if (eps <= 0.0 && delta <= 0.0) {
+            // eps = 1e-4 max_p L_p/2 and delta = |(L_1, L_2, L_3)|/2, the corner
+            // of the kernel's truncation box (L_p = 2 n_p h_p)
+            double mx = 0.0, sq = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                const double half = (double)n[a] * h[a];
+                mx = std::max(mx, half);
+                sq += half * half;
+            }
+            eps = 1e-4 * mx;
+            delta = std::sqrt(sq);
         }
-        eps = 1e-4 * mx;
-        delta = std::sqrt(sq);
-    }
-    return create_plan(n, h, R, dtype, eps, delta, out);
+        return create_plan(n, h, R, dtype, eps, delta, out);
+    });
 }
 
 psp_status psp_plan_create_box(int n, const double *h, int R, psp_dtype dtype, double eps, double delta,
                                psp_plan **out) {
-    const int ns[3] = {n, n, n};
-    return psp_plan_create_grid(ns, h, R, dtype, eps, delta, out);
+    return guarded([&]() -> psp_status {
+        const int ns[3] = {n, n, n};
+        return psp_plan_create_grid(ns, h, R, dtype, eps, delta, out);
+    });
 }
 
 psp_status psp_plan_create(int n, double h, int R, psp_dtype dtype, psp_plan **out) {
-    // eps = 1e-4 L/2 and delta = sqrt(3) L/2 with L = 2 n h (the default cutoff
-    // in units where L = 2, and the corner of the kernel's truncation box)
-    const double half = (double)n * h;
-    return psp_plan_create_ex(n, h, R, dtype, 1e-4 * half, std::sqrt(3.0) * half, out);
+    return guarded([&]() -> psp_status {
+        // eps = 1e-4 L/2 and delta = sqrt(3) L/2 with L = 2 n h (the default cutoff
+        // in units where L = 2, and the corner of the kernel's truncation box)
+        const double half = (double)n * h;
+        return psp_plan_create_ex(n, h, R, dtype, 1e-4 * half, std::sqrt(3.0) * half, out);
+    });
 }
 
 static void profile_clear(psp_plan *p) {
@@ -382,272 +393,301 @@ static void profile_clear(psp_plan *p) {
 }
 
 void psp_plan_destroy(psp_plan *p) {
-    if (!p) return;
-    profile_clear(p);
-    for (auto &kv : p->ws) free_workspace(&kv.second);
-    delete p;
+    try {
+        if (!p) return;
+        profile_clear(p);
+        for (auto &kv : p->ws) free_workspace(&kv.second);
+        delete p;
+    } catch (...) {
+    }
 }
 
 psp_status psp_plan_get_gs(const psp_plan *p, double *omega, double *alpha) {
-    if (!p || !omega || !alpha) return fail(PSP_EINVAL, "NULL argument");
-    std::memcpy(omega, p->omega.data(), sizeof(double) * p->R);
-    std::memcpy(alpha, p->alpha.data(), sizeof(double) * p->R);
-    return PSP_OK;
+    return guarded([&]() -> psp_status {
+        if (!p || !omega || !alpha) return fail(PSP_EINVAL, "NULL argument");
+        std::memcpy(omega, p->omega.data(), sizeof(double) * p->R);
+        std::memcpy(alpha, p->alpha.data(), sizeof(double) * p->R);
+        return PSP_OK;
+    });
 }
 
 psp_status psp_plan_get_tables(psp_plan *p, double *J0, double *J2) {
-    if (!p || !J0 || !J2) return fail(PSP_EINVAL, "NULL argument");
-    if (p->precomputed) {
-        psp_status s = current_device_of(p);
-        if (s != PSP_OK) return s;
-    }
-    TableUpload hold;
-    SpecTables tabs;
-    const double *dw = nullptr;
-    double *d = nullptr;
-    psp_status rs = device_tables(p, nullptr, hold, &d, &tabs, &dw);
-    const size_t tb = sizeof(double) * (size_t)p->R * (p->n + 1);
-    hipError_t e = hipSuccess;
-    if (rs == PSP_OK && (e = hipMemcpy(J0, tabs.J0[0], tb, hipMemcpyDeviceToHost)) == hipSuccess)
-        e = hipMemcpy(J2, tabs.J2[0], tb, hipMemcpyDeviceToHost);
-    if (d) (void)hipFree(d);
-    if (rs != PSP_OK) return rs;
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(tables)");
-    return PSP_OK;
-}
-
-psp_status psp_plan_workspace_bytes(const psp_plan *p, size_t *bytes) {
-    if (!p || !bytes) return fail(PSP_EINVAL, "NULL argument");
-    *bytes = p->grid ? workspace_bytes_dims(Dims{p->ns[0], p->ns[1], p->ns[2]}, p->dtype == PSP_F32)
-                     : workspace_bytes(p->n, p->dtype == PSP_F32, p->chunk_tiles, p->i1_group);
-    return PSP_OK;
-}
-
-psp_status psp_plan_spectrum_bytes(const psp_plan *p, size_t *bytes) {
-    if (!p || !bytes) return fail(PSP_EINVAL, "NULL argument");
-    *bytes = p->grid ? spectrum_bytes_dims(Dims{p->ns[0], p->ns[1], p->ns[2]}) : spectrum_bytes(p->n);
-    return PSP_OK;
-}
-
-psp_status psp_kernel_precompute(psp_plan *p, void *stream) {
-    if (!p) return fail(PSP_EINVAL, "plan is NULL");
-    hipStream_t st = (hipStream_t)stream;
-    if (p->precomputed) return current_device_of(p);
-    int dev = -1;
-    PSP_HIP(hipGetDevice(&dev), "hipGetDevice");
-    for (int a = 0; a < 3; ++a) {
-        psp_status rs = get_twiddles(dev, 2 * p->ns[a], &p->tws[a]);
-        if (rs != PSP_OK) return rs;
-    }
-    p->tw = p->tws[0];
-    const SpecKey key{dev, p->ns[0], p->ns[1], p->ns[2], p->hs[0], p->hs[1], p->hs[2], p->R, p->eps, p->delta};
-    std::shared_ptr<DevSpectrum> spec;
-    {
-        std::lock_guard<std::mutex> lk(g_cache_mu);
-        auto it = g_spec_cache.find(key);
-        if (it != g_spec_cache.end()) spec = it->second.lock();
-    }
-    if (!spec) {
-        const int R = p->R, P = pitch_for(p->ns[2]);
-        spec = std::make_shared<DevSpectrum>();
-        spec->device = dev;
-        spec->bytes = spectrum_bytes_dims(Dims{p->ns[0], p->ns[1], p->ns[2]});
-        hipError_t e = hipMalloc(&spec->mult, spec->bytes);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            spec->mult = nullptr;
-            return fail(PSP_ENOMEM, "spectrum allocation of %zu bytes failed", spec->bytes);
+    return guarded([&]() -> psp_status {
+        if (!p || !J0 || !J2) return fail(PSP_EINVAL, "NULL argument");
+        if (p->precomputed) {
+            psp_status s = current_device_of(p);
+            if (s != PSP_OK) return s;
         }
         TableUpload hold;
         SpecTables tabs;
-        const double *dW = nullptr;
-        double *dJ = nullptr;
-        psp_status out = device_tables(p, st, hold, &dJ, &tabs, &dW);
-        do {
-            if (out != PSP_OK) break;
-            hipError_t ee;
-            if ((ee = hipMemsetAsync(spec->mult, 0, spec->bytes, st)) != hipSuccess) {
-                out = hip_fail(ee, "precompute upload");
-                break;
-            }
-            const double pi = 3.14159265358979323846;
-            SpecScale sc;
-            for (int a = 0; a < 3; ++a) sc.w[a] = (2.0 * pi / p->Ls[a]) * (2.0 * pi / p->Ls[a]);
-            sc.scale = -1.0 / ((2.0 * p->ns[0]) * (2.0 * p->ns[1]) * (2.0 * p->ns[2]));
-            if ((ee = launch_spectrum(tabs, dW, R, P, sc, spec->mult, st)) != hipSuccess) {
-                out = hip_fail(ee, "spectrum kernel launch");
-                break;
-            }
-            if ((ee = hipStreamSynchronize(st)) != hipSuccess) {
-                out = hip_fail(ee, "spectrum kernel");
-                break;
-            }
-        } while (0);
-        if (dJ) {
-            if (out != PSP_OK) (void)hipStreamSynchronize(st);   // nothing may still read it
-            (void)hipFree(dJ);
+        const double *dw = nullptr;
+        double *d = nullptr;
+        psp_status rs = device_tables(p, nullptr, hold, &d, &tabs, &dw);
+        const size_t tb = sizeof(double) * (size_t)p->R * (p->n + 1);
+        hipError_t e = hipSuccess;
+        if (rs == PSP_OK && (e = hipMemcpy(J0, tabs.J0[0], tb, hipMemcpyDeviceToHost)) == hipSuccess)
+            e = hipMemcpy(J2, tabs.J2[0], tb, hipMemcpyDeviceToHost);
+        if (d) (void)hipFree(d);
+        if (rs != PSP_OK) return rs;
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpy(tables)");
+        return PSP_OK;
+    });
+}
+
+psp_status psp_plan_workspace_bytes(const psp_plan *p, size_t *bytes) {
+    return guarded([&]() -> psp_status {
+        if (!p || !bytes) return fail(PSP_EINVAL, "NULL argument");
+        *bytes = p->grid ? workspace_bytes_dims(Dims{p->ns[0], p->ns[1], p->ns[2]}, p->dtype == PSP_F32)
+                         : workspace_bytes(p->n, p->dtype == PSP_F32, p->chunk_tiles, p->i1_group);
+        return PSP_OK;
+    });
+}
+
+psp_status psp_plan_spectrum_bytes(const psp_plan *p, size_t *bytes) {
+    return guarded([&]() -> psp_status {
+        if (!p || !bytes) return fail(PSP_EINVAL, "NULL argument");
+        *bytes = p->grid ? spectrum_bytes_dims(Dims{p->ns[0], p->ns[1], p->ns[2]}) : spectrum_bytes(p->n);
+        return PSP_OK;
+    });
+}
+
+psp_status psp_kernel_precompute(psp_plan *p, void *stream) {
+    return guarded([&]() -> psp_status {
+        if (!p) return fail(PSP_EINVAL, "plan is NULL");
+        hipStream_t st = (hipStream_t)stream;
+        if (p->precomputed) return current_device_of(p);
+        int dev = -1;
+        PSP_HIP(hipGetDevice(&dev), "hipGetDevice");
+        for (int a = 0; a < 3; ++a) {
+            psp_status rs = get_twiddles(dev, 2 * p->ns[a], &p->tws[a]);
+            if (rs != PSP_OK) return rs;
         }
-        if (out != PSP_OK) return out;
-        std::lock_guard<std::mutex> lk(g_cache_mu);
-        g_spec_cache[key] = spec;
-    }
-    p->spec = spec;
-    p->device = dev;
-    p->precomputed = true;
-    return PSP_OK;
+        p->tw = p->tws[0];
+        const SpecKey key{dev, p->ns[0], p->ns[1], p->ns[2], p->hs[0], p->hs[1], p->hs[2], p->R, p->eps, p->delta};
+        std::shared_ptr<DevSpectrum> spec;
+        {
+            std::lock_guard<std::mutex> lk(g_cache_mu);
+            auto it = g_spec_cache.find(key);
+            if (it != g_spec_cache.end()) spec = it->second.lock();
+        }
+        if (!spec) {
+            const int R = p->R, P = pitch_for(p->ns[2]);
+            spec = std::make_shared<DevSpectrum>();
+            spec->device = dev;
+            spec->bytes = spectrum_bytes_dims(Dims{p->ns[0], p->ns[1], p->ns[2]});
+            hipError_t e = hipMalloc(&spec->mult, spec->bytes);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                spec->mult = nullptr;
+                return fail(PSP_ENOMEM, "spectrum allocation of %zu bytes failed", spec->bytes);
+            }
+            TableUpload hold;
+            SpecTables tabs;
+            const double *dW = nullptr;
+            double *dJ = nullptr;
+            psp_status out = device_tables(p, st, hold, &dJ, &tabs, &dW);
+            do {
+                if (out != PSP_OK) break;
+                hipError_t ee;
+                if ((ee = hipMemsetAsync(spec->mult, 0, spec->bytes, st)) != hipSuccess) {
+                    out = hip_fail(ee, "precompute upload");
+                    break;
+                }
+                const double pi = 3.14159265358979323846;
+                SpecScale sc;
+                for (int a = 0; a < 3; ++a) sc.w[a] = (2.0 * pi / p->Ls[a]) * (2.0 * pi / p->Ls[a]);
+                sc.scale = -1.0 / ((2.0 * p->ns[0]) * (2.0 * p->ns[1]) * (2.0 * p->ns[2]));
+                if ((ee = launch_spectrum(tabs, dW, R, P, sc, spec->mult, st)) != hipSuccess) {
+                    out = hip_fail(ee, "spectrum kernel launch");
+                    break;
+                }
+                if ((ee = hipStreamSynchronize(st)) != hipSuccess) {
+                    out = hip_fail(ee, "spectrum kernel");
+                    break;
+                }
+            } while (0);
+            if (dJ) {
+                if (out != PSP_OK) (void)hipStreamSynchronize(st);   // nothing may still read it
+                (void)hipFree(dJ);
+            }
+            if (out != PSP_OK) return out;
+            std::lock_guard<std::mutex> lk(g_cache_mu);
+            g_spec_cache[key] = spec;
+        }
+        p->spec = spec;
+        p->device = dev;
+        p->precomputed = true;
+        return PSP_OK;
+    });
 }
 
 psp_status psp_plan_get_multiplier(psp_plan *p, double *m_host) {
-    if (!p || !m_host) return fail(PSP_EINVAL, "NULL argument");
-    if (!p->precomputed) return fail(PSP_ESTATE, "multiplier requested before psp_kernel_precompute");
-    const Dims d{p->ns[0], p->ns[1], p->ns[2]};
-    const int P = pitch_for(d.n3);
-    const size_t bytes = spectrum_bytes_dims(d);
-    std::vector<double> blk(bytes / 8);
-    PSP_HIP(hipMemcpy(blk.data(), p->spec->mult, bytes, hipMemcpyDeviceToHost), "hipMemcpy(mult)");
-    const size_t na = (size_t)d.n1 + 1, nb = (size_t)d.n2 + 1, nc = (size_t)d.n3 + 1;
-    for (size_t a = 0; a < na; ++a)
-        for (size_t b = 0; b < nb; ++b)
-            for (size_t c = 0; c < nc; ++c)
-                m_host[(a * nb + b) * nc + c] = blk[((b * (P / 8) + c / 8) * na + a) * 8 + (c & 7)];
-    return PSP_OK;
+    return guarded([&]() -> psp_status {
+        if (!p || !m_host) return fail(PSP_EINVAL, "NULL argument");
+        if (!p->precomputed) return fail(PSP_ESTATE, "multiplier requested before psp_kernel_precompute");
+        const Dims d{p->ns[0], p->ns[1], p->ns[2]};
+        const int P = pitch_for(d.n3);
+        const size_t bytes = spectrum_bytes_dims(d);
+        std::vector<double> blk(bytes / 8);
+        PSP_HIP(hipMemcpy(blk.data(), p->spec->mult, bytes, hipMemcpyDeviceToHost), "hipMemcpy(mult)");
+        const size_t na = (size_t)d.n1 + 1, nb = (size_t)d.n2 + 1, nc = (size_t)d.n3 + 1;
+        for (size_t a = 0; a < na; ++a)
+            for (size_t b = 0; b < nb; ++b)
+                for (size_t c = 0; c < nc; ++c)
+                    m_host[(a * nb + b) * nc + c] = blk[((b * (P / 8) + c / 8) * na + a) * 8 + (c & 7)];
+        return PSP_OK;
+    });
 }
 
 psp_status psp_solve(psp_plan *p, const void *rho_dev, void *u_dev, void *stream) {
-    if (!p || !rho_dev || !u_dev) return fail(PSP_EINVAL, "NULL argument");
-    if (!p->precomputed) return fail(PSP_ESTATE, "psp_solve before psp_kernel_precompute");
-    if (rho_dev == u_dev) return fail(PSP_EINVAL, "rho and u must not alias");
-    psp_status st = current_device_of(p);
-    if (st != PSP_OK) return st;
-    Workspace *w = nullptr;
-    st = plan_workspace(p, (hipStream_t)stream, &w);
-    if (st != PSP_OK) return st;
-    SolveArgs a = solve_args(p, *w, rho_dev, u_dev);
-    {
-        std::lock_guard<std::mutex> lk(p->mu);
-        if (p->prof_used < p->prof_cap) {
-            a.ev = &p->prof_ev[(size_t)p->prof_nev * p->prof_used];
-            a.ev_pass = &p->prof_pass[(size_t)p->prof_nev * p->prof_used];
-            a.nev = p->prof_nev;
-            p->prof_used++;
+    return guarded([&]() -> psp_status {
+        if (!p || !rho_dev || !u_dev) return fail(PSP_EINVAL, "NULL argument");
+        if (!p->precomputed) return fail(PSP_ESTATE, "psp_solve before psp_kernel_precompute");
+        if (rho_dev == u_dev) return fail(PSP_EINVAL, "rho and u must not alias");
+        psp_status st = current_device_of(p);
+        if (st != PSP_OK) return st;
+        Workspace *w = nullptr;
+        st = plan_workspace(p, (hipStream_t)stream, &w);
+        if (st != PSP_OK) return st;
+        SolveArgs a = solve_args(p, *w, rho_dev, u_dev);
+        {
+            std::lock_guard<std::mutex> lk(p->mu);
+            if (p->prof_used < p->prof_cap) {
+                a.ev = &p->prof_ev[(size_t)p->prof_nev * p->prof_used];
+                a.ev_pass = &p->prof_pass[(size_t)p->prof_nev * p->prof_used];
+                a.nev = p->prof_nev;
+                p->prof_used++;
+            }
         }
-    }
-    hipError_t e = launch_solve(a, (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e, "solve launch");
-    return PSP_OK;
+        hipError_t e = launch_solve(a, (hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(e, "solve launch");
+        return PSP_OK;
+    });
 }
 
 psp_status psp_profile_enable(psp_plan *p, int max_solves) {
-    if (!p || max_solves < 0 || max_solves > 100000) return fail(PSP_EINVAL, "bad profile arguments");
-    if (p->grid) return fail(PSP_EUNSUPPORTED, "per-pass profiling needs equal point counts per axis");
-    std::lock_guard<std::mutex> lk(p->mu);
-    profile_clear(p);
-    p->prof_nev = solve_launches(p->n, p->dtype == PSP_F32, p->chunk_tiles, p->i1_group) + 1;
-    p->prof_ev.resize((size_t)p->prof_nev * max_solves, nullptr);
-    p->prof_pass.assign((size_t)p->prof_nev * max_solves, -1);
-    for (auto &e : p->prof_ev) {
-        // timing only: no system-scope cache writeback at every record
-        if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) {
-            e = nullptr;
-            profile_clear(p);
-            return fail(PSP_EHIP, "hipEventCreate failed");
+    return guarded([&]() -> psp_status {
+        if (!p || max_solves < 0 || max_solves > 100000) return fail(PSP_EINVAL, "bad profile arguments");
+        if (p->grid) return fail(PSP_EUNSUPPORTED, "per-pass profiling needs equal point counts per axis");
+        std::lock_guard<std::mutex> lk(p->mu);
+        profile_clear(p);
+        p->prof_nev = solve_launches(p->n, p->dtype == PSP_F32, p->chunk_tiles, p->i1_group) + 1;
+        p->prof_ev.resize((size_t)p->prof_nev * max_solves, nullptr);
+        p->prof_pass.assign((size_t)p->prof_nev * max_solves, -1);
+        for (auto &e : p->prof_ev) {
+            // timing only: no system-scope cache writeback at every record
+            if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) {
+                e = nullptr;
+                profile_clear(p);
+                return fail(PSP_EHIP, "hipEventCreate failed");
+            }
         }
-    }
-    p->prof_cap = max_solves;
-    return PSP_OK;
+        p->prof_cap = max_solves;
+        return PSP_OK;
+    });
 }
 
 psp_status psp_profile_read(psp_plan *p, int *count, double *pass_ms) {
-    if (!p || !count || !pass_ms) return fail(PSP_EINVAL, "NULL argument");
-    std::lock_guard<std::mutex> lk(p->mu);
-    for (int i = 0; i < 6; ++i) pass_ms[i] = 0.0;
-    *count = p->prof_used;
-    const int nev = p->prof_nev;
-    for (int k = 0; k < p->prof_used; ++k) {
-        hipEvent_t *ev = &p->prof_ev[(size_t)nev * k];
-        const int *pass = &p->prof_pass[(size_t)nev * k];
-        PSP_HIP(hipEventSynchronize(ev[nev - 1]), "hipEventSynchronize");
-        for (int i = 0; i + 1 < nev; ++i) {
-            float ms = 0;
-            PSP_HIP(hipEventElapsedTime(&ms, ev[i], ev[i + 1]), "hipEventElapsedTime");
-            if (pass[i] >= 0 && pass[i] < 5) pass_ms[pass[i]] += ms;
+    return guarded([&]() -> psp_status {
+        if (!p || !count || !pass_ms) return fail(PSP_EINVAL, "NULL argument");
+        std::lock_guard<std::mutex> lk(p->mu);
+        for (int i = 0; i < 6; ++i) pass_ms[i] = 0.0;
+        *count = p->prof_used;
+        const int nev = p->prof_nev;
+        for (int k = 0; k < p->prof_used; ++k) {
+            hipEvent_t *ev = &p->prof_ev[(size_t)nev * k];
+            const int *pass = &p->prof_pass[(size_t)nev * k];
+            PSP_HIP(hipEventSynchronize(ev[nev - 1]), "hipEventSynchronize");
+            for (int i = 0; i + 1 < nev; ++i) {
+                float ms = 0;
+                PSP_HIP(hipEventElapsedTime(&ms, ev[i], ev[i + 1]), "hipEventElapsedTime");
+                if (pass[i] >= 0 && pass[i] < 5) pass_ms[pass[i]] += ms;
+            }
+            float tot = 0;
+            PSP_HIP(hipEventElapsedTime(&tot, ev[0], ev[nev - 1]), "hipEventElapsedTime");
+            pass_ms[5] += tot;
         }
-        float tot = 0;
-        PSP_HIP(hipEventElapsedTime(&tot, ev[0], ev[nev - 1]), "hipEventElapsedTime");
-        pass_ms[5] += tot;
-    }
-    if (p->prof_used > 0)
-        for (int i = 0; i < 6; ++i) pass_ms[i] /= p->prof_used;
-    profile_clear(p);
-    return PSP_OK;
+        if (p->prof_used > 0)
+            for (int i = 0; i < 6; ++i) pass_ms[i] /= p->prof_used;
+        profile_clear(p);
+        return PSP_OK;
+    });
 }
 
 psp_status psp_plan_set_tuning(psp_plan *p, int k3_tiles, int i1_group) {
-    if (!p || k3_tiles < 0 || i1_group < 0) return fail(PSP_EINVAL, "bad tuning arguments");
-    if (p->grid && (k3_tiles != 0 || i1_group != 0))
-        return fail(PSP_EUNSUPPORTED, "k3 chunks and i1 groups need equal point counts per axis");
-    std::lock_guard<std::mutex> lk(p->mu);
-    if (p->prof_cap > 0) return fail(PSP_ESTATE, "cannot change the tuning while profiling");
-    if (k3_tiles != p->chunk_tiles || i1_group != p->i1_group) {
-        // existing workspaces were sized for the old layout
-        if (!p->ws.empty()) (void)hipDeviceSynchronize();
-        for (auto &kv : p->ws) free_workspace(&kv.second);
-        p->ws.clear();
-        p->chunk_tiles = k3_tiles;
-        p->i1_group = i1_group;
-    }
-    return PSP_OK;
+    return guarded([&]() -> psp_status {
+        if (!p || k3_tiles < 0 || i1_group < 0) return fail(PSP_EINVAL, "bad tuning arguments");
+        if (p->grid && (k3_tiles != 0 || i1_group != 0))
+            return fail(PSP_EUNSUPPORTED, "k3 chunks and i1 groups need equal point counts per axis");
+        std::lock_guard<std::mutex> lk(p->mu);
+        if (p->prof_cap > 0) return fail(PSP_ESTATE, "cannot change the tuning while profiling");
+        if (k3_tiles != p->chunk_tiles || i1_group != p->i1_group) {
+            // existing workspaces were sized for the old layout
+            if (!p->ws.empty()) (void)hipDeviceSynchronize();
+            for (auto &kv : p->ws) free_workspace(&kv.second);
+            p->ws.clear();
+            p->chunk_tiles = k3_tiles;
+            p->i1_group = i1_group;
+        }
+        return PSP_OK;
+    });
 }
 
 psp_status psp_debug_guards(int enable) {
-    g_guards.store(enable != 0);
-    return PSP_OK;
+    return guarded([&]() -> psp_status {
+        g_guards.store(enable != 0);
+        return PSP_OK;
+    });
 }
 
 psp_status psp_plan_check_guards(psp_plan *p, int *intact) {
-    if (!p || !intact) return fail(PSP_EINVAL, "NULL argument");
-    std::lock_guard<std::mutex> lk(p->mu);
-    PSP_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
-    bool all = true;
-    for (auto &kv : p->ws) {
-        bool ok = true;
-        psp_status st = check_guards(kv.second, &ok);
-        if (st != PSP_OK) return st;
-        all = all && ok;
-    }
-    *intact = all ? 1 : 0;
-    return PSP_OK;
+    return guarded([&]() -> psp_status {
+        if (!p || !intact) return fail(PSP_EINVAL, "NULL argument");
+        std::lock_guard<std::mutex> lk(p->mu);
+        PSP_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
+        bool all = true;
+        for (auto &kv : p->ws) {
+            bool ok = true;
+            psp_status st = check_guards(kv.second, &ok);
+            if (st != PSP_OK) return st;
+            all = all && ok;
+        }
+        *intact = all ? 1 : 0;
+        return PSP_OK;
+    });
 }
 
 psp_status psp_solve_padded_debug(psp_plan *p, const void *rho_dev, void *upad_dev, void *stream) {
-    if (!p || !rho_dev || !upad_dev) return fail(PSP_EINVAL, "NULL argument");
-    if (!p->precomputed) return fail(PSP_ESTATE, "psp_solve_padded_debug before psp_kernel_precompute");
-    if (p->grid) return fail(PSP_EUNSUPPORTED, "the uncropped output needs equal point counts per axis");
-    // the uncropped passes run over one chunk of all k3 tiles and every i1
-    // slab, which a workspace shrunk by psp_plan_set_tuning cannot hold
-    if (p->chunk_tiles != 0 || p->i1_group != 0)
-        return fail(PSP_EUNSUPPORTED, "the uncropped output needs the default tuning (no k3 chunks, no i1 groups)");
-    psp_status st = current_device_of(p);
-    if (st != PSP_OK) return st;
-    hipStream_t s = (hipStream_t)stream;
-    Workspace *w = nullptr;
-    st = plan_workspace(p, s, &w);
-    if (st != PSP_OK) return st;
-    SolveArgs a = solve_args(p, *w, rho_dev, upad_dev);
-    a.full = true;
-    const size_t c = a.f32 ? 8 : 16, N = 2 * (size_t)p->n;
-    const size_t big = c * N * N * (size_t)a.P;
-    PSP_HIP(hipMalloc(&a.A2, big), "hipMalloc(debug)");
-    if (hipMalloc(&a.Y2, big) != hipSuccess) {
+    return guarded([&]() -> psp_status {
+        if (!p || !rho_dev || !upad_dev) return fail(PSP_EINVAL, "NULL argument");
+        if (!p->precomputed) return fail(PSP_ESTATE, "psp_solve_padded_debug before psp_kernel_precompute");
+        if (p->grid) return fail(PSP_EUNSUPPORTED, "the uncropped output needs equal point counts per axis");
+        // the uncropped passes run over one chunk of all k3 tiles and every i1
+        // slab, which a workspace shrunk by psp_plan_set_tuning cannot hold
+        if (p->chunk_tiles != 0 || p->i1_group != 0)
+            return fail(PSP_EUNSUPPORTED, "the uncropped output needs the default tuning (no k3 chunks, no i1 groups)");
+        psp_status st = current_device_of(p);
+        if (st != PSP_OK) return st;
+        hipStream_t s = (hipStream_t)stream;
+        Workspace *w = nullptr;
+        st = plan_workspace(p, s, &w);
+        if (st != PSP_OK) return st;
+        SolveArgs a = solve_args(p, *w, rho_dev, upad_dev);
+        a.full = true;
+        const size_t c = a.f32 ? 8 : 16, N = 2 * (size_t)p->n;
+        const size_t big = c * N * N * (size_t)a.P;
+        PSP_HIP(hipMalloc(&a.A2, big), "hipMalloc(debug)");
+        if (hipMalloc(&a.Y2, big) != hipSuccess) {
+            (void)hipFree(a.A2);
+            return fail(PSP_ENOMEM, "debug allocation failed");
+        }
+        hipError_t e = launch_solve(a, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
         (void)hipFree(a.A2);
-        return fail(PSP_ENOMEM, "debug allocation failed");
-    }
-    hipError_t e = launch_solve(a, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    (void)hipFree(a.A2);
-    (void)hipFree(a.Y2);
-    if (e != hipSuccess) return hip_fail(e, "padded debug solve");
-    return PSP_OK;
+        (void)hipFree(a.Y2);
+        if (e != hipSuccess) return hip_fail(e, "padded debug solve");
+        return PSP_OK;
+    });
 }
 
 }  // extern "C"

@@ -242,67 +242,71 @@ hipError_t launch_batch(int count, const SolveArgs *args, hipStream_t st) {
 using namespace psp;
 
 extern "C" psp_status psp_set_batch_mode(int mode) {
-    if (mode < 0 || mode > 2) return fail(PSP_EINVAL, "batch mode must be 0, 1 or 2 (got %d)", mode);
-    g_batch_mode.store(mode);
-    return PSP_OK;
+    return guarded([&]() -> psp_status {
+        if (mode < 0 || mode > 2) return fail(PSP_EINVAL, "batch mode must be 0, 1 or 2 (got %d)", mode);
+        g_batch_mode.store(mode);
+        return PSP_OK;
+    });
 }
 
 extern "C" psp_status psp_solve_batched(int count, psp_plan *const *plans, const void *const *rho_dev,
                                         void *const *u_dev, void *stream) {
-    if (count < 0 || (count > 0 && (!plans || !rho_dev || !u_dev))) return fail(PSP_EINVAL, "bad batch arguments");
-    if (count == 0) return PSP_OK;
-    if (count > 65535) return fail(PSP_EINVAL, "at most 65535 solves per batch");
-    for (int i = 0; i < count; ++i) {
-        if (!plans[i] || !rho_dev[i] || !u_dev[i]) return fail(PSP_EINVAL, "NULL entry %d in batch", i);
-        if (!plans[i]->precomputed) return fail(PSP_ESTATE, "batch entry %d not precomputed", i);
-        if (plans[i]->dtype != plans[0]->dtype) return fail(PSP_EINVAL, "batch mixes dtypes");
-        if (plans[i]->device != plans[0]->device) return fail(PSP_EINVAL, "batch mixes devices");
-        if (rho_dev[i] == u_dev[i]) return fail(PSP_EINVAL, "entry %d: rho and u must not alias", i);
-    }
-    int dev = -1;
-    if (hipGetDevice(&dev) != hipSuccess || dev != plans[0]->device)
-        return fail(PSP_EINVAL, "plans were precomputed on device %d, current is %d", plans[0]->device, dev);
-    hipStream_t st = (hipStream_t)stream;
-    const bool f32 = plans[0]->dtype == PSP_F32;
-    std::vector<int> cube, grid;
-    for (int i = 0; i < count; ++i) (plans[i]->grid ? grid : cube).push_back(i);
-    std::lock_guard<std::mutex> lk(g_batch_mu);
-    StreamBatch &B = g_batch[{dev, st}];
-    // grid workspaces first: an allocation failure leaves nothing enqueued
-    std::vector<Workspace *> gws;
-    for (int i : grid) {
-        const psp_plan *p = plans[i];
-        auto key = std::make_pair(std::vector<int>{p->ns[0], p->ns[1], p->ns[2]}, f32);
-        auto it = B.grid_ws.find(key);
-        if (it == B.grid_ws.end()) {
-            Workspace w;
-            psp_status rs = alloc_workspace_dims(Dims{p->ns[0], p->ns[1], p->ns[2]}, f32, &w);
+    return guarded([&]() -> psp_status {
+        if (count < 0 || (count > 0 && (!plans || !rho_dev || !u_dev))) return fail(PSP_EINVAL, "bad batch arguments");
+        if (count == 0) return PSP_OK;
+        if (count > 65535) return fail(PSP_EINVAL, "at most 65535 solves per batch");
+        for (int i = 0; i < count; ++i) {
+            if (!plans[i] || !rho_dev[i] || !u_dev[i]) return fail(PSP_EINVAL, "NULL entry %d in batch", i);
+            if (!plans[i]->precomputed) return fail(PSP_ESTATE, "batch entry %d not precomputed", i);
+            if (plans[i]->dtype != plans[0]->dtype) return fail(PSP_EINVAL, "batch mixes dtypes");
+            if (plans[i]->device != plans[0]->device) return fail(PSP_EINVAL, "batch mixes devices");
+            if (rho_dev[i] == u_dev[i]) return fail(PSP_EINVAL, "entry %d: rho and u must not alias", i);
+        }
+        int dev = -1;
+        if (hipGetDevice(&dev) != hipSuccess || dev != plans[0]->device)
+            return fail(PSP_EINVAL, "plans were precomputed on device %d, current is %d", plans[0]->device, dev);
+        hipStream_t st = (hipStream_t)stream;
+        const bool f32 = plans[0]->dtype == PSP_F32;
+        std::vector<int> cube, grid;
+        for (int i = 0; i < count; ++i) (plans[i]->grid ? grid : cube).push_back(i);
+        std::lock_guard<std::mutex> lk(g_batch_mu);
+        StreamBatch &B = g_batch[{dev, st}];
+        // grid workspaces first: an allocation failure leaves nothing enqueued
+        std::vector<Workspace *> gws;
+        for (int i : grid) {
+            const psp_plan *p = plans[i];
+            auto key = std::make_pair(std::vector<int>{p->ns[0], p->ns[1], p->ns[2]}, f32);
+            auto it = B.grid_ws.find(key);
+            if (it == B.grid_ws.end()) {
+                Workspace w;
+                psp_status rs = alloc_workspace_dims(Dims{p->ns[0], p->ns[1], p->ns[2]}, f32, &w);
+                if (rs != PSP_OK) return rs;
+                it = B.grid_ws.emplace(key, w).first;
+            }
+            gws.push_back(&it->second);
+        }
+        if (!cube.empty()) {
+            std::vector<int> ns;
+            for (int i : cube) ns.push_back(plans[i]->n);
+            std::vector<Workspace *> ws;
+            psp_status rs = batch_workspaces(B, ns, f32, ws);
             if (rs != PSP_OK) return rs;
-            it = B.grid_ws.emplace(key, w).first;
+            std::vector<BatchMember> m(cube.size());
+            for (size_t j = 0; j < cube.size(); ++j) {
+                const int i = cube[j];
+                m[j].job = Job{rho_dev[i], u_dev[i], ws[j]->X, ws[j]->A, plans[i]->spec->mult, nullptr, nullptr};
+                m[j].n = plans[i]->n;
+                m[j].shape = plans[i]->shape;
+                m[j].tw64 = plans[i]->tw->w64;
+            }
+            rs = run_batch(B.stage, m, f32, st);
+            if (rs != PSP_OK) return rs;
         }
-        gws.push_back(&it->second);
-    }
-    if (!cube.empty()) {
-        std::vector<int> ns;
-        for (int i : cube) ns.push_back(plans[i]->n);
-        std::vector<Workspace *> ws;
-        psp_status rs = batch_workspaces(B, ns, f32, ws);
-        if (rs != PSP_OK) return rs;
-        std::vector<BatchMember> m(cube.size());
-        for (size_t j = 0; j < cube.size(); ++j) {
-            const int i = cube[j];
-            m[j].job = Job{rho_dev[i], u_dev[i], ws[j]->X, ws[j]->A, plans[i]->spec->mult, nullptr, nullptr};
-            m[j].n = plans[i]->n;
-            m[j].shape = plans[i]->shape;
-            m[j].tw64 = plans[i]->tw->w64;
+        for (size_t j = 0; j < grid.size(); ++j) {
+            const int i = grid[j];
+            const hipError_t e = launch_solve(solve_args(plans[i], *gws[j], rho_dev[i], u_dev[i]), st);
+            if (e != hipSuccess) return hip_fail(e, "batched grid solve");
         }
-        rs = run_batch(B.stage, m, f32, st);
-        if (rs != PSP_OK) return rs;
-    }
-    for (size_t j = 0; j < grid.size(); ++j) {
-        const int i = grid[j];
-        const hipError_t e = launch_solve(solve_args(plans[i], *gws[j], rho_dev[i], u_dev[i]), st);
-        if (e != hipSuccess) return hip_fail(e, "batched grid solve");
-    }
-    return PSP_OK;
+        return PSP_OK;
+    });
 }

@@ -4,7 +4,9 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <exception>
 #include <map>
+#include <new>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -19,6 +21,20 @@ namespace psp {
 // thread-local error detail; returns e for convenience
 psp_status fail(psp_status e, const char *fmt, ...);
 psp_status hip_fail(hipError_t err, const char *what);
+
+// Runs an entry point's body so that no C++ exception crosses the C ABI: a
+// failed host allocation becomes PSP_ENOMEM, anything else PSP_EHIP.
+template <typename F> psp_status guarded(F &&body) noexcept {
+    try {
+        return body();
+    } catch (const std::bad_alloc &) {
+        return fail(PSP_ENOMEM, "host memory allocation failed");
+    } catch (const std::exception &e) {
+        return fail(PSP_EHIP, "internal error: %s", e.what());
+    } catch (...) {
+        return fail(PSP_EHIP, "internal error");
+    }
+}
 
 // ---- S0: Gaussian-sum weights and exponents (sinc quadrature) -------------
 void gs_fit(int R, double eps, double delta, std::vector<double> &omega, std::vector<double> &alpha);

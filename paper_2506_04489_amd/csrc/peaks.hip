@@ -49,53 +49,55 @@ using namespace psp;
 
 extern "C" psp_status psp_device_peaks(void *buf_a, void *buf_b, size_t bytes, void *stream, double *copy_gbps,
                                        double *fp64_mfma_tflops) {
-    if (!buf_a || !buf_b || !copy_gbps || !fp64_mfma_tflops) return fail(PSP_EINVAL, "NULL argument");
-    if (bytes < (1u << 20) || (bytes & 15)) return fail(PSP_EINVAL, "bytes must be >= 1 MiB and a multiple of 16");
-    hipStream_t st = (hipStream_t)stream;
-    int dev = -1, cus = 0;
-    hipError_t he = hipGetDevice(&dev);
-    if (he == hipSuccess) he = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (he != hipSuccess) return hip_fail(he, "device query");
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if ((he = hipEventCreate(&e0)) != hipSuccess) return hip_fail(he, "hipEventCreate");
-    if ((he = hipEventCreate(&e1)) != hipSuccess) {
-        (void)hipEventDestroy(e0);
-        return hip_fail(he, "hipEventCreate");
-    }
-    psp_status out = PSP_OK;
-    auto timed = [&](auto launch, int reps, float *best) -> hipError_t {
-        hipError_t e = hipSuccess;
-        *best = 1e30f;
-        for (int r = 0; r < reps + 1 && e == hipSuccess; ++r) {   // the first run warms up
-            if ((e = hipEventRecord(e0, st)) != hipSuccess) break;
-            launch();
-            if ((e = hipGetLastError()) != hipSuccess || (e = hipEventRecord(e1, st)) != hipSuccess ||
-                (e = hipEventSynchronize(e1)) != hipSuccess)
-                break;
-            float ms = 0;
-            if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
-            if (r > 0) *best = std::min(*best, ms);
+    return guarded([&]() -> psp_status {
+        if (!buf_a || !buf_b || !copy_gbps || !fp64_mfma_tflops) return fail(PSP_EINVAL, "NULL argument");
+        if (bytes < (1u << 20) || (bytes & 15)) return fail(PSP_EINVAL, "bytes must be >= 1 MiB and a multiple of 16");
+        hipStream_t st = (hipStream_t)stream;
+        int dev = -1, cus = 0;
+        hipError_t he = hipGetDevice(&dev);
+        if (he == hipSuccess) he = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (he != hipSuccess) return hip_fail(he, "device query");
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if ((he = hipEventCreate(&e0)) != hipSuccess) return hip_fail(he, "hipEventCreate");
+        if ((he = hipEventCreate(&e1)) != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            return hip_fail(he, "hipEventCreate");
         }
-        return e;
-    };
-    const size_t count = bytes / 16;
-    float ms = 0;
-    hipError_t e = timed(
-        [&] {
-            hipLaunchKernelGGL(k_peak_copy, dim3(cus * 16), dim3(256), 0, st, (const double2 *)buf_a, (double2 *)buf_b,
-                               count);
-        },
-        5, &ms);
-    if (e != hipSuccess) out = hip_fail(e, "copy peak");
-    else *copy_gbps = 2.0 * (double)bytes / (ms * 1e-3) / 1e9;
-    if (out == PSP_OK) {
-        const int iters = 2048, blocks = cus * 8;    // 4 waves per block
-        e = timed([&] { hipLaunchKernelGGL(k_peak_mfma, dim3(blocks), dim3(256), 0, st, (double *)buf_b, iters, 1e-3); },
-                  5, &ms);
-        if (e != hipSuccess) out = hip_fail(e, "MFMA peak");
-        else *fp64_mfma_tflops = (double)blocks * 4 * iters * PEAK_ACC * 2048.0 / (ms * 1e-3) / 1e12;
-    }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    return out;
+        psp_status out = PSP_OK;
+        auto timed = [&](auto launch, int reps, float *best) -> hipError_t {
+            hipError_t e = hipSuccess;
+            *best = 1e30f;
+            for (int r = 0; r < reps + 1 && e == hipSuccess; ++r) {   // the first run warms up
+                if ((e = hipEventRecord(e0, st)) != hipSuccess) break;
+                launch();
+                if ((e = hipGetLastError()) != hipSuccess || (e = hipEventRecord(e1, st)) != hipSuccess ||
+                    (e = hipEventSynchronize(e1)) != hipSuccess)
+                    break;
+                float ms = 0;
+                if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+                if (r > 0) *best = std::min(*best, ms);
+            }
+            return e;
+        };
+        const size_t count = bytes / 16;
+        float ms = 0;
+        hipError_t e = timed(
+            [&] {
+                hipLaunchKernelGGL(k_peak_copy, dim3(cus * 16), dim3(256), 0, st, (const double2 *)buf_a, (double2 *)buf_b,
+                                   count);
+            },
+            5, &ms);
+        if (e != hipSuccess) out = hip_fail(e, "copy peak");
+        else *copy_gbps = 2.0 * (double)bytes / (ms * 1e-3) / 1e9;
+        if (out == PSP_OK) {
+            const int iters = 2048, blocks = cus * 8;    // 4 waves per block
+            e = timed([&] { hipLaunchKernelGGL(k_peak_mfma, dim3(blocks), dim3(256), 0, st, (double *)buf_b, iters, 1e-3); },
+                      5, &ms);
+            if (e != hipSuccess) out = hip_fail(e, "MFMA peak");
+            else *fp64_mfma_tflops = (double)blocks * 4 * iters * PEAK_ACC * 2048.0 / (ms * 1e-3) / 1e12;
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return out;
+    });
 }

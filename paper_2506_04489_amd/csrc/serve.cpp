@@ -225,121 +225,159 @@ static void retire(psp_server *sv, bool wait) {
     }
 }
 
+// One scheduling round: retire finished batches, admit and launch what fits.
+// Returns true once the server is stopping and nothing is left.
+static bool schedule_round(psp_server *sv) {
+    retire(sv, false);
+    // snapshot the queue head under the lock
+    std::vector<std::pair<uint64_t, ServeReq>> cand;
+    {
+        std::unique_lock<std::mutex> lk(sv->mu);
+        if (sv->queue.empty() && sv->inflight.empty()) {
+            if (sv->stop) return true;
+            sv->cv_work.wait_for(lk, std::chrono::milliseconds(2));
+            return false;
+        }
+        for (uint64_t id : sv->queue) {
+            if ((int)cand.size() + sv->slots_used >= sv->max_slots) break;
+            cand.emplace_back(id, sv->reqs[id]);
+        }
+    }
+    // admit in order; batches per (tier, size class), so that a small
+    // request never waits for a large one's completion event
+    std::vector<uint64_t> admitted;
+    std::vector<SolveArgs> args[kBatchKinds];
+    std::vector<uint64_t> ids[kBatchKinds];
+    std::vector<PooledWs> wss[kBatchKinds];
+    std::vector<std::tuple<int, double, int>> keys[kBatchKinds];
+    for (auto &c : cand) {
+        const ServeReq &r = c.second;
+        const auto key = std::make_tuple(r.n, r.h, r.R);
+        const bool f32 = r.tier == PSP_F32;
+        auto sit = sv->specs.find(key);
+        const bool cached = sit != sv->specs.end() && (sit->second.plan[0] || sit->second.plan[1]);
+        bool have_ws = false;
+        for (auto &p : sv->pool) have_ws |= (p.n == r.n && p.f32 == f32);
+        const size_t need = (cached ? 0 : spectrum_bytes(r.n)) + (have_ws ? 0 : ws_bytes(r.n, f32));
+        if (!make_room(sv, need, &key)) break;   // head of line waits for memory
+        psp_plan *p = nullptr;
+        bool hit = false;
+        psp_status st = get_plan(sv, r, &p, &hit);
+        PooledWs w;
+        if (st == PSP_OK) st = take_ws(sv, r.n, f32, &w);
+        admitted.push_back(c.first);
+        if (st != PSP_OK) {
+            finish(sv, c.first, st);
+            continue;
+        }
+        (hit ? sv->hits : sv->misses)++;
+        sv->specs[key].users++;
+        const int t = (f32 ? 1 : 0) + (r.n > kSmallN ? 2 : 0);
+        args[t].push_back(solve_args(p, w.w, r.rho, r.u));
+        ids[t].push_back(c.first);
+        wss[t].push_back(w);
+        keys[t].push_back(key);
+    }
+    if (!admitted.empty()) {
+        // claim the admitted requests; one canceled since the snapshot is
+        // no longer queued (and already finished): drop it from the launch
+        std::vector<uint64_t> gone;
+        {
+            std::lock_guard<std::mutex> lk(sv->mu);
+            for (uint64_t id : admitted) {
+                auto it = std::find(sv->queue.begin(), sv->queue.end(), id);
+                if (it != sv->queue.end())
+                    sv->queue.erase(it);
+                else
+                    gone.push_back(id);
+            }
+        }
+        for (uint64_t id : gone)
+            for (int t = 0; t < kBatchKinds; ++t)
+                for (size_t i = 0; i < ids[t].size(); ++i)
+                    if (ids[t][i] == id) {
+                        sv->pool.push_back(wss[t][i]);
+                        sv->specs[keys[t][i]].users--;
+                        ids[t].erase(ids[t].begin() + i);
+                        wss[t].erase(wss[t].begin() + i);
+                        keys[t].erase(keys[t].begin() + i);
+                        args[t].erase(args[t].begin() + i);
+                        break;
+                    }
+    }
+    for (int t = 0; t < kBatchKinds; ++t) {
+        if (ids[t].empty()) continue;
+        // the stream with the fewest batches in flight
+        std::vector<int> load(sv->streams.size(), 0);
+        for (auto &b : sv->inflight) load[b.stream]++;
+        const int si = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        hipStream_t st = sv->streams[si];
+        Batch b;
+        b.stream = si;
+        hipError_t e = launch_batch((int)args[t].size(), args[t].data(), st);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b.ev, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(b.ev, st);
+        if (e != hipSuccess) {
+            for (uint64_t id : ids[t]) finish(sv, id, PSP_EHIP);
+            for (auto &w : wss[t]) sv->pool.push_back(w);
+            for (auto &k : keys[t]) sv->specs[k].users--;
+            continue;
+        }
+        b.ids = ids[t];
+        b.ws = wss[t];
+        b.keys = keys[t];
+        sv->slots_used += (int)b.ids.size();
+        sv->inflight.push_back(std::move(b));
+    }
+    if (admitted.empty()) {
+        // nothing admitted: wait for a completion or a new request
+        if (!sv->inflight.empty()) {
+            std::this_thread::sleep_for(std::chrono::microseconds(20));
+        } else {
+            std::unique_lock<std::mutex> lk(sv->mu);
+            sv->cv_work.wait_for(lk, std::chrono::milliseconds(1));
+        }
+    }
+    return false;
+}
+
+// A host allocation failed inside a round: the requests that round had taken
+// off the queue but not launched are finished with PSP_ENOMEM, so that no
+// caller waits for them; queued and in-flight requests carry on.  (Their
+// workspaces and spectrum references of that round are not returned.)
+static void fail_unlaunched(psp_server *sv) noexcept {
+    try {
+        std::vector<uint64_t> live;
+        for (auto &b : sv->inflight) live.insert(live.end(), b.ids.begin(), b.ids.end());
+        std::lock_guard<std::mutex> lk(sv->mu);
+        std::vector<uint64_t> lost;
+        for (auto &kv : sv->reqs) {
+            if (kv.second.done) continue;
+            if (std::find(sv->queue.begin(), sv->queue.end(), kv.first) != sv->queue.end()) continue;
+            if (std::find(live.begin(), live.end(), kv.first) != live.end()) continue;
+            lost.push_back(kv.first);
+        }
+        for (uint64_t id : lost) finish_locked(sv, id, PSP_ENOMEM);
+    } catch (...) {
+    }
+}
+
 static void scheduler(psp_server *sv) {
     (void)hipSetDevice(sv->device);
     for (;;) {
-        retire(sv, false);
-        // snapshot the queue head under the lock
-        std::vector<std::pair<uint64_t, ServeReq>> cand;
-        {
-            std::unique_lock<std::mutex> lk(sv->mu);
-            if (sv->queue.empty() && sv->inflight.empty()) {
-                if (sv->stop) break;
-                sv->cv_work.wait_for(lk, std::chrono::milliseconds(2));
-                continue;
-            }
-            for (uint64_t id : sv->queue) {
-                if ((int)cand.size() + sv->slots_used >= sv->max_slots) break;
-                cand.emplace_back(id, sv->reqs[id]);
-            }
+        bool stop = false;
+        try {
+            stop = schedule_round(sv);
+        } catch (...) {
+            fail_unlaunched(sv);
+            std::this_thread::sleep_for(std::chrono::milliseconds(1));
         }
-        // admit in order; batches per (tier, size class), so that a small
-        // request never waits for a large one's completion event
-        std::vector<uint64_t> admitted;
-        std::vector<SolveArgs> args[kBatchKinds];
-        std::vector<uint64_t> ids[kBatchKinds];
-        std::vector<PooledWs> wss[kBatchKinds];
-        std::vector<std::tuple<int, double, int>> keys[kBatchKinds];
-        for (auto &c : cand) {
-            const ServeReq &r = c.second;
-            const auto key = std::make_tuple(r.n, r.h, r.R);
-            const bool f32 = r.tier == PSP_F32;
-            auto sit = sv->specs.find(key);
-            const bool cached = sit != sv->specs.end() && (sit->second.plan[0] || sit->second.plan[1]);
-            bool have_ws = false;
-            for (auto &p : sv->pool) have_ws |= (p.n == r.n && p.f32 == f32);
-            const size_t need = (cached ? 0 : spectrum_bytes(r.n)) + (have_ws ? 0 : ws_bytes(r.n, f32));
-            if (!make_room(sv, need, &key)) break;   // head of line waits for memory
-            psp_plan *p = nullptr;
-            bool hit = false;
-            psp_status st = get_plan(sv, r, &p, &hit);
-            PooledWs w;
-            if (st == PSP_OK) st = take_ws(sv, r.n, f32, &w);
-            admitted.push_back(c.first);
-            if (st != PSP_OK) {
-                finish(sv, c.first, st);
-                continue;
-            }
-            (hit ? sv->hits : sv->misses)++;
-            sv->specs[key].users++;
-            const int t = (f32 ? 1 : 0) + (r.n > kSmallN ? 2 : 0);
-            args[t].push_back(solve_args(p, w.w, r.rho, r.u));
-            ids[t].push_back(c.first);
-            wss[t].push_back(w);
-            keys[t].push_back(key);
-        }
-        if (!admitted.empty()) {
-            // claim the admitted requests; one canceled since the snapshot is
-            // no longer queued (and already finished): drop it from the launch
-            std::vector<uint64_t> gone;
-            {
-                std::lock_guard<std::mutex> lk(sv->mu);
-                for (uint64_t id : admitted) {
-                    auto it = std::find(sv->queue.begin(), sv->queue.end(), id);
-                    if (it != sv->queue.end())
-                        sv->queue.erase(it);
-                    else
-                        gone.push_back(id);
-                }
-            }
-            for (uint64_t id : gone)
-                for (int t = 0; t < kBatchKinds; ++t)
-                    for (size_t i = 0; i < ids[t].size(); ++i)
-                        if (ids[t][i] == id) {
-                            sv->pool.push_back(wss[t][i]);
-                            sv->specs[keys[t][i]].users--;
-                            ids[t].erase(ids[t].begin() + i);
-                            wss[t].erase(wss[t].begin() + i);
-                            keys[t].erase(keys[t].begin() + i);
-                            args[t].erase(args[t].begin() + i);
-                            break;
-                        }
-        }
-        for (int t = 0; t < kBatchKinds; ++t) {
-            if (ids[t].empty()) continue;
-            // the stream with the fewest batches in flight
-            std::vector<int> load(sv->streams.size(), 0);
-            for (auto &b : sv->inflight) load[b.stream]++;
-            const int si = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-            hipStream_t st = sv->streams[si];
-            Batch b;
-            b.stream = si;
-            hipError_t e = launch_batch((int)args[t].size(), args[t].data(), st);
-            if (e == hipSuccess) e = hipEventCreateWithFlags(&b.ev, hipEventDisableTiming);
-            if (e == hipSuccess) e = hipEventRecord(b.ev, st);
-            if (e != hipSuccess) {
-                for (uint64_t id : ids[t]) finish(sv, id, PSP_EHIP);
-                for (auto &w : wss[t]) sv->pool.push_back(w);
-                for (auto &k : keys[t]) sv->specs[k].users--;
-                continue;
-            }
-            b.ids = ids[t];
-            b.ws = wss[t];
-            b.keys = keys[t];
-            sv->slots_used += (int)b.ids.size();
-            sv->inflight.push_back(std::move(b));
-        }
-        if (admitted.empty()) {
-            // nothing admitted: wait for a completion or a new request
-            if (!sv->inflight.empty()) {
-                std::this_thread::sleep_for(std::chrono::microseconds(20));
-            } else {
-                std::unique_lock<std::mutex> lk(sv->mu);
-                sv->cv_work.wait_for(lk, std::chrono::milliseconds(1));
-            }
-        }
+        if (stop) break;
     }
-    retire(sv, true);
+    try {
+        retire(sv, true);
+    } catch (...) {
+    }
 }
 
 }  // namespace psp
@@ -347,116 +385,131 @@ static void scheduler(psp_server *sv) {
 extern "C" {
 
 psp_status psp_serve_create(size_t hbm_budget_bytes, int max_slots, psp_server **out) {
-    if (!out) return fail(PSP_EINVAL, "out is NULL");
-    *out = nullptr;
-    if (hbm_budget_bytes == 0 || max_slots < 1) return fail(PSP_EINVAL, "budget and max_slots must be positive");
-    psp_server *sv = new (std::nothrow) psp_server;
-    if (!sv) return fail(PSP_ENOMEM, "host allocation failed");
-    sv->budget = hbm_budget_bytes;
-    sv->max_slots = max_slots;
-    if (hipGetDevice(&sv->device) != hipSuccess) {
-        delete sv;
-        return fail(PSP_EHIP, "hipGetDevice failed");
-    }
-    for (int i = 0; i < 4; ++i) {
-        hipStream_t s;
-        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
-            for (auto x : sv->streams) (void)hipStreamDestroy(x);
+    return guarded([&]() -> psp_status {
+        if (!out) return fail(PSP_EINVAL, "out is NULL");
+        *out = nullptr;
+        if (hbm_budget_bytes == 0 || max_slots < 1) return fail(PSP_EINVAL, "budget and max_slots must be positive");
+        psp_server *sv = new (std::nothrow) psp_server;
+        if (!sv) return fail(PSP_ENOMEM, "host allocation failed");
+        sv->budget = hbm_budget_bytes;
+        sv->max_slots = max_slots;
+        if (hipGetDevice(&sv->device) != hipSuccess) {
             delete sv;
-            return fail(PSP_EHIP, "hipStreamCreate failed");
+            return fail(PSP_EHIP, "hipGetDevice failed");
         }
-        sv->streams.push_back(s);
-    }
-    sv->sched = std::thread(scheduler, sv);
-    *out = sv;
-    return PSP_OK;
+        for (int i = 0; i < 4; ++i) {
+            hipStream_t s;
+            if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+                for (auto x : sv->streams) (void)hipStreamDestroy(x);
+                delete sv;
+                return fail(PSP_EHIP, "hipStreamCreate failed");
+            }
+            sv->streams.push_back(s);
+        }
+        sv->sched = std::thread(scheduler, sv);
+        *out = sv;
+        return PSP_OK;
+    });
 }
 
 psp_status psp_serve_submit(psp_server *sv, int n, double h, int R, psp_dtype tier, const void *rho_dev,
                             void *u_dev, uint64_t *ticket) {
-    if (!sv || !rho_dev || !u_dev || !ticket) return fail(PSP_EINVAL, "NULL argument");
-    if (tier != PSP_F64 && tier != PSP_F32) return fail(PSP_EINVAL, "unknown tier");
-    const double half = (double)n * h;
-    psp_status st = check_create(n, h, R, 1e-4 * half, std::sqrt(3.0) * half);
-    if (st != PSP_OK) return st;
-    if (spectrum_bytes(n) + ws_bytes(n, tier == PSP_F32) > sv->budget)
-        return fail(PSP_ENOMEM, "request footprint exceeds the whole budget");
-    std::lock_guard<std::mutex> lk(sv->mu);
-    if (sv->queue.size() >= 65536) return fail(PSP_EBUSY, "queue full");
-    ServeReq r;
-    r.n = n;
-    r.h = h;
-    r.R = R;
-    r.tier = tier;
-    r.rho = rho_dev;
-    r.u = u_dev;
-    r.t_submit = Clock::now();
-    const uint64_t id = sv->next_id++;
-    sv->reqs.emplace(id, r);
-    sv->queue.push_back(id);
-    sv->pending_total++;
-    *ticket = id;
-    sv->cv_work.notify_one();
-    return PSP_OK;
+    return guarded([&]() -> psp_status {
+        if (!sv || !rho_dev || !u_dev || !ticket) return fail(PSP_EINVAL, "NULL argument");
+        if (tier != PSP_F64 && tier != PSP_F32) return fail(PSP_EINVAL, "unknown tier");
+        const double half = (double)n * h;
+        psp_status st = check_create(n, h, R, 1e-4 * half, std::sqrt(3.0) * half);
+        if (st != PSP_OK) return st;
+        if (spectrum_bytes(n) + ws_bytes(n, tier == PSP_F32) > sv->budget)
+            return fail(PSP_ENOMEM, "request footprint exceeds the whole budget");
+        std::lock_guard<std::mutex> lk(sv->mu);
+        if (sv->queue.size() >= 65536) return fail(PSP_EBUSY, "queue full");
+        ServeReq r;
+        r.n = n;
+        r.h = h;
+        r.R = R;
+        r.tier = tier;
+        r.rho = rho_dev;
+        r.u = u_dev;
+        r.t_submit = Clock::now();
+        const uint64_t id = sv->next_id++;
+        sv->reqs.emplace(id, r);
+        sv->queue.push_back(id);
+        sv->pending_total++;
+        *ticket = id;
+        sv->cv_work.notify_one();
+        return PSP_OK;
+    });
 }
 
 psp_status psp_serve_cancel(psp_server *sv, uint64_t ticket) {
-    if (!sv) return fail(PSP_EINVAL, "server is NULL");
-    std::lock_guard<std::mutex> lk(sv->mu);
-    auto it = sv->reqs.find(ticket);
-    if (it == sv->reqs.end() || it->second.done)
-        return fail(PSP_EINVAL, "unknown or finished ticket %llu", (unsigned long long)ticket);
-    auto q = std::find(sv->queue.begin(), sv->queue.end(), ticket);
-    if (q == sv->queue.end()) return fail(PSP_EBUSY, "request %llu is on the device", (unsigned long long)ticket);
-    sv->queue.erase(q);
-    finish_locked(sv, ticket, PSP_ECANCELED);
-    return PSP_OK;
+    return guarded([&]() -> psp_status {
+        if (!sv) return fail(PSP_EINVAL, "server is NULL");
+        std::lock_guard<std::mutex> lk(sv->mu);
+        auto it = sv->reqs.find(ticket);
+        if (it == sv->reqs.end() || it->second.done)
+            return fail(PSP_EINVAL, "unknown or finished ticket %llu", (unsigned long long)ticket);
+        auto q = std::find(sv->queue.begin(), sv->queue.end(), ticket);
+        if (q == sv->queue.end()) return fail(PSP_EBUSY, "request %llu is on the device", (unsigned long long)ticket);
+        sv->queue.erase(q);
+        finish_locked(sv, ticket, PSP_ECANCELED);
+        return PSP_OK;
+    });
 }
 
 psp_status psp_serve_poll(psp_server *sv, uint64_t ticket, int *done, psp_status *result, double *latency_ms) {
-    if (!sv) return fail(PSP_EINVAL, "server is NULL");
-    std::lock_guard<std::mutex> lk(sv->mu);
-    auto it = sv->reqs.find(ticket);
-    if (it == sv->reqs.end())
-        return fail(PSP_EINVAL, "unknown or expired ticket %llu", (unsigned long long)ticket);
-    if (done) *done = it->second.done ? 1 : 0;
-    if (result) *result = it->second.result;
-    if (latency_ms) *latency_ms = it->second.latency_ms;
-    return PSP_OK;
+    return guarded([&]() -> psp_status {
+        if (!sv) return fail(PSP_EINVAL, "server is NULL");
+        std::lock_guard<std::mutex> lk(sv->mu);
+        auto it = sv->reqs.find(ticket);
+        if (it == sv->reqs.end())
+            return fail(PSP_EINVAL, "unknown or expired ticket %llu", (unsigned long long)ticket);
+        if (done) *done = it->second.done ? 1 : 0;
+        if (result) *result = it->second.result;
+        if (latency_ms) *latency_ms = it->second.latency_ms;
+        return PSP_OK;
+    });
 }
 
 psp_status psp_serve_drain(psp_server *sv) {
-    if (!sv) return fail(PSP_EINVAL, "server is NULL");
-    std::unique_lock<std::mutex> lk(sv->mu);
-    sv->cv_done.wait(lk, [&] { return sv->pending_total == 0; });
-    return PSP_OK;
+    return guarded([&]() -> psp_status {
+        if (!sv) return fail(PSP_EINVAL, "server is NULL");
+        std::unique_lock<std::mutex> lk(sv->mu);
+        sv->cv_done.wait(lk, [&] { return sv->pending_total == 0; });
+        return PSP_OK;
+    });
 }
 
 psp_status psp_serve_stats(psp_server *sv, size_t *bytes_in_use, size_t *bytes_peak, uint64_t *completed,
                            uint64_t *cache_hits, uint64_t *cache_misses) {
-    if (!sv) return fail(PSP_EINVAL, "server is NULL");
-    if (bytes_in_use) *bytes_in_use = sv->bytes_in_use.load();
-    if (bytes_peak) *bytes_peak = sv->bytes_peak.load();
-    if (completed) *completed = sv->completed.load();
-    if (cache_hits) *cache_hits = sv->hits.load();
-    if (cache_misses) *cache_misses = sv->misses.load();
-    return PSP_OK;
+    return guarded([&]() -> psp_status {
+        if (!sv) return fail(PSP_EINVAL, "server is NULL");
+        if (bytes_in_use) *bytes_in_use = sv->bytes_in_use.load();
+        if (bytes_peak) *bytes_peak = sv->bytes_peak.load();
+        if (completed) *completed = sv->completed.load();
+        if (cache_hits) *cache_hits = sv->hits.load();
+        if (cache_misses) *cache_misses = sv->misses.load();
+        return PSP_OK;
+    });
 }
 
 void psp_serve_destroy(psp_server *sv) {
-    if (!sv) return;
-    psp_serve_drain(sv);
-    {
-        std::lock_guard<std::mutex> lk(sv->mu);
-        sv->stop = true;
-        sv->cv_work.notify_all();
+    try {
+        if (!sv) return;
+        psp_serve_drain(sv);
+        {
+            std::lock_guard<std::mutex> lk(sv->mu);
+            sv->stop = true;
+            sv->cv_work.notify_all();
+        }
+        sv->sched.join();
+        for (auto &w : sv->pool) free_ws(sv, w);
+        for (auto &kv : sv->specs)
+            for (int t = 0; t < 2; ++t) psp_plan_destroy(kv.second.plan[t]);
+        for (auto s : sv->streams) (void)hipStreamDestroy(s);
+        delete sv;
+    } catch (...) {
     }
-    sv->sched.join();
-    for (auto &w : sv->pool) free_ws(sv, w);
-    for (auto &kv : sv->specs)
-        for (int t = 0; t < 2; ++t) psp_plan_destroy(kv.second.plan[t]);
-    for (auto s : sv->streams) (void)hipStreamDestroy(s);
-    delete sv;
 }
 
 }  // extern "C"

@@ -72,161 +72,171 @@ using namespace psp;
 extern "C" {
 
 psp_status psp_plan_set_shape(psp_plan *p, const int *plan, const int *tile) {
-    if (!p) return fail(PSP_EINVAL, "plan is NULL");
-    if (p->grid) return fail(PSP_EUNSUPPORTED, "launch shapes of a plan with unequal point counts come from the table");
-    Shape s;
-    psp_status rs = shape_from(p->n, plan, tile, &s);
-    if (rs != PSP_OK) return rs;
-    std::lock_guard<std::mutex> lk(p->mu);
-    p->shape = s;
-    return PSP_OK;
+    return guarded([&]() -> psp_status {
+        if (!p) return fail(PSP_EINVAL, "plan is NULL");
+        if (p->grid) return fail(PSP_EUNSUPPORTED, "launch shapes of a plan with unequal point counts come from the table");
+        Shape s;
+        psp_status rs = shape_from(p->n, plan, tile, &s);
+        if (rs != PSP_OK) return rs;
+        std::lock_guard<std::mutex> lk(p->mu);
+        p->shape = s;
+        return PSP_OK;
+    });
 }
 
 psp_status psp_plan_get_shape(const psp_plan *p, int *plan, int *tile) {
-    if (!p || !plan || !tile) return fail(PSP_EINVAL, "NULL argument");
-    shape_to(p->shape, plan, tile);
-    return PSP_OK;
+    return guarded([&]() -> psp_status {
+        if (!p || !plan || !tile) return fail(PSP_EINVAL, "NULL argument");
+        shape_to(p->shape, plan, tile);
+        return PSP_OK;
+    });
 }
 
 psp_status psp_tuning_set(int n, psp_dtype dtype, const int *plan, const int *tile) {
-    if (dtype != PSP_F64 && dtype != PSP_F32) return fail(PSP_EINVAL, "unknown dtype %d", (int)dtype);
-    if (n < 4 || n > 384 || (n & 1) || !supported_length(2 * n)) return fail(PSP_EUNSUPPORTED, "unsupported n = %d", n);
-    Shape s;
-    psp_status rs = shape_from(n, plan, tile, &s);
-    if (rs != PSP_OK) return rs;
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune[{n, dtype == PSP_F32}] = s;
-    return PSP_OK;
+    return guarded([&]() -> psp_status {
+        if (dtype != PSP_F64 && dtype != PSP_F32) return fail(PSP_EINVAL, "unknown dtype %d", (int)dtype);
+        if (n < 4 || n > 384 || (n & 1) || !supported_length(2 * n)) return fail(PSP_EUNSUPPORTED, "unsupported n = %d", n);
+        Shape s;
+        psp_status rs = shape_from(n, plan, tile, &s);
+        if (rs != PSP_OK) return rs;
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[{n, dtype == PSP_F32}] = s;
+        return PSP_OK;
+    });
 }
 
 psp_status psp_tuning_get(int n, psp_dtype dtype, int *plan, int *tile) {
-    if (!plan || !tile) return fail(PSP_EINVAL, "NULL argument");
-    if (dtype != PSP_F64 && dtype != PSP_F32) return fail(PSP_EINVAL, "unknown dtype %d", (int)dtype);
-    shape_to(tuned_shape(n, dtype == PSP_F32), plan, tile);
-    return PSP_OK;
+    return guarded([&]() -> psp_status {
+        if (!plan || !tile) return fail(PSP_EINVAL, "NULL argument");
+        if (dtype != PSP_F64 && dtype != PSP_F32) return fail(PSP_EINVAL, "unknown dtype %d", (int)dtype);
+        shape_to(tuned_shape(n, dtype == PSP_F32), plan, tile);
+        return PSP_OK;
+    });
 }
 
 psp_status psp_autotune(psp_plan *p, int reps, void *stream, int *best_plan, int *best_tile, float *best_ms,
                         float *cand_ms) {
-    if (!p) return fail(PSP_EINVAL, "plan is NULL");
-    if (reps < 1 || reps > 1000) return fail(PSP_EINVAL, "reps must be in [1, 1000] (got %d)", reps);
-    if (!p->precomputed) return fail(PSP_ESTATE, "autotune before psp_kernel_precompute");
-    if (p->grid) return fail(PSP_EUNSUPPORTED, "autotune a cube of each axis's size instead");
-    {
-        std::lock_guard<std::mutex> lk(p->mu);
-        if (p->prof_cap > 0) return fail(PSP_ESTATE, "autotune while profiling");
-    }
-    int dev = -1;
-    if (hipGetDevice(&dev) != hipSuccess || dev != p->device)
-        return fail(PSP_EINVAL, "plan was precomputed on device %d, current is %d", p->device, dev);
-    hipStream_t st = (hipStream_t)stream;
-    Workspace *w = nullptr;
-    psp_status rs = plan_workspace(p, st, &w);
-    if (rs != PSP_OK) return rs;
-    const int n = p->n;
-    const bool f32 = p->dtype == PSP_F32;
-    const size_t bytes = (size_t)n * n * n * (f32 ? 4 : 8);
-    void *rho = nullptr, *u = nullptr;
-    if (hipMalloc(&rho, bytes) != hipSuccess || hipMalloc(&u, bytes) != hipSuccess) {
-        (void)hipGetLastError();
-        if (rho) (void)hipFree(rho);
-        return fail(PSP_ENOMEM, "autotune buffers of %zu bytes failed", 2 * bytes);
-    }
-    const int nev = solve_launches(n, f32, p->chunk_tiles, p->i1_group) + 1;
-    std::vector<hipEvent_t> ev(nev, nullptr);
-    std::vector<int> ev_pass(nev, -1);
-    std::vector<std::vector<std::pair<int, int>>> cand(kPasses);
-    size_t rounds = 0;
-    for (int i = 0; i < kPasses; ++i) {
-        cand[i] = candidates(n, i);
-        rounds = std::max(rounds, cand[i].size());
-    }
-    // every timing of every candidate; the pick uses the median
-    std::vector<std::vector<std::vector<float>>> samples(kPasses);
-    for (int i = 0; i < kPasses; ++i) samples[i].resize(cand[i].size());
-    psp_status out = PSP_OK;
-    const size_t count = (size_t)n * n * n;
-    if (f32)
-        hipLaunchKernelGGL(k_fill_hash<float>, dim3(1024), dim3(256), 0, st, (float *)rho, count);
-    else
-        hipLaunchKernelGGL(k_fill_hash<double>, dim3(1024), dim3(256), 0, st, (double *)rho, count);
-    hipError_t e = hipGetLastError();
-    // timing only: no system-scope cache writeback at every record
-    for (int k = 0; k < nev && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&ev[k], hipEventDisableSystemFence);
-    if (e != hipSuccess) out = hip_fail(e, "autotune set-up");
-    // round r runs candidate r mod (count) of every pass at once: each pass
-    // is timed by its own events, so one round measures five candidates
-    for (size_t r = 0; r < rounds && out == PSP_OK; ++r) {
-        Shape s;
+    return guarded([&]() -> psp_status {
+        if (!p) return fail(PSP_EINVAL, "plan is NULL");
+        if (reps < 1 || reps > 1000) return fail(PSP_EINVAL, "reps must be in [1, 1000] (got %d)", reps);
+        if (!p->precomputed) return fail(PSP_ESTATE, "autotune before psp_kernel_precompute");
+        if (p->grid) return fail(PSP_EUNSUPPORTED, "autotune a cube of each axis's size instead");
+        {
+            std::lock_guard<std::mutex> lk(p->mu);
+            if (p->prof_cap > 0) return fail(PSP_ESTATE, "autotune while profiling");
+        }
+        int dev = -1;
+        if (hipGetDevice(&dev) != hipSuccess || dev != p->device)
+            return fail(PSP_EINVAL, "plan was precomputed on device %d, current is %d", p->device, dev);
+        hipStream_t st = (hipStream_t)stream;
+        Workspace *w = nullptr;
+        psp_status rs = plan_workspace(p, st, &w);
+        if (rs != PSP_OK) return rs;
+        const int n = p->n;
+        const bool f32 = p->dtype == PSP_F32;
+        const size_t bytes = (size_t)n * n * n * (f32 ? 4 : 8);
+        void *rho = nullptr, *u = nullptr;
+        if (hipMalloc(&rho, bytes) != hipSuccess || hipMalloc(&u, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            if (rho) (void)hipFree(rho);
+            return fail(PSP_ENOMEM, "autotune buffers of %zu bytes failed", 2 * bytes);
+        }
+        const int nev = solve_launches(n, f32, p->chunk_tiles, p->i1_group) + 1;
+        std::vector<hipEvent_t> ev(nev, nullptr);
+        std::vector<int> ev_pass(nev, -1);
+        std::vector<std::vector<std::pair<int, int>>> cand(kPasses);
+        size_t rounds = 0;
         for (int i = 0; i < kPasses; ++i) {
-            const auto &c = cand[i][r % cand[i].size()];
-            s.plan[i] = c.first;
-            s.tile[i] = c.second;
+            cand[i] = candidates(n, i);
+            rounds = std::max(rounds, cand[i].size());
         }
-        SolveArgs a = solve_args(p, *w, rho, u);
-        a.shape = s;
-        if ((e = launch_solve(a, st)) != hipSuccess) {   // warm-up
-            out = hip_fail(e, "autotune launch");
-            break;
-        }
-        a.ev = ev.data();
-        a.ev_pass = ev_pass.data();
-        a.nev = nev;
-        for (int rep = 0; rep < reps && out == PSP_OK; ++rep) {
-            if ((e = launch_solve(a, st)) != hipSuccess || (e = hipEventSynchronize(ev[nev - 1])) != hipSuccess) {
-                out = hip_fail(e, "autotune solve");
+        // every timing of every candidate; the pick uses the median
+        std::vector<std::vector<std::vector<float>>> samples(kPasses);
+        for (int i = 0; i < kPasses; ++i) samples[i].resize(cand[i].size());
+        psp_status out = PSP_OK;
+        const size_t count = (size_t)n * n * n;
+        if (f32)
+            hipLaunchKernelGGL(k_fill_hash<float>, dim3(1024), dim3(256), 0, st, (float *)rho, count);
+        else
+            hipLaunchKernelGGL(k_fill_hash<double>, dim3(1024), dim3(256), 0, st, (double *)rho, count);
+        hipError_t e = hipGetLastError();
+        // timing only: no system-scope cache writeback at every record
+        for (int k = 0; k < nev && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&ev[k], hipEventDisableSystemFence);
+        if (e != hipSuccess) out = hip_fail(e, "autotune set-up");
+        // round r runs candidate r mod (count) of every pass at once: each pass
+        // is timed by its own events, so one round measures five candidates
+        for (size_t r = 0; r < rounds && out == PSP_OK; ++r) {
+            Shape s;
+            for (int i = 0; i < kPasses; ++i) {
+                const auto &c = cand[i][r % cand[i].size()];
+                s.plan[i] = c.first;
+                s.tile[i] = c.second;
+            }
+            SolveArgs a = solve_args(p, *w, rho, u);
+            a.shape = s;
+            if ((e = launch_solve(a, st)) != hipSuccess) {   // warm-up
+                out = hip_fail(e, "autotune launch");
                 break;
             }
-            float pass_ms[kPasses] = {0, 0, 0, 0, 0};
-            for (int k = 0; k + 1 < nev; ++k) {
-                float ms = 0;
-                if ((e = hipEventElapsedTime(&ms, ev[k], ev[k + 1])) != hipSuccess) {
-                    out = hip_fail(e, "autotune timing");
+            a.ev = ev.data();
+            a.ev_pass = ev_pass.data();
+            a.nev = nev;
+            for (int rep = 0; rep < reps && out == PSP_OK; ++rep) {
+                if ((e = launch_solve(a, st)) != hipSuccess || (e = hipEventSynchronize(ev[nev - 1])) != hipSuccess) {
+                    out = hip_fail(e, "autotune solve");
                     break;
                 }
-                if (ev_pass[k] >= 0 && ev_pass[k] < kPasses) pass_ms[ev_pass[k]] += ms;
+                float pass_ms[kPasses] = {0, 0, 0, 0, 0};
+                for (int k = 0; k + 1 < nev; ++k) {
+                    float ms = 0;
+                    if ((e = hipEventElapsedTime(&ms, ev[k], ev[k + 1])) != hipSuccess) {
+                        out = hip_fail(e, "autotune timing");
+                        break;
+                    }
+                    if (ev_pass[k] >= 0 && ev_pass[k] < kPasses) pass_ms[ev_pass[k]] += ms;
+                }
+                for (int i = 0; i < kPasses; ++i) samples[i][r % cand[i].size()].push_back(pass_ms[i]);
             }
-            for (int i = 0; i < kPasses; ++i) samples[i][r % cand[i].size()].push_back(pass_ms[i]);
         }
-    }
-    if (out == PSP_OK && (e = hipStreamSynchronize(st)) != hipSuccess) out = hip_fail(e, "autotune");
-    for (auto x : ev)
-        if (x) (void)hipEventDestroy(x);
-    (void)hipFree(rho);
-    (void)hipFree(u);
-    if (out != PSP_OK) return out;
-    std::vector<std::vector<float>> best(kPasses);
-    for (int i = 0; i < kPasses; ++i)
-        for (auto &v : samples[i]) {
-            std::sort(v.begin(), v.end());
-            best[i].push_back(v.empty() ? FLT_MAX : v[v.size() / 2]);
-        }
-    Shape chosen;
-    for (int i = 0; i < kPasses; ++i) {
-        size_t pick = 0;   // candidate 0 is the default shape of the pass
-        for (size_t c = 1; c < cand[i].size(); ++c)
-            if (best[i][c] < 0.99f * best[i][0] && best[i][c] < best[i][pick]) pick = c;
-        chosen.plan[i] = cand[i][pick].first;
-        chosen.tile[i] = cand[i][pick].second;
-        if (best_ms) best_ms[i] = best[i][pick];
-    }
-    {
-        std::lock_guard<std::mutex> lk(p->mu);
-        p->shape = chosen;
-    }
-    {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tune[{n, f32}] = chosen;
-    }
-    shape_to(chosen, best_plan, best_tile);
-    if (cand_ms) {
-        constexpr int stride = kMaxPlans * kMaxTiles;
-        for (int i = 0; i < kPasses * stride; ++i) cand_ms[i] = -1.0f;
+        if (out == PSP_OK && (e = hipStreamSynchronize(st)) != hipSuccess) out = hip_fail(e, "autotune");
+        for (auto x : ev)
+            if (x) (void)hipEventDestroy(x);
+        (void)hipFree(rho);
+        (void)hipFree(u);
+        if (out != PSP_OK) return out;
+        std::vector<std::vector<float>> best(kPasses);
         for (int i = 0; i < kPasses; ++i)
-            for (size_t c = 0; c < cand[i].size(); ++c)
-                cand_ms[i * stride + cand[i][c].first * kMaxTiles + cand[i][c].second] = best[i][c];
-    }
-    return PSP_OK;
+            for (auto &v : samples[i]) {
+                std::sort(v.begin(), v.end());
+                best[i].push_back(v.empty() ? FLT_MAX : v[v.size() / 2]);
+            }
+        Shape chosen;
+        for (int i = 0; i < kPasses; ++i) {
+            size_t pick = 0;   // candidate 0 is the default shape of the pass
+            for (size_t c = 1; c < cand[i].size(); ++c)
+                if (best[i][c] < 0.99f * best[i][0] && best[i][c] < best[i][pick]) pick = c;
+            chosen.plan[i] = cand[i][pick].first;
+            chosen.tile[i] = cand[i][pick].second;
+            if (best_ms) best_ms[i] = best[i][pick];
+        }
+        {
+            std::lock_guard<std::mutex> lk(p->mu);
+            p->shape = chosen;
+        }
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            g_tune[{n, f32}] = chosen;
+        }
+        shape_to(chosen, best_plan, best_tile);
+        if (cand_ms) {
+            constexpr int stride = kMaxPlans * kMaxTiles;
+            for (int i = 0; i < kPasses * stride; ++i) cand_ms[i] = -1.0f;
+            for (int i = 0; i < kPasses; ++i)
+                for (size_t c = 0; c < cand[i].size(); ++c)
+                    cand_ms[i * stride + cand[i][c].first * kMaxTiles + cand[i][c].second] = best[i][c];
+        }
+        return PSP_OK;
+    });
 }
 
 }  // extern "C"
