@@ -66,9 +66,9 @@ template <int R> __device__ __forceinline__ void twiddle_powers(double2 *p) {
     if constexpr (R > 8) {
         p[8] = cmul64(p[4], p[4]);
 #pragma unroll
-        for (int k = 1; k < 8; ++k) p[8 + k] = cmul64(p[8], p[k]);
+        for (int k = 1; k < R - 8; ++k) p[8 + k] = cmul64(p[8], p[k]);
     }
-    static_assert(R == 2 || R == 3 || R == 4 || R == 8 || R == 16, "radix");
+    static_assert(R == 2 || R == 3 || R == 4 || R == 8 || R == 12 || R == 16, "radix");
 }
 
 template <typename T> struct Twiddle {
@@ -209,6 +209,48 @@ template <bool INV, typename C> struct DFT<16, INV, C> {
     }
 };
 
+// v *= W12^E (forward W12 = exp(-2 pi i/12)) for the split of a length-12
+// DFT into four 3-point DFTs (inputs 4 n1 + n2) and three 4-point DFTs
+// (outputs k1 + 3 k2), with the twelfth roots of unity written out
+template <int E, bool INV, typename C> __device__ __forceinline__ C mul_w12(C a) {
+    using T = decltype(a.x);
+    const T h3 = T(0.86602540378443864676372317075293618);   // cos(pi/6)
+    T wr, wi;
+    if constexpr (E == 3) return c_mul_mi<INV>(a);
+    else if constexpr (E == 6) return C{-a.x, -a.y};
+    else {
+        if constexpr (E == 1) { wr = h3; wi = T(-0.5); }
+        else if constexpr (E == 2) { wr = T(0.5); wi = -h3; }
+        else { static_assert(E == 4, "exponent"); wr = T(-0.5); wi = -h3; }
+        if (INV) wi = -wi;
+        return C{fmadd(a.x, wr, -(a.y * wi)), fmadd(a.x, wi, a.y * wr)};
+    }
+}
+template <bool INV, typename C> struct DFT<12, INV, C> {
+    __device__ __forceinline__ static void run(C *v) {
+        C a[4][3];
+#pragma unroll
+        for (int n2 = 0; n2 < 4; ++n2) {
+#pragma unroll
+            for (int n1 = 0; n1 < 3; ++n1) a[n2][n1] = v[4 * n1 + n2];
+            DFT<3, INV, C>::run(a[n2]);            // a[n2][k1]
+        }
+        a[1][1] = mul_w12<1, INV>(a[1][1]);
+        a[1][2] = mul_w12<2, INV>(a[1][2]);
+        a[2][1] = mul_w12<2, INV>(a[2][1]);
+        a[2][2] = mul_w12<4, INV>(a[2][2]);
+        a[3][1] = mul_w12<3, INV>(a[3][1]);
+        a[3][2] = mul_w12<6, INV>(a[3][2]);
+#pragma unroll
+        for (int k1 = 0; k1 < 3; ++k1) {
+            C b[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
+            DFT<4, INV, C>::run(b);                 // b[k2]
+#pragma unroll
+            for (int k2 = 0; k2 < 4; ++k2) v[k1 + 3 * k2] = b[k2];
+        }
+    }
+};
+
 // ------------------------------------------------------------ radix plans
 // Forward radix sequence per padded length; variant PV = 0 is the default,
 // PV = 1 an alternative ordering or factorisation and PV = 2 a factorisation
@@ -239,15 +281,15 @@ PSP_PLAN(768, 0, 8, 8, 4, 3)
 PSP_PLAN(128, 1, 4, 8, 4)
 PSP_PLAN(256, 1, 4, 8, 8)
 PSP_PLAN(512, 1, 8, 4, 4, 4)
-PSP_PLAN(768, 1, 8, 4, 8, 3)
-// radix-16 alternatives: one FFT stage (and LDS exchange) fewer where the
-// length allows it
+PSP_PLAN(768, 1, 12, 8, 8)
+// radix-16 alternatives (radix 12 for 768): one FFT stage (and LDS exchange)
+// fewer where the length allows it
 PSP_PLAN(128, 2, 16, 8)
 PSP_PLAN(192, 2, 16, 4, 3)
 PSP_PLAN(256, 2, 16, 16)
 PSP_PLAN(384, 2, 16, 8, 3)
 PSP_PLAN(512, 2, 16, 8, 4)
-PSP_PLAN(768, 2, 16, 16, 3)
+PSP_PLAN(768, 2, 8, 8, 12)
 #undef PSP_PLAN
 
 template <int N, bool INV, int PV> struct Seq {

@@ -18,7 +18,8 @@ struct Job {
 // Launch shape of the five passes H1..H5 (index p = 0..4): the autotuner's
 // search space.
 //   plan[p]: radix plan of the pass (0: default, 1: an alternative ordering,
-//            2: a radix-16 factorisation, where the padded length has them;
+//            2: a radix-16 (radix-12 for 768) factorisation, where the
+//            padded length has them;
 //            a different rounding, same accuracy class)
 //   tile[p]: H1/H5 (p = 0, 4): workgroup size, 0: 256 threads, 1: 128, 2: 512;
 //            H2-H4 (p = 1..3): 0: one 128-byte row tile of k3 columns per
@@ -73,7 +74,7 @@ struct Shape {
 };
 // radix plans of a padded length: 0 the default; 1 an alternative ordering or
 // factorisation (2n in {128, 256, 512, 768}); 2 a radix-16 factorisation (2n
-// in {128, 192, 256, 384, 512, 768})
+// in {128, 192, 256, 384, 512}) or for 768 one with radix 12
 constexpr bool alt_plan_exists(int N) { return N == 128 || N == 256 || N == 512 || N == 768; }
 constexpr bool r16_plan_exists(int N) { return N == 128 || N == 192 || N == 256 || N == 384 || N == 512 || N == 768; }
 constexpr bool plan_exists(int N, int pv) {
