@@ -185,7 +185,7 @@ psp_status psp_plan_set_tuning(psp_plan *p, int k3_tiles, int i1_group);
 /* Launch shape of the five passes H1..H5 (index 0..4), the autotuner's search
  * space, as two int[5] arrays:
  *   plan[i]: radix plan of pass i: 0 the default factorisation of 2n, 1 an
- *            alternative for 2n in {128, 256, 512, 768}, 2 a radix-16
+ *            alternative for 2n in {128, 256, 384, 512, 768}, 2 a radix-16
  *            factorisation for 2n in {128, 192, 256, 384, 512} or a radix-12
  *            one for 768 (other lengths have only 0);
  *   tile[i]: passes 0 and 4 (transforms along i3): workgroup size, 0: 256

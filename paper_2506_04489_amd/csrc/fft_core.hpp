@@ -280,6 +280,7 @@ PSP_PLAN(768, 0, 8, 8, 4, 3)
 // alternatives
 PSP_PLAN(128, 1, 4, 8, 4)
 PSP_PLAN(256, 1, 4, 8, 8)
+PSP_PLAN(384, 1, 12, 4, 8)
 PSP_PLAN(512, 1, 8, 4, 4, 4)
 PSP_PLAN(768, 1, 12, 8, 8)
 // radix-16 alternatives (radix 12 for 768): one FFT stage (and LDS exchange)

@@ -73,9 +73,9 @@ struct Shape {
     }
 };
 // radix plans of a padded length: 0 the default; 1 an alternative ordering or
-// factorisation (2n in {128, 256, 512, 768}); 2 a radix-16 factorisation (2n
+// factorisation (2n in {128, 256, 384, 512, 768}); 2 a radix-16 factorisation (2n
 // in {128, 192, 256, 384, 512}) or for 768 one with radix 12
-constexpr bool alt_plan_exists(int N) { return N == 128 || N == 256 || N == 512 || N == 768; }
+constexpr bool alt_plan_exists(int N) { return N == 128 || N == 256 || N == 384 || N == 512 || N == 768; }
 constexpr bool r16_plan_exists(int N) { return N == 128 || N == 192 || N == 256 || N == 384 || N == 512 || N == 768; }
 constexpr bool plan_exists(int N, int pv) {
     return pv == 0 || (pv == 1 && alt_plan_exists(N)) || (pv == 2 && r16_plan_exists(N));

@@ -43,7 +43,7 @@ TILES = [3, 7, 21, 7, 3]         # tile choices of passes H1..H5
 def radix_plans(n):
     """Radix plans the library has for padded length 2n."""
     N = 2 * n
-    return [0] + ([1] if N in (128, 256, 512, 768) else []) + ([2] if N in (128, 192, 256, 384, 512, 768) else [])
+    return [0] + ([1] if N in (128, 256, 384, 512, 768) else []) + ([2] if N in (128, 192, 256, 384, 512, 768) else [])
 
 
 def shape_rounds(n):
