@@ -36,7 +36,9 @@ static void image_layout(const std::vector<BatchMember> &m, BatchImage *img) {
     img->grouped.clear();
     const bool pers = persistent_enabled();
     for (int i = 0; i < (int)m.size(); ++i) {
-        // the persistent kernels size their LDS for radices up to 8
+        // the persistent kernels size their LDS for radices up to 8: up to
+        // 2n = PB_MAX_N only plan 2 has a larger one (persist.hpp checks
+        // plans 0 and 1 at compile time)
         bool r16 = false;
         for (int p = 0; p < kPasses; ++p) r16 |= m[i].shape.plan[p] == 2;
         (pers && !r16 && 2 * m[i].n <= PB_MAX_N ? img->persist : img->grouped).push_back(i);

@@ -230,6 +230,9 @@ __device__ __forceinline__ void pb_dispatch(const PJob *jp, int N, int pv, int i
     switch (N) {
 #define PSP_PB(NN)                                                              \
     case NN:                                                                    \
+        static_assert(MaxRadix<NN, 0>::value() <= 8 &&                          \
+                          MaxRadix<NN, alt_plan_exists(NN) ? 1 : 0>::value() <= 8, \
+                      "persistent bodies hold radices up to 8: plans 0 and 1");  \
         if (alt_plan_exists(NN) && pv == 1)                                     \
             pb_run<T, PASS, NN, alt_plan_exists(NN) ? 1 : 0>(jp, item);    \
         else                                                                    \
