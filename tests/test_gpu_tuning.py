@@ -26,7 +26,7 @@ def _density(n, seed, dtype):
 
 
 @pytest.mark.parametrize("n,dtype", [(48, "f64"), (64, "f64"), (64, "f32"), (96, "f64"), (128, "f64"),
-                                     (384, "f64"), (384, "f32"), (256, "f64")])
+                                     (192, "f64"), (192, "f32"), (384, "f64"), (384, "f32"), (256, "f64")])
 def test_every_shape_matches(n, dtype):
     import torch
     h = 2.0 / n
