@@ -189,7 +189,7 @@ psp_status psp_plan_set_tuning(psp_plan *p, int k3_tiles, int i1_group);
  *            factorisation for 2n in {128, 192, 256, 384, 512} or a radix-12
  *            one for 768 (other lengths have only 0);
  *   tile[i]: passes 0 and 4 (transforms along i3): workgroup size, 0: 256
- *            threads, 1: 128, 2: 512; passes 1..3 (along i2, i1, i2): 0: one
+ *            threads, 1: 128, 2: 512, 3: 64; passes 1..3 (along i2, i1, i2): 0: one
  *            128-byte row of k3 columns per workgroup (8 FP64 or 16 FP32
  *            columns), 1: half of one, 2: one row with the exchanges between
  *            FFT stages through half-size LDS buffers by position half,

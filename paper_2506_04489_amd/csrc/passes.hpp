@@ -406,6 +406,8 @@ template <typename F> inline void with_threads(int tile, F &&f) {
         f(std::integral_constant<int, 128>{});
     else if (tile == 2)
         f(std::integral_constant<int, 512>{});
+    else if (tile == 3)
+        f(std::integral_constant<int, 64>{});
     else
         f(std::integral_constant<int, 256>{});
 }

@@ -195,7 +195,7 @@ def test_shape_validation_and_roundtrip():
     p.set_shape([0] * 5, [0, 0, 20, 0, 0])           # H3: tile 6 with nontemporal loads and stores
     assert p.shape() == ([0] * 5, [0, 0, 20, 0, 0])
     for plan, tile in [([1, 0, 0, 0, 0], [0] * 5),   # no alternative plan for 2n = 64
-                       ([0] * 5, [3, 0, 0, 0, 0]),   # three workgroup sizes for H1
+                       ([0] * 5, [4, 0, 0, 0, 0]),   # four workgroup sizes for H1
                        ([0] * 5, [0, 7, 0, 0, 0]),   # seven tile choices for H2
                        ([0] * 5, [0, 0, 21, 0, 0]),  # twenty-one for H3 (three cache policies)
                        ([0] * 5, [0, 0, 0, 0, -1])]:
