@@ -321,10 +321,23 @@ k_z_c2r(JobRef jr, int npairs, int P, Twiddle<T> tw) {
     const C *yb = ya + P;
     IdxLine idx{q * Cfg::LINE};
     // each half-spectrum bin is read once (coalesced) and gives
-    // Z[k] = A[k] + i B[k] and Z[N-k] = conj A[k] + i conj B[k]
-    if (active) {
-        for (int k = t; k <= n; k += Cfg::TPC) {
-            C A = ya[k], B = yb[k];
+    // Z[k] = A[k] + i B[k] and Z[N-k] = conj A[k] + i conj B[k]; all of a
+    // thread's loads are issued before the first LDS write
+    constexpr int KB = (n + 1 + Cfg::TPC - 1) / Cfg::TPC;   // bins per thread
+    C ba[KB], bb[KB];
+#pragma unroll
+    for (int i = 0; i < KB; ++i) {
+        const int k = t + i * Cfg::TPC;
+        if (active && k <= n) {
+            ba[i] = ya[k];
+            bb[i] = yb[k];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < KB; ++i) {
+        const int k = t + i * Cfg::TPC;
+        if (active && k <= n) {
+            C A = ba[i], B = bb[i];
             if (k == 0 || k == n) {
                 A.y = 0;
                 B.y = 0;
