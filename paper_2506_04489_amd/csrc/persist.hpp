@@ -189,9 +189,21 @@ __device__ __noinline__ void pb_z_c2r(const PJob *jp, int item) {
     const C *ya = (const C *)jb.X + (size_t)(2 * pair) * jb.P;
     const C *yb = ya + jb.P;
     IdxLine idx{q * Cfg::LINE};
-    if (active) {
-        for (int k = t; k <= n; k += Cfg::TPC) {
-            C A = ya[k], B = yb[k];
+    constexpr int KB = (n + 1 + Cfg::TPC - 1) / Cfg::TPC;   // bins per thread
+    C ba[KB], bb[KB];
+#pragma unroll
+    for (int i = 0; i < KB; ++i) {
+        const int k = t + i * Cfg::TPC;
+        if (active && k <= n) {
+            ba[i] = ya[k];
+            bb[i] = yb[k];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < KB; ++i) {
+        const int k = t + i * Cfg::TPC;
+        if (active && k <= n) {
+            C A = ba[i], B = bb[i];
             if (k == 0 || k == n) {
                 A.y = 0;
                 B.y = 0;
