@@ -4,9 +4,12 @@ TEST INFRASTRUCTURE.  Only the tests, the smoke check and the CPU-baseline leg
 of the benchmark may import this module.  It shares no code with the GPU
 library: its own Gaussian-sum construction, its own Gauss-Legendre 1D
 quadrature, a plain triple loop for the kernel spectrum, its own naive
-recursive mixed-radix (2 and 3) FFT, and a direct (FFT-free) evaluation of the
-discrete convolution operator.  Everything is float64 numpy, except the
-1D integral sums, which run in extended precision (see tables_1d).
+recursive mixed-radix (2 and 3) FFT (in numpy, fft_naive, and the same
+recursion in plain C, naive_fft.c, which the solve uses by default so that
+whole grids up to n = 384 finish in seconds), and a direct (FFT-free)
+evaluation of the discrete convolution operator.  Everything is float64,
+except the 1D integral sums, which run in extended precision (see
+tables_1d).
 
 The method (Exl & Schaffer, "Near-field-free super-potential FFT method for
 the three-dimensional free-space Poisson equation"):
@@ -53,14 +56,16 @@ notes of the repository):
 """
 from __future__ import annotations
 
+import concurrent.futures as _futures
 import math
+import os
 
 import numpy as np
 
 __all__ = [
     "spacings", "counts", "default_eps_delta", "gs_parameters", "gs_weights", "gs_biharmonic",
     "gauss_legendre", "tables_1d", "spectrum_octant", "multiplier_octant",
-    "fft_naive", "fftn_naive", "solve", "solve_padded", "direct_operator",
+    "fft_naive", "fftn_naive", "fftn_c", "solve", "solve_padded", "direct_operator",
     "direct_points", "Setup", "setup",
 ]
 
@@ -212,8 +217,9 @@ def tables_1d(alpha, n: int, L: float):
     k = np.arange(n + 1).astype(_LD)
     J0 = np.empty((alpha.size, n + 1))
     J2 = np.empty((alpha.size, n + 1))
-    for s, a64 in enumerate(alpha):
-        a = _LD(a64)
+
+    def row(s):
+        a = _LD(alpha[s])
         b = min(Ll / 2, _LD(9) / np.sqrt(a))
         width = min(Ll / (2 * n + 2), 1 / np.sqrt(a), b)
         panels = int(math.ceil(float(b / width) - 1e-12))
@@ -226,6 +232,11 @@ def tables_1d(alpha, n: int, L: float):
         c = np.cos((two_pi / Ll) * np.outer(k, y))
         J0[s] = (2 * (c @ g)).astype(np.float64)
         J2[s] = (2 * (c @ (y * y * g))).astype(np.float64)
+
+    # the Gaussian-sum terms are independent: one row per thread (numpy
+    # releases the interpreter lock inside these array operations)
+    with _futures.ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        list(ex.map(row, range(alpha.size)))
     return J0, J2
 
 
@@ -244,16 +255,21 @@ def spectrum_octant(omega, J0, J2):
     one table pair shared by the axes, or a sequence of three).
 
     Vhat is even in every wavenumber component, so this octant of
-    non-negative |k_p| holds the whole padded-grid spectrum.  A plain loop
-    over the Gaussian-sum terms, one outer product per term and direction.
+    non-negative |k_p| holds the whole padded-grid spectrum.  Each of the
+    three terms is a sum over s of products of three 1D factors: written as
+    one matrix product (library routine) of the (a, b) products and the c
+    factor.
     """
     (x0, y0, z0), (x2, y2, z2) = _per_axis(J0), _per_axis(J2)
-    V = np.zeros((x0.shape[1], y0.shape[1], z0.shape[1]))
-    for s in range(len(omega)):
-        V += omega[s] * (x2[s][:, None, None] * y0[s][None, :, None] * z0[s][None, None, :]
-                         + x0[s][:, None, None] * y2[s][None, :, None] * z0[s][None, None, :]
-                         + x0[s][:, None, None] * y0[s][None, :, None] * z2[s][None, None, :])
-    return V
+    na, nb, nc = x0.shape[1], y0.shape[1], z0.shape[1]
+    om = np.asarray(omega, dtype=np.float64)
+    V = np.zeros((na * nb, nc))
+    # each of the three sums over s is one matrix product: the (a, b) rows
+    # w_s f_s(a) g_s(b) times the s-by-c table of the third factor
+    for fa, fb, fc in ((x2, y0, z0), (x0, y2, z0), (x0, y0, z2)):
+        ab = (om[:, None, None] * fa[:, :, None] * fb[:, None, :]).reshape(len(om), na * nb)
+        V += ab.T @ fc
+    return V.reshape(na, nb, nc)
 
 
 def multiplier_octant(V, n, L):
@@ -370,9 +386,22 @@ def fftn_naive(x, sign: int = -1):
 # --------------------------------------------------------------------------
 
 
-def solve_padded(rho, h, R, eps=None, delta=None, su: Setup | None = None):
+def fftn_c(x, sign: int = -1):
+    """The transform of fftn_naive computed by the oracle's C naive FFT
+    (``naive_fft.c``: the same recursive radix-2/3 decimation in time, in
+    plain C with OpenMP over the independent lines)."""
+    from oracle import native
+    y = np.array(x, dtype=np.complex128, order="C", copy=True)
+    for ax in range(3):
+        native.fft_axis_inplace(y, ax, sign)
+    return y
+
+
+def solve_padded(rho, h, R, eps=None, delta=None, su: Setup | None = None, impl: str = "c"):
     """The uncropped result of Algorithm 2 on the padded grid (2 n_p per
-    axis; real part).  rho has shape (n_1, n_2, n_3)."""
+    axis; real part).  rho has shape (n_1, n_2, n_3).  impl selects the
+    oracle's FFT: "c" (naive_fft.c, fast enough for the full-size grids) or
+    "py" (fft_naive, numpy); both are the same unpruned radix-2/3 recursion."""
     rho = np.asarray(rho, dtype=np.float64)
     assert rho.ndim == 3
     if su is None:
@@ -380,15 +409,25 @@ def solve_padded(rho, h, R, eps=None, delta=None, su: Setup | None = None):
     n1, n2, n3 = rho.shape
     pad = np.zeros((2 * n1, 2 * n2, 2 * n3), dtype=np.complex128)
     pad[:n1, :n2, :n3] = rho                    # zero padding, factor 2
-    rhohat = fftn_naive(pad, -1)                # forward DFT (1/(2n)^3 is in m)
-    prod = su.full_multiplier() * rhohat        # multiply (eq. convtheorem)
-    return fftn_naive(prod, +1).real            # inverse sum, real part
+    if impl == "py":
+        rhohat = fftn_naive(pad, -1)            # forward DFT (1/(2n)^3 is in m)
+        prod = su.full_multiplier() * rhohat    # multiply (eq. convtheorem)
+        return fftn_naive(prod, +1).real        # inverse sum, real part
+    if impl != "c":
+        raise ValueError("impl must be 'c' or 'py'")
+    from oracle import native
+    for ax in range(3):                         # forward DFT, in place
+        native.fft_axis_inplace(pad, ax, -1)
+    pad *= su.full_multiplier()                 # multiply (eq. convtheorem)
+    for ax in range(3):                         # inverse sum, in place
+        native.fft_axis_inplace(pad, ax, +1)
+    return pad.real
 
 
-def solve(rho, h, R, eps=None, delta=None, su: Setup | None = None):
+def solve(rho, h, R, eps=None, delta=None, su: Setup | None = None, impl: str = "c"):
     """u on the original grid (Algorithm 2 with the crop)."""
     n1, n2, n3 = np.asarray(rho).shape
-    return solve_padded(rho, h, R, eps, delta, su)[:n1, :n2, :n3]
+    return np.ascontiguousarray(solve_padded(rho, h, R, eps, delta, su, impl)[:n1, :n2, :n3])
 
 
 def _count_of(rho):
