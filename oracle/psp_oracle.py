@@ -208,7 +208,9 @@ def tables_1d(alpha, n: int, L: float):
     The sums run in x87 extended precision (numpy longdouble) and are rounded
     to float64 at the end: for wide Gaussians the box-truncated integrals at
     high k are ~k^2 smaller than the integrand, so float64 node positions and
-    cosine arguments alone would leave ~1e-12 relative errors there.
+    cosine arguments alone would leave ~1e-12 relative errors there.  Where
+    the interval is the whole half box (b = L/2) the cosine's phase is
+    reduced exactly by its integer part (see the code).
     """
     alpha = np.asarray(alpha, dtype=np.float64)
     xg, wg = gauss_legendre(_GL_POINTS, _LD)
@@ -218,18 +220,29 @@ def tables_1d(alpha, n: int, L: float):
     J0 = np.empty((alpha.size, n + 1))
     J2 = np.empty((alpha.size, n + 1))
 
+    t = (1 + xg) / 2                      # node offsets within a panel, in panel widths
+    kint = np.arange(n + 1, dtype=np.int64)
+
     def row(s):
         a = _LD(alpha[s])
         b = min(Ll / 2, _LD(9) / np.sqrt(a))
         width = min(Ll / (2 * n + 2), 1 / np.sqrt(a), b)
         panels = int(math.ceil(float(b / width) - 1e-12))
-        edges = b * np.arange(panels + 1).astype(_LD) / panels
-        mid = (edges[:-1] + edges[1:]) / 2
-        half = (edges[1:] - edges[:-1]) / 2
-        y = (mid[:, None] + half[:, None] * xg[None, :]).ravel()
-        wy = (half[:, None] * wg[None, :]).ravel()
+        j = np.arange(panels)
+        y = (b * (j[:, None] + t[None, :]) / panels).ravel()     # node j + t of panel j
+        wy = np.tile(wg, panels) * (b / (2 * panels))
         g = np.exp(-a * y * y) * wy
-        c = np.cos((two_pi / Ll) * np.outer(k, y))
+        if b == Ll / 2:
+            # the phase k y / L of node y = b (j + t) / P is k (j + t) / (2P):
+            # its integer part k j is reduced mod 2P exactly, so the cosine's
+            # argument carries only the rounding of k t (with the phase
+            # formed from y itself, the rounding of y alone left ~1e-17 of
+            # the tables' scale at k = n against 40-digit mpmath)
+            kj = (kint[:, None] * j[None, :]) % (2 * panels)
+            num = kj[:, :, None].astype(_LD) + k[:, None, None] * t[None, None, :]
+            c = np.cos(two_pi * num.reshape(n + 1, -1) / _LD(2 * panels))
+        else:
+            c = np.cos((two_pi / Ll) * np.outer(k, y))
         J0[s] = (2 * (c @ g)).astype(np.float64)
         J2[s] = (2 * (c @ (y * y * g))).astype(np.float64)
 

@@ -94,3 +94,26 @@ def test_high_wavenumber_value_accuracy():
             # value-relative, down to the extended-precision floor of the scale
             assert abs(J0[s, k] - float(v0)) < 5e-14 * abs(float(v0)) + 1e-18 * L, (al, k)
             assert abs(J2[s, k] - float(v2)) < 5e-14 * abs(float(v2)) + 1e-18 * L ** 3, (al, k)
+
+
+def test_highest_wavenumber_at_full_size():
+    # n = 256 (the benchmark size), wide and medium Gaussians at k = n - 1 and
+    # n, where the multiplier's sum over Gaussian-sum terms cancels most: the
+    # tables must sit far below one ulp of their scale (the exactly reduced
+    # cosine phase; phases formed from rounded node positions were ~1e-17 of
+    # the scale off at k = n)
+    mp.mp.dps = 30
+    n = 256
+    L = 4.0
+    alphas = np.array([4.28e-10, 1.86e-6, 0.536])
+    J0, J2 = O.tables_1d(alphas, n, L)
+    for s, al in enumerate(alphas):
+        a = mp.mpf(al)
+        for k in (n - 1, n):
+            xi = mp.mpf(2) * mp.pi * k / mp.mpf(L)
+            pts = [mp.mpf(0)] + [(j + mp.mpf(0.5)) * mp.mpf(L) / (2 * k) for j in range(k)] + [mp.mpf(L) / 2]
+            pts = sorted(p for p in pts if p <= mp.mpf(L) / 2)
+            v0 = mp.quad(lambda y: 2 * mp.exp(-a * y * y) * mp.cos(xi * y), pts)
+            v2 = mp.quad(lambda y: 2 * y * y * mp.exp(-a * y * y) * mp.cos(xi * y), pts)
+            assert abs(J0[s, k] - float(v0)) < 5e-20 * L, (al, k)
+            assert abs(J2[s, k] - float(v2)) < 5e-20 * L ** 3 / 12, (al, k)
