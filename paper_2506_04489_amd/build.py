@@ -46,8 +46,18 @@ NO_CONTRACT = {"passes_f64_lo.hip", "passes_f64_hi.hip", "passes_f32_lo.hip", "p
                "persist_f64.hip", "persist_f32.hip", "tables.hip"}
 
 
-def _compile(src: str) -> str:
+def _newest_header() -> float:
+    heads = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".h"))]
+    heads += [os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))]
+    return max(os.path.getmtime(f) for f in heads)
+
+
+def _compile(src: str, incremental: bool = False) -> str:
     obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
+    if incremental and os.path.exists(obj):
+        t = os.path.getmtime(obj)
+        if t >= os.path.getmtime(os.path.join(CSRC, src)) and t >= _newest_header():
+            return obj
     extra = ["-ffp-contract=off"] if src in NO_CONTRACT else []
     cmd = [hipcc()] + HIP_FLAGS + COMMON + extra + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -56,12 +66,13 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source and link libpsp.so; returns its path."""
+def build(verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every source (with incremental, only those older than their
+    object) and link libpsp.so; returns its path."""
     os.makedirs(BUILD_DIR, exist_ok=True)
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(_compile, srcs))
+        objs = list(ex.map(lambda s: _compile(s, incremental), srcs))
     tmp = OUT + ".tmp"
     cmd = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -74,5 +85,5 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, incremental="--incremental" in sys.argv)
     sys.exit(0)
