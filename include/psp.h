@@ -117,6 +117,22 @@ psp_status psp_kernel_precompute(psp_plan *p, void *stream);
  * first call with that stream.  Returns PSP_ESTATE before precompute. */
 psp_status psp_solve(psp_plan *p, const void *rho_dev, void *u_dev, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the solve
+ * of psp_solve, with the same kernels and bitwise the same result, whose two
+ * intermediates live in a fixed array of 128 MiB (134217728 bytes) that the
+ * library holds on every GPU it runs on until the process ends, instead of
+ * a workspace allocation.  Allocates nothing (no hipMalloc, hipFree or
+ * allocating library call); the caller passes rho and u as for psp_solve.
+ * PSP_ENOMEM if the plan's intermediates do not fit the array (for a cube:
+ * n <= 128 in FP64, n <= 162 in FP32; see psp_plan_workspace_bytes),
+ * PSP_ESTATE before precompute, PSP_EINVAL for NULL or aliased pointers or
+ * another current device.  Every call on one GPU uses that GPU's array:
+ * calls whose solves overlap on the device (other streams, other threads)
+ * race and give undefined results; calls on one stream are ordered and
+ * safe.  Nothing in the array needs to start at zero. */
+psp_status psp_solve_noalloc(const psp_plan *p, const void *rho_dev, void *u_dev, void *stream);
+
 /* `count` (<= 65535) independent solves: one launch per pass for each
  * distinct n in the batch (the pass kernels read each solve's pointers from
  * a device job table).  plans may differ in n (and h, R) but must share one

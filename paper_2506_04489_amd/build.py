@@ -20,7 +20,7 @@ BUILD_DIR = os.path.join(ROOT, "_build")
 ARCH = "gfx950"
 
 SOURCES = ["passes_f64_lo.hip", "passes_f64_hi.hip", "passes_f32_lo.hip", "passes_f32_hi.hip", "persist_f64.hip",
-           "persist_f32.hip", "spectrum.hip", "tables.hip", "peaks.hip", "batched.hip", "setup.cpp", "api.cpp", "serve.cpp", "graph.cpp", "tuning.cpp"]
+           "persist_f32.hip", "spectrum.hip", "tables.hip", "peaks.hip", "batched.hip", "noalloc.hip", "setup.cpp", "api.cpp", "serve.cpp", "graph.cpp", "tuning.cpp"]
 
 COMMON = [
     "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",

@@ -31,6 +31,7 @@ SIGNATURES = {
     "psp_device_peaks": (_i, [_vp, _vp, _sz, _vp, _P(_d), _P(_d)]),
     "psp_kernel_precompute": (_i, [_vp, _vp]),
     "psp_solve": (_i, [_vp, _vp, _vp, _vp]),
+    "psp_solve_noalloc": (_i, [_vp, _vp, _vp, _vp]),
     "psp_solve_batched": (_i, [_i, _P(_vp), _P(_vp), _P(_vp), _vp]),
     "psp_set_batch_mode": (_i, [_i]),
     "psp_solve_padded_debug": (_i, [_vp, _vp, _vp, _vp]),
@@ -275,6 +276,14 @@ class Plan:
             u = torch.empty_like(rho)
         self._check_tensor(u, self.shape3)
         _check(lib().psp_solve(self._h, rho.data_ptr(), u.data_ptr(), _stream_ptr(stream)))
+        return u
+
+    def solve_noalloc(self, rho, u, stream=None):
+        """psp_solve_noalloc: the solve with its intermediates in the
+        library's fixed device array; u must be given (nothing is allocated)."""
+        self._check_tensor(rho, self.shape3)
+        self._check_tensor(u, self.shape3)
+        _check(lib().psp_solve_noalloc(self._h, rho.data_ptr(), u.data_ptr(), _stream_ptr(stream)))
         return u
 
     def solve_padded_debug(self, rho, stream=None):
