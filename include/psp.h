@@ -54,7 +54,7 @@ typedef enum {
     PSP_OK = 0,
     PSP_EINVAL = -1,        /* bad argument (h <= 0, R < 1, NULL pointer ...) */
     PSP_ENOMEM = -2,        /* device or host allocation failed, or over budget */
-    PSP_EUNSUPPORTED = -3,  /* n not one of the built sizes (see psp_plan_create),
+    PSP_EUNSUPPORTED = -3,  /* n odd, out of [4, 384] or 2n not 2^a 3^b,
                                or an entry point a grid plan cannot use */
     PSP_ESTATE = -4,        /* call order (solve before precompute ...) */
     PSP_EHIP = -5,          /* a HIP runtime call failed */
@@ -67,9 +67,11 @@ typedef enum {
  * weights and exponents on the host (Section 2, eq. sin_1_x: sinc quadrature
  * of 1/(8 pi r) on (eps, delta] with eps = 1e-4 * n h and
  * delta = sqrt(3) * n h).  Host work only; no device memory is touched.
- * n: points per axis, one of 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192,
- * 256, 384 (padded lengths 2n = 2^a or 3 * 2^a, the lengths whose FFT
- * kernels are built); h > 0 finite; 1 <= R <= 2048.
+ * n: points per axis, even, 4 <= n <= 384, with 2n = 2^a 3^b (Algorithm 1
+ * takes any grid size; the FFT passes are built for every such length:
+ * n = 4, 6, 8, 12, 16, 18, 24, 32, 36, 48, 54, 64, 72, 96, 108, 128, 144,
+ * 162, 192, 216, 256, 288, 324, 384); h > 0 finite; 1 <= R <= 2048.
+ * Other n: PSP_EUNSUPPORTED.
  * *out receives the plan (NULL on failure). */
 psp_status psp_plan_create(int n, double h, int R, psp_dtype dtype, psp_plan **out);
 
@@ -115,7 +117,7 @@ psp_status psp_kernel_precompute(psp_plan *p, void *stream);
 /* Algorithm 2: u = crop(IFFT(m * FFT(pad(rho)))).  rho and u must not alias.
  * Uses a library-owned workspace bound to (plan, stream), allocated on the
  * first call with that stream.  Returns PSP_ESTATE before precompute. */
-psp_status psp_solve(psp_plan *p, const void *rho_dev, void *u_dev, void *stream);
+psp_status psp_solve(const psp_plan *p, const void *rho_dev, void *u_dev, void *stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the solve
@@ -142,7 +144,7 @@ psp_status psp_solve_noalloc(const psp_plan *p, const void *rho_dev, void *u_dev
  * equal to psp_solve of the same plan and rho.  Workspaces (one per cubic
  * solve of the batch, one per distinct grid) are library-owned, bound to the
  * stream and reused by later batches on it. */
-psp_status psp_solve_batched(int count, psp_plan *const *plans,
+psp_status psp_solve_batched(int count, const psp_plan *const *plans,
                              const void *const *rho_dev, void *const *u_dev,
                              void *stream);
 
@@ -160,7 +162,7 @@ psp_status psp_set_batch_mode(int mode);
 /* Test hook: the uncropped (2n)^3 result of Algorithm 2 (real part), C-order
  * with side 2n, dtype of the plan.  PSP_EUNSUPPORTED for grids with unequal
  * counts and for plans whose workspace psp_plan_set_tuning shrank. */
-psp_status psp_solve_padded_debug(psp_plan *p, const void *rho_dev, void *upad_dev,
+psp_status psp_solve_padded_debug(const psp_plan *p, const void *rho_dev, void *upad_dev,
                                   void *stream);
 
 /* Debugging of out-of-bounds writes: with enable != 0, every workspace
@@ -281,8 +283,8 @@ void psp_plan_destroy(psp_plan *p);
  * keeps pointers to rho/u and to the plans' spectra, which must outlive it.
  * Capture synchronises `stream`. */
 typedef struct psp_graph psp_graph;
-psp_status psp_graph_capture(psp_plan *p, const void *rho_dev, void *u_dev, void *stream, psp_graph **out);
-psp_status psp_graph_capture_batched(int count, psp_plan *const *plans, const void *const *rho_dev,
+psp_status psp_graph_capture(const psp_plan *p, const void *rho_dev, void *u_dev, void *stream, psp_graph **out);
+psp_status psp_graph_capture_batched(int count, const psp_plan *const *plans, const void *const *rho_dev,
                                      void *const *u_dev, void *stream, psp_graph **out);
 psp_status psp_graph_launch(psp_graph *g, void *stream);
 void psp_graph_destroy(psp_graph *g);

@@ -19,7 +19,8 @@ OUT = os.path.join(HERE, "libpsp.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 ARCH = "gfx950"
 
-SOURCES = ["passes_f64_lo.hip", "passes_f64_hi.hip", "passes_f32_lo.hip", "passes_f32_hi.hip", "persist_f64.hip",
+SOURCES = ["passes_f64_lo.hip", "passes_f64_hi.hip", "passes_f32_lo.hip", "passes_f32_hi.hip", "passes_f64_x1.hip",
+           "passes_f64_x2.hip", "passes_f32_x1.hip", "passes_f32_x2.hip", "persist_f64.hip",
            "persist_f32.hip", "spectrum.hip", "tables.hip", "peaks.hip", "batched.hip", "noalloc.hip", "setup.cpp", "api.cpp", "serve.cpp", "graph.cpp", "tuning.cpp"]
 
 COMMON = [
@@ -43,6 +44,7 @@ def hipcc() -> str:
 # the FFT passes round every instantiation the same way: no automatic
 # contraction of a*b+c, the kernels write their fused multiply-adds out
 NO_CONTRACT = {"passes_f64_lo.hip", "passes_f64_hi.hip", "passes_f32_lo.hip", "passes_f32_hi.hip",
+               "passes_f64_x1.hip", "passes_f64_x2.hip", "passes_f32_x1.hip", "passes_f32_x2.hip",
                "persist_f64.hip", "persist_f32.hip", "tables.hip"}
 
 

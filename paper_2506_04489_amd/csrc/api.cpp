@@ -85,8 +85,7 @@ psp_status check_create(int n, double h, int R, double eps, double delta) {
         return fail(PSP_EINVAL, "need 0 < eps < delta finite (got %g, %g)", eps, delta);
     if (n < 4 || n > 384 || (n & 1)) return fail(PSP_EUNSUPPORTED, "n must be even and in [4, 384] (got %d)", n);
     if (!supported_length(2 * n))
-        return fail(PSP_EUNSUPPORTED,
-                    "n = %d is not one of the built sizes 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384", n);
+        return fail(PSP_EUNSUPPORTED, "2n = %d is not of the form 2^a 3^b (n = %d)", 2 * n, n);
     return PSP_OK;
 }
 
@@ -175,7 +174,7 @@ psp_status check_guards(const Workspace &w, bool *intact) {
     return PSP_OK;
 }
 
-psp_status plan_workspace(psp_plan *p, hipStream_t st, Workspace **out) {
+psp_status plan_workspace(const psp_plan *p, hipStream_t st, Workspace **out) {
     std::lock_guard<std::mutex> lk(p->mu);
     auto it = p->ws.find(st);
     if (it != p->ws.end()) {
@@ -539,7 +538,7 @@ psp_status psp_plan_get_multiplier(psp_plan *p, double *m_host) {
     });
 }
 
-psp_status psp_solve(psp_plan *p, const void *rho_dev, void *u_dev, void *stream) {
+psp_status psp_solve(const psp_plan *p, const void *rho_dev, void *u_dev, void *stream) {
     return guarded([&]() -> psp_status {
         if (!p || !rho_dev || !u_dev) return fail(PSP_EINVAL, "NULL argument");
         if (!p->precomputed) return fail(PSP_ESTATE, "psp_solve before psp_kernel_precompute");
@@ -657,7 +656,7 @@ psp_status psp_plan_check_guards(psp_plan *p, int *intact) {
     });
 }
 
-psp_status psp_solve_padded_debug(psp_plan *p, const void *rho_dev, void *upad_dev, void *stream) {
+psp_status psp_solve_padded_debug(const psp_plan *p, const void *rho_dev, void *upad_dev, void *stream) {
     return guarded([&]() -> psp_status {
         if (!p || !rho_dev || !upad_dev) return fail(PSP_EINVAL, "NULL argument");
         if (!p->precomputed) return fail(PSP_ESTATE, "psp_solve_padded_debug before psp_kernel_precompute");

@@ -41,7 +41,10 @@ static void image_layout(const std::vector<BatchMember> &m, BatchImage *img) {
         // plans 0 and 1 at compile time)
         bool r16 = false;
         for (int p = 0; p < kPasses; ++p) r16 |= m[i].shape.plan[p] == 2;
-        (pers && !r16 && 2 * m[i].n <= PB_MAX_N ? img->persist : img->grouped).push_back(i);
+        // and exist for the lengths whose threads per column divide their
+        // workgroup (persist_tpc is 0 for the others)
+        const bool built = 2 * m[i].n <= PB_MAX_N && persist_tpc(2 * m[i].n, 0) > 0;
+        (pers && !r16 && built ? img->persist : img->grouped).push_back(i);
     }
     // persistent jobs by decreasing n (the largest items are taken first);
     // grouped jobs by (n, shape) so that each group is a contiguous slice
@@ -251,7 +254,7 @@ extern "C" psp_status psp_set_batch_mode(int mode) {
     });
 }
 
-extern "C" psp_status psp_solve_batched(int count, psp_plan *const *plans, const void *const *rho_dev,
+extern "C" psp_status psp_solve_batched(int count, const psp_plan *const *plans, const void *const *rho_dev,
                                         void *const *u_dev, void *stream) {
     return guarded([&]() -> psp_status {
         if (count < 0 || (count > 0 && (!plans || !rho_dev || !u_dev))) return fail(PSP_EINVAL, "bad batch arguments");

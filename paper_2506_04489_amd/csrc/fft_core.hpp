@@ -277,6 +277,18 @@ PSP_PLAN(256, 0, 8, 8, 4)
 PSP_PLAN(384, 0, 8, 4, 4, 3)
 PSP_PLAN(512, 0, 8, 8, 8)
 PSP_PLAN(768, 0, 8, 8, 4, 3)
+// lengths 2^a 3^b with b >= 2: radix-3 stages (radix 12 where it saves a
+// stage and keeps every thread busy)
+PSP_PLAN(36, 0, 4, 3, 3)
+PSP_PLAN(72, 0, 8, 3, 3)
+PSP_PLAN(108, 0, 4, 3, 3, 3)
+PSP_PLAN(144, 0, 8, 2, 3, 3)
+PSP_PLAN(216, 0, 8, 3, 3, 3)
+PSP_PLAN(288, 0, 8, 4, 3, 3)
+PSP_PLAN(324, 0, 12, 3, 3, 3)
+PSP_PLAN(432, 0, 12, 12, 3)
+PSP_PLAN(576, 0, 12, 12, 4)
+PSP_PLAN(648, 0, 8, 3, 3, 3, 3)
 // alternatives
 PSP_PLAN(128, 1, 4, 8, 4)
 PSP_PLAN(256, 1, 4, 8, 8)

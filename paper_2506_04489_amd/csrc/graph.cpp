@@ -58,7 +58,7 @@ using namespace psp;
 
 extern "C" {
 
-psp_status psp_graph_capture(psp_plan *p, const void *rho_dev, void *u_dev, void *stream, psp_graph **out) {
+psp_status psp_graph_capture(const psp_plan *p, const void *rho_dev, void *u_dev, void *stream, psp_graph **out) {
     return guarded([&]() -> psp_status {
         if (!out) return fail(PSP_EINVAL, "out is NULL");
         *out = nullptr;
@@ -88,7 +88,7 @@ psp_status psp_graph_capture(psp_plan *p, const void *rho_dev, void *u_dev, void
     });
 }
 
-psp_status psp_graph_capture_batched(int count, psp_plan *const *plans, const void *const *rho_dev,
+psp_status psp_graph_capture_batched(int count, const psp_plan *const *plans, const void *const *rho_dev,
                                      void *const *u_dev, void *stream, psp_graph **out) {
     return guarded([&]() -> psp_status {
         if (!out) return fail(PSP_EINVAL, "out is NULL");

@@ -154,21 +154,23 @@ struct psp_plan {
     std::shared_ptr<psp::DevSpectrum> spec;
     const psp::Twiddles *tw = nullptr;
     bool precomputed = false;
-    std::mutex mu;
-    std::map<hipStream_t, psp::Workspace> ws;   // one workspace per stream
+    // per-stream workspaces and profiling state change under const solves
+    // (the solve entry points take const plans): guarded by mu
+    mutable std::mutex mu;
+    mutable std::map<hipStream_t, psp::Workspace> ws;   // one workspace per stream
     int chunk_tiles = 0;                        // H2-H4 chunking (0: one chunk)
     int i1_group = 0;                           // H1-H2 / H4-H5 i1 grouping (0: none)
     psp::Shape shape;                           // launch shape of the passes
     // per-pass profiling: prof_nev events (and launch-to-pass ids) per solve
-    std::vector<hipEvent_t> prof_ev;
-    std::vector<int> prof_pass;
-    int prof_cap = 0, prof_used = 0, prof_nev = 0;
+    mutable std::vector<hipEvent_t> prof_ev;
+    mutable std::vector<int> prof_pass;
+    mutable int prof_cap = 0, prof_used = 0, prof_nev = 0;
 };
 
 namespace psp {
 psp_status check_create(int n, double h, int R, double eps, double delta);
 // the process-wide tuned launch shape for (n, tier); the default shape if none
 Shape tuned_shape(int n, bool f32);
-psp_status plan_workspace(psp_plan *p, hipStream_t st, Workspace **out);
+psp_status plan_workspace(const psp_plan *p, hipStream_t st, Workspace **out);
 SolveArgs solve_args(const psp_plan *p, const Workspace &w, const void *rho, void *u);
 }  // namespace psp

@@ -189,13 +189,18 @@ hipError_t launch_spectrum(const SpecTables &tb, const double *omega, int R, int
 // kernel launches of one solve (its profiling events are one more)
 int solve_launches(int n, bool f32, int chunk_tiles, int i1_group);
 
-// supported padded lengths
+// supported padded lengths: every 2^a 3^b from 8 to 768 whose half n is even
 inline bool supported_length(int N) {
     switch (N) {
         case 8: case 12: case 16: case 24: case 32: case 48: case 64: case 96:
         case 128: case 192: case 256: case 384: case 512: case 768: return true;
+        case 36: case 72: case 108: case 144: case 216: case 288: case 324: case 432: case 576: case 648:
+            return true;
         default: return false;
     }
 }
+// lengths with a factor 9 (two or more radix-3 stages): instantiated in the
+// passes_{f64,f32}_x*.hip files
+inline bool nine_length(int N) { return N % 9 == 0; }
 
 }  // namespace psp

@@ -121,9 +121,25 @@ hipError_t passes_f32_lo(int N, const Job &one, const Job *table, int count, int
 hipError_t passes_f32_hi(int N, const Job &one, const Job *table, int count, int P, int chunk_tiles, int i1_group,
                          const Shape &sh, bool full, const void *tw64, hipEvent_t *ev,
                          int *ev_pass, int nev, const Dims &dm, int mask, hipStream_t st);
+hipError_t passes_f64_x1(int N, const Job &one, const Job *table, int count, int P, int chunk_tiles, int i1_group,
+                         const Shape &sh, bool full, const void *tw64, hipEvent_t *ev,
+                         int *ev_pass, int nev, const Dims &dm, int mask, hipStream_t st);
+hipError_t passes_f64_x2(int N, const Job &one, const Job *table, int count, int P, int chunk_tiles, int i1_group,
+                         const Shape &sh, bool full, const void *tw64, hipEvent_t *ev,
+                         int *ev_pass, int nev, const Dims &dm, int mask, hipStream_t st);
+hipError_t passes_f32_x1(int N, const Job &one, const Job *table, int count, int P, int chunk_tiles, int i1_group,
+                         const Shape &sh, bool full, const void *tw64, hipEvent_t *ev,
+                         int *ev_pass, int nev, const Dims &dm, int mask, hipStream_t st);
+hipError_t passes_f32_x2(int N, const Job &one, const Job *table, int count, int P, int chunk_tiles, int i1_group,
+                         const Shape &sh, bool full, const void *tw64, hipEvent_t *ev,
+                         int *ev_pass, int nev, const Dims &dm, int mask, hipStream_t st);
 
 // the instantiation holding padded length N
 static auto passes_for(bool f32, int N) {
+    if (nine_length(N)) {
+        if (f32) return N <= 216 ? passes_f32_x1 : passes_f32_x2;
+        return N <= 216 ? passes_f64_x1 : passes_f64_x2;
+    }
     if (f32) return N <= 192 ? passes_f32_lo : passes_f32_hi;
     return N <= 192 ? passes_f64_lo : passes_f64_hi;
 }

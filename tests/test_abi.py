@@ -35,6 +35,8 @@ def test_every_declared_symbol_is_exported():
     (10, 0.1, 40, "PSP_EUNSUPPORTED"),    # 2n = 20 has a factor 5
     (2, 0.1, 40, "PSP_EUNSUPPORTED"),     # too small
     (512, 0.1, 40, "PSP_EUNSUPPORTED"),   # above the supported maximum
+    (30, 0.1, 40, "PSP_EUNSUPPORTED"),    # 2n = 60 has a factor 5
+    (486, 0.1, 40, "PSP_EUNSUPPORTED"),   # 2n = 972 = 4 * 3^5, above 384
     (32, 0.0, 40, "PSP_EINVAL"),
     (32, -1.0, 40, "PSP_EINVAL"),
     (32, float("inf"), 40, "PSP_EINVAL"),
@@ -46,6 +48,26 @@ def test_plan_create_rejects(n, h, R, code):
     with pytest.raises(B.PspError) as ei:
         B.Plan(n, h, R)
     assert B.STATUS[ei.value.status] == code
+
+
+def test_every_2a3b_size_is_accepted():
+    # Algorithm 1 takes any grid size: every even n in [4, 384] with
+    # 2n = 2^a 3^b gets a plan, every other n in that range is refused
+    def smooth(m):
+        while m % 2 == 0:
+            m //= 2
+        while m % 3 == 0:
+            m //= 3
+        return m == 1
+    for n in range(4, 385, 2):
+        if smooth(2 * n):
+            p = B.Plan(n, 2.0 / n, 8)
+            assert p.workspace_bytes() > 0
+            p.close()
+        else:
+            with pytest.raises(B.PspError) as ei:
+                B.Plan(n, 2.0 / n, 8)
+            assert B.STATUS[ei.value.status] == "PSP_EUNSUPPORTED"
 
 
 def test_plan_create_ex_rejects_bad_cutoff():
