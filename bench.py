@@ -417,50 +417,80 @@ def bench_box(torch, B, sizes=(64, 128), R=461, reps=20):
     return out
 
 
-def cpu_baseline(n: int, budget_s: float = 12.0):
-    """The oracle (as it stands) on a bounded sample of the same workload: its
-    naive FFT on a batch of length-2n pencils, scaled to one full solve
-    (6 (2n)^2 pencil transforms: three axes forward, three inverse)."""
+def cpu_baseline_and_parity(n, rho_big, gpu_u, gpu_u32=None, reps_small=10, reps_mid=3):
+    """The oracle (as it stands) timed on the host, solve phase only (the
+    set-up of Algorithm 1 excluded, as in the paper's protocol, Section 3),
+    with its C naive FFT on one thread and on all of them:
+      * n = 32 Gaussian: reps_small solves each way (median and mean);
+      * n = 128 oscillatory: reps_mid solves on all threads, one on one;
+      * the headline n (bump, rho_big: the density the GPU solved, copied
+        back): one whole solve on all threads, whose output is compared
+        element by element with the timed GPU result (FP64 tier, and the
+        FP32 tier when given): eq. error_infty over every grid point.
+    value/unit: the headline solve on all threads, in solves/s."""
+    import statistics
     import numpy as np
+    from oracle import native
     from oracle import psp_oracle as O
-    N = 2 * n
-    batch = 2048
-    rng = np.random.default_rng(0)
-    x = rng.standard_normal((batch, N)) + 1j * rng.standard_normal((batch, N))
-    O.fft_naive(x[:8], -1)
-    calls, t0 = 0, time.perf_counter()
-    while True:
-        O.fft_naive(x, -1 if calls % 2 == 0 else 1)
-        calls += 1
-        el = time.perf_counter() - t0
-        if el > budget_s or calls >= 64:
-            break
-    per_pencil = el / (calls * batch)
-    solve_s = per_pencil * 6 * N * N
-    # beside it, one whole oracle solve of the small configuration (n = 32
-    # Gaussian, R = 40: set-up and solve), timed end to end
-    h32 = 2.0 / 32
-    xs = -1.0 + h32 * np.arange(32)
-    r2 = xs[:, None, None] ** 2 + xs[None, :, None] ** 2 + xs[None, None, :] ** 2
-    t0 = time.perf_counter()
-    O.solve(np.exp(-r2 / 0.15 ** 2), h32, 40)
-    n32_s = time.perf_counter() - t0
-    return {"value": 1.0 / solve_s, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": "%d calls of the oracle's naive radix-2/3 FFT on %d length-%d pencils (%.1f s); "
-                      "one n=%d solve needs 6*%d^2 such pencil transforms; pad/multiply/crop not timed"
-                      % (calls, batch, N, el, n, N),
-            "est_solve_s": solve_s, "n32_whole_solve_s": round(n32_s, 3),
-            "host_cpus": os.cpu_count(),
-            "threads_note": "the oracle's FFT is a Python recursion over numpy vector operations on one core"}
+    from paper_2506_04489_amd import densities as D
+    all_threads = native.set_threads(0)
+
+    def timed(rho, h, su, reps, threads):
+        native.set_threads(threads)
+        O.solve(rho[:4, :4, :4], h, 4)                     # warm the library
+        ts, u = [], None
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            u = O.solve(rho, h, su.R, su=su)
+            ts.append(time.perf_counter() - t0)
+        return ts, u
+
+    out = {"kind": "oracle", "unit": "solves/s", "cores": all_threads, "host_cpus": os.cpu_count(),
+           "protocol": "solve phase only (set-up excluded); C naive radix-2/3 FFT with OpenMP over lines, "
+                       "pad/multiply/crop in numpy"}
+    runs = {}
+    h = 2.0 / 32
+    su = O.setup(32, h, 40)
+    rho = D.gaussian(32, h, -1.0, 0.15)
+    for th in (1, all_threads):
+        ts, _ = timed(rho, h, su, reps_small, th)
+        runs["n32_gaussian_%dthr" % th] = {"solves": reps_small, "median_s": round(statistics.median(ts), 5),
+                                          "mean_s": round(sum(ts) / len(ts), 5)}
+    h = 2.0 / 128
+    su = O.setup(128, h, 40)
+    rho = D.oscillatory(128, h, -1.0, a=0.2, omega=20.0)
+    for th, reps in ((all_threads, reps_mid), (1, 1)):
+        ts, _ = timed(rho, h, su, reps, th)
+        runs["n128_oscillatory_%dthr" % th] = {"solves": reps, "median_s": round(statistics.median(ts), 4),
+                                              "mean_s": round(sum(ts) / len(ts), 4)}
+    h = 2.0 / n
+    su = O.setup(n, h, 40)
+    ts, want = timed(rho_big, h, su, 1, all_threads)
+    runs["n%d_bump_%dthr" % (n, all_threads)] = {"solves": 1, "median_s": round(ts[0], 3), "mean_s": round(ts[0], 3)}
+    native.set_threads(0)
+    out["runs"] = runs
+    out["value"] = 1.0 / ts[0]
+    out["sample"] = ("one whole n=%d bump solve on %d threads (%.1f s); beside it n=32 x%d and n=128 x%d on all "
+                     "threads and on one" % (n, all_threads, ts[0], reps_small, reps_mid))
+    scale = float(np.max(np.abs(want)))
+    parity = {"points": int(want.size), "metric": "max|u_gpu - u_oracle| / max|u_oracle| over every grid point",
+              "f64": float(np.max(np.abs(gpu_u - want)) / scale), "tol_f64": 1e-12}
+    parity["f64_ok"] = parity["f64"] <= 1e-12
+    if gpu_u32 is not None:
+        parity["f32"] = float(np.max(np.abs(gpu_u32 - want)) / scale)
+        parity["tol_f32"] = 1e-5
+        parity["f32_ok"] = parity["f32"] <= 1e-5
+    return out, parity
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--n", type=int, default=256)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-cpu", action="store_true",
+                    help="skip the oracle CPU baseline and the element-wise check of the timed result")
     ap.add_argument("--no-f32", action="store_true", help="skip the FP32 tier")
     ap.add_argument("--chunk", type=int, default=0, help="k3 tiles per H2-H4 chunk (0: library default)")
     ap.add_argument("--group", type=int, default=0, help="i1 slabs per H1-H2/H4-H5 group (0: library default)")
@@ -540,6 +570,7 @@ def main():
         # FP32-tier error against the FP64 result of the same workload
         u64 = res["u"]
         err = float((r32["u"].double() - u64).abs().max() / u64.abs().max())
+        out["_u32"] = r32["u"].double().cpu().numpy()
         out["f32_tier"] = {"solves_per_s": round(args.steps / r32["wall_s"], 3),
                            "ms_per_step": round(1e3 * r32["wall_s"] / args.steps, 4),
                            "pass_ms": [round(v, 4) for v in r32["pass_ms"]],
@@ -557,7 +588,12 @@ def main():
     if not args.no_box:
         out["box_rows"] = bench_box(torch, B)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(n)
+        # the timed results themselves, checked against the oracle's
+        # whole-grid solve (timed as the CPU baseline)
+        u32 = out.pop("_u32", None)
+        out["cpu_baseline"], out["parity"] = cpu_baseline_and_parity(n, res["rho"].cpu().numpy(),
+                                                                     res["u"].cpu().numpy(), u32)
+    out.pop("_u32", None)
     print(json.dumps(out))
 
 

@@ -22,6 +22,7 @@
  * is copied to a contiguous buffer, transformed and copied back.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -64,6 +65,13 @@ static void dft_rec(const cpx *x, long xs, long N, const cpx *tw, long step, cpx
         out[k].im = im;
         if (++kk == M) kk = 0;
     }
+}
+
+/* Threads of the following transforms (OpenMP); t <= 0 keeps the default
+ * (OMP_NUM_THREADS or the core count).  Returns the count now in force. */
+int oracle_set_threads(int t) {
+    if (t > 0) omp_set_num_threads(t);
+    return omp_get_max_threads();
 }
 
 /* DFT along `axis` (0, 1 or 2) of the C-ordered array a[d0][d1][d2] of

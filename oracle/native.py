@@ -51,8 +51,16 @@ def lib():
             L.oracle_fft_axis.restype = ctypes.c_int
             L.oracle_fft_axis.argtypes = [ctypes.c_void_p, ctypes.c_long, ctypes.c_long, ctypes.c_long,
                                           ctypes.c_int, ctypes.c_int]
+            L.oracle_set_threads.restype = ctypes.c_int
+            L.oracle_set_threads.argtypes = [ctypes.c_int]
             _lib = L
     return _lib
+
+
+def set_threads(t: int) -> int:
+    """Threads of the C FFT's later calls (t <= 0: the OpenMP default);
+    returns the count in force."""
+    return int(lib().oracle_set_threads(int(t)))
 
 
 def fft_axis_inplace(a: np.ndarray, axis: int, sign: int) -> None:

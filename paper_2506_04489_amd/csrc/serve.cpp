@@ -3,18 +3,24 @@
 // A scheduler thread owns the device work.  Each turn it
 //   1. retires launched batches whose completion event has fired (their
 //      workspaces go back to a pool, their slots free up, latency is the
-//      host time from submit to the observed completion);
+//      host time from submit to the observed completion) and takes over the
+//      plans whose spectrum a precompute thread has finished;
 //   2. admits queued requests in arrival order while a slot is free and the
 //      request's footprint fits the HBM budget: a workspace for (n, tier)
-//      (reused from the pool when one is free) and, on a spectrum-cache miss,
-//      the multiplier octant (8 (n+1)^2 round_up(n+1,16) bytes).  Idle cached
-//      spectra and pooled workspaces are evicted, least recently used first,
-//      to make room; the queue head waits when nothing more can be freed;
+//      (reused from the pool when one is free) and the multiplier octant
+//      (8 (n+1)^2 round_up(n+1,16) bytes).  On a spectrum-cache miss the
+//      octant's bytes are reserved and the precompute (Algorithm 1) is handed
+//      to the precompute thread, which runs it on a stream of its own; the
+//      request stays queued, and later requests whose spectra are cached are
+//      admitted past it meanwhile.  Idle cached spectra and pooled workspaces
+//      are evicted, least recently used first, to make room; the queue head
+//      waits when nothing more can be freed;
 //   3. launches the admitted requests of one tier and size class (n <= 128 or
-//      larger) as one batch on the pool's stream with the fewest batches in
-//      flight and records a completion event, so requests that arrive while
-//      others run are admitted and overlap on the device, and a small request
-//      does not wait for a large one's completion.
+//      larger) as one batch on a stream of that class (two streams per
+//      class, the one with fewer batches in flight) and records a completion
+//      event, so requests that arrive while others run are admitted and
+//      overlap on the device, and a small request never waits in stream
+//      order behind a large one.
 // Every solve runs the same kernels on its own workspace, so a result is
 // bitwise the same alone and in any mix.
 #include <algorithm>
@@ -49,16 +55,36 @@ struct ServeReq {
     void *u = nullptr;
     Clock::time_point t_submit;
     bool done = false;
+    bool missed = false;            // its spectrum was not cached on arrival
     psp_status result = PSP_OK;
     double latency_ms = 0;
 };
 
+using SpecKey3 = std::tuple<int, double, int>;
+
 struct CachedSpec {                 // plans of both tiers for one (n, h, R)
     psp_plan *plan[2] = {nullptr, nullptr};
-    size_t bytes = 0;
+    bool pending[2] = {false, false};   // a precompute of that tier is running
+    size_t bytes = 0;               // the octant's bytes, accounted once per key
     int users = 0;
     Clock::time_point last_use;
 };
+
+// a precompute handed to the precompute thread, and its outcome
+struct PreJob {
+    SpecKey3 key;
+    int tier = 0;
+};
+struct PreDone {
+    SpecKey3 key;
+    int tier = 0;
+    psp_plan *plan = nullptr;
+    psp_status st = PSP_OK;
+    std::string detail;
+};
+
+// streams: kClassStreams for n <= kSmallN, as many for larger n
+constexpr int kClassStreams = 2;
 
 struct PooledWs {
     Workspace w;
@@ -90,8 +116,16 @@ struct psp_server {
     uint64_t next_id = 1;
     size_t pending_total = 0;
     bool stop = false;
+    // precompute thread: jobs in, finished plans out (under pre_mu)
+    std::mutex pre_mu;
+    std::condition_variable pre_cv;
+    std::deque<PreJob> pre_jobs;
+    std::vector<PreDone> pre_done;
+    bool pre_stop = false;
+    hipStream_t pre_stream = nullptr;
+    std::thread pre_thread;
     // scheduler-thread state
-    std::map<std::tuple<int, double, int>, CachedSpec> specs;
+    std::map<SpecKey3, CachedSpec> specs;
     std::vector<PooledWs> pool;
     std::list<Batch> inflight;
     std::vector<hipStream_t> streams;
@@ -130,7 +164,8 @@ static bool make_room(psp_server *sv, size_t need, const std::tuple<int, double,
         }
         auto victim = sv->specs.end();
         for (auto it = sv->specs.begin(); it != sv->specs.end(); ++it) {
-            if (it->second.users > 0 || (keep && it->first == *keep)) continue;
+            if (it->second.users > 0 || it->second.pending[0] || it->second.pending[1] || (keep && it->first == *keep))
+                continue;
             if (victim == sv->specs.end() || it->second.last_use < victim->second.last_use) victim = it;
         }
         if (victim == sv->specs.end()) return false;
@@ -141,29 +176,90 @@ static bool make_room(psp_server *sv, size_t need, const std::tuple<int, double,
     return true;
 }
 
-static psp_status get_plan(psp_server *sv, const ServeReq &r, psp_plan **out, bool *hit) {
-    auto key = std::make_tuple(r.n, r.h, r.R);
-    auto &cs = sv->specs[key];
-    const int t = r.tier == PSP_F32 ? 1 : 0;
-    *hit = cs.plan[0] || cs.plan[1];
-    if (!cs.plan[t]) {
-        psp_plan *p = nullptr;
-        psp_status st = psp_plan_create(r.n, r.h, r.R, r.tier, &p);
-        if (st != PSP_OK) return st;
-        st = psp_kernel_precompute(p, sv->streams[0]);
-        if (st != PSP_OK) {
-            psp_plan_destroy(p);
-            return st;
+// The precompute thread: creates the plan of a job and runs its precompute
+// (Algorithm 1: 1D tables and the spectrum contraction, synchronous on the
+// thread's own stream), then hands the plan to the scheduler.
+static void precompute_worker(psp_server *sv) {
+    (void)hipSetDevice(sv->device);
+    for (;;) {
+        PreJob job;
+        {
+            std::unique_lock<std::mutex> lk(sv->pre_mu);
+            sv->pre_cv.wait(lk, [&] { return sv->pre_stop || !sv->pre_jobs.empty(); });
+            if (sv->pre_jobs.empty()) return;              // stopping, nothing left
+            job = sv->pre_jobs.front();
+            sv->pre_jobs.pop_front();
         }
-        cs.plan[t] = p;
-        if (cs.bytes == 0) {
-            cs.bytes = spectrum_bytes(r.n);
-            account(sv, (long)cs.bytes);
+        PreDone d;
+        d.key = job.key;
+        d.tier = job.tier;
+        try {
+            psp_plan *p = nullptr;
+            d.st = psp_plan_create(std::get<0>(job.key), std::get<1>(job.key), std::get<2>(job.key),
+                                   job.tier ? PSP_F32 : PSP_F64, &p);
+            if (d.st == PSP_OK) {
+                d.st = psp_kernel_precompute(p, sv->pre_stream);
+                if (d.st != PSP_OK) {
+                    d.detail = psp_last_error();
+                    psp_plan_destroy(p);
+                    p = nullptr;
+                }
+            } else {
+                d.detail = psp_last_error();
+            }
+            d.plan = p;
+        } catch (...) {
+            d.st = PSP_ENOMEM;
+        }
+        {
+            std::lock_guard<std::mutex> lk(sv->pre_mu);
+            try {
+                sv->pre_done.push_back(d);
+            } catch (...) {
+                if (d.plan) psp_plan_destroy(d.plan);
+            }
+        }
+        {
+            std::lock_guard<std::mutex> lk(sv->mu);
+            sv->cv_work.notify_one();
         }
     }
-    cs.last_use = Clock::now();
-    *out = cs.plan[t];
-    return PSP_OK;
+}
+
+// finish a request that is still queued (and not done): it leaves the queue
+// in the same critical section, so a concurrent cancel cannot finish it twice
+static void finish_if_queued(psp_server *sv, uint64_t id, psp_status st);
+
+// scheduler: take over finished precomputes; a failed one finishes the
+// queued requests of its (key, tier) with its status
+static void collect_precomputes(psp_server *sv) {
+    std::vector<PreDone> done;
+    {
+        std::lock_guard<std::mutex> lk(sv->pre_mu);
+        done.swap(sv->pre_done);
+    }
+    for (auto &d : done) {
+        auto &cs = sv->specs[d.key];
+        cs.pending[d.tier] = false;
+        if (d.st == PSP_OK) {
+            cs.plan[d.tier] = d.plan;
+            cs.last_use = Clock::now();
+            continue;
+        }
+        if (!cs.plan[0] && !cs.plan[1] && !cs.pending[0] && !cs.pending[1] && cs.bytes) {
+            account(sv, -(long)cs.bytes);      // the reservation is given back
+            cs.bytes = 0;
+        }
+        std::vector<uint64_t> ids;
+        {
+            std::lock_guard<std::mutex> lk(sv->mu);
+            for (uint64_t id : sv->queue) {
+                const ServeReq &r = sv->reqs[id];
+                if (std::make_tuple(r.n, r.h, r.R) == d.key && (r.tier == PSP_F32 ? 1 : 0) == d.tier) ids.push_back(id);
+            }
+        }
+        for (uint64_t id : ids) finish_if_queued(sv, id, d.st);
+    }
 }
 
 static psp_status take_ws(psp_server *sv, int n, bool f32, PooledWs *out) {
@@ -208,6 +304,14 @@ static void finish(psp_server *sv, uint64_t id, psp_status st) {
     finish_locked(sv, id, st);
 }
 
+static void finish_if_queued(psp_server *sv, uint64_t id, psp_status st) {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto q = std::find(sv->queue.begin(), sv->queue.end(), id);
+    if (q == sv->queue.end() || sv->reqs[id].done) return;   // canceled meanwhile
+    sv->queue.erase(q);
+    finish_locked(sv, id, st);
+}
+
 static void retire(psp_server *sv, bool wait) {
     for (auto it = sv->inflight.begin(); it != sv->inflight.end();) {
         hipError_t q = wait ? hipEventSynchronize(it->ev) : hipEventQuery(it->ev);
@@ -229,7 +333,10 @@ static void retire(psp_server *sv, bool wait) {
 // Returns true once the server is stopping and nothing is left.
 static bool schedule_round(psp_server *sv) {
     retire(sv, false);
-    // snapshot the queue head under the lock
+    collect_precomputes(sv);
+    // snapshot the queue under the lock: up to the free slots' worth of
+    // requests, skipping those whose spectrum is still being precomputed
+    // (bounded scan)
     std::vector<std::pair<uint64_t, ServeReq>> cand;
     {
         std::unique_lock<std::mutex> lk(sv->mu);
@@ -238,9 +345,13 @@ static bool schedule_round(psp_server *sv) {
             sv->cv_work.wait_for(lk, std::chrono::milliseconds(2));
             return false;
         }
+        int scanned = 0;
         for (uint64_t id : sv->queue) {
-            if ((int)cand.size() + sv->slots_used >= sv->max_slots) break;
-            cand.emplace_back(id, sv->reqs[id]);
+            if ((int)cand.size() + sv->slots_used >= sv->max_slots || ++scanned > 4096) break;
+            const ServeReq &r = sv->reqs[id];
+            auto sit = sv->specs.find(std::make_tuple(r.n, r.h, r.R));
+            if (sit != sv->specs.end() && sit->second.pending[r.tier == PSP_F32 ? 1 : 0]) continue;
+            cand.emplace_back(id, r);
         }
     }
     // admit in order; batches per (tier, size class), so that a small
@@ -249,38 +360,78 @@ static bool schedule_round(psp_server *sv) {
     std::vector<SolveArgs> args[kBatchKinds];
     std::vector<uint64_t> ids[kBatchKinds];
     std::vector<PooledWs> wss[kBatchKinds];
-    std::vector<std::tuple<int, double, int>> keys[kBatchKinds];
+    std::vector<SpecKey3> keys[kBatchKinds];
+    bool issued = false;
     for (auto &c : cand) {
         const ServeReq &r = c.second;
-        const auto key = std::make_tuple(r.n, r.h, r.R);
+        const SpecKey3 key = std::make_tuple(r.n, r.h, r.R);
         const bool f32 = r.tier == PSP_F32;
-        auto sit = sv->specs.find(key);
-        const bool cached = sit != sv->specs.end() && (sit->second.plan[0] || sit->second.plan[1]);
-        bool have_ws = false;
-        for (auto &p : sv->pool) have_ws |= (p.n == r.n && p.f32 == f32);
-        const size_t need = (cached ? 0 : spectrum_bytes(r.n)) + (have_ws ? 0 : ws_bytes(r.n, f32));
-        if (!make_room(sv, need, &key)) break;   // head of line waits for memory
-        psp_plan *p = nullptr;
-        bool hit = false;
-        psp_status st = get_plan(sv, r, &p, &hit);
-        PooledWs w;
-        if (st == PSP_OK) st = take_ws(sv, r.n, f32, &w);
-        admitted.push_back(c.first);
-        if (st != PSP_OK) {
-            finish(sv, c.first, st);
+        const int ti = f32 ? 1 : 0;
+        CachedSpec &cs = sv->specs[key];
+        if (cs.pending[ti]) continue;                 // issued earlier in this round
+        if (!cs.plan[ti]) {
+            // spectrum-cache miss: reserve the octant (once per key), hand the
+            // precompute to its thread; the request stays queued
+            const size_t need = cs.bytes ? 0 : spectrum_bytes(r.n);
+            if (!make_room(sv, need, &key)) break;    // head of line waits for memory
+            if (need) {
+                cs.bytes = need;
+                account(sv, (long)need);
+            }
+            cs.pending[ti] = true;
+            cs.last_use = Clock::now();
+            {
+                std::lock_guard<std::mutex> lk(sv->pre_mu);
+                sv->pre_jobs.push_back(PreJob{key, ti});
+                sv->pre_cv.notify_one();
+            }
+            {
+                std::lock_guard<std::mutex> lk(sv->mu);
+                sv->reqs[c.first].missed = true;
+            }
+            issued = true;
             continue;
         }
-        (hit ? sv->hits : sv->misses)++;
-        sv->specs[key].users++;
-        const int t = (f32 ? 1 : 0) + (r.n > kSmallN ? 2 : 0);
-        args[t].push_back(solve_args(p, w.w, r.rho, r.u));
+        // a pooled workspace of this (n, tier) is taken out of the pool before
+        // making room, so that making room cannot evict it; a new one counts
+        // against the budget
+        PooledWs w;
+        bool have_ws = false;
+        for (size_t i = 0; i < sv->pool.size(); ++i)
+            if (sv->pool[i].n == r.n && sv->pool[i].f32 == f32) {
+                w = sv->pool[i];
+                sv->pool.erase(sv->pool.begin() + i);
+                have_ws = true;
+                break;
+            }
+        if (!make_room(sv, have_ws ? 0 : ws_bytes(r.n, f32), &key)) {
+            if (have_ws) sv->pool.push_back(w);
+            break;                                    // head of line waits for memory
+        }
+        psp_status st = PSP_OK;
+        if (!have_ws) st = take_ws(sv, r.n, f32, &w);
+        admitted.push_back(c.first);
+        if (st != PSP_OK) {
+            finish_if_queued(sv, c.first, st);
+            continue;
+        }
+        bool missed = false;
+        {
+            std::lock_guard<std::mutex> lk(sv->mu);
+            missed = sv->reqs[c.first].missed;
+        }
+        (missed ? sv->misses : sv->hits)++;
+        cs.users++;
+        cs.last_use = Clock::now();
+        const int t = ti + (r.n > kSmallN ? 2 : 0);
+        args[t].push_back(solve_args(cs.plan[ti], w.w, r.rho, r.u));
         ids[t].push_back(c.first);
         wss[t].push_back(w);
         keys[t].push_back(key);
     }
     if (!admitted.empty()) {
-        // claim the admitted requests; one canceled since the snapshot is
-        // no longer queued (and already finished): drop it from the launch
+        // claim the admitted requests; one canceled (or failed) since the
+        // snapshot is no longer queued: drop it from the launch
         std::vector<uint64_t> gone;
         {
             std::lock_guard<std::mutex> lk(sv->mu);
@@ -307,10 +458,12 @@ static bool schedule_round(psp_server *sv) {
     }
     for (int t = 0; t < kBatchKinds; ++t) {
         if (ids[t].empty()) continue;
-        // the stream with the fewest batches in flight
+        // the stream of this size class with the fewest batches in flight
         std::vector<int> load(sv->streams.size(), 0);
         for (auto &b : sv->inflight) load[b.stream]++;
-        const int si = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        const int first = t >= 2 ? kClassStreams : 0;
+        const int si = (int)(std::min_element(load.begin() + first, load.begin() + first + kClassStreams) -
+                             load.begin());
         hipStream_t st = sv->streams[si];
         Batch b;
         b.stream = si;
@@ -329,7 +482,7 @@ static bool schedule_round(psp_server *sv) {
         sv->slots_used += (int)b.ids.size();
         sv->inflight.push_back(std::move(b));
     }
-    if (admitted.empty()) {
+    if (admitted.empty() && !issued) {
         // nothing admitted: wait for a completion or a new request
         if (!sv->inflight.empty()) {
             std::this_thread::sleep_for(std::chrono::microseconds(20));
@@ -397,15 +550,20 @@ psp_status psp_serve_create(size_t hbm_budget_bytes, int max_slots, psp_server *
             delete sv;
             return fail(PSP_EHIP, "hipGetDevice failed");
         }
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < 2 * kClassStreams + 1; ++i) {
             hipStream_t s;
             if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
                 for (auto x : sv->streams) (void)hipStreamDestroy(x);
+                if (sv->pre_stream) (void)hipStreamDestroy(sv->pre_stream);
                 delete sv;
                 return fail(PSP_EHIP, "hipStreamCreate failed");
             }
-            sv->streams.push_back(s);
+            if (i < 2 * kClassStreams)
+                sv->streams.push_back(s);
+            else
+                sv->pre_stream = s;
         }
+        sv->pre_thread = std::thread(precompute_worker, sv);
         sv->sched = std::thread(scheduler, sv);
         *out = sv;
         return PSP_OK;
@@ -503,10 +661,19 @@ void psp_serve_destroy(psp_server *sv) {
             sv->cv_work.notify_all();
         }
         sv->sched.join();
+        {
+            std::lock_guard<std::mutex> lk(sv->pre_mu);
+            sv->pre_stop = true;
+            sv->pre_cv.notify_all();
+        }
+        sv->pre_thread.join();
+        for (auto &d : sv->pre_done)
+            if (d.plan) psp_plan_destroy(d.plan);
         for (auto &w : sv->pool) free_ws(sv, w);
         for (auto &kv : sv->specs)
             for (int t = 0; t < 2; ++t) psp_plan_destroy(kv.second.plan[t]);
         for (auto s : sv->streams) (void)hipStreamDestroy(s);
+        (void)hipStreamDestroy(sv->pre_stream);
         delete sv;
     } catch (...) {
     }
