@@ -48,9 +48,16 @@ typedef struct psp_server psp_server;   /* opaque, library owned */
 /* Precision tier.  PSP_F32 keeps the kernel spectrum, Gaussian-sum data and
  * the multiply in FP64 and runs the FFT passes in FP32 (twiddles formed in
  * FP64 and rounded once to FP32). */
-typedef enum { PSP_F64 = 0, PSP_F32 = 1 } psp_dtype;
+#ifdef __cplusplus
+/* int-sized in C++ too, so that any value a C caller passes is a value of
+ * the type (the library rejects the unknown ones) */
+#define PSP_ENUM_INT : int
+#else
+#define PSP_ENUM_INT
+#endif
+typedef enum PSP_ENUM_INT { PSP_F64 = 0, PSP_F32 = 1 } psp_dtype;
 
-typedef enum {
+typedef enum PSP_ENUM_INT {
     PSP_OK = 0,
     PSP_EINVAL = -1,        /* bad argument (h <= 0, R < 1, NULL pointer ...) */
     PSP_ENOMEM = -2,        /* device or host allocation failed, or over budget */
