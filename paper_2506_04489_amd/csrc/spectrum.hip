@@ -22,14 +22,19 @@ namespace psp {
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 // one wave: SPEC_AT 16-row a-tiles for one b against SPEC_CT consecutive
-// 16-wide c-tiles (1 x 6: 272 rows and 288 columns for n + 1 = 257); every A
+// 16-wide c-tiles (1 x 9: 272 rows and 288 columns for n + 1 = 257); every A
 // operand of a k-step feeds SPEC_CT MFMAs and every B operand SPEC_AT, and
-// the operands of step k + 4 are loaded before the MFMAs of step k are
-// issued, so the table loads' latency overlaps the matrix work (measured on
-// MI355X at n = 256: 1 x 6 144 us; 2 x 6 171 us, its 244 registers leaving
+// the operands of the next SPEC_PF k-steps (of 4) are in flight while the
+// MFMAs of the current one run, so the table loads' latency overlaps the
+// matrix work.  Measured on MI355X at n = 256, R = 40 (us per build, the
+// result bitwise the same for every choice): 1 x 9 with 2 steps in flight
+// 112.5, 3 steps 113.8, 4 steps 140.5; 1 x 6 with 1 step 144, 3 steps 121,
+// 5 steps 131, 6 steps 148; 1 x 8 with 4 steps 166; 1 x 17 with 2 or 3
+// steps 173; 1 x 4 with 5 steps 182; 2 x 6 with 1 step 171 (244 registers,
 // two waves per SIMD)
 constexpr int SPEC_AT = 1;
-constexpr int SPEC_CT = 6;
+constexpr int SPEC_CT = 9;
+constexpr int SPEC_PF = 2;
 
 struct SpecOps {
     double av[SPEC_AT];
@@ -79,16 +84,25 @@ k_spectrum(SpecTables tb, const double *__restrict__ omega, int R, int P, SpecSc
     for (int t = 0; t < SPEC_AT; ++t)
 #pragma unroll
         for (int q = 0; q < SPEC_CT; ++q) acc[t][q] = v4d{0.0, 0.0, 0.0, 0.0};
-    SpecOps cur, nxt;
-    spec_load(cur, 0, kq, abase, b, cbase, R, tb, omega);
-    for (int k0 = 0; k0 < 2 * R; k0 += 4) {
-        if (k0 + 4 < 2 * R) spec_load(nxt, k0 + 4, kq, abase, b, cbase, R, tb, omega);
+    // a ring of SPEC_PF k-steps of operands, indexed statically (the loop
+    // body covers SPEC_PF steps); step k's slot is refilled with step
+    // k + SPEC_PF right after its MFMAs are issued
+    SpecOps ops[SPEC_PF];
 #pragma unroll
-        for (int t = 0; t < SPEC_AT; ++t)
+    for (int d = 0; d < SPEC_PF; ++d) spec_load(ops[d], 4 * d, kq, abase, b, cbase, R, tb, omega);
+    for (int k0 = 0; k0 < 2 * R; k0 += 4 * SPEC_PF) {
 #pragma unroll
-            for (int q = 0; q < SPEC_CT; ++q)
-                acc[t][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur.av[t], cur.bv[q], acc[t][q], 0, 0, 0);
-        cur = nxt;
+        for (int d = 0; d < SPEC_PF; ++d) {
+            if (k0 + 4 * d < 2 * R) {
+#pragma unroll
+                for (int t = 0; t < SPEC_AT; ++t)
+#pragma unroll
+                    for (int q = 0; q < SPEC_CT; ++q)
+                        acc[t][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(ops[d].av[t], ops[d].bv[q], acc[t][q], 0, 0, 0);
+                if (k0 + 4 * (d + SPEC_PF) < 2 * R)
+                    spec_load(ops[d], k0 + 4 * (d + SPEC_PF), kq, abase, b, cbase, R, tb, omega);
+            }
+        }
     }
 #pragma unroll
     for (int t = 0; t < SPEC_AT; ++t)
