@@ -13,9 +13,11 @@
 //    e^-74 of its peak), panels no wider than half a cosine period at k = n
 //    (the rule's error there is ~1e-18 of the integrand) or half the
 //    Gaussian's width; all of it in double-double (tables.hpp).
-// One wave per (s, block of 64 wavenumbers): it stages 64 nodes at a time in
-// LDS (phase, weights), then every lane sums its wavenumber over them in a
-// fixed order, so the tables are deterministic.
+// One workgroup of TAB_W waves per (s, block of 64 wavenumbers): wave w takes
+// the w-th contiguous share of the nodes, stages 64 of them at a time in LDS
+// (phase, weights) and every lane sums its wavenumber over them in order;
+// the waves' partial sums are then added in wave order, so the tables are
+// deterministic.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -25,41 +27,56 @@
 
 namespace psp {
 
-constexpr int TAB_K = 64;   // wavenumbers per workgroup (one wave)
+constexpr int TAB_K = 64;   // wavenumbers per workgroup (one per lane)
+constexpr int TAB_W = 8;    // waves per workgroup, each over its share of the nodes
 
-__global__ void __launch_bounds__(TAB_K)
+__global__ void __launch_bounds__(TAB_K * TAB_W)
 k_tables(const TabJob *__restrict__ jobs, const TabTrig *__restrict__ trig_g, TabRule rule, dd inv_l,
          dd two_pi_l, int n, double *__restrict__ J0, double *__restrict__ J2) {
     __shared__ TabTrig trig[TAB_TRIG / 2 + 1];
-    __shared__ dd sq[TAB_K], sg0[TAB_K], sg2[TAB_K];
+    __shared__ dd sq[TAB_W][TAB_K], sg0[TAB_W][TAB_K], sg2[TAB_W][TAB_K];
+    __shared__ dd p0[TAB_W][TAB_K], p2[TAB_W][TAB_K];
     const int s = blockIdx.y;
-    const int k = blockIdx.x * TAB_K + threadIdx.x;
+    const int lane = threadIdx.x % TAB_K, w = threadIdx.x / TAB_K;
+    const int k = blockIdx.x * TAB_K + lane;
     const TabJob jb = jobs[s];
     double *j0 = J0 + (size_t)s * (n + 1), *j2 = J2 + (size_t)s * (n + 1);
-    if (jb.closed) {
-        if (k <= n) tab_closed(jb.a, two_pi_l, k, rule, &j0[k], &j2[k]);
+    if (jb.closed) {                                  // uniform over the workgroup
+        if (w == 0 && k <= n) tab_closed(jb.a, two_pi_l, k, rule, &j0[k], &j2[k]);
         return;
     }
-    for (int i = threadIdx.x; i <= TAB_TRIG / 2; i += TAB_K) trig[i] = trig_g[i];
-    dd s0{0.0, 0.0}, s2{0.0, 0.0};
+    for (int i = threadIdx.x; i <= TAB_TRIG / 2; i += TAB_K * TAB_W) trig[i] = trig_g[i];
+    // wave w: nodes [w * share, (w + 1) * share), in blocks of TAB_K; every
+    // wave runs the same number of blocks, so the barriers stay uniform
     const int nodes = 15 * jb.panels;
-    for (int base = 0; base < nodes; base += TAB_K) {
-        const int idx = base + threadIdx.x;
-        if (idx < nodes) tab_node(rule, jb, inv_l, idx, &sq[threadIdx.x], &sg0[threadIdx.x], &sg2[threadIdx.x]);
+    const int share = (nodes + TAB_W - 1) / TAB_W;
+    const int lo = w * share, hi = min(nodes, lo + share);
+    dd s0{0.0, 0.0}, s2{0.0, 0.0};
+    for (int base = 0; base < share; base += TAB_K) {
+        const int idx = lo + base + lane;
+        if (idx < hi) tab_node(rule, jb, inv_l, idx, &sq[w][lane], &sg0[w][lane], &sg2[w][lane]);
         __syncthreads();
-        const int cnt = min(TAB_K, nodes - base);
+        const int cnt = max(0, min(TAB_K, hi - (lo + base)));
         if (k <= n) {
             for (int i = 0; i < cnt; ++i) {
-                const dd c = tab_cos(rule, trig, k, sq[i]);
-                s0 = dd_add(s0, dd_mul(sg0[i], c));
-                s2 = dd_add(s2, dd_mul(sg2[i], c));
+                const dd c = tab_cos(rule, trig, k, sq[w][i]);
+                s0 = dd_add(s0, dd_mul(sg0[w][i], c));
+                s2 = dd_add(s2, dd_mul(sg2[w][i], c));
             }
         }
         __syncthreads();
     }
-    if (k <= n) {
-        j0[k] = 2.0 * (s0.hi + s0.lo);
-        j2[k] = 2.0 * (s2.hi + s2.lo);
+    p0[w][lane] = s0;
+    p2[w][lane] = s2;
+    __syncthreads();
+    if (w == 0 && k <= n) {
+        dd t0 = p0[0][lane], t2 = p2[0][lane];
+        for (int v = 1; v < TAB_W; ++v) {
+            t0 = dd_add(t0, p0[v][lane]);
+            t2 = dd_add(t2, p2[v][lane]);
+        }
+        j0[k] = 2.0 * (t0.hi + t0.lo);
+        j2[k] = 2.0 * (t2.hi + t2.lo);
     }
 }
 
@@ -142,8 +159,8 @@ hipError_t launch_tables(const std::vector<TabJob> &jobs, const std::vector<TabT
     dd two_pi_l;
     split(6.283185307179586476925286766559005768L / (ld)L, &two_pi_l.hi, &two_pi_l.lo);
     dim3 grid((n + 1 + TAB_K - 1) / TAB_K, R);
-    hipLaunchKernelGGL(k_tables, grid, dim3(TAB_K), 0, st, jobs_dev, trig_dev, table_rule(), inv_l, two_pi_l, n, J0,
-                       J2);
+    hipLaunchKernelGGL(k_tables, grid, dim3(TAB_K * TAB_W), 0, st, jobs_dev, trig_dev, table_rule(), inv_l, two_pi_l,
+                       n, J0, J2);
     return hipGetLastError();
 }
 
