@@ -221,8 +221,9 @@ psp_status psp_plan_set_tuning(psp_plan *p, int k3_tiles, int i1_group);
  *            3: one row with half the threads per column (two butterflies
  *            per thread and stage), 4: 2 and 3 together, 5: one row with the
  *            exchanges through half-size LDS buffers by column half, 6: 5 and
- *            3 together; pass 2 also 7..13: 0..6 with nontemporal stores of
- *            the intermediate, 14..20: 0..6 with nontemporal loads and
+ *            3 together; 7..13: 0..6 with nontemporal accesses to the
+ *            intermediate (pass 1 its stores, pass 2 its stores, pass 3 its
+ *            loads); pass 2 also 14..20: 0..6 with nontemporal loads and
  *            stores.
  * A tile choice changes only which workgroup transforms which column, how
  * values move between stages and the accesses' cache policy: the results
@@ -240,15 +241,16 @@ psp_status psp_tuning_set(int n, psp_dtype dtype, const int *plan, const int *ti
 psp_status psp_tuning_get(int n, psp_dtype dtype, int *plan, int *tile);
 
 /* Autotuner: times every (radix plan, tile) candidate of every pass on this
- * plan's own workspace on `stream` (a hashed pseudo-random input, `reps` timed
- * solves per candidate round after one warm-up, median over repetitions,
+ * plan's own workspace on `stream` (two inputs, a hashed pseudo-random density
+ * and a smooth compactly supported bump; `reps` timed solves per candidate
+ * round and input after one warm-up, median over the repetitions on both,
  * HIP events around each launch), picks per pass the fastest candidate (the
  * default unless another is at least 1% faster), sets it as the plan's shape
  * and enters it in the tuning table.  Outputs (host arrays, each may be
  * NULL): best_plan[5], best_tile[5], best_ms[5] the chosen candidate and
  * that pass's time in ms; cand_ms[5 * 63]: the time of candidate
  * (plan, tile) of pass i at cand_ms[i * 63 + plan * 21 + tile], -1 where the
- * candidate does not exist.  Allocates two n^3
+ * candidate does not exist.  Allocates three n^3
  * buffers for the duration; synchronises `stream`.  PSP_ESTATE before
  * precompute or while profiling; PSP_EINVAL for reps outside [1, 1000]. */
 psp_status psp_autotune(psp_plan *p, int reps, void *stream, int *best_plan, int *best_tile,

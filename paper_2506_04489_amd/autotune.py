@@ -28,7 +28,7 @@ def main(argv=None) -> int:
     ap.add_argument("--out", required=True)
     ap.add_argument("--n", type=int, nargs="*", default=SIZES)
     ap.add_argument("--dtype", nargs="*", default=["f64", "f32"])
-    ap.add_argument("--reps", type=int, default=9)
+    ap.add_argument("--reps", type=int, default=31)
     args = ap.parse_args(argv)
     import os
     os.environ["PSP_TUNING_FILE"] = "none"      # start from the default shapes

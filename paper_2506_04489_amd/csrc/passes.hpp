@@ -150,38 +150,15 @@ __device__ __forceinline__ size_t a_index(const Chunk &ck, int c, int k2, int i1
     return (size_t)i1 * ck.plane + (size_t)k2 * ck.pa + c;
 }
 
-// ------------------------------------------------------------------- H2
-template <typename T, int N, int PV, int W, int XC, bool HF>
-__global__ void __launch_bounds__((StridedCfg<T, N, PV, W, XC, HF>::THREADS))
-k_y_fwd(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
-    using C = cplx<T>;
-    using Cfg = StridedCfg<T, N, PV, W, XC, HF>;
-    using E = Engine<T, N, Cfg::TPC, false, PV>;
-    constexpr int n = N / 2;
-    __shared__ C lds[Cfg::LDS_ELEMS];
-    const Job jb = jr.get();
-    const int nsub = ck.ntile * Cfg::SUB;
-    const int col = threadIdx.x % W, t = threadIdx.x / W;
-    const int i1 = blockIdx.x / nsub, c = (blockIdx.x % nsub) * W + col;
-    const int cg = ck.tile0 * LayoutTile<T>::W + c;
-    const bool valid = cg <= ck.n3;
-    const C *src = (const C *)jb.X + (size_t)i1 * n * P + cg;      // rows i2 of X
-    C *dst = (C *)jb.A + a_index(ck, c, 0, i1);                    // rows k2 of A
-    C v[E::V];
-    E::for_inputs(v, t, [&](int pos, int r) -> C {
-        if (r < E::R(0) / 2 && valid) return src[(size_t)pos * P];
-        return c_zero<C>();
-    });
-    strided_stages<E, Cfg, W>(v, lds, t, col, tw);
-    E::for_outputs(v, t, [&](int pos, int, C &val) { dst[(size_t)pos * ck.pa] = val; });
-}
-
-// ------------------------------------------------------------------- H3
-// Cache policy CP of H3's accesses to the intermediate: 0 ordinary, 1
-// nontemporal stores, 2 nontemporal loads and stores (streaming hints that
-// keep the stream of A from displacing the multiplier blocks the paired
-// workgroups share in L2; which one pays depends on the size and tier, so
-// it is a tuning choice).  The pointers are global memory.
+// Cache policy CP of the strided passes' accesses to the intermediate A:
+// 0 ordinary, 1 nontemporal stores, 2 nontemporal loads and stores.  The
+// streaming hints let the rows a workgroup touches (128 bytes each, a plane
+// or a row pitch apart) go to and come from HBM in the order the workgroups
+// issue them instead of as scattered L2 evictions; in H3 they also keep the
+// stream of A from displacing the multiplier blocks the paired workgroups
+// share in L2.  Which one pays depends on the size and tier, so it is a
+// tuning choice (H2: its stores, H3: both, H4: its loads).  The pointers are
+// global memory.
 template <typename C> struct VecOf;
 template <> struct VecOf<double2> { typedef double type __attribute__((ext_vector_type(2))); };
 template <> struct VecOf<float2> { typedef float type __attribute__((ext_vector_type(2))); };
@@ -206,6 +183,33 @@ template <int CP, typename C> __device__ __forceinline__ void a_store(C *p, cons
     }
 }
 
+// ------------------------------------------------------------------- H2
+template <typename T, int N, int PV, int W, int XC, bool HF, int CP>
+__global__ void __launch_bounds__((StridedCfg<T, N, PV, W, XC, HF>::THREADS))
+k_y_fwd(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
+    using C = cplx<T>;
+    using Cfg = StridedCfg<T, N, PV, W, XC, HF>;
+    using E = Engine<T, N, Cfg::TPC, false, PV>;
+    constexpr int n = N / 2;
+    __shared__ C lds[Cfg::LDS_ELEMS];
+    const Job jb = jr.get();
+    const int nsub = ck.ntile * Cfg::SUB;
+    const int col = threadIdx.x % W, t = threadIdx.x / W;
+    const int i1 = blockIdx.x / nsub, c = (blockIdx.x % nsub) * W + col;
+    const int cg = ck.tile0 * LayoutTile<T>::W + c;
+    const bool valid = cg <= ck.n3;
+    const C *src = (const C *)jb.X + (size_t)i1 * n * P + cg;      // rows i2 of X
+    C *dst = (C *)jb.A + a_index(ck, c, 0, i1);                    // rows k2 of A
+    C v[E::V];
+    E::for_inputs(v, t, [&](int pos, int r) -> C {
+        if (r < E::R(0) / 2 && valid) return src[(size_t)pos * P];
+        return c_zero<C>();
+    });
+    strided_stages<E, Cfg, W>(v, lds, t, col, tw);
+    E::for_outputs(v, t, [&](int pos, int, C &val) { a_store<CP>(&dst[(size_t)pos * ck.pa], val); });
+}
+
+// ------------------------------------------------------------------- H3
 // Work item (b, sub-tile, side): column k2 = b (side 0) or N - b (side 1),
 // both reading the same multiplier block.  Items (b, ., 0) and (b, ., 1) go
 // to workgroups g and g + 8, which the dispatcher places on the same XCD at
@@ -263,7 +267,7 @@ k_x_fused(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
 // ------------------------------------------------------------------- H4
 // FULL (test hook): reads A2[i1][k2][k3] for all N rows i1 and writes all N
 // outputs to Y2[i1][i2][k3] (pitch P).
-template <typename T, int N, int PV, int W, int XC, bool HF, bool FULL>
+template <typename T, int N, int PV, int W, int XC, bool HF, bool FULL, int CP>
 __global__ void __launch_bounds__((StridedCfg<T, N, PV, W, XC, HF>::THREADS))
 k_y_inv(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
     using C = cplx<T>;
@@ -281,7 +285,7 @@ k_y_inv(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
     if constexpr (!FULL) {
         const C *src = (const C *)jb.A + a_index(ck, c, 0, i1);         // rows k2
         E::for_inputs(v, t, [&](int pos, int) -> C {
-            if (valid) return src[(size_t)pos * ck.pa];
+            if (valid) return a_load<CP>(&src[(size_t)pos * ck.pa]);
             return c_zero<C>();
         });
     } else {
@@ -414,6 +418,16 @@ template <typename T, typename F> inline void with_h3_tile(int tile, F &&f) {
         }
     });
 }
+// H2's and H4's tile choice: the strided tile (tile mod 7) and, for tiles
+// 7..13, the nontemporal policy NT (H2: its stores of A, H4: its loads)
+template <typename T, int NT, typename F> inline void with_y_tile(int tile, F &&f) {
+    with_cols<T>(tile % 7, [&](auto w) {
+        if (tile / 7 == 1)
+            f(w, std::integral_constant<int, NT>{});
+        else
+            f(w, std::integral_constant<int, 0>{});
+    });
+}
 template <typename F> inline void with_threads(int tile, F &&f) {
     if (tile == 1)
         f(std::integral_constant<int, 128>{});
@@ -463,10 +477,10 @@ hipError_t passes_impl(const Job &one, const Job *table, int count, int P, int c
         const Chunk ck{0, ntile, ntile * LW, n, n, (long long)a_plane(n, n, ntile * LW, sizeof(cplx<T>))};
         hipLaunchKernelGGL((k_z_r2c<T, N, 0, 256>), dim3(ceil_div(n * n / 2, LC::Q), y), dim3(LC::THREADS), 0, st,
                            jr, n * n / 2, P, tw);
-        hipLaunchKernelGGL((k_y_fwd<T, N, 0, LW, 0, false>), dim3(n * ntile, y), dim3(SC::THREADS), 0, st, jr, ck, P, tw);
+        hipLaunchKernelGGL((k_y_fwd<T, N, 0, LW, 0, false, 0>), dim3(n * ntile, y), dim3(SC::THREADS), 0, st, jr, ck, P, tw);
         hipLaunchKernelGGL((k_x_fused<T, N, 0, LW, 0, false, true, 0>), dim3(ceil_div((long)(n + 1) * ntile, 8) * 16, y),
                            dim3(SC::THREADS), 0, st, jr, ck, P, tw);
-        hipLaunchKernelGGL((k_y_inv<T, N, 0, LW, 0, false, true>), dim3(N * ntile, y), dim3(SC::THREADS), 0, st, jr, ck, P,
+        hipLaunchKernelGGL((k_y_inv<T, N, 0, LW, 0, false, true, 0>), dim3(N * ntile, y), dim3(SC::THREADS), 0, st, jr, ck, P,
                            tw);
         hipLaunchKernelGGL((k_z_c2r<T, N, 0, 256, true>), dim3(ceil_div(N * N / 2, LC::Q), y), dim3(LC::THREADS),
                            0, st, jr, N * N / 2, P, tw);
@@ -484,12 +498,13 @@ hipError_t passes_impl(const Job &one, const Job *table, int count, int P, int c
     };
     auto h2 = [&](const JobRef &jr, const Chunk &ck, int rows) {
         with_plan<N>(sh.plan[1], [&](auto pv) {
-            with_cols<T>(sh.tile[1], [&](auto w) {
+            with_y_tile<T, 1>(sh.tile[1], [&](auto w, auto cp) {
                 constexpr int PV = decltype(pv)::value, W = decltype(w)::W;
                 constexpr int XC = decltype(w)::XC;
                 constexpr bool HF = decltype(w)::HF;
+                constexpr int CP = decltype(cp)::value;
                 using SC = StridedCfg<T, N, PV, W, XC, HF>;
-                hipLaunchKernelGGL((k_y_fwd<T, N, PV, W, XC, HF>), dim3(rows * ck.ntile * SC::SUB, y),
+                hipLaunchKernelGGL((k_y_fwd<T, N, PV, W, XC, HF, CP>), dim3(rows * ck.ntile * SC::SUB, y),
                                    dim3(SC::THREADS), 0, st, jr, ck, P, tw);
             });
         });
@@ -510,12 +525,13 @@ hipError_t passes_impl(const Job &one, const Job *table, int count, int P, int c
     };
     auto h4 = [&](const JobRef &jr, const Chunk &ck, int rows) {
         with_plan<N>(sh.plan[3], [&](auto pv) {
-            with_cols<T>(sh.tile[3], [&](auto w) {
+            with_y_tile<T, 2>(sh.tile[3], [&](auto w, auto cp) {
                 constexpr int PV = decltype(pv)::value, W = decltype(w)::W;
                 constexpr int XC = decltype(w)::XC;
                 constexpr bool HF = decltype(w)::HF;
+                constexpr int CP = decltype(cp)::value;
                 using SC = StridedCfg<T, N, PV, W, XC, HF>;
-                hipLaunchKernelGGL((k_y_inv<T, N, PV, W, XC, HF, false>), dim3(rows * ck.ntile * SC::SUB, y),
+                hipLaunchKernelGGL((k_y_inv<T, N, PV, W, XC, HF, false, CP>), dim3(rows * ck.ntile * SC::SUB, y),
                                    dim3(SC::THREADS), 0, st, jr, ck, P, tw);
             });
         });

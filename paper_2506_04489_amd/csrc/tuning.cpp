@@ -40,9 +40,9 @@ static void shape_to(const Shape &s, int *plan, int *tile) {
     }
 }
 
-// a timing input with the statistics of real data: values in [-1, 1) from
-// an integer hash of the index (all-zero input draws less power and so
-// times the arithmetic-heavy candidates too kindly)
+// one timing input: values in [-1, 1) from an integer hash of the index,
+// dense like measured data (all-zero input draws less power and so times
+// the arithmetic-heavy candidates too kindly)
 template <typename T>
 __global__ void k_fill_hash(T *p, size_t count) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) {
@@ -53,6 +53,22 @@ __global__ void k_fill_hash(T *p, size_t count) {
         x *= 0x846ca68bu;
         x ^= x >> 16;
         p[i] = T((double)x * (2.0 / 4294967296.0) - 1.0);
+    }
+}
+
+// the other timing input: a smooth density of compact support, the C-infinity
+// bump exp(-1/(1 - r^2/0.36)) for r < 0.6 on [-1, 1)^3 (zero on 97% of the
+// grid, the kind of input the solver is meant for); its near-zero
+// intermediates draw less power than pseudo-random values, and the order of
+// near candidates differs between the two
+template <typename T>
+__global__ void k_fill_bump(T *p, int n) {
+    const size_t count = (size_t)n * n * n;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) {
+        const int i3 = (int)(i % n), i2 = (int)((i / n) % n), i1 = (int)(i / ((size_t)n * n));
+        const double x = -1.0 + 2.0 * i1 / n, y = -1.0 + 2.0 * i2 / n, z = -1.0 + 2.0 * i3 / n;
+        const double q = (x * x + y * y + z * z) / 0.36;
+        p[i] = q < 1.0 ? T(exp(-1.0 / (1.0 - q))) : T(0);
     }
 }
 
@@ -135,11 +151,13 @@ psp_status psp_autotune(psp_plan *p, int reps, void *stream, int *best_plan, int
         const int n = p->n;
         const bool f32 = p->dtype == PSP_F32;
         const size_t bytes = (size_t)n * n * n * (f32 ? 4 : 8);
-        void *rho = nullptr, *u = nullptr;
-        if (hipMalloc(&rho, bytes) != hipSuccess || hipMalloc(&u, bytes) != hipSuccess) {
+        void *rho = nullptr, *rho_b = nullptr, *u = nullptr;
+        if (hipMalloc(&rho, bytes) != hipSuccess || hipMalloc(&rho_b, bytes) != hipSuccess ||
+            hipMalloc(&u, bytes) != hipSuccess) {
             (void)hipGetLastError();
             if (rho) (void)hipFree(rho);
-            return fail(PSP_ENOMEM, "autotune buffers of %zu bytes failed", 2 * bytes);
+            if (rho_b) (void)hipFree(rho_b);
+            return fail(PSP_ENOMEM, "autotune buffers of %zu bytes failed", 3 * bytes);
         }
         const int nev = solve_launches(n, f32, p->chunk_tiles, p->i1_group) + 1;
         std::vector<hipEvent_t> ev(nev, nullptr);
@@ -155,24 +173,29 @@ psp_status psp_autotune(psp_plan *p, int reps, void *stream, int *best_plan, int
         for (int i = 0; i < kPasses; ++i) samples[i].resize(cand[i].size());
         psp_status out = PSP_OK;
         const size_t count = (size_t)n * n * n;
-        if (f32)
+        if (f32) {
             hipLaunchKernelGGL(k_fill_hash<float>, dim3(1024), dim3(256), 0, st, (float *)rho, count);
-        else
+            hipLaunchKernelGGL(k_fill_bump<float>, dim3(1024), dim3(256), 0, st, (float *)rho_b, n);
+        } else {
             hipLaunchKernelGGL(k_fill_hash<double>, dim3(1024), dim3(256), 0, st, (double *)rho, count);
+            hipLaunchKernelGGL(k_fill_bump<double>, dim3(1024), dim3(256), 0, st, (double *)rho_b, n);
+        }
         hipError_t e = hipGetLastError();
         // timing only: no system-scope cache writeback at every record
         for (int k = 0; k < nev && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&ev[k], hipEventDisableSystemFence);
         if (e != hipSuccess) out = hip_fail(e, "autotune set-up");
         // round r runs candidate r mod (count) of every pass at once: each pass
-        // is timed by its own events, so one round measures five candidates
-        for (size_t r = 0; r < rounds && out == PSP_OK; ++r) {
+        // is timed by its own events, so one round measures five candidates;
+        // every round runs on both inputs, and a candidate's samples from
+        // both go into its median
+        for (size_t r = 0; r < 2 * rounds && out == PSP_OK; ++r) {
             Shape s;
             for (int i = 0; i < kPasses; ++i) {
-                const auto &c = cand[i][r % cand[i].size()];
+                const auto &c = cand[i][(r / 2) % cand[i].size()];
                 s.plan[i] = c.first;
                 s.tile[i] = c.second;
             }
-            SolveArgs a = solve_args(p, *w, rho, u);
+            SolveArgs a = solve_args(p, *w, (r & 1) ? rho_b : rho, u);
             a.shape = s;
             if ((e = launch_solve(a, st)) != hipSuccess) {   // warm-up
                 out = hip_fail(e, "autotune launch");
@@ -195,13 +218,14 @@ psp_status psp_autotune(psp_plan *p, int reps, void *stream, int *best_plan, int
                     }
                     if (ev_pass[k] >= 0 && ev_pass[k] < kPasses) pass_ms[ev_pass[k]] += ms;
                 }
-                for (int i = 0; i < kPasses; ++i) samples[i][r % cand[i].size()].push_back(pass_ms[i]);
+                for (int i = 0; i < kPasses; ++i) samples[i][(r / 2) % cand[i].size()].push_back(pass_ms[i]);
             }
         }
         if (out == PSP_OK && (e = hipStreamSynchronize(st)) != hipSuccess) out = hip_fail(e, "autotune");
         for (auto x : ev)
             if (x) (void)hipEventDestroy(x);
         (void)hipFree(rho);
+        (void)hipFree(rho_b);
         (void)hipFree(u);
         if (out != PSP_OK) return out;
         std::vector<std::vector<float>> best(kPasses);

@@ -216,9 +216,12 @@ def test_shape_validation_and_roundtrip():
     assert p.shape() == ([0] * 5, [2, 1, 2, 1, 1])
     p.set_shape([0] * 5, [0, 0, 20, 0, 0])           # H3: tile 6 with nontemporal loads and stores
     assert p.shape() == ([0] * 5, [0, 0, 20, 0, 0])
+    p.set_shape([0] * 5, [0, 13, 0, 9, 0])           # H2, H4: tiles 6 and 2 with nontemporal A accesses
+    assert p.shape() == ([0] * 5, [0, 13, 0, 9, 0])
     for plan, tile in [([1, 0, 0, 0, 0], [0] * 5),   # no alternative plan for 2n = 64
                        ([0] * 5, [4, 0, 0, 0, 0]),   # four workgroup sizes for H1
-                       ([0] * 5, [0, 7, 0, 0, 0]),   # seven tile choices for H2
+                       ([0] * 5, [0, 14, 0, 0, 0]),  # fourteen for H2 (two cache policies)
+                       ([0] * 5, [0, 0, 0, 14, 0]),  # and for H4
                        ([0] * 5, [0, 0, 21, 0, 0]),  # twenty-one for H3 (three cache policies)
                        ([0] * 5, [0, 0, 0, 0, -1])]:
         with pytest.raises(B.PspError) as ei:
