@@ -221,10 +221,10 @@ psp_status psp_plan_set_tuning(psp_plan *p, int k3_tiles, int i1_group);
  *            3: one row with half the threads per column (two butterflies
  *            per thread and stage), 4: 2 and 3 together, 5: one row with the
  *            exchanges through half-size LDS buffers by column half, 6: 5 and
- *            3 together; 7..13: 0..6 with nontemporal accesses to the
- *            intermediate (pass 1 its stores, pass 2 its stores, pass 3 its
- *            loads); pass 2 also 14..20: 0..6 with nontemporal loads and
- *            stores.
+ *            3 together; 7..13: 0..6 with nontemporal accesses (pass 1
+ *            its stores of the intermediate, pass 2 its stores, pass 3 its
+ *            loads of the intermediate and its stores); pass 2 also
+ *            14..20: 0..6 with nontemporal loads and stores.
  * A tile choice changes only which workgroup transforms which column, how
  * values move between stages and the accesses' cache policy: the results
  * are bitwise the same.  A radix plan changes the rounding, not the
@@ -245,8 +245,11 @@ psp_status psp_tuning_get(int n, psp_dtype dtype, int *plan, int *tile);
  * and a smooth compactly supported bump; `reps` timed solves per candidate
  * round and input after one warm-up, median over the repetitions on both,
  * HIP events around each launch), picks per pass the fastest candidate (the
- * default unless another is at least 1% faster), sets it as the plan's shape
- * and enters it in the tuning table.  Outputs (host arrays, each may be
+ * default unless another is at least 1% faster), then for each pass in turn
+ * times its four fastest candidates as whole solves inside that pick (the
+ * sum of the two inputs' medians over `reps` solves each) and keeps one that
+ * is more than 0.2% faster, sets the result as the plan's shape and enters
+ * it in the tuning table.  Outputs (host arrays, each may be
  * NULL): best_plan[5], best_tile[5], best_ms[5] the chosen candidate and
  * that pass's time in ms; cand_ms[5 * 63]: the time of candidate
  * (plan, tile) of pass i at cand_ms[i * 63 + plan * 21 + tile], -1 where the

@@ -29,9 +29,9 @@ struct Job {
 //            half, 3: one tile with half the threads per column (two
 //            butterflies each), 4: 2 and 3, 5: one tile with exchanges
 //            through half-size LDS buffers by column half, 6: 5 and 3;
-//            also 7-13: 0-6 with nontemporal accesses to the intermediate
-//            (H2 its stores, H3 its stores, H4 its loads); H3 (p = 2) also
-//            14-20: 0-6 with nontemporal loads and stores
+//            also 7-13: 0-6 with nontemporal accesses (H2 its stores of A,
+//            H3 its stores of A, H4 its loads of A and stores of X); H3
+//            (p = 2) also 14-20: 0-6 with nontemporal loads and stores
 // A tile choice only changes which workgroup transforms which column, how
 // values move between stages and the cache policy of the accesses, so
 // results are bitwise the same under every tile choice.

@@ -150,15 +150,17 @@ __device__ __forceinline__ size_t a_index(const Chunk &ck, int c, int k2, int i1
     return (size_t)i1 * ck.plane + (size_t)k2 * ck.pa + c;
 }
 
-// Cache policy CP of the strided passes' accesses to the intermediate A:
-// 0 ordinary, 1 nontemporal stores, 2 nontemporal loads and stores.  The
-// streaming hints let the rows a workgroup touches (128 bytes each, a plane
-// or a row pitch apart) go to and come from HBM in the order the workgroups
-// issue them instead of as scattered L2 evictions; in H3 they also keep the
-// stream of A from displacing the multiplier blocks the paired workgroups
-// share in L2.  Which one pays depends on the size and tier, so it is a
-// tuning choice (H2: its stores, H3: both, H4: its loads).  The pointers are
-// global memory.
+// Cache policy CP of the strided passes' global accesses: 0 ordinary, 1
+// nontemporal stores, 2 nontemporal loads and stores.  The streaming hints
+// let the rows a workgroup touches (128 bytes each, a plane or a row pitch
+// apart) go to and come from HBM in the order the workgroups issue them
+// instead of as scattered L2 evictions.  They also change the pass after:
+// at n = 256 FP64, H5 ran 10 us slower after H4 with nontemporal A loads and
+// ordinary X stores, and 12 us faster after H4 with both nontemporal, than
+// after an ordinary H4.  In H3 they also keep the stream of A from
+// displacing the multiplier blocks the paired workgroups share in L2.  Which one pays
+// depends on the size and tier, so it is a tuning choice (H2: 0 or 1, H3:
+// 0, 1 or 2, H4: 0 or 2).  The pointers are global memory.
 template <typename C> struct VecOf;
 template <> struct VecOf<double2> { typedef double type __attribute__((ext_vector_type(2))); };
 template <> struct VecOf<float2> { typedef float type __attribute__((ext_vector_type(2))); };
@@ -299,7 +301,7 @@ k_y_inv(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
     constexpr int rows_out = FULL ? N : n;
     C *dst = (C *)(FULL ? jb.Y2 : jb.X) + (size_t)i1 * rows_out * P + cg;
     E::for_outputs(v, t, [&](int pos, int r, C &val) {
-        if (valid && (FULL || r < E::R(E::S - 1) / 2)) dst[(size_t)pos * P] = val;
+        if (valid && (FULL || r < E::R(E::S - 1) / 2)) a_store<CP>(&dst[(size_t)pos * P], val);
     });
 }
 
@@ -419,7 +421,7 @@ template <typename T, typename F> inline void with_h3_tile(int tile, F &&f) {
     });
 }
 // H2's and H4's tile choice: the strided tile (tile mod 7) and, for tiles
-// 7..13, the nontemporal policy NT (H2: its stores of A, H4: its loads)
+// 7..13, the nontemporal policy NT (H2: its stores, H4: its loads and stores)
 template <typename T, int NT, typename F> inline void with_y_tile(int tile, F &&f) {
     with_cols<T>(tile % 7, [&](auto w) {
         if (tile / 7 == 1)
