@@ -214,7 +214,8 @@ psp_status psp_plan_set_tuning(psp_plan *p, int k3_tiles, int i1_group);
  *            factorisation for 2n in {128, 192, 256, 384, 512} or a radix-12
  *            one for 768 (other lengths have only 0);
  *   tile[i]: passes 0 and 4 (transforms along i3): workgroup size, 0: 256
- *            threads, 1: 128, 2: 512, 3: 64; passes 1..3 (along i2, i1, i2): 0: one
+ *            threads, 1: 128, 2: 512, 3: 64, 4..7: 0..3 with nontemporal
+ *            stores of the pass's output; passes 1..3 (along i2, i1, i2): 0: one
  *            128-byte row of k3 columns per workgroup (8 FP64 or 16 FP32
  *            columns), 1: half of one, 2: one row with the exchanges between
  *            FFT stages through half-size LDS buffers by position half,
@@ -246,10 +247,11 @@ psp_status psp_tuning_get(int n, psp_dtype dtype, int *plan, int *tile);
  * round and input after one warm-up, median over the repetitions on both,
  * HIP events around each launch), picks per pass the fastest candidate (the
  * default unless another is at least 1% faster), then for each pass in turn
- * times its four fastest candidates as whole solves inside that pick (the
- * sum of the two inputs' medians over `reps` solves each) and keeps one that
- * is more than 0.2% faster, sets the result as the plan's shape and enters
- * it in the tuning table.  Outputs (host arrays, each may be
+ * times its four fastest candidates and the other cache policies of its pick
+ * as whole solves inside that pick (the sum of the two inputs' medians over
+ * `reps` solves each; a cache policy can slow its own pass and speed up the
+ * next) and keeps one that is more than 0.2% faster, sets the result as the
+ * plan's shape and enters it in the tuning table.  Outputs (host arrays, each may be
  * NULL): best_plan[5], best_tile[5], best_ms[5] the chosen candidate and
  * that pass's time in ms; cand_ms[5 * 63]: the time of candidate
  * (plan, tile) of pass i at cand_ms[i * 63 + plan * 21 + tile], -1 where the

@@ -22,7 +22,8 @@ struct Job {
 //            padded length has them;
 //            a different rounding, same accuracy class)
 //   tile[p]: H1/H5 (p = 0, 4): workgroup size, 0: 256 threads, 1: 128, 2: 512,
-//            3: 64 (one line per workgroup where a line takes 64 threads);
+//            3: 64 (one line per workgroup where a line takes 64 threads),
+//            4-7: 0-3 with nontemporal stores (H1 of X, H5 of u);
 //            H2-H4 (p = 1..3): 0: one 128-byte row tile of k3 columns per
 //            workgroup (8 FP64 / 16 FP32 columns), 1: half of one, 2: one
 //            tile with exchanges through half-size LDS buffers by position
@@ -36,7 +37,7 @@ struct Job {
 // values move between stages and the cache policy of the accesses, so
 // results are bitwise the same under every tile choice.
 constexpr int kPasses = 5;
-constexpr int kTileChoices[kPasses] = {4, 14, 21, 14, 4};
+constexpr int kTileChoices[kPasses] = {8, 14, 21, 14, 8};
 constexpr int kMaxTiles = 21;     // the largest of kTileChoices
 constexpr int kMaxPlans = 3;      // radix plans 0..2
 // points along i1, i2, i3 (the slowest to the contiguous axis of rho)

@@ -88,11 +88,53 @@ struct JobRef {
     __device__ __forceinline__ Job get() const { return table ? table[blockIdx.y] : arg; }
 };
 
+// Cache policy CP of a pass's global accesses: 0 ordinary, 1 nontemporal
+// stores, 2 nontemporal loads and stores.  The streaming hints
+// let the rows a workgroup touches (128 bytes each, a plane or a row pitch
+// apart) go to and come from HBM in the order the workgroups issue them
+// instead of as scattered L2 evictions.  They also change the pass after:
+// at n = 256 FP64, H5 ran 10 us slower after H4 with nontemporal A loads and
+// ordinary X stores, and 12 us faster after H4 with both nontemporal, than
+// after an ordinary H4.  In H3 they also keep the stream of A from
+// displacing the multiplier blocks the paired workgroups share in L2.  Which one pays
+// depends on the size and tier, so it is a tuning choice (H1, H2, H5: 0 or
+// 1, H3: 0, 1 or 2, H4: 0 or 2).  The pointers are global memory.
+template <typename C> struct VecOf;
+template <> struct VecOf<double2> { typedef double type __attribute__((ext_vector_type(2))); };
+template <> struct VecOf<float2> { typedef float type __attribute__((ext_vector_type(2))); };
+template <int CP, typename C> __device__ __forceinline__ C a_load(const C *p) {
+    if constexpr (CP == 2) {
+        typedef const __attribute__((address_space(1))) typename VecOf<C>::type *G;
+        const auto t = __builtin_nontemporal_load((G)p);
+        return C{t.x, t.y};
+    } else {
+        return *p;
+    }
+}
+template <int CP, typename C> __device__ __forceinline__ void a_store(C *p, const C &v) {
+    if constexpr (CP >= 1) {
+        typedef __attribute__((address_space(1))) typename VecOf<C>::type *G;
+        typename VecOf<C>::type t;
+        t.x = v.x;
+        t.y = v.y;
+        __builtin_nontemporal_store(t, (G)p);
+    } else {
+        *p = v;
+    }
+}
+template <int CP, typename T> __device__ __forceinline__ void s_store(T *p, T v) {
+    if constexpr (CP >= 1) {
+        __builtin_nontemporal_store(v, (__attribute__((address_space(1))) T *)p);
+    } else {
+        *p = v;
+    }
+}
+
 // ------------------------------------------------------------------- H1
 // Two real lines a, b (flattened (i1, i2) = 2q, 2q+1) form z = a + i b.  The
 // padded length-N line has data in [0, n) only.  After the transform,
 // A[k] = (Z[k] + conj Z[N-k])/2 and B[k] = (Z[k] - conj Z[N-k])/(2i).
-template <typename T, int N, int PV, int THR>
+template <typename T, int N, int PV, int THR, int CP>
 __global__ void __launch_bounds__((LineCfg<T, N, PV, THR>::THREADS))
 k_z_r2c(JobRef jr, int npairs, int P, Twiddle<T> tw) {
     using C = cplx<T>;
@@ -121,9 +163,9 @@ k_z_r2c(JobRef jr, int npairs, int P, Twiddle<T> tw) {
         for (int k = t; k <= n; k += Cfg::TPC) {
             const C z = lds[idx(k)];
             const C zc = lds[idx(k == 0 ? 0 : N - k)];
-            xa[k] = C{T(0.5) * (z.x + zc.x), T(0.5) * (z.y - zc.y)};
+            a_store<CP>(&xa[k], C{T(0.5) * (z.x + zc.x), T(0.5) * (z.y - zc.y)});
             const C d = C{z.x - zc.x, z.y + zc.y};     // Z[k] - conj Z[N-k]
-            xb[k] = C{T(0.5) * d.y, -T(0.5) * d.x};   // d / (2i)
+            a_store<CP>(&xb[k], C{T(0.5) * d.y, -T(0.5) * d.x});   // d / (2i)
         }
     }
 }
@@ -148,41 +190,6 @@ struct Chunk {
 
 __device__ __forceinline__ size_t a_index(const Chunk &ck, int c, int k2, int i1) {
     return (size_t)i1 * ck.plane + (size_t)k2 * ck.pa + c;
-}
-
-// Cache policy CP of the strided passes' global accesses: 0 ordinary, 1
-// nontemporal stores, 2 nontemporal loads and stores.  The streaming hints
-// let the rows a workgroup touches (128 bytes each, a plane or a row pitch
-// apart) go to and come from HBM in the order the workgroups issue them
-// instead of as scattered L2 evictions.  They also change the pass after:
-// at n = 256 FP64, H5 ran 10 us slower after H4 with nontemporal A loads and
-// ordinary X stores, and 12 us faster after H4 with both nontemporal, than
-// after an ordinary H4.  In H3 they also keep the stream of A from
-// displacing the multiplier blocks the paired workgroups share in L2.  Which one pays
-// depends on the size and tier, so it is a tuning choice (H2: 0 or 1, H3:
-// 0, 1 or 2, H4: 0 or 2).  The pointers are global memory.
-template <typename C> struct VecOf;
-template <> struct VecOf<double2> { typedef double type __attribute__((ext_vector_type(2))); };
-template <> struct VecOf<float2> { typedef float type __attribute__((ext_vector_type(2))); };
-template <int CP, typename C> __device__ __forceinline__ C a_load(const C *p) {
-    if constexpr (CP == 2) {
-        typedef const __attribute__((address_space(1))) typename VecOf<C>::type *G;
-        const auto t = __builtin_nontemporal_load((G)p);
-        return C{t.x, t.y};
-    } else {
-        return *p;
-    }
-}
-template <int CP, typename C> __device__ __forceinline__ void a_store(C *p, const C &v) {
-    if constexpr (CP >= 1) {
-        typedef __attribute__((address_space(1))) typename VecOf<C>::type *G;
-        typename VecOf<C>::type t;
-        t.x = v.x;
-        t.y = v.y;
-        __builtin_nontemporal_store(t, (G)p);
-    } else {
-        *p = v;
-    }
 }
 
 // ------------------------------------------------------------------- H2
@@ -310,7 +317,7 @@ k_y_inv(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
 // full length N; the inverse transform gives a + i b.  The imaginary parts
 // of the k = 0 and k = n bins are dropped (real transform).  FULL: rows of
 // Y2 (N*N lines) and all N outputs.
-template <typename T, int N, int PV, int THR, bool FULL>
+template <typename T, int N, int PV, int THR, bool FULL, int CP>
 __global__ void __launch_bounds__((LineCfg<T, N, PV, THR>::THREADS))
 k_z_c2r(JobRef jr, int npairs, int P, Twiddle<T> tw) {
     using C = cplx<T>;
@@ -361,8 +368,8 @@ k_z_c2r(JobRef jr, int npairs, int P, Twiddle<T> tw) {
     T *ub = ua + len_out;
     E::for_outputs(v, t, [&](int pos, int r, C &val) {
         if (active && (FULL || r < E::R(E::S - 1) / 2)) {
-            ua[pos] = val.x;
-            ub[pos] = val.y;
+            s_store<CP>(&ua[pos], val.x);
+            s_store<CP>(&ub[pos], val.y);
         }
     });
 }
@@ -430,15 +437,21 @@ template <typename T, int NT, typename F> inline void with_y_tile(int tile, F &&
             f(w, std::integral_constant<int, 0>{});
     });
 }
+// H1's and H5's tile choice: the workgroup size (tile mod 4) and, for tiles
+// 4..7, nontemporal stores (H1: of X, H5: of u)
 template <typename F> inline void with_threads(int tile, F &&f) {
-    if (tile == 1)
-        f(std::integral_constant<int, 128>{});
-    else if (tile == 2)
-        f(std::integral_constant<int, 512>{});
-    else if (tile == 3)
-        f(std::integral_constant<int, 64>{});
-    else
-        f(std::integral_constant<int, 256>{});
+    auto go = [&](auto thr) {
+        if (tile / 4 == 1)
+            f(thr, std::integral_constant<int, 1>{});
+        else
+            f(thr, std::integral_constant<int, 0>{});
+    };
+    switch (tile % 4) {
+        case 1: go(std::integral_constant<int, 128>{}); break;
+        case 2: go(std::integral_constant<int, 512>{}); break;
+        case 3: go(std::integral_constant<int, 64>{}); break;
+        default: go(std::integral_constant<int, 256>{}); break;
+    }
 }
 
 // the five passes for `count` solves of one padded length: a single solve
@@ -477,23 +490,23 @@ hipError_t passes_impl(const Job &one, const Job *table, int count, int P, int c
         using LC = LineCfg<T, N, 0, 256>;
         const JobRef jr{one, table};
         const Chunk ck{0, ntile, ntile * LW, n, n, (long long)a_plane(n, n, ntile * LW, sizeof(cplx<T>))};
-        hipLaunchKernelGGL((k_z_r2c<T, N, 0, 256>), dim3(ceil_div(n * n / 2, LC::Q), y), dim3(LC::THREADS), 0, st,
+        hipLaunchKernelGGL((k_z_r2c<T, N, 0, 256, 0>), dim3(ceil_div(n * n / 2, LC::Q), y), dim3(LC::THREADS), 0, st,
                            jr, n * n / 2, P, tw);
         hipLaunchKernelGGL((k_y_fwd<T, N, 0, LW, 0, false, 0>), dim3(n * ntile, y), dim3(SC::THREADS), 0, st, jr, ck, P, tw);
         hipLaunchKernelGGL((k_x_fused<T, N, 0, LW, 0, false, true, 0>), dim3(ceil_div((long)(n + 1) * ntile, 8) * 16, y),
                            dim3(SC::THREADS), 0, st, jr, ck, P, tw);
         hipLaunchKernelGGL((k_y_inv<T, N, 0, LW, 0, false, true, 0>), dim3(N * ntile, y), dim3(SC::THREADS), 0, st, jr, ck, P,
                            tw);
-        hipLaunchKernelGGL((k_z_c2r<T, N, 0, 256, true>), dim3(ceil_div(N * N / 2, LC::Q), y), dim3(LC::THREADS),
+        hipLaunchKernelGGL((k_z_c2r<T, N, 0, 256, true, 0>), dim3(ceil_div(N * N / 2, LC::Q), y), dim3(LC::THREADS),
                            0, st, jr, N * N / 2, P, tw);
         return hipGetLastError();
     }
     auto h1 = [&](const JobRef &jr, int npairs) {
         with_plan<N>(sh.plan[0], [&](auto pv) {
-            with_threads(sh.tile[0], [&](auto thr) {
-                constexpr int PV = decltype(pv)::value, THR = decltype(thr)::value;
+            with_threads(sh.tile[0], [&](auto thr, auto cp) {
+                constexpr int PV = decltype(pv)::value, THR = decltype(thr)::value, CP = decltype(cp)::value;
                 using LC = LineCfg<T, N, PV, THR>;
-                hipLaunchKernelGGL((k_z_r2c<T, N, PV, THR>), dim3(ceil_div(npairs, LC::Q), y), dim3(LC::THREADS),
+                hipLaunchKernelGGL((k_z_r2c<T, N, PV, THR, CP>), dim3(ceil_div(npairs, LC::Q), y), dim3(LC::THREADS),
                                    0, st, jr, npairs, P, tw);
             });
         });
@@ -540,10 +553,10 @@ hipError_t passes_impl(const Job &one, const Job *table, int count, int P, int c
     };
     auto h5 = [&](const JobRef &jr, int npairs) {
         with_plan<N>(sh.plan[4], [&](auto pv) {
-            with_threads(sh.tile[4], [&](auto thr) {
-                constexpr int PV = decltype(pv)::value, THR = decltype(thr)::value;
+            with_threads(sh.tile[4], [&](auto thr, auto cp) {
+                constexpr int PV = decltype(pv)::value, THR = decltype(thr)::value, CP = decltype(cp)::value;
                 using LC = LineCfg<T, N, PV, THR>;
-                hipLaunchKernelGGL((k_z_c2r<T, N, PV, THR, false>), dim3(ceil_div(npairs, LC::Q), y),
+                hipLaunchKernelGGL((k_z_c2r<T, N, PV, THR, false, CP>), dim3(ceil_div(npairs, LC::Q), y),
                                    dim3(LC::THREADS), 0, st, jr, npairs, P, tw);
             });
         });

@@ -244,11 +244,13 @@ psp_status psp_autotune(psp_plan *p, int reps, void *stream, int *best_plan, int
         };
         // Whole-solve refinement.  A pass's launch changes the cache state
         // the next pass starts from (dirty lines, what stays in L2), which
-        // per-pass medians over mixed neighbours do not see.  For each pass
-        // in turn, its kRefine fastest candidates are timed as whole solves
-        // inside the current pick (reps solves per input, the sum of the two
-        // inputs' medians), and a candidate replaces the pick when it is
-        // faster by more than 0.2%.
+        // per-pass medians over mixed neighbours do not see: a cache policy
+        // can slow its own pass and speed up the next one by more.  For each
+        // pass in turn, its kRefine fastest candidates and the other cache
+        // policies of its current pick are timed as whole solves inside the
+        // current pick (reps solves per input, the sum of the two inputs'
+        // medians), and a candidate replaces the pick when it is faster by
+        // more than 0.2%.
         constexpr size_t kRefine = 4;
         auto whole = [&](const Shape &sh, float *score) -> psp_status {
             *score = 0;
@@ -278,8 +280,17 @@ psp_status psp_autotune(psp_plan *p, int reps, void *stream, int *best_plan, int
             std::vector<size_t> order(cand[i].size());
             for (size_t c = 0; c < order.size(); ++c) order[c] = c;
             std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return best[i][a] < best[i][b]; });
-            for (size_t k = 0; k < std::min(kRefine, order.size()) && out == PSP_OK; ++k) {
-                if (order[k] == pick[i]) continue;
+            order.resize(std::min(kRefine, order.size()));
+            // the same plan and tile shape under the pass's other cache policies
+            const int stride = (i == 0 || i == 4) ? 4 : 7;
+            const int pl = cand[i][pick[i]].first, shape_t = cand[i][pick[i]].second % stride;
+            for (size_t c = 0; c < cand[i].size(); ++c)
+                if (cand[i][c].first == pl && cand[i][c].second % stride == shape_t &&
+                    std::find(order.begin(), order.end(), c) == order.end())
+                    order.push_back(c);
+            const std::vector<size_t> base = pick;
+            for (size_t k = 0; k < order.size() && out == PSP_OK; ++k) {
+                if (order[k] == base[i] || order[k] == pick[i]) continue;
                 std::vector<size_t> trial = pick;
                 trial[i] = order[k];
                 float score = 0;

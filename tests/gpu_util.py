@@ -37,7 +37,7 @@ def sample_points(n, rng, extra=(), count=48, distinct_j3=6):
     return np.array(pts, dtype=np.int64)
 
 
-TILES = [4, 14, 21, 14, 4]       # tile choices of passes H1..H5
+TILES = [8, 14, 21, 14, 8]       # tile choices of passes H1..H5
 
 
 def radix_plans(n):

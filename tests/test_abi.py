@@ -218,8 +218,11 @@ def test_shape_validation_and_roundtrip():
     assert p.shape() == ([0] * 5, [0, 0, 20, 0, 0])
     p.set_shape([0] * 5, [0, 13, 0, 9, 0])           # H2, H4: tiles 6 and 2 with nontemporal A accesses
     assert p.shape() == ([0] * 5, [0, 13, 0, 9, 0])
+    p.set_shape([0] * 5, [7, 0, 0, 0, 4])            # H1, H5: nontemporal stores
+    assert p.shape() == ([0] * 5, [7, 0, 0, 0, 4])
     for plan, tile in [([1, 0, 0, 0, 0], [0] * 5),   # no alternative plan for 2n = 64
-                       ([0] * 5, [4, 0, 0, 0, 0]),   # four workgroup sizes for H1
+                       ([0] * 5, [8, 0, 0, 0, 0]),   # four workgroup sizes for H1, two cache policies
+                       ([0] * 5, [0, 0, 0, 0, 8]),   # and for H5
                        ([0] * 5, [0, 14, 0, 0, 0]),  # fourteen for H2 (two cache policies)
                        ([0] * 5, [0, 0, 0, 14, 0]),  # and for H4
                        ([0] * 5, [0, 0, 21, 0, 0]),  # twenty-one for H3 (three cache policies)
