@@ -19,6 +19,12 @@ import time
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
+# hardware queues for the serving leg's streams (two per size class and one
+# for precomputes, beside this script's own): with HIP's default of 4, a
+# small request's stream can share a queue with a large solve and wait behind
+# it in order.  Read when HIP initialises, so it is set before torch loads;
+# the single-solve legs measured the same with 4 and 8.
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, published
 COPY_CAL_BYTES = 1 << 30   # plain device copy used to calibrate the byte counters

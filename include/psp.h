@@ -313,7 +313,11 @@ void psp_graph_destroy(psp_graph *g);
  * are cached per (n, h, R) on the device in LRU order inside the budget.
  * rho_dev/u_dev stay caller-owned and must live until the request is done;
  * rho must be fully written (its producing work complete) when submitted,
- * since the loop reads it on its own streams. */
+ * since the loop reads it on its own streams.  The server uses five streams
+ * (two per size class and one for spectrum precomputes); small requests are
+ * kept from waiting in order behind large ones only while those streams have
+ * hardware queues of their own, so run the process with GPU_MAX_HW_QUEUES
+ * of at least 8 (HIP's default of 4 makes streams share queues). */
 psp_status psp_serve_create(size_t hbm_budget_bytes, int max_slots, psp_server **out);
 
 /* Non-blocking enqueue; *ticket identifies the request.  PSP_EBUSY if the

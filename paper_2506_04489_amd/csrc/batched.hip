@@ -145,11 +145,26 @@ hipError_t launch_batch_image(const std::vector<BatchMember> &m, const BatchImag
     return hipSuccess;
 }
 
-struct Staging {
+// A stream's batch tables go up through a ring of kStageSlots slots, each a
+// pinned host copy and the device image it is copied to.  A slot's host copy
+// is rewritten only once its previous upload has read it (its event); its
+// device image is overwritten by a copy that runs, in stream order, after the
+// kernels that read it.  With a single slot, every batch waited on the host
+// for the stream to reach the previous batch's upload, i.e. for all work
+// queued before that: a serving loop then stalled for milliseconds behind
+// large solves.  The host now blocks only when kStageSlots uploads are still
+// queued on the stream.
+struct StageSlot {
     unsigned char *h = nullptr;   // pinned host copy of the image
     unsigned char *d = nullptr;   // device image
     size_t cap = 0;
-    hipEvent_t uploaded = nullptr;   // the last upload has read the pinned copy
+    hipEvent_t uploaded = nullptr;   // the last upload from this slot has read h
+    bool used = false;
+};
+constexpr int kStageSlots = 8;
+struct Staging {
+    StageSlot slot[kStageSlots];
+    int next = 0;
 };
 
 struct StreamBatch {
@@ -164,8 +179,10 @@ static std::mutex g_batch_mu;
 static std::map<std::pair<int, hipStream_t>, StreamBatch> g_batch;   // (device, stream)
 
 // build, upload through pinned memory and launch
-static psp_status run_batch(Staging &S, const std::vector<BatchMember> &m, bool f32, hipStream_t st) {
-    if (S.uploaded) {
+static psp_status run_batch(Staging &ring, const std::vector<BatchMember> &m, bool f32, hipStream_t st) {
+    StageSlot &S = ring.slot[ring.next];
+    ring.next = (ring.next + 1) % kStageSlots;
+    if (S.used) {
         hipError_t e = hipEventSynchronize(S.uploaded);
         if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize(batch table)");
     }
@@ -199,6 +216,7 @@ static psp_status run_batch(Staging &S, const std::vector<BatchMember> &m, bool 
     hipError_t e = hipMemcpyAsync(S.d, S.h, img.bytes, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipEventRecord(S.uploaded, st);
     if (e != hipSuccess) return hip_fail(e, "batch table upload");
+    S.used = true;
     e = launch_batch_image(m, img, f32, S.d, false, st);
     if (e != hipSuccess) return hip_fail(e, "batched pass launch");
     return PSP_OK;

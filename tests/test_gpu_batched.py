@@ -82,6 +82,28 @@ def test_batched_repeated_calls_reuse_staging(batch_mode):
             assert torch.equal(u, p.solve(r * (rep + 1)))
 
 
+def test_batched_more_batches_than_staging_slots(batch_mode):
+    """Twelve batches queued back to back on one stream without a host wait:
+    their tables go up through a ring of eight staging slots, so slots are
+    reused while earlier batches are still queued; each result is bitwise
+    that of single solves."""
+    import torch
+    items, plans, rhos = _setup(12, "f64", 23)
+    ps = [plans[it.n] for it in items]
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    outs = []
+    for k in range(1, 13):
+        us = [torch.empty_like(r) for r in rhos[:k]]
+        st.wait_stream(torch.cuda.current_stream())
+        B.solve_batched(ps[:k], rhos[:k], us, stream=st)
+        outs.append(us)
+    st.synchronize()
+    for us in outs:
+        for p, r, u in zip(ps, rhos, us):
+            assert torch.equal(u, p.solve(r))
+
+
 def test_batched_rejects_mixed_dtypes():
     import torch
     p64 = B.Plan(16, 0.125, 40).precompute()
