@@ -26,8 +26,8 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // batch mode (psp_set_batch_mode): 0 grouped launches, 1 persistent kernels
 // for 2n <= 256, 2 the same kernels with one workgroup per item.  Measured on
-// MI355X for the 64-mixture batch (n = 32..128, FP64): grouped 29.2k
-// solves/s, flat 24.9k, persistent 18.8k, one solve at a time 20.8k (each
+// MI355X for the 64-mixture batch (n = 32..128, FP64): grouped 29.9k
+// solves/s, flat 25.6k, persistent 19.0k, one solve at a time 21.9k (each
 // persistent workgroup runs its items one after another and exposes every
 // item's load latency); so grouped launches are the default.
 static std::atomic<int> g_batch_mode{0};
