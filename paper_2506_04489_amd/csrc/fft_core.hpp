@@ -90,6 +90,27 @@ template <typename T> struct Twiddle {
     }
 };
 
+// The FP32 tier's strided and line passes instead read FP32 powers from a
+// copy of the table in their workgroup's LDS: entries W^e for e <= N (W^N =
+// 1), each the FP64 entry rounded once.  At stage s a butterfly's twiddle
+// index is m = k N/(Ns R) with k < Ns, so m r < N for every leg r < R: the
+// power W^{m r} is an entry, read as it is (the inverse reads W^{N - m r},
+// its conjugate), with no FP64 instruction and no power tree.  The FP64 tree
+// above lands within a few FP64 ulp of the same root, so rounding either to
+// FP32 gives the same float except when the root lies within that distance
+// of a rounding boundary; the solves measured with both are bitwise equal.
+template <int NN> struct LdsTwiddle32 {
+    const float2 *t;   // NN + 1 entries in LDS
+    template <int R, bool INV> __device__ __forceinline__ void apply(float2 *v, int m) const {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+            const int e = m * r;
+            const float2 p = t[INV ? NN - e : e];
+            v[r] = float2{fmadd(v[r].x, p.x, -(v[r].y * p.y)), fmadd(v[r].x, p.y, v[r].y * p.x)};
+        }
+    }
+};
+
 // ------------------------------------------------------------- butterflies
 template <int R, bool INV, typename C> struct DFT;
 
@@ -344,8 +365,8 @@ template <typename T, int N, int TPC, bool INV, int PV = 0> struct Engine {
     static constexpr int V = maxv();
 
     // butterflies of stage s on registers (twiddle, then radix-R DFT)
-    template <int s>
-    __device__ __forceinline__ static void compute(C *v, int t, const Twiddle<T> &tw) {
+    template <int s, typename TW>
+    __device__ __forceinline__ static void compute(C *v, int t, const TW &tw) {
         constexpr int r_ = R(s), ns_ = NS(s), nb = N / r_;
 #pragma unroll
         for (int b = 0; b < BPT(s); ++b) {
@@ -453,8 +474,8 @@ template <typename T, int N, int TPC, bool INV, int PV = 0> struct Engine {
     // stages [s, S) given stage-s inputs in registers; on return registers
     // hold the last stage's outputs at positions j + r N/R(S-1).  SPLIT: each
     // exchange goes through an LDS buffer of N/2 positions in two phases.
-    template <int s, bool SPLIT = false, typename Idx>
-    __device__ __forceinline__ static void run_from(C *v, C *lds, int t, Idx idx, const Twiddle<T> &tw) {
+    template <int s, bool SPLIT = false, typename Idx, typename TW>
+    __device__ __forceinline__ static void run_from(C *v, C *lds, int t, Idx idx, const TW &tw) {
         compute<s>(v, t, tw);
         if constexpr (s + 1 < S) {
             if constexpr (SPLIT) {
@@ -485,8 +506,8 @@ template <typename T, int N, int TPC, bool INV, int PV = 0> struct Engine {
     // through an LDS buffer of half the columns, then those of the second
     // half (idx addresses the half buffer).  Each thread stores all its
     // values before loading, so no value needs a staging register.
-    template <int s, typename Idx>
-    __device__ __forceinline__ static void run_from_cols(C *v, C *lds, int t, Idx idx, const Twiddle<T> &tw,
+    template <int s, typename Idx, typename TW>
+    __device__ __forceinline__ static void run_from_cols(C *v, C *lds, int t, Idx idx, const TW &tw,
                                                          bool first_half) {
         compute<s>(v, t, tw);
         if constexpr (s + 1 < S) {

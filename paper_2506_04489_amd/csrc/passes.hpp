@@ -70,9 +70,35 @@ struct IdxLine {                     // column-major, one padding slot per 8 pos
     __device__ __forceinline__ int operator()(int pos) const { return base + pos + (pos >> 3); }
 };
 
+// The twiddle source of a pass kernel: the FP64 table itself (FP64 tier, and
+// FP32 workgroups of fewer than 256 threads, for which copying the table
+// would cost more than the power trees) or its FP32 copy in the workgroup's
+// LDS (FP32 tier: tw_lds_elems more elements at the end of the kernel's LDS
+// array, filled by pass_twiddle, which every thread of the workgroup must
+// call before its first stage).  Both give the same FP32 twiddles.
+template <typename T, int THREADS> constexpr bool tw_in_lds() { return std::is_same<T, float>::value && THREADS >= 256; }
+template <typename T, int NN, int THREADS> constexpr int tw_lds_elems() { return tw_in_lds<T, THREADS>() ? NN + 1 : 0; }
+template <typename T, int NN, bool LDS> struct PassTwiddle { using type = Twiddle<T>; };
+template <int NN> struct PassTwiddle<float, NN, true> { using type = LdsTwiddle32<NN>; };
+template <typename T, int NN, int THREADS>
+__device__ __forceinline__ typename PassTwiddle<T, NN, tw_in_lds<T, THREADS>()>::type
+pass_twiddle(const Twiddle<T> &tw, cplx<T> *buf) {
+    if constexpr (tw_in_lds<T, THREADS>()) {
+        for (int e = threadIdx.x; e <= NN; e += blockDim.x) {
+            const double2 w = tw.w[e == NN ? 0 : e];
+            buf[e] = float2{(float)w.x, (float)w.y};
+        }
+        __syncthreads();
+        return LdsTwiddle32<NN>{buf};
+    } else {
+        (void)buf;
+        return tw;
+    }
+}
+
 // the FFT stages of a strided pass with the configuration's exchange
-template <typename E, typename Cfg, int W, typename C, typename T>
-__device__ __forceinline__ void strided_stages(C *v, C *lds, int t, int col, const Twiddle<T> &tw) {
+template <typename E, typename Cfg, int W, typename C, typename TW>
+__device__ __forceinline__ void strided_stages(C *v, C *lds, int t, int col, const TW &tw) {
     if constexpr (Cfg::XCH == 2)
         E::template run_from_cols<0>(v, lds, t, IdxInter<W / 2>{col % (W / 2)}, tw, col < W / 2);
     else
@@ -141,7 +167,8 @@ k_z_r2c(JobRef jr, int npairs, int P, Twiddle<T> tw) {
     using Cfg = LineCfg<T, N, PV, THR>;
     using E = Engine<T, N, Cfg::TPC, false, PV>;
     constexpr int n = N / 2;
-    __shared__ C lds[Cfg::Q * Cfg::LINE];
+    __shared__ C lds[Cfg::Q * Cfg::LINE + tw_lds_elems<T, N, Cfg::THREADS>()];
+    const auto twx = pass_twiddle<T, N, Cfg::THREADS>(tw, lds + Cfg::Q * Cfg::LINE);
     const Job jb = jr.get();
     const int t = threadIdx.x % Cfg::TPC, q = threadIdx.x / Cfg::TPC;
     const int pair = blockIdx.x * Cfg::Q + q;
@@ -154,7 +181,7 @@ k_z_r2c(JobRef jr, int npairs, int P, Twiddle<T> tw) {
         return c_zero<C>();
     });
     IdxLine idx{q * Cfg::LINE};
-    E::template run_from<0>(v, lds, t, idx, tw);
+    E::template run_from<0>(v, lds, t, idx, twx);
     E::for_outputs(v, t, [&](int pos, int, C &val) { lds[idx(pos)] = val; });
     __syncthreads();
     if (active) {
@@ -200,7 +227,8 @@ k_y_fwd(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
     using Cfg = StridedCfg<T, N, PV, W, XC, HF>;
     using E = Engine<T, N, Cfg::TPC, false, PV>;
     constexpr int n = N / 2;
-    __shared__ C lds[Cfg::LDS_ELEMS];
+    __shared__ C lds[Cfg::LDS_ELEMS + tw_lds_elems<T, N, Cfg::THREADS>()];
+    const auto twx = pass_twiddle<T, N, Cfg::THREADS>(tw, lds + Cfg::LDS_ELEMS);
     const Job jb = jr.get();
     const int nsub = ck.ntile * Cfg::SUB;
     const int col = threadIdx.x % W, t = threadIdx.x / W;
@@ -214,7 +242,7 @@ k_y_fwd(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
         if (r < E::R(0) / 2 && valid) return src[(size_t)pos * P];
         return c_zero<C>();
     });
-    strided_stages<E, Cfg, W>(v, lds, t, col, tw);
+    strided_stages<E, Cfg, W>(v, lds, t, col, twx);
     E::for_outputs(v, t, [&](int pos, int, C &val) { a_store<CP>(&dst[(size_t)pos * ck.pa], val); });
 }
 
@@ -232,13 +260,14 @@ k_x_fused(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
     using EF = Engine<T, N, Cfg::TPC, false, PV>;
     using EI = Engine<T, N, Cfg::TPC, true, PV>;
     constexpr int n = N / 2;
-    __shared__ C lds[Cfg::LDS_ELEMS];
+    __shared__ C lds[Cfg::LDS_ELEMS + tw_lds_elems<T, N, Cfg::THREADS>()];
     const int nsub = ck.ntile * Cfg::SUB;
     const int g = blockIdx.x;
     const int pi = (g / 16) * 8 + (g % 8), side = (g % 16) / 8;
     if (pi >= (ck.n2 + 1) * nsub) return;           // uniform over the workgroup
     const int b = pi / nsub, sub = pi % nsub;
     if (side && (b == 0 || b == ck.n2)) return;
+    const auto twx = pass_twiddle<T, N, Cfg::THREADS>(tw, lds + Cfg::LDS_ELEMS);
     const Job jb = jr.get();
     const int k2 = side ? 2 * ck.n2 - b : b;        // rows k2 < 2 n2 of A per i1
     const int col = threadIdx.x % W, t = threadIdx.x / W;
@@ -253,13 +282,13 @@ k_x_fused(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
         if (r < EF::R(0) / 2 && valid) return a_load<CP>(&src[pos * step]);
         return c_zero<C>();
     });
-    strided_stages<EF, Cfg, W>(v, lds, t, col, tw);
+    strided_stages<EF, Cfg, W>(v, lds, t, col, twx);
     EF::for_outputs(v, t, [&](int pos, int, C &val) {
         const int a = pos <= n ? pos : N - pos;
         const double m = mrow[(size_t)a * 8];
         val = C{T((double)val.x * m), T((double)val.y * m)};
     });
-    strided_stages<EI, Cfg, W>(v, lds, t, col, tw);
+    strided_stages<EI, Cfg, W>(v, lds, t, col, twx);
     if constexpr (!FULL) {
         C *dst = (C *)jb.A + (size_t)k2 * ck.pa + c;
         EI::for_outputs(v, t, [&](int pos, int r, C &val) {
@@ -283,7 +312,8 @@ k_y_inv(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
     using Cfg = StridedCfg<T, N, PV, W, XC, HF>;
     using E = Engine<T, N, Cfg::TPC, true, PV>;
     constexpr int n = N / 2;
-    __shared__ C lds[Cfg::LDS_ELEMS];
+    __shared__ C lds[Cfg::LDS_ELEMS + tw_lds_elems<T, N, Cfg::THREADS>()];
+    const auto twx = pass_twiddle<T, N, Cfg::THREADS>(tw, lds + Cfg::LDS_ELEMS);
     const Job jb = jr.get();
     const int nsub = ck.ntile * Cfg::SUB;
     const int col = threadIdx.x % W, t = threadIdx.x / W;
@@ -304,7 +334,7 @@ k_y_inv(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
             return c_zero<C>();
         });
     }
-    strided_stages<E, Cfg, W>(v, lds, t, col, tw);
+    strided_stages<E, Cfg, W>(v, lds, t, col, twx);
     constexpr int rows_out = FULL ? N : n;
     C *dst = (C *)(FULL ? jb.Y2 : jb.X) + (size_t)i1 * rows_out * P + cg;
     E::for_outputs(v, t, [&](int pos, int r, C &val) {
@@ -325,7 +355,8 @@ k_z_c2r(JobRef jr, int npairs, int P, Twiddle<T> tw) {
     using E = Engine<T, N, Cfg::TPC, true, PV>;
     constexpr int n = N / 2;
     constexpr int len_out = FULL ? N : n;
-    __shared__ C lds[Cfg::Q * Cfg::LINE];
+    __shared__ C lds[Cfg::Q * Cfg::LINE + tw_lds_elems<T, N, Cfg::THREADS>()];
+    const auto twx = pass_twiddle<T, N, Cfg::THREADS>(tw, lds + Cfg::Q * Cfg::LINE);
     const Job jb = jr.get();
     const int t = threadIdx.x % Cfg::TPC, q = threadIdx.x / Cfg::TPC;
     const int pair = blockIdx.x * Cfg::Q + q;
@@ -363,7 +394,7 @@ k_z_c2r(JobRef jr, int npairs, int P, Twiddle<T> tw) {
     C v[E::V];
     E::template load_lds<0>(v, lds, t, idx);
     __syncthreads();
-    E::template run_from<0>(v, lds, t, idx, tw);
+    E::template run_from<0>(v, lds, t, idx, twx);
     T *ua = (T *)jb.u + (size_t)(2 * pair) * len_out;
     T *ub = ua + len_out;
     E::for_outputs(v, t, [&](int pos, int r, C &val) {
