@@ -90,23 +90,26 @@ template <typename T> struct Twiddle {
     }
 };
 
-// The FP32 tier's strided and line passes instead read FP32 powers from a
-// copy of the table in their workgroup's LDS: entries W^e for e <= N (W^N =
-// 1), each the FP64 entry rounded once.  At stage s a butterfly's twiddle
-// index is m = k N/(Ns R) with k < Ns, so m r < N for every leg r < R: the
-// power W^{m r} is an entry, read as it is (the inverse reads W^{N - m r},
-// its conjugate), with no FP64 instruction and no power tree.  The FP64 tree
-// above lands within a few FP64 ulp of the same root, so rounding either to
-// FP32 gives the same float except when the root lies within that distance
-// of a rounding boundary; the solves measured with both are bitwise equal.
-template <int NN> struct LdsTwiddle32 {
-    const float2 *t;   // NN + 1 entries in LDS
-    template <int R, bool INV> __device__ __forceinline__ void apply(float2 *v, int m) const {
+// Most passes instead read each power from a table of the roots themselves:
+// at stage s a butterfly's twiddle index is m = k N/(Ns R) with k < Ns, so
+// m r < N for every leg r < R and W^{m r} is an entry (the inverse reads
+// W^{N - m r}, its conjugate; the table has N + 1 entries, W^N = W^0).  No
+// power tree, and in FP64 each power is correctly rounded instead of a few
+// ulp off.  The table is the FP64 one (FP64 tier) or its entries rounded once
+// to FP32 (FP32 tier), as a copy in the workgroup's LDS or, in the persistent
+// batched kernels, read from the FP64 table in global memory.  An FP32 entry
+// rounded from the root equals the FP64 tree's power rounded to FP32 except
+// when the root lies within a few FP64 ulp of an FP32 rounding boundary (the
+// solves measured with both are bitwise equal), so FP32 passes that keep the
+// trees (small workgroups) agree with the table ones.
+template <typename T, int NN> struct TableTwiddle {
+    const cplx<T> *t;   // NN + 1 entries
+    template <int R, bool INV> __device__ __forceinline__ void apply(cplx<T> *v, int m) const {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
             const int e = m * r;
-            const float2 p = t[INV ? NN - e : e];
-            v[r] = float2{fmadd(v[r].x, p.x, -(v[r].y * p.y)), fmadd(v[r].x, p.y, v[r].y * p.x)};
+            const cplx<T> p = t[INV ? NN - e : e];
+            v[r] = cplx<T>{fmadd(v[r].x, p.x, -(v[r].y * p.y)), fmadd(v[r].x, p.y, v[r].y * p.x)};
         }
     }
 };

@@ -70,26 +70,32 @@ struct IdxLine {                     // column-major, one padding slot per 8 pos
     __device__ __forceinline__ int operator()(int pos) const { return base + pos + (pos >> 3); }
 };
 
-// The twiddle source of a pass kernel: the FP64 table itself (FP64 tier, and
-// FP32 workgroups of fewer than 256 threads, for which copying the table
-// would cost more than the power trees) or its FP32 copy in the workgroup's
-// LDS (FP32 tier: tw_lds_elems more elements at the end of the kernel's LDS
-// array, filled by pass_twiddle, which every thread of the workgroup must
-// call before its first stage).  Both give the same FP32 twiddles.
-template <typename T, int THREADS> constexpr bool tw_in_lds() { return std::is_same<T, float>::value && THREADS >= 256; }
-template <typename T, int NN, int THREADS> constexpr int tw_lds_elems() { return tw_in_lds<T, THREADS>() ? NN + 1 : 0; }
+// The twiddle source of a pass kernel (STRIDED: H2-H4, else H1/H5): a copy of
+// the roots in the workgroup's LDS for the strided passes of both tiers and
+// for FP32 line passes of at least 256 threads (tw_lds_elems more elements at
+// the end of the kernel's LDS array, filled by pass_twiddle, which every
+// thread of the workgroup must call before its first stage), else the FP64
+// power trees: FP64 line passes (every shape of a pass reads the same
+// twiddles, so every shape gives bitwise the same result) and small FP32
+// line workgroups, for which the copy costs more than the trees.
+template <typename T, int THREADS, bool STRIDED> constexpr bool tw_in_lds() {
+    return std::is_same<T, float>::value ? (STRIDED || THREADS >= 256) : STRIDED;
+}
+template <typename T, int NN, int THREADS, bool STRIDED> constexpr int tw_lds_elems() {
+    return tw_in_lds<T, THREADS, STRIDED>() ? NN + 1 : 0;
+}
 template <typename T, int NN, bool LDS> struct PassTwiddle { using type = Twiddle<T>; };
-template <int NN> struct PassTwiddle<float, NN, true> { using type = LdsTwiddle32<NN>; };
-template <typename T, int NN, int THREADS>
-__device__ __forceinline__ typename PassTwiddle<T, NN, tw_in_lds<T, THREADS>()>::type
+template <typename T, int NN> struct PassTwiddle<T, NN, true> { using type = TableTwiddle<T, NN>; };
+template <typename T, int NN, int THREADS, bool STRIDED>
+__device__ __forceinline__ typename PassTwiddle<T, NN, tw_in_lds<T, THREADS, STRIDED>()>::type
 pass_twiddle(const Twiddle<T> &tw, cplx<T> *buf) {
-    if constexpr (tw_in_lds<T, THREADS>()) {
+    if constexpr (tw_in_lds<T, THREADS, STRIDED>()) {
         for (int e = threadIdx.x; e <= NN; e += blockDim.x) {
-            const double2 w = tw.w[e == NN ? 0 : e];
-            buf[e] = float2{(float)w.x, (float)w.y};
+            const double2 w = tw.w[e];
+            buf[e] = cplx<T>{T(w.x), T(w.y)};
         }
         __syncthreads();
-        return LdsTwiddle32<NN>{buf};
+        return TableTwiddle<T, NN>{buf};
     } else {
         (void)buf;
         return tw;
@@ -167,8 +173,8 @@ k_z_r2c(JobRef jr, int npairs, int P, Twiddle<T> tw) {
     using Cfg = LineCfg<T, N, PV, THR>;
     using E = Engine<T, N, Cfg::TPC, false, PV>;
     constexpr int n = N / 2;
-    __shared__ C lds[Cfg::Q * Cfg::LINE + tw_lds_elems<T, N, Cfg::THREADS>()];
-    const auto twx = pass_twiddle<T, N, Cfg::THREADS>(tw, lds + Cfg::Q * Cfg::LINE);
+    __shared__ C lds[Cfg::Q * Cfg::LINE + tw_lds_elems<T, N, Cfg::THREADS, false>()];
+    const auto twx = pass_twiddle<T, N, Cfg::THREADS, false>(tw, lds + Cfg::Q * Cfg::LINE);
     const Job jb = jr.get();
     const int t = threadIdx.x % Cfg::TPC, q = threadIdx.x / Cfg::TPC;
     const int pair = blockIdx.x * Cfg::Q + q;
@@ -227,8 +233,8 @@ k_y_fwd(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
     using Cfg = StridedCfg<T, N, PV, W, XC, HF>;
     using E = Engine<T, N, Cfg::TPC, false, PV>;
     constexpr int n = N / 2;
-    __shared__ C lds[Cfg::LDS_ELEMS + tw_lds_elems<T, N, Cfg::THREADS>()];
-    const auto twx = pass_twiddle<T, N, Cfg::THREADS>(tw, lds + Cfg::LDS_ELEMS);
+    __shared__ C lds[Cfg::LDS_ELEMS + tw_lds_elems<T, N, Cfg::THREADS, true>()];
+    const auto twx = pass_twiddle<T, N, Cfg::THREADS, true>(tw, lds + Cfg::LDS_ELEMS);
     const Job jb = jr.get();
     const int nsub = ck.ntile * Cfg::SUB;
     const int col = threadIdx.x % W, t = threadIdx.x / W;
@@ -260,14 +266,14 @@ k_x_fused(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
     using EF = Engine<T, N, Cfg::TPC, false, PV>;
     using EI = Engine<T, N, Cfg::TPC, true, PV>;
     constexpr int n = N / 2;
-    __shared__ C lds[Cfg::LDS_ELEMS + tw_lds_elems<T, N, Cfg::THREADS>()];
+    __shared__ C lds[Cfg::LDS_ELEMS + tw_lds_elems<T, N, Cfg::THREADS, true>()];
     const int nsub = ck.ntile * Cfg::SUB;
     const int g = blockIdx.x;
     const int pi = (g / 16) * 8 + (g % 8), side = (g % 16) / 8;
     if (pi >= (ck.n2 + 1) * nsub) return;           // uniform over the workgroup
     const int b = pi / nsub, sub = pi % nsub;
     if (side && (b == 0 || b == ck.n2)) return;
-    const auto twx = pass_twiddle<T, N, Cfg::THREADS>(tw, lds + Cfg::LDS_ELEMS);
+    const auto twx = pass_twiddle<T, N, Cfg::THREADS, true>(tw, lds + Cfg::LDS_ELEMS);
     const Job jb = jr.get();
     const int k2 = side ? 2 * ck.n2 - b : b;        // rows k2 < 2 n2 of A per i1
     const int col = threadIdx.x % W, t = threadIdx.x / W;
@@ -312,8 +318,8 @@ k_y_inv(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
     using Cfg = StridedCfg<T, N, PV, W, XC, HF>;
     using E = Engine<T, N, Cfg::TPC, true, PV>;
     constexpr int n = N / 2;
-    __shared__ C lds[Cfg::LDS_ELEMS + tw_lds_elems<T, N, Cfg::THREADS>()];
-    const auto twx = pass_twiddle<T, N, Cfg::THREADS>(tw, lds + Cfg::LDS_ELEMS);
+    __shared__ C lds[Cfg::LDS_ELEMS + tw_lds_elems<T, N, Cfg::THREADS, true>()];
+    const auto twx = pass_twiddle<T, N, Cfg::THREADS, true>(tw, lds + Cfg::LDS_ELEMS);
     const Job jb = jr.get();
     const int nsub = ck.ntile * Cfg::SUB;
     const int col = threadIdx.x % W, t = threadIdx.x / W;
@@ -355,8 +361,8 @@ k_z_c2r(JobRef jr, int npairs, int P, Twiddle<T> tw) {
     using E = Engine<T, N, Cfg::TPC, true, PV>;
     constexpr int n = N / 2;
     constexpr int len_out = FULL ? N : n;
-    __shared__ C lds[Cfg::Q * Cfg::LINE + tw_lds_elems<T, N, Cfg::THREADS>()];
-    const auto twx = pass_twiddle<T, N, Cfg::THREADS>(tw, lds + Cfg::Q * Cfg::LINE);
+    __shared__ C lds[Cfg::Q * Cfg::LINE + tw_lds_elems<T, N, Cfg::THREADS, false>()];
+    const auto twx = pass_twiddle<T, N, Cfg::THREADS, false>(tw, lds + Cfg::Q * Cfg::LINE);
     const Job jb = jr.get();
     const int t = threadIdx.x % Cfg::TPC, q = threadIdx.x / Cfg::TPC;
     const int pair = blockIdx.x * Cfg::Q + q;

@@ -41,6 +41,17 @@ template <typename T> __device__ __forceinline__ Twiddle<T> pb_twiddle(const PJo
     tw.w = (const double2 *)jb.tw64;
     return tw;
 }
+// the strided passes' twiddles, the same values as the per-size kernels
+// read: FP64 roots straight from the global table (the per-size kernels read
+// a copy of it in LDS), FP32 the trees (rounding to the same floats)
+template <typename T, int N> struct PbStridedTw { using type = Twiddle<T>; };
+template <int N> struct PbStridedTw<double, N> { using type = TableTwiddle<double, N>; };
+template <typename T, int N> __device__ __forceinline__ typename PbStridedTw<T, N>::type pb_strided_twiddle(const PJob &jb) {
+    if constexpr (std::is_same<T, double>::value)
+        return TableTwiddle<double, N>{(const double2 *)jb.tw64};
+    else
+        return pb_twiddle<T>(jb);
+}
 
 // ------------------------------------------------------------------- H1
 template <typename T, int N, int PV>
@@ -89,7 +100,7 @@ __device__ __noinline__ void pb_y_fwd(const PJob *jp, int item) {
     using Cfg = PBCfg<N, PV>;
     using E = Engine<T, N, Cfg::TPC, false, PV>;
     constexpr int n = N / 2, W = Cfg::W;
-    const Twiddle<T> tw = pb_twiddle<T>(jb);
+    const auto tw = pb_strided_twiddle<T, N>(jb);
     const int col = threadIdx.x % W, t = threadIdx.x / W;
     const int f = item * W + col;
     const int i1 = f / (n + 1), c = f % (n + 1);
@@ -118,7 +129,7 @@ __device__ __noinline__ void pb_x_fused(const PJob *jp, int item) {
     using EF = Engine<T, N, Cfg::TPC, false, PV>;
     using EI = Engine<T, N, Cfg::TPC, true, PV>;
     constexpr int n = N / 2, W = Cfg::W;
-    const Twiddle<T> tw = pb_twiddle<T>(jb);
+    const auto tw = pb_strided_twiddle<T, N>(jb);
     const int col = threadIdx.x % W, t = threadIdx.x / W;
     const int f = item * W + col;
     const int k2 = f / (n + 1), c = f % (n + 1);
@@ -155,7 +166,7 @@ __device__ __noinline__ void pb_y_inv(const PJob *jp, int item) {
     using Cfg = PBCfg<N, PV>;
     using E = Engine<T, N, Cfg::TPC, true, PV>;
     constexpr int n = N / 2, W = Cfg::W;
-    const Twiddle<T> tw = pb_twiddle<T>(jb);
+    const auto tw = pb_strided_twiddle<T, N>(jb);
     const int col = threadIdx.x % W, t = threadIdx.x / W;
     const int f = item * W + col;
     const int i1 = f / (n + 1), c = f % (n + 1);
