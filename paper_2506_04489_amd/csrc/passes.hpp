@@ -102,6 +102,17 @@ pass_twiddle(const Twiddle<T> &tw, cplx<T> *buf) {
     }
 }
 
+// The multiply of H3: a mode times its FP64 multiplier entry, in FP64 for the
+// FP64 tier; for the FP32 tier the entry is rounded once to FP32 and the
+// product taken in FP32 (one conversion and two FP32 products per mode
+// instead of four conversions and two FP64 products; the rounding of the
+// entry adds at most one FP32 unit to the product's own).
+__device__ __forceinline__ double2 scale_mode(double2 v, double m) { return double2{v.x * m, v.y * m}; }
+__device__ __forceinline__ float2 scale_mode(float2 v, double m) {
+    const float mf = (float)m;
+    return float2{v.x * mf, v.y * mf};
+}
+
 // the FFT stages of a strided pass with the configuration's exchange
 template <typename E, typename Cfg, int W, typename C, typename TW>
 __device__ __forceinline__ void strided_stages(C *v, C *lds, int t, int col, const TW &tw) {
@@ -291,8 +302,7 @@ k_x_fused(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
     strided_stages<EF, Cfg, W>(v, lds, t, col, twx);
     EF::for_outputs(v, t, [&](int pos, int, C &val) {
         const int a = pos <= n ? pos : N - pos;
-        const double m = mrow[(size_t)a * 8];
-        val = C{T((double)val.x * m), T((double)val.y * m)};
+        val = scale_mode(val, mrow[(size_t)a * 8]);
     });
     strided_stages<EI, Cfg, W>(v, lds, t, col, twx);
     if constexpr (!FULL) {

@@ -146,8 +146,7 @@ __device__ __noinline__ void pb_x_fused(const PJob *jp, int item) {
     EF::template run_from<0>(v, lds, t, IdxInter<W>{col}, tw);
     EF::for_outputs(v, t, [&](int pos, int, C &val) {
         const int a = pos <= n ? pos : N - pos;
-        const double m = valid ? mrow[(size_t)a * 8] : 0.0;
-        val = C{T((double)val.x * m), T((double)val.y * m)};
+        val = scale_mode(val, valid ? mrow[(size_t)a * 8] : 0.0);
     });
     EI::template run_from<0>(v, lds, t, IdxInter<W>{col}, tw);
     C *dst = (C *)jb.A + (size_t)k2 * jb.pa + c;
