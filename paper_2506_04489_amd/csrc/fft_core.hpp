@@ -40,13 +40,15 @@ __device__ __forceinline__ double fmadd(double a, double b, double c) { return _
 __device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
 // --------------------------------------------------------------- twiddles
-// Table of W_N^m = exp(-2 pi i m / N), m < N, in FP64 for both tiers.  A
-// radix-R butterfly loads the one entry W^m and forms the powers W^{m r},
-// r = 1..R-1, by a multiplication tree of depth <= 4 (a few ulp of FP64):
-// one load instead of R-1 (wave-wide loads cost L1 return bandwidth per
-// lane).  The FP32 tier forms the powers in FP64 too (an FP32 tree would
-// add its own rounding at every level), rounds each once to FP32 and
-// multiplies in FP32.
+// Table of W_N^m = exp(-2 pi i m / N), m <= N (W^N = W^0), in FP64 for both
+// tiers.  Two ways to get a butterfly's powers W^{m r}, r = 1..R-1:
+// Twiddle loads the one entry W^m from the global table and forms the powers
+// by a multiplication tree of depth <= 4 (a few ulp of FP64; one load instead
+// of R-1, since wave-wide loads cost L1 return bandwidth per lane), in FP64
+// for both tiers (an FP32 tree would add its own rounding at every level),
+// rounding each power once for the FP32 tier; TableTwiddle (below) reads
+// each power from a copy of the table in LDS.  The passes pick per kernel
+// (passes.hpp, pass_twiddle).
 __device__ __forceinline__ double2 cmul64(double2 a, double2 t) {
     return double2{fmadd(a.x, t.x, -(a.y * t.y)), fmadd(a.x, t.y, a.y * t.x)};
 }
