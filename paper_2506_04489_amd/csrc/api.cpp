@@ -61,9 +61,7 @@ psp_status get_twiddles(int device, int N, const Twiddles **out) {
         *out = &it->second;
         return PSP_OK;
     }
-    // N + 1 entries, entry N a copy of entry 0 (= 1), so that a pass can read
-    // the inverse transform's W^{N - e} for every e in [0, N)
-    std::vector<double> w(2 * (size_t)(N + 1));
+    std::vector<double> w(2 * (size_t)N);
     const long double two_pi = 6.283185307179586476925286766559005768L;
     for (int m = 0; m < N; ++m) {
         // exp(-2 pi i m / N), long double evaluation rounded once
@@ -72,8 +70,6 @@ psp_status get_twiddles(int device, int N, const Twiddles **out) {
         w[2 * m] = c;
         w[2 * m + 1] = s;
     }
-    w[2 * (size_t)N] = w[0];
-    w[2 * (size_t)N + 1] = w[1];
     Twiddles t;
     PSP_HIP(hipMalloc(&t.w64, w.size() * 8), "hipMalloc(twiddles)");
     PSP_HIP(hipMemcpy(t.w64, w.data(), w.size() * 8, hipMemcpyHostToDevice), "hipMemcpy(twiddles)");

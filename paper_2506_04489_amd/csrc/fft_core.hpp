@@ -94,8 +94,8 @@ template <typename T> struct Twiddle {
 
 // Most passes instead read each power from a table of the roots themselves:
 // at stage s a butterfly's twiddle index is m = k N/(Ns R) with k < Ns, so
-// m r < N for every leg r < R and W^{m r} is an entry (the inverse reads
-// W^{N - m r}, its conjugate; the table has N + 1 entries, W^N = W^0).  No
+// m r < N for every leg r < R and W^{m r} is an entry (the inverse
+// multiplies by its conjugate; the table has the N roots W^0 .. W^{N-1}).  No
 // power tree, and in FP64 each power is correctly rounded instead of a few
 // ulp off.  The table is the FP64 one (FP64 tier) or its entries rounded once
 // to FP32 (FP32 tier), as a copy in the workgroup's LDS or, in the persistent
@@ -105,13 +105,13 @@ template <typename T> struct Twiddle {
 // solves measured with both are bitwise equal), so FP32 passes that keep the
 // trees (small workgroups) agree with the table ones.
 template <typename T, int NN> struct TableTwiddle {
-    const cplx<T> *t;   // NN + 1 entries
+    const cplx<T> *t;   // NN entries, W^e for e < NN
     template <int R, bool INV> __device__ __forceinline__ void apply(cplx<T> *v, int m) const {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-            const int e = m * r;
-            const cplx<T> p = t[INV ? NN - e : e];
-            v[r] = cplx<T>{fmadd(v[r].x, p.x, -(v[r].y * p.y)), fmadd(v[r].x, p.y, v[r].y * p.x)};
+            const cplx<T> p = t[m * r];
+            const T py = INV ? -p.y : p.y;   // the inverse multiplies by the conjugate
+            v[r] = cplx<T>{fmadd(v[r].x, p.x, -(v[r].y * py)), fmadd(v[r].x, py, v[r].y * p.x)};
         }
     }
 };

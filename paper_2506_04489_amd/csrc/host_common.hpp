@@ -60,7 +60,7 @@ struct DevSpectrum {            // the multiplier octant, shared between plans
 };
 
 struct Twiddles {               // per (device, N), process lifetime
-    void *w64 = nullptr;        // double2[N + 1]: W^m, m <= N (W^N = W^0)
+    void *w64 = nullptr;        // double2[N]: W^m = exp(-2 pi i m / N), m < N
 };
 psp_status get_twiddles(int device, int N, const Twiddles **out);
 

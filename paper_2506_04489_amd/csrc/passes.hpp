@@ -82,7 +82,7 @@ template <typename T, int THREADS, bool STRIDED> constexpr bool tw_in_lds() {
     return std::is_same<T, float>::value ? (STRIDED || THREADS >= 256) : STRIDED;
 }
 template <typename T, int NN, int THREADS, bool STRIDED> constexpr int tw_lds_elems() {
-    return tw_in_lds<T, THREADS, STRIDED>() ? NN + 1 : 0;
+    return tw_in_lds<T, THREADS, STRIDED>() ? NN : 0;
 }
 template <typename T, int NN, bool LDS> struct PassTwiddle { using type = Twiddle<T>; };
 template <typename T, int NN> struct PassTwiddle<T, NN, true> { using type = TableTwiddle<T, NN>; };
@@ -90,7 +90,7 @@ template <typename T, int NN, int THREADS, bool STRIDED>
 __device__ __forceinline__ typename PassTwiddle<T, NN, tw_in_lds<T, THREADS, STRIDED>()>::type
 pass_twiddle(const Twiddle<T> &tw, cplx<T> *buf) {
     if constexpr (tw_in_lds<T, THREADS, STRIDED>()) {
-        for (int e = threadIdx.x; e <= NN; e += blockDim.x) {
+        for (int e = threadIdx.x; e < NN; e += blockDim.x) {
             const double2 w = tw.w[e];
             buf[e] = cplx<T>{T(w.x), T(w.y)};
         }
