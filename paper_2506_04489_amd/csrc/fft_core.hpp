@@ -48,7 +48,7 @@ __device__ __forceinline__ float fmadd(float a, float b, float c) { return __bui
 // for both tiers (an FP32 tree would add its own rounding at every level),
 // rounding each power once for the FP32 tier; TableTwiddle (below) reads
 // each power from a copy of the table in LDS.  The passes pick per kernel
-// (passes.hpp, pass_twiddle).
+// (passes.hpp, tw_commit).
 __device__ __forceinline__ double2 cmul64(double2 a, double2 t) {
     return double2{fmadd(a.x, t.x, -(a.y * t.y)), fmadd(a.x, t.y, a.y * t.x)};
 }

@@ -70,33 +70,100 @@ struct IdxLine {                     // column-major, one padding slot per 8 pos
     __device__ __forceinline__ int operator()(int pos) const { return base + pos + (pos >> 3); }
 };
 
+// Plain accesses to the solve's buffers, all global memory, made through
+// global-address-space pointers.  A pointer read from a job table is generic
+// to the compiler, which then emits flat instructions; a flat load in flight
+// also holds the LDS wait counter, so each LDS exchange after it waited for
+// the load's HBM latency as well.
+template <typename C> struct VecOf;
+template <> struct VecOf<double2> { typedef double type __attribute__((ext_vector_type(2))); };
+template <> struct VecOf<float2> { typedef float type __attribute__((ext_vector_type(2))); };
+template <typename T> struct GlobalRep { using type = T; };
+template <> struct GlobalRep<double2> { using type = VecOf<double2>::type; };
+template <> struct GlobalRep<float2> { using type = VecOf<float2>::type; };
+template <typename T> __device__ __forceinline__ T g_load(const T *p) {
+    using V = typename GlobalRep<T>::type;
+    const V t = *(const __attribute__((address_space(1))) V *)p;
+    if constexpr (std::is_same<V, T>::value)
+        return t;
+    else
+        return T{t.x, t.y};
+}
+template <typename T> __device__ __forceinline__ void g_store(T *p, const T &v) {
+    using V = typename GlobalRep<T>::type;
+    if constexpr (std::is_same<V, T>::value) {
+        *(__attribute__((address_space(1))) V *)p = v;
+    } else {
+        V t;
+        t.x = v.x;
+        t.y = v.y;
+        *(__attribute__((address_space(1))) V *)p = t;
+    }
+}
+
 // The twiddle source of a pass kernel (STRIDED: H2-H4, else H1/H5): a copy of
 // the roots in the workgroup's LDS for the strided passes of both tiers and
 // for FP32 line passes of at least 256 threads (tw_lds_elems more elements at
-// the end of the kernel's LDS array, filled by pass_twiddle, which every
-// thread of the workgroup must call before its first stage), else the FP64
-// power trees: FP64 line passes (every shape of a pass reads the same
-// twiddles, so every shape gives bitwise the same result) and small FP32
-// line workgroups, for which the copy costs more than the trees.
+// the end of the kernel's LDS array), else the FP64 power trees: FP64 line
+// passes (every shape of a pass reads the same twiddles, so every shape gives
+// bitwise the same result) and small FP32 line workgroups, for which the copy
+// costs more than the trees.
+//
+// The copy takes two calls that every thread of the workgroup makes:
+// tw_fetch, which issues the global loads of the thread's roots into
+// registers, and tw_commit, which stores them to LDS and (SYNC) ends with the
+// workgroup barrier.  A pass issues its own input loads between the two, so
+// the latencies of the table and of the inputs overlap instead of following
+// one another.  Where a thread would hold more than kTwRegs roots the fetch
+// is empty and the commit copies the table in a loop.
+constexpr int kTwRegs = 4;
 template <typename T, int THREADS, bool STRIDED> constexpr bool tw_in_lds() {
     return std::is_same<T, float>::value ? (STRIDED || THREADS >= 256) : STRIDED;
 }
 template <typename T, int NN, int THREADS, bool STRIDED> constexpr int tw_lds_elems() {
     return tw_in_lds<T, THREADS, STRIDED>() ? NN : 0;
 }
+template <typename T, int NN, int THREADS, bool STRIDED> struct TwFetch {
+    static constexpr int K = tw_in_lds<T, THREADS, STRIDED>() ? (NN + THREADS - 1) / THREADS : 0;
+    static constexpr bool REGS = K > 0 && K <= kTwRegs;
+    double2 w[REGS ? K : 1];
+};
 template <typename T, int NN, bool LDS> struct PassTwiddle { using type = Twiddle<T>; };
 template <typename T, int NN> struct PassTwiddle<T, NN, true> { using type = TableTwiddle<T, NN>; };
 template <typename T, int NN, int THREADS, bool STRIDED>
-__device__ __forceinline__ typename PassTwiddle<T, NN, tw_in_lds<T, THREADS, STRIDED>()>::type
-pass_twiddle(const Twiddle<T> &tw, cplx<T> *buf) {
-    if constexpr (tw_in_lds<T, THREADS, STRIDED>()) {
-        for (int e = threadIdx.x; e < NN; e += blockDim.x) {
-            const double2 w = tw.w[e];
-            buf[e] = cplx<T>{T(w.x), T(w.y)};
+__device__ __forceinline__ TwFetch<T, NN, THREADS, STRIDED> tw_fetch(const Twiddle<T> &tw) {
+    using F = TwFetch<T, NN, THREADS, STRIDED>;
+    F f;
+    if constexpr (F::REGS) {
+#pragma unroll
+        for (int k = 0; k < F::K; ++k) {
+            const int e = (int)threadIdx.x + k * THREADS;
+            if (NN % THREADS == 0 || e < NN) f.w[k] = g_load(&tw.w[e]);
         }
-        __syncthreads();
+    }
+    return f;
+}
+template <typename T, int NN, int THREADS, bool STRIDED, bool SYNC = true>
+__device__ __forceinline__ typename PassTwiddle<T, NN, tw_in_lds<T, THREADS, STRIDED>()>::type
+tw_commit(const Twiddle<T> &tw, const TwFetch<T, NN, THREADS, STRIDED> &f, cplx<T> *buf) {
+    using F = TwFetch<T, NN, THREADS, STRIDED>;
+    if constexpr (tw_in_lds<T, THREADS, STRIDED>()) {
+        if constexpr (F::REGS) {
+#pragma unroll
+            for (int k = 0; k < F::K; ++k) {
+                const int e = (int)threadIdx.x + k * THREADS;
+                if (NN % THREADS == 0 || e < NN) buf[e] = cplx<T>{T(f.w[k].x), T(f.w[k].y)};
+            }
+        } else {
+            for (int e = threadIdx.x; e < NN; e += THREADS) {
+                const double2 w = g_load(&tw.w[e]);
+                buf[e] = cplx<T>{T(w.x), T(w.y)};
+            }
+        }
+        if constexpr (SYNC) __syncthreads();
         return TableTwiddle<T, NN>{buf};
     } else {
+        (void)f;
         (void)buf;
         return tw;
     }
@@ -142,16 +209,13 @@ struct JobRef {
 // displacing the multiplier blocks the paired workgroups share in L2.  Which one pays
 // depends on the size and tier, so it is a tuning choice (H1, H2, H5: 0 or
 // 1, H3: 0, 1 or 2, H4: 0 or 2).  The pointers are global memory.
-template <typename C> struct VecOf;
-template <> struct VecOf<double2> { typedef double type __attribute__((ext_vector_type(2))); };
-template <> struct VecOf<float2> { typedef float type __attribute__((ext_vector_type(2))); };
 template <int CP, typename C> __device__ __forceinline__ C a_load(const C *p) {
     if constexpr (CP == 2) {
         typedef const __attribute__((address_space(1))) typename VecOf<C>::type *G;
         const auto t = __builtin_nontemporal_load((G)p);
         return C{t.x, t.y};
     } else {
-        return *p;
+        return g_load(p);
     }
 }
 template <int CP, typename C> __device__ __forceinline__ void a_store(C *p, const C &v) {
@@ -162,14 +226,14 @@ template <int CP, typename C> __device__ __forceinline__ void a_store(C *p, cons
         t.y = v.y;
         __builtin_nontemporal_store(t, (G)p);
     } else {
-        *p = v;
+        g_store(p, v);
     }
 }
 template <int CP, typename T> __device__ __forceinline__ void s_store(T *p, T v) {
     if constexpr (CP >= 1) {
         __builtin_nontemporal_store(v, (__attribute__((address_space(1))) T *)p);
     } else {
-        *p = v;
+        g_store(p, v);
     }
 }
 
@@ -185,7 +249,7 @@ k_z_r2c(JobRef jr, int npairs, int P, Twiddle<T> tw) {
     using E = Engine<T, N, Cfg::TPC, false, PV>;
     constexpr int n = N / 2;
     __shared__ C lds[Cfg::Q * Cfg::LINE + tw_lds_elems<T, N, Cfg::THREADS, false>()];
-    const auto twx = pass_twiddle<T, N, Cfg::THREADS, false>(tw, lds + Cfg::Q * Cfg::LINE);
+    const auto twf = tw_fetch<T, N, Cfg::THREADS, false>(tw);
     const Job jb = jr.get();
     const int t = threadIdx.x % Cfg::TPC, q = threadIdx.x / Cfg::TPC;
     const int pair = blockIdx.x * Cfg::Q + q;
@@ -194,9 +258,10 @@ k_z_r2c(JobRef jr, int npairs, int P, Twiddle<T> tw) {
     const T *rb = ra + n;
     C v[E::V];
     E::for_inputs(v, t, [&](int pos, int r) -> C {
-        if (r < E::R(0) / 2 && active) return C{ra[pos], rb[pos]};
+        if (r < E::R(0) / 2 && active) return C{g_load(&ra[pos]), g_load(&rb[pos])};
         return c_zero<C>();
     });
+    const auto twx = tw_commit<T, N, Cfg::THREADS, false>(tw, twf, lds + Cfg::Q * Cfg::LINE);
     IdxLine idx{q * Cfg::LINE};
     E::template run_from<0>(v, lds, t, idx, twx);
     E::for_outputs(v, t, [&](int pos, int, C &val) { lds[idx(pos)] = val; });
@@ -245,7 +310,8 @@ k_y_fwd(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
     using E = Engine<T, N, Cfg::TPC, false, PV>;
     constexpr int n = N / 2;
     __shared__ C lds[Cfg::LDS_ELEMS + tw_lds_elems<T, N, Cfg::THREADS, true>()];
-    const auto twx = pass_twiddle<T, N, Cfg::THREADS, true>(tw, lds + Cfg::LDS_ELEMS);
+    const auto twx = tw_commit<T, N, Cfg::THREADS, true>(tw, tw_fetch<T, N, Cfg::THREADS, true>(tw),
+                                                         lds + Cfg::LDS_ELEMS);
     const Job jb = jr.get();
     const int nsub = ck.ntile * Cfg::SUB;
     const int col = threadIdx.x % W, t = threadIdx.x / W;
@@ -256,7 +322,7 @@ k_y_fwd(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
     C *dst = (C *)jb.A + a_index(ck, c, 0, i1);                    // rows k2 of A
     C v[E::V];
     E::for_inputs(v, t, [&](int pos, int r) -> C {
-        if (r < E::R(0) / 2 && valid) return src[(size_t)pos * P];
+        if (r < E::R(0) / 2 && valid) return g_load(&src[(size_t)pos * P]);
         return c_zero<C>();
     });
     strided_stages<E, Cfg, W>(v, lds, t, col, twx);
@@ -284,7 +350,7 @@ k_x_fused(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
     if (pi >= (ck.n2 + 1) * nsub) return;           // uniform over the workgroup
     const int b = pi / nsub, sub = pi % nsub;
     if (side && (b == 0 || b == ck.n2)) return;
-    const auto twx = pass_twiddle<T, N, Cfg::THREADS, true>(tw, lds + Cfg::LDS_ELEMS);
+    const auto twf = tw_fetch<T, N, Cfg::THREADS, true>(tw);
     const Job jb = jr.get();
     const int k2 = side ? 2 * ck.n2 - b : b;        // rows k2 < 2 n2 of A per i1
     const int col = threadIdx.x % W, t = threadIdx.x / W;
@@ -299,10 +365,11 @@ k_x_fused(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
         if (r < EF::R(0) / 2 && valid) return a_load<CP>(&src[pos * step]);
         return c_zero<C>();
     });
+    const auto twx = tw_commit<T, N, Cfg::THREADS, true>(tw, twf, lds + Cfg::LDS_ELEMS);
     strided_stages<EF, Cfg, W>(v, lds, t, col, twx);
     EF::for_outputs(v, t, [&](int pos, int, C &val) {
         const int a = pos <= n ? pos : N - pos;
-        val = scale_mode(val, mrow[(size_t)a * 8]);
+        val = scale_mode(val, g_load(&mrow[(size_t)a * 8]));
     });
     strided_stages<EI, Cfg, W>(v, lds, t, col, twx);
     if constexpr (!FULL) {
@@ -329,7 +396,8 @@ k_y_inv(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
     using E = Engine<T, N, Cfg::TPC, true, PV>;
     constexpr int n = N / 2;
     __shared__ C lds[Cfg::LDS_ELEMS + tw_lds_elems<T, N, Cfg::THREADS, true>()];
-    const auto twx = pass_twiddle<T, N, Cfg::THREADS, true>(tw, lds + Cfg::LDS_ELEMS);
+    const auto twx = tw_commit<T, N, Cfg::THREADS, true>(tw, tw_fetch<T, N, Cfg::THREADS, true>(tw),
+                                                         lds + Cfg::LDS_ELEMS);
     const Job jb = jr.get();
     const int nsub = ck.ntile * Cfg::SUB;
     const int col = threadIdx.x % W, t = threadIdx.x / W;
@@ -372,7 +440,7 @@ k_z_c2r(JobRef jr, int npairs, int P, Twiddle<T> tw) {
     constexpr int n = N / 2;
     constexpr int len_out = FULL ? N : n;
     __shared__ C lds[Cfg::Q * Cfg::LINE + tw_lds_elems<T, N, Cfg::THREADS, false>()];
-    const auto twx = pass_twiddle<T, N, Cfg::THREADS, false>(tw, lds + Cfg::Q * Cfg::LINE);
+    const auto twf = tw_fetch<T, N, Cfg::THREADS, false>(tw);
     const Job jb = jr.get();
     const int t = threadIdx.x % Cfg::TPC, q = threadIdx.x / Cfg::TPC;
     const int pair = blockIdx.x * Cfg::Q + q;
@@ -389,10 +457,12 @@ k_z_c2r(JobRef jr, int npairs, int P, Twiddle<T> tw) {
     for (int i = 0; i < KB; ++i) {
         const int k = t + i * Cfg::TPC;
         if (active && k <= n) {
-            ba[i] = ya[k];
-            bb[i] = yb[k];
+            ba[i] = g_load(&ya[k]);
+            bb[i] = g_load(&yb[k]);
         }
     }
+    // the roots go to LDS with the bins; the barrier below covers both
+    const auto twx = tw_commit<T, N, Cfg::THREADS, false, false>(tw, twf, lds + Cfg::Q * Cfg::LINE);
 #pragma unroll
     for (int i = 0; i < KB; ++i) {
         const int k = t + i * Cfg::TPC;
