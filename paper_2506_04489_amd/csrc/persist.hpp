@@ -70,7 +70,7 @@ __device__ __noinline__ void pb_z_r2c(const PJob *jp, int item) {
     const T *rb = ra + n;
     C v[E::V];
     E::for_inputs(v, t, [&](int pos, int r) -> C {
-        if (r < E::R(0) / 2 && active) return C{ra[pos], rb[pos]};
+        if (r < E::R(0) / 2 && active) return C{g_load(&ra[pos]), g_load(&rb[pos])};
         return c_zero<C>();
     });
     IdxLine idx{q * Cfg::LINE};
@@ -83,9 +83,9 @@ __device__ __noinline__ void pb_z_r2c(const PJob *jp, int item) {
         for (int k = t; k <= n; k += Cfg::TPC) {
             const C z = lds[idx(k)];
             const C zc = lds[idx(k == 0 ? 0 : N - k)];
-            xa[k] = C{T(0.5) * (z.x + zc.x), T(0.5) * (z.y - zc.y)};
+            g_store(&xa[k], C{T(0.5) * (z.x + zc.x), T(0.5) * (z.y - zc.y)});
             const C d = C{z.x - zc.x, z.y + zc.y};
-            xb[k] = C{T(0.5) * d.y, -T(0.5) * d.x};
+            g_store(&xb[k], C{T(0.5) * d.y, -T(0.5) * d.x});
         }
     }
 }
@@ -109,12 +109,12 @@ __device__ __noinline__ void pb_y_fwd(const PJob *jp, int item) {
     C *dst = (C *)jb.A + (size_t)i1 * jb.plane + c;
     C v[E::V];
     E::for_inputs(v, t, [&](int pos, int r) -> C {
-        if (r < E::R(0) / 2 && valid) return src[(size_t)pos * jb.P];
+        if (r < E::R(0) / 2 && valid) return g_load(&src[(size_t)pos * jb.P]);
         return c_zero<C>();
     });
     E::template run_from<0>(v, lds, t, IdxInter<W>{col}, tw);
     E::for_outputs(v, t, [&](int pos, int, C &val) {
-        if (valid) dst[(size_t)pos * jb.pa] = val;
+        if (valid) g_store(&dst[(size_t)pos * jb.pa], val);
     });
 }
 
@@ -140,18 +140,18 @@ __device__ __noinline__ void pb_x_fused(const PJob *jp, int item) {
     const double *mrow = jb.mult + ((size_t)(b * (jb.P / 8) + c / 8) * (n + 1)) * 8 + (c & 7);
     C v[EF::V];
     EF::for_inputs(v, t, [&](int pos, int r) -> C {
-        if (r < EF::R(0) / 2 && valid) return src[pos * step];
+        if (r < EF::R(0) / 2 && valid) return g_load(&src[pos * step]);
         return c_zero<C>();
     });
     EF::template run_from<0>(v, lds, t, IdxInter<W>{col}, tw);
     EF::for_outputs(v, t, [&](int pos, int, C &val) {
         const int a = pos <= n ? pos : N - pos;
-        val = scale_mode(val, valid ? mrow[(size_t)a * 8] : 0.0);
+        val = scale_mode(val, valid ? g_load(&mrow[(size_t)a * 8]) : 0.0);
     });
     EI::template run_from<0>(v, lds, t, IdxInter<W>{col}, tw);
     C *dst = (C *)jb.A + (size_t)k2 * jb.pa + c;
     EI::for_outputs(v, t, [&](int pos, int r, C &val) {
-        if (valid && r < EI::R(EI::S - 1) / 2) dst[pos * step] = val;
+        if (valid && r < EI::R(EI::S - 1) / 2) g_store(&dst[pos * step], val);
     });
 }
 
@@ -173,13 +173,13 @@ __device__ __noinline__ void pb_y_inv(const PJob *jp, int item) {
     const C *src = (const C *)jb.A + (size_t)i1 * jb.plane + c;   // rows k2
     C v[E::V];
     E::for_inputs(v, t, [&](int pos, int) -> C {
-        if (valid) return src[(size_t)pos * jb.pa];
+        if (valid) return g_load(&src[(size_t)pos * jb.pa]);
         return c_zero<C>();
     });
     E::template run_from<0>(v, lds, t, IdxInter<W>{col}, tw);
     C *dst = (C *)jb.X + (size_t)i1 * n * jb.P + c;
     E::for_outputs(v, t, [&](int pos, int r, C &val) {
-        if (valid && r < E::R(E::S - 1) / 2) dst[(size_t)pos * jb.P] = val;
+        if (valid && r < E::R(E::S - 1) / 2) g_store(&dst[(size_t)pos * jb.P], val);
     });
 }
 
@@ -205,8 +205,8 @@ __device__ __noinline__ void pb_z_c2r(const PJob *jp, int item) {
     for (int i = 0; i < KB; ++i) {
         const int k = t + i * Cfg::TPC;
         if (active && k <= n) {
-            ba[i] = ya[k];
-            bb[i] = yb[k];
+            ba[i] = g_load(&ya[k]);
+            bb[i] = g_load(&yb[k]);
         }
     }
 #pragma unroll
@@ -231,8 +231,8 @@ __device__ __noinline__ void pb_z_c2r(const PJob *jp, int item) {
     T *ub = ua + n;
     E::for_outputs(v, t, [&](int pos, int r, C &val) {
         if (active && r < E::R(E::S - 1) / 2) {
-            ua[pos] = val.x;
-            ub[pos] = val.y;
+            g_store(&ua[pos], val.x);
+            g_store(&ub[pos], val.y);
         }
     });
 }
