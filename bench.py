@@ -35,14 +35,45 @@ KERNEL_SOURCES = ["paper_2506_04489_amd/csrc/fft_core.hpp", "paper_2506_04489_am
                   "paper_2506_04489_amd/tuning_gfx950.json"]
 
 
+def _code_only(text: str) -> str:
+    """C++ source without its comments and with whitespace runs collapsed,
+    so that an edit of the commentary leaves the record of the kernels valid."""
+    out = []
+    i, n = 0, len(text)
+    while i < n:
+        c = text[i]
+        if c in "\"'":                      # string or character literal
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def kernel_source_hash() -> str:
+    """Hash of what decides the pass kernels: the code of their sources
+    (comments and layout aside) and the launch-shape table."""
     import hashlib
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
         path = os.path.join(HERE, rel)
         if os.path.exists(path):
             with open(path, "rb") as f:
-                h.update(f.read())
+                data = f.read()
+            if rel.endswith((".hpp", ".h", ".hip", ".cpp")):
+                data = _code_only(data.decode("utf-8")).encode("utf-8")
+            h.update(data)
     return h.hexdigest()
 
 

@@ -45,9 +45,9 @@ extern "C" {
 typedef struct psp_plan psp_plan;       /* opaque, library owned */
 typedef struct psp_server psp_server;   /* opaque, library owned */
 
-/* Precision tier.  PSP_F32 keeps the kernel spectrum, Gaussian-sum data and
- * the multiply in FP64 and runs the FFT passes in FP32 (twiddles formed in
- * FP64 and rounded once to FP32). */
+/* Precision tier.  PSP_F32 keeps the kernel spectrum and the Gaussian-sum
+ * data in FP64 and runs the FFT passes and the multiply in FP32: twiddles
+ * and multiplier entries are the FP64 values rounded once to FP32. */
 #ifdef __cplusplus
 /* int-sized in C++ too, so that any value a C caller passes is a value of
  * the type (the library rejects the unknown ones) */

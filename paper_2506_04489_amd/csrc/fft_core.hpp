@@ -40,7 +40,7 @@ __device__ __forceinline__ double fmadd(double a, double b, double c) { return _
 __device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
 // --------------------------------------------------------------- twiddles
-// Table of W_N^m = exp(-2 pi i m / N), m <= N (W^N = W^0), in FP64 for both
+// Table of W_N^m = exp(-2 pi i m / N), 0 <= m < N, in FP64 for both
 // tiers.  Two ways to get a butterfly's powers W^{m r}, r = 1..R-1:
 // Twiddle loads the one entry W^m from the global table and forms the powers
 // by a multiplication tree of depth <= 4 (a few ulp of FP64; one load instead
