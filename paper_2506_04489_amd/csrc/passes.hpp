@@ -359,25 +359,32 @@ k_x_fused(JobRef jr, Chunk ck, int P, Twiddle<T> tw) {
     const int c = sub * W + col;
     const int cg = ck.tile0 * LayoutTile<T>::W + c;
     const bool valid = cg <= ck.n3;
-    const C *src = (const C *)jb.A + (size_t)k2 * ck.pa + c;        // rows i1
-    const size_t step = (size_t)ck.plane;
-    const double *mrow = jb.mult + ((size_t)(b * (P / 8) + cg / 8) * (n + 1)) * 8 + (cg & 7);
+    // 32-bit byte offsets from the buffers' bases (every buffer of a solve is
+    // far below 4 GB): one VALU add per access instead of 64-bit address
+    // arithmetic, and the bases stay in scalar registers
+    unsigned char *abase = (unsigned char *)jb.A;
+    const unsigned acol = (unsigned)(((size_t)k2 * ck.pa + c) * sizeof(C));   // rows i1
+    const unsigned astep = (unsigned)((size_t)ck.plane * sizeof(C));
+    const unsigned char *mbase = (const unsigned char *)jb.mult;
+    const unsigned mcol = (unsigned)((((size_t)(b * (P / 8) + cg / 8) * (n + 1)) * 8 + (cg & 7)) * sizeof(double));
     C v[EF::V];
     EF::for_inputs(v, t, [&](int pos, int r) -> C {
-        if (r < EF::R(0) / 2 && valid) return a_load<CP>(&src[pos * step]);
+        if (r < EF::R(0) / 2 && valid) return a_load<CP>((const C *)(abase + (acol + (unsigned)pos * astep)));
         return c_zero<C>();
     });
     const auto twx = tw_commit<T, N, Cfg::THREADS, true>(tw, twf, lds + Cfg::LDS_ELEMS);
     strided_stages<EF, Cfg, W>(v, lds, t, col, twx);
-    EF::for_outputs(v, t, [&](int pos, int, C &val) {
-        const int a = pos <= n ? pos : N - pos;
-        val = scale_mode(val, g_load(&mrow[(size_t)a * 8]));
+    EF::for_outputs(v, t, [&](int pos, int r, C &val) {
+        // the mode's multiplier row |k1|: for an even last radix, legs below
+        // R/2 hold the positions below n and the others those from n up
+        constexpr int RL = EF::R(EF::S - 1);
+        const int a = (RL % 2 == 0) ? (r < RL / 2 ? pos : N - pos) : (pos <= n ? pos : N - pos);
+        val = scale_mode(val, g_load((const double *)(mbase + (mcol + (unsigned)a * (8 * sizeof(double))))));
     });
     strided_stages<EI, Cfg, W>(v, lds, t, col, twx);
     if constexpr (!FULL) {
-        C *dst = (C *)jb.A + (size_t)k2 * ck.pa + c;
         EI::for_outputs(v, t, [&](int pos, int r, C &val) {
-            if (valid && r < EI::R(EI::S - 1) / 2) a_store<CP>(&dst[pos * step], val);
+            if (valid && r < EI::R(EI::S - 1) / 2) a_store<CP>((C *)(abase + (acol + (unsigned)pos * astep)), val);
         });
     } else {
         C *dst = (C *)jb.A2 + (size_t)k2 * P + cg;
